@@ -1,0 +1,196 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module is the only code that the product and the oracle both use.  It
+draws random data and rounds it once to its storage precision; it holds none of
+the method's arithmetic (no problem mapping, no partition, no solver step).
+
+Recipes (all numpy PCG64 ``default_rng(data_seed)``):
+
+* least squares  -- D N x n iid N(0,1); x_true iid N(0,1); y = D x_true + 0.01 N(0,1).
+  Stands in for the linear-regression use of Sec.3.1 (the lambda = 0 case).
+* LASSO          -- D iid N(0,1) with columns scaled to unit l2 norm; x_true has
+  nnz entries of random sign and magnitude U(1,3); y = D x_true + 0.05 N(0,1);
+  lambda = frac * lambda_max with lambda_max = |D'y|_inf / (N alpha).  Stands in
+  for the sparse-solution regression of Table 1 / Table 2 (dense data).
+* elastic-net batch -- instance sizes log-uniform, Gaussian D, 10% of x_true
+  non-zero, a 16-point log lambda grid per instance (Sec.3.1 cross-validation grids).
+* SVM            -- two Gaussian classes with means +-0.5 * 1 and identity covariance,
+  5% of labels flipped (stands in for the LIBSVM sets of Table 8, linear kernel).
+
+Storage: data are generated in float64 and rounded once (round to nearest even)
+to their storage type ("f64", "f32" or "bf16").  Both sides receive the rounded
+values; for "bf16" the values are held in float32 arrays whose entries are
+exactly representable in bfloat16.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def round_bf16(a) -> np.ndarray:
+    """Round to the nearest bfloat16 value (ties to even); returns float32."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    bits = f.view(np.uint32).astype(np.uint64)
+    bias = np.uint64(0x7FFF) + ((bits >> np.uint64(16)) & np.uint64(1))
+    r = ((bits + bias) >> np.uint64(16)) << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32).reshape(np.shape(a))
+
+
+def to_storage(a, storage: str) -> np.ndarray:
+    if storage == "f64":
+        return np.asarray(a, dtype=np.float64)
+    if storage == "f32":
+        return np.asarray(a, dtype=np.float32)
+    if storage == "bf16":
+        return round_bf16(np.asarray(a, dtype=np.float32))
+    raise ValueError(storage)
+
+
+@dataclass
+class RegressionWorkload:
+    """Elastic-net family instance: min 1/(2N)|y - D x|^2 + lam*(alpha|x|_1 + (1-alpha)/2|x|^2)."""
+    name: str
+    D: np.ndarray          # N x n, Fortran order, values exact in `storage`
+    y: np.ndarray          # N, float64
+    lam: float
+    alpha: float
+    block_size: int
+    beta0: float
+    storage: str
+    seed: int = 0          # partition seed
+    x_true: np.ndarray | None = None
+
+    @property
+    def N(self):
+        return self.D.shape[0]
+
+    @property
+    def n(self):
+        return self.D.shape[1]
+
+
+@dataclass
+class SVMWorkload:
+    """C-SVC dual instance (linear kernel): samples X (n x r) with labels y in {-1,+1}."""
+    name: str
+    X: np.ndarray          # n x r, C order (row i = sample i), values exact in `storage`
+    labels: np.ndarray     # n, float64 in {-1, +1}
+    C: float
+    block_size: int
+    beta0: float
+    storage: str
+    seed: int = 0
+
+    @property
+    def n(self):
+        return self.X.shape[0]
+
+    @property
+    def r(self):
+        return self.X.shape[1]
+
+
+def least_squares(N=2000, n=200, noise=0.01, data_seed=0, block_size=20, beta0=1.0,
+                  storage="f64", name="ols") -> RegressionWorkload:
+    rng = np.random.default_rng(data_seed)
+    D = rng.standard_normal((N, n))
+    x_true = rng.standard_normal(n)
+    Ds = to_storage(D, storage)
+    y = Ds.astype(np.float64) @ x_true + noise * rng.standard_normal(N)
+    return RegressionWorkload(name, np.asfortranarray(Ds), y, 0.0, 1.0, block_size, beta0,
+                              storage, 0, x_true)
+
+
+def lasso(N=20000, n=2000, nnz_frac=0.05, noise=0.05, lam_frac=0.1, alpha=1.0, data_seed=2,
+          block_size=64, storage="f32", normalize=True, name="lasso",
+          beta0=None) -> RegressionWorkload:
+    rng = np.random.default_rng(data_seed)
+    D = rng.standard_normal((N, n))
+    if normalize:
+        D /= np.linalg.norm(D, axis=0, keepdims=True)
+    nnz = max(1, int(round(nnz_frac * n)))
+    x_true = np.zeros(n)
+    pos = rng.choice(n, size=nnz, replace=False)
+    x_true[pos] = rng.choice([-1.0, 1.0], size=nnz) * rng.uniform(1.0, 3.0, size=nnz)
+    Ds = to_storage(D, storage)
+    Df = Ds.astype(np.float64)
+    y = Df @ x_true + noise * rng.standard_normal(N)
+    lam_max = np.max(np.abs(Df.T @ y)) / (N * alpha)
+    lam = lam_frac * lam_max
+    b0 = 0.1 * lam if beta0 is None else beta0   # gamma = 0.1 lambda for dense data (Sec.3.1)
+    return RegressionWorkload(name, np.asfortranarray(Ds), y, lam, alpha, block_size, b0,
+                              storage, 0, x_true)
+
+
+def gaussian_en(N, n, nnz_frac=0.1, noise=0.05, lam_frac=0.1, alpha=0.5, data_seed=3,
+                block_size=64, storage="bf16", name="en", beta0=None) -> RegressionWorkload:
+    """Gaussian (unnormalised) design; x_true with nnz_frac non-zeros drawn N(0,1)."""
+    rng = np.random.default_rng(data_seed)
+    D = rng.standard_normal((N, n), dtype=np.float32)
+    nnz = max(1, int(round(nnz_frac * n)))
+    x_true = np.zeros(n)
+    pos = rng.choice(n, size=nnz, replace=False)
+    x_true[pos] = rng.standard_normal(nnz)
+    Ds = to_storage(D, storage)
+    Df = Ds.astype(np.float64)
+    y = Df @ x_true + noise * rng.standard_normal(N)
+    lam_max = np.max(np.abs(Df.T @ y)) / (N * alpha)
+    lam = lam_frac * lam_max
+    b0 = 0.1 * lam if beta0 is None else beta0
+    return RegressionWorkload(name, np.asfortranarray(Ds), y, lam, alpha, block_size, b0,
+                              storage, 0, x_true)
+
+
+def lambda_grid(lam_max, points=16, ratio=0.01):
+    """lambda_j = lam_max * ratio^(j/(points-1)), j = 0..points-1 (a log grid)."""
+    j = np.arange(points)
+    return lam_max * ratio ** (j / (points - 1))
+
+
+def en_batch_sizes(count=256, data_seed=3, Nlo=1000, Nhi=20000, nlo=100, nhi=4000):
+    """Log-uniform instance sizes (N_i, n_i) for the batched elastic-net paths."""
+    rng = np.random.default_rng(data_seed)
+    N = np.round(np.exp(rng.uniform(np.log(Nlo), np.log(Nhi), size=count))).astype(np.int64)
+    n = np.round(np.exp(rng.uniform(np.log(nlo), np.log(nhi), size=count))).astype(np.int64)
+    return N, n
+
+
+def svm(n=20000, r=256, shift=0.5, flip=0.05, Cbox=1.0, data_seed=4, block_size=128,
+        storage="f32", name="svm", beta0=None) -> SVMWorkload:
+    rng = np.random.default_rng(data_seed)
+    labels = rng.choice([-1.0, 1.0], size=n)
+    X = shift * labels[:, None] * np.ones((1, r)) + rng.standard_normal((n, r))
+    nflip = int(round(flip * n))
+    idx = rng.choice(n, size=nflip, replace=False)
+    labels = labels.copy()
+    labels[idx] = -labels[idx]
+    Xs = to_storage(X, storage)
+    p = -(-n // block_size)
+    b0 = 0.1 * p if beta0 is None else beta0       # beta = 0.1 p (Sec.3.2)
+    return SVMWorkload(name, np.ascontiguousarray(Xs), labels, float(Cbox), block_size, b0,
+                       storage, 0)
+
+
+# The five benchmark workloads ------------------------------------------------
+
+def ols_2000x200():
+    """Least squares, D 2000x200 FP64, p = 10 blocks of 20, beta = 1, 300 iterations, seed 0."""
+    return least_squares(2000, 200, 0.01, 0, 20, 1.0, "f64", name="ols_2000x200")
+
+
+def lasso_20000x2000(storage="f32"):
+    """LASSO, D 20000x2000 unit-norm columns (FP32), 5% non-zeros, lambda = 0.1 lambda_max, s = 64."""
+    return lasso(20000, 2000, 0.05, 0.05, 0.1, 1.0, 2, 64, storage, name="lasso_20000x2000")
+
+
+def svm_20000x256():
+    """SVM dual, 20000 samples x 256 features (FP32), C = 1, s = 128, beta = 0.1 p."""
+    return svm(20000, 256, 0.5, 0.05, 1.0, 4, 128, "f32", name="svm_20000x256")
+
+
+def lasso_10000x100000(storage="bf16"):
+    """High-dimensional LASSO, D 10000x100000 (BF16), 1% non-zeros, lambda = 0.05 lambda_max, s = 128."""
+    return gaussian_en(10000, 100000, 0.01, 0.05, 0.05, 1.0, 5, 128, storage,
+                       name="lasso_10000x100000")
