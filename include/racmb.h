@@ -1,0 +1,201 @@
+/*
+ * racmb.h -- C ABI of the MI355X (gfx950) RAC-MBADMM library.
+ *
+ * RAC-MBADMM is the randomly assembled cyclic multi-block ADMM of Zhu, Mihic and
+ * Ye, "On a Randomized Multi-Block ADMM for Solving Selected Machine Learning
+ * Problems" (arXiv 1907.01995).  The library solves the convex QP of Eq.(1) in
+ * the split form used by the paper's machine-learning applications (Sec.3):
+ *
+ *     min_x  1/2 x'(F'F/Ns + diag h) x + c'x + P(z) + obj_const
+ *     s.t.   a'x = b          (optional single equality row; Eq.(9)'s y'z = 0)
+ *            x - z = 0        (the split of Eq.(7)/(8); z is solved as one block)
+ *
+ * with P = 0 (least squares), the elastic-net penalty of Eq.(6)
+ * lambda*(alpha*|z|_1 + (1-alpha)/2*|z|^2), or the indicator of a box [lo, hi]
+ * (the C-SVC dual of Eq.(9)).  For regression F = X (N x n) and Ns = N, so that
+ * H = X'X/N and c = -X'y/N (Sec.3.1); for the linear-kernel SVM dual F = G'
+ * with G = diag(y) X, Ns = 1, c = -e and a = y (Sec.3.2).
+ *
+ * One iteration (Eq.(3)): draw a random partition of the n variables into p
+ * balanced blocks, minimise the augmented Lagrangian (Eq.(2), one penalty beta
+ * on every constraint row) exactly over each block in the drawn order, then over
+ * z, then take the dual step xi <- xi - beta(x - z), mu <- mu - beta(a'x - b).
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented as "device" are HIP device pointers owned by the
+ *    caller; the library never frees them and reads them only during calls
+ *    (a solver handle keeps borrowing the problem's pointers until destroyed).
+ *  - Arrays are FP64 unless stated; F is column-major with leading dimension ldF.
+ *  - Work is enqueued on the caller's stream; calls that return results
+ *    synchronise that stream before returning.
+ *  - Errors are returned as rac_status codes, never thrown across the ABI.
+ *    A non-finite scalar argument, a non-positive beta, p < 1 or p > n, and
+ *    a block larger than RAC_MAX_BLOCK give RAC_ERR_ARG.
+ */
+#ifndef RACMB_H
+#define RACMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RAC_MAX_BLOCK 128   /* largest block size ceil(n/p) the kernels accept */
+#define RAC_MLP_IN 8        /* controller features */
+#define RAC_MLP_HIDDEN 64   /* controller hidden width */
+#define RAC_MLP_NPARAM (RAC_MLP_HIDDEN * RAC_MLP_IN + RAC_MLP_HIDDEN + \
+                        RAC_MLP_HIDDEN * RAC_MLP_HIDDEN + RAC_MLP_HIDDEN + RAC_MLP_HIDDEN + 1)
+
+typedef enum {
+  RAC_OK = 0,
+  RAC_ERR_ARG = 1,         /* invalid argument (see conventions above) */
+  RAC_ERR_NOT_PD = 2,      /* Assumption 2.1 violated: a block matrix H_BB + beta(I + a_B a_B')
+                              had a non-positive Cholesky pivot; the failing (iteration, block)
+                              is reported in rac_result */
+  RAC_ERR_DEVICE = 3,      /* a HIP call failed */
+  RAC_ERR_NOMEM = 4,       /* workspace allocation failed */
+  RAC_ERR_UNSUPPORTED = 5  /* valid but not implemented (e.g. dtype/precision pair) */
+} rac_status;
+
+typedef enum { RAC_RUN_CONVERGED = 0, RAC_RUN_MAX_ITER = 1, RAC_RUN_DIVERGED = 2 } rac_run_status;
+typedef enum { RAC_PROX_NONE = 0, RAC_PROX_ELASTIC_NET = 1, RAC_PROX_BOX = 2 } rac_prox;
+typedef enum { RAC_DT_F64 = 0, RAC_DT_F32 = 1, RAC_DT_BF16 = 2 } rac_dtype;
+/* FP64: block Grams formed in FP64.  MIXED: block Grams formed on the matrix cores
+ * in the data's own precision (FP32 or BF16 inputs, FP32 accumulation), summed over
+ * row chunks in FP64; gradients, residual maintenance, Cholesky pivots, duals and
+ * norms stay FP64 in both modes, so the fixed point is the FP64 one. */
+typedef enum { RAC_PREC_FP64 = 0, RAC_PREC_MIXED = 1 } rac_precision;
+/* Penalty schedule: fixed; residual balancing (multiply by tau when r_p > mu_rb r_d,
+ * divide when r_d > mu_rb r_p); the controller network (falls back to residual
+ * balancing when its output is not finite); or a given per-iteration schedule. */
+typedef enum { RAC_BETA_FIXED = 0, RAC_BETA_RESBAL = 1, RAC_BETA_MLP = 2, RAC_BETA_SCHEDULE = 3 } rac_beta_mode;
+
+typedef struct {
+  int64_t n;            /* number of variables (>= 1) */
+  int64_t rows;         /* rows of F (>= 1) */
+  const void* F;        /* device, column-major rows x n, element type F_dtype */
+  int64_t ldF;          /* leading dimension of F (>= rows) */
+  int32_t F_dtype;      /* rac_dtype */
+  int32_t prox;         /* rac_prox */
+  double Ns;            /* H = F'F/Ns + diag h (> 0) */
+  const double* h;      /* device, n, or NULL */
+  const double* c;      /* device, n */
+  const double* a;      /* device, n, or NULL: the equality row a'x = b */
+  double b;
+  double lambda, alpha; /* elastic net: lambda >= 0, 0 <= alpha <= 1 */
+  double lo, hi;        /* box bounds (lo <= hi) */
+  double obj_const;     /* constant added to the reported objective */
+} rac_problem;
+
+typedef struct {
+  int64_t num_blocks;   /* p (1 <= p <= n, ceil(n/p) <= RAC_MAX_BLOCK) */
+  uint64_t seed;        /* partition seed */
+  uint64_t instance;    /* instance id mixed into the partition keys */
+  int32_t precision;    /* rac_precision */
+  int32_t beta_mode;    /* rac_beta_mode */
+  double beta0;         /* initial penalty (> 0) */
+  double rb_mu, rb_tau; /* residual balancing thresholds (defaults 10, 2 when <= 0) */
+  const double* beta_schedule;  /* host, max_iter entries, for RAC_BETA_SCHEDULE */
+  const float* mlp_weights;     /* device, RAC_MLP_NPARAM floats, for RAC_BETA_MLP */
+  double mlp_ymax;      /* bound of the controller's log multiplier (default ln 10) */
+  int64_t check_every;  /* T: KKT check and penalty decision every T iterations (>= 1) */
+  int64_t max_iter;     /* iteration budget of one rac_solver_run call; history capacity */
+  double tol;           /* stop at the first check with KKT residual <= tol */
+  int32_t sweep_groups; /* workgroups cooperating in the sweep (0 = automatic) */
+  int32_t row_chunks;   /* row chunks of the block Gram contraction (0 = automatic) */
+} rac_opts;
+
+typedef struct {
+  int64_t iters;        /* iterations completed by the last run */
+  int32_t status;       /* rac_run_status */
+  int32_t pad0;
+  double kkt;           /* KKT residual at the last check */
+  double beta;          /* penalty after the last iteration */
+  double objective;     /* objective at z after the run */
+  int64_t fail_iter;    /* RAC_ERR_NOT_PD: failing iteration (global count) and block */
+  int64_t fail_block;
+} rac_result;
+
+typedef struct rac_solver_s* rac_solver;
+
+/* Create a solver for `prob` with options `opts` on the current HIP device.
+ * Validates the arguments, allocates the workspace (partitions, block factors,
+ * sweep partials, state, history) and zeroes the state (x = z = xi = 0, mu = 0).
+ * The problem's device arrays are borrowed until rac_solver_destroy. */
+rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_solver* out);
+rac_status rac_solver_destroy(rac_solver s);
+
+/* Run up to opts.max_iter iterations (Eq.(3)) from the current state, stopping at
+ * the first KKT check <= tol, on `stream` (a hipStream_t; NULL = default stream).
+ * Synchronises the stream and fills *res.  Returns RAC_ERR_NOT_PD when
+ * Assumption 2.1 failed (res->fail_iter, res->fail_block name the block). */
+rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res);
+
+/* Copy the state in or out (device pointers, n doubles each; mu on the host).
+ * Setting the state recomputes the maintained residuals u = Fx and t = a'x. */
+rac_status rac_solver_set_state(rac_solver s, const double* x, const double* z, const double* xi,
+                                double mu, double beta, int64_t iter, void* stream);
+rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, double* mu,
+                                double* beta, int64_t* iter, void* stream);
+
+/* Per-iteration history of the last run: 4 doubles per iteration, (r_p, r_d,
+ * beta, KKT or NaN), copied to host memory `out` (capacity max_iter*4). */
+rac_status rac_solver_history(rac_solver s, double* out, int64_t capacity, int64_t* count);
+
+/* Serialise / restore the complete solver state (x, z, xi, mu, t, beta, iteration
+ * counter and controller memory) to / from a host buffer, for checkpoint/resume.
+ * With buf == NULL, *bytes receives the size needed. */
+rac_status rac_state_export(rac_solver s, void* buf, size_t* bytes);
+rac_status rac_state_import(rac_solver s, const void* buf, size_t bytes);
+
+/* The random partition of Eq.(3) for (seed, instance, iter): perm (device, n int32)
+ * lists the variables sorted by their SplitMix64 key (ties by index); block i
+ * holds perm[floor(i n/p) .. floor((i+1) n/p)).  Bit-identical to the oracle. */
+rac_status rac_permutation(uint64_t seed, uint64_t instance, int64_t iter, int64_t n,
+                           int32_t* perm, void* stream);
+
+/* KKT residual of the split problem at (x, z, xi, mu) (device vectors, n each):
+ * out[0] = max of the three parts, out[1] = primal feasibility, out[2] =
+ * stationarity, out[3] = dual feasibility (host, 4 doubles).  Definitions:
+ *   feas = |x-z|_inf/(1+max(|x|_inf,|z|_inf)), and |a'x-b|/(1+|b|+|a|_inf|x|_inf)
+ *   stat = |F'Fx/Ns + h.x + c - xi - mu a|_inf / scale
+ *   dual = dist(-xi, subdifferential of P at z) / scale
+ *   scale = max(|F'Fx/Ns + h.x|_inf, |c|_inf, |xi|_inf, |mu||a|_inf, 1e-300). */
+rac_status rac_kkt(const rac_problem* prob, const double* x, const double* z, const double* xi,
+                   double mu, void* stream, double* out);
+
+/* Objective 1/2 z'Hz + c'z + P(z) + obj_const at device vector z (host result). */
+rac_status rac_objective(const rac_problem* prob, const double* z, void* stream, double* out);
+
+/* Regression set-up on the device: c = -F'y/Ns (y device, rows doubles). */
+rac_status rac_regression_c(const void* F, int32_t F_dtype, int64_t rows, int64_t n, int64_t ldF,
+                            double Ns, const double* y, double* c, void* stream);
+
+/* Block matrices of one iteration, for inspection: writes, for each block i,
+ * H_BB + beta(I + a_B a_B') (lower triangle valid, padded stride sp = block
+ * size rounded up to 16) to out (device, p*sp*sp doubles). */
+rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed, uint64_t instance,
+                              int64_t iter, double beta, int32_t precision, double* out,
+                              int64_t* sp_out, void* stream);
+
+/* Controller network (8 -> 64 -> 64 -> 1, tanh hidden, y = ymax tanh(o)), FP32.
+ * Parameters (device, RAC_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64], b2[64],
+ * W3[64], b3.  Forward: feats (device, batch x 8) -> y (device, batch). */
+rac_status rac_mlp_forward(const float* w, const float* feats, int64_t batch, float ymax, float* y,
+                           void* stream);
+/* Mean squared loss 1/(2B) sum (y - target)^2 and its gradient (device, NPARAM floats);
+ * *loss (host) receives the loss. */
+rac_status rac_mlp_loss_grad(const float* w, const float* feats, const float* target, int64_t batch,
+                             float ymax, float* grad, double* loss, void* stream);
+/* One Adam step (bias-corrected, step t >= 1) on w with moments m, v (device). */
+rac_status rac_mlp_adam(float* w, const float* grad, float* m, float* v, int64_t t, float lr,
+                        float b1, float b2, float eps, void* stream);
+
+const char* rac_status_str(rac_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RACMB_H */

@@ -1,0 +1,172 @@
+// rac_internal.h -- shared declarations of the HIP kernels' host launchers and
+// the device-side helpers used by every kernel file of the gfx950 library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "racmb.h"
+
+namespace rac {
+
+constexpr int kMaxBlock = RAC_MAX_BLOCK;
+constexpr int kThreads = 256;           // four 64-wide wavefronts per workgroup
+constexpr int kFlagStride = 16;         // uint64 words between sweep flags (128 B lines)
+
+// Mutable scalar state kept on the device so the whole iteration runs without
+// host round trips; the host reads it back once per chunk of T iterations.
+struct DevScalars {
+  double t;          // a'x, maintained by the sweep
+  double mu;         // multiplier of the equality row
+  double beta;       // current penalty
+  double kkt;        // KKT residual at the last check
+  double kkt_prev;   // KKT residual at the check before
+  double last_l10;   // log10 of the last penalty multiplier
+  double rp_first;   // primal residual of the first iteration (divergence test)
+  double rp, rd;     // residuals of the last iteration
+  double rp_win, rd_win;  // residuals at the first iteration of the current window
+  double objective;
+  int64_t k;         // iterations completed (global count)
+  int64_t decisions; // controller decisions taken
+  uint64_t fail_key; // (iteration << 32 | block) of the first non-PD block, or ~0
+  int32_t status;    // 0 running, 1 converged, 2 diverged
+  int32_t pad;
+};
+
+// Element loads of the data matrix, converted exactly to FP64 / FP32.
+__device__ __forceinline__ double ld_f64(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ double ld_f64(const float* p, int64_t i) { return (double)p[i]; }
+__device__ __forceinline__ double ld_f64(const uint16_t* p, int64_t i) {
+  return (double)__uint_as_float(((uint32_t)p[i]) << 16);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): state += 0x9e3779b97f4a7c15; output = mix(state).
+__host__ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ULL;
+
+__host__ __device__ __forceinline__ int64_t block_start(int64_t i, int64_t n, int64_t p) {
+  return (i * n) / p;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (one per kernel family).  All return hipError_t of the launch.
+
+struct PermWork {          // scratch of the bucketed key sort (per iteration of a chunk)
+  uint64_t* keys;          // [T][n]
+  uint32_t* count;         // [T][nb]  (kept zero between uses)
+  uint32_t* offset;        // [T][nb+1]
+  uint32_t* fill;          // [T][nb]  (kept zero between uses)
+  int32_t* members;        // [T][n]
+  int64_t nb;              // buckets per iteration (power of two >= n)
+  int log2nb;
+};
+hipError_t launch_permutations(uint64_t seed, uint64_t inst, int64_t iter0, int64_t T, int64_t n,
+                               const PermWork& w, int32_t* perm /* [T][n] */, hipStream_t st);
+
+struct GramArgs {
+  const void* F; int32_t dtype; int64_t ldF; int64_t rows; int64_t n; int64_t p;
+  const int32_t* perm;     // this iteration's permutation
+  int32_t precision;       // rac_precision
+  int R;                   // row chunks
+  int sp;                  // padded block size (multiple of 16, <= 128)
+  double* partial;         // [p][R][sp*sp]
+};
+hipError_t launch_gram(const GramArgs& a, hipStream_t st);
+
+struct FactorArgs {
+  const double* partial; int R; int sp; int64_t n; int64_t p; const int32_t* perm;
+  double Ns; const double* h; const double* a; const double* beta_ptr; double beta_val;
+  double* Minv;            // [p][sp*sp] inverse block matrices (or the block matrices
+  int write_matrix;        //  themselves when write_matrix != 0)
+  DevScalars* sc;          // failure reporting (may be null)
+  int64_t iter_global;
+  int publish_beta;        // write the beta used into sc->beta (given schedules)
+};
+hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
+
+struct SweepArgs {
+  const void* F; int32_t dtype; int64_t ldF; int64_t rows; int64_t n; int64_t p;
+  const int32_t* perm; const double* Minv; int sp;
+  const double* c; const double* h; const double* a; double b; double Ns;
+  double* x; const double* z; const double* xi; double* u;
+  DevScalars* sc;
+  double* partials;        // [2][K][kMaxBlock]
+  uint64_t* flags;         // [K * kFlagStride], monotone epochs
+  uint64_t epoch_base;
+  int K;
+};
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
+
+struct UpdateArgs {
+  int64_t n; int32_t prox; double lam, alpha, lo, hi; double b; int has_eq;
+  const double* x; double* z; double* xi; double* zprev;
+  DevScalars* sc;
+  double* red;             // reduction scratch (>= 2 per workgroup)
+  uint32_t* done;          // completion counter (kept zero between uses)
+  double* hist;            // [cap][4] or null
+  int64_t hist_cap;
+  int64_t hist_base;       // global iteration index of this run's first iteration
+  int64_t T;               // check period (window start bookkeeping)
+};
+hipError_t launch_zdual(const UpdateArgs& a, hipStream_t st);
+
+constexpr int kRedSlots = 10 * 256;   // doubles of reduction scratch needed by any kernel
+
+struct KKTArgs {
+  const void* F; int32_t dtype; int64_t ldF; int64_t rows; int64_t n; double Ns;
+  const double* h; const double* c; const double* a; double b; int32_t prox;
+  double lam, alpha, lo, hi;
+  const double* x; const double* z; const double* xi;
+  const double* u;         // F x (rows)
+  const double* mu_ptr; double mu_val;   // mu from the device scalars, or a value
+  double* red;             // kRedSlots doubles
+  uint32_t* done;
+  double* out;             // [4] KKT, feas, stat, dual
+};
+hipError_t launch_kkt(const KKTArgs& a, hipStream_t st);
+
+struct ControlArgs {
+  DevScalars* sc; const double* kkt_out; int32_t beta_mode; double rb_mu, rb_tau, tol;
+  const float* mlp_w; double mlp_ymax; int decide; double* hist; int64_t hist_cap;
+  int64_t hist_base;
+};
+hipError_t launch_control(const ControlArgs& a, hipStream_t st);
+
+// u = F x through nparts column-chunk partials (part: nparts*rows doubles), fixed-order sum.
+hipError_t launch_matvec_F_parts(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,
+                                 const double* x, double* u, double* part, int nparts,
+                                 hipStream_t st);
+// out = scale F'u
+hipError_t launch_matvec_Ft(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,
+                            const double* u, double scale, double* out, hipStream_t st);
+hipError_t launch_dot_red(const double* a, const double* x, int64_t n, double* red, uint32_t* done,
+                          double* out, hipStream_t st);
+// objective from u = F z
+hipError_t launch_objective_red(int64_t rows, int64_t n, double Ns, const double* h, const double* c,
+                                int32_t prox, double lam, double alpha, double cst, const double* z,
+                                const double* u, double* red, uint32_t* done, double* out,
+                                hipStream_t st);
+
+// Controller network
+hipError_t launch_mlp_forward(const float* w, const float* feats, int64_t batch, float ymax,
+                              float* y, hipStream_t st);
+hipError_t launch_mlp_loss_grad(const float* w, const float* feats, const float* target,
+                                int64_t batch, float ymax, float* grad, float* partial_grad,
+                                float* loss_part, int nparts, hipStream_t st);
+hipError_t launch_mlp_adam(float* w, const float* g, float* m, float* v, int64_t t, float lr,
+                           float b1, float b2, float eps, hipStream_t st);
+
+}  // namespace rac

@@ -1,0 +1,652 @@
+// solver.cpp -- host side of the library: argument validation, workspace,
+// the per-chunk launch sequence of RAC-MBADMM, and the C ABI of racmb.h.
+//
+// One iteration (Eq.(3)) is four device phases, all enqueued on the caller's
+// stream with no host round trip:
+//   assemble  k_gram + k_factor : every block matrix of the drawn partition and
+//                                 its inverse, all blocks in parallel;
+//   sweep     k_sweep           : the sequential Gauss-Seidel pass (one
+//                                 cooperative persistent launch);
+//   z + dual  k_zdual           : z block, dual step, residual norms, history.
+// The partitions of a whole chunk of T iterations are drawn by one set of
+// sort launches up front (they depend only on the seed and the iteration
+// index).  After the chunk, k_kkt evaluates the KKT residual and k_control
+// applies the stopping test and the penalty rule; the host then reads the
+// 144-byte scalar block once to decide whether to continue.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rac_internal.h"
+#include "racmb.h"
+
+using namespace rac;
+
+namespace {
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return RAC_ERR_DEVICE;       \
+  } while (0)
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+size_t dtype_size(int32_t dt) {
+  switch (dt) {
+    case RAC_DT_F64: return 8;
+    case RAC_DT_F32: return 4;
+    case RAC_DT_BF16: return 2;
+    default: return 0;
+  }
+}
+
+rac_status validate_problem(const rac_problem* P) {
+  if (!P) return RAC_ERR_ARG;
+  if (P->n < 1 || P->rows < 1 || !P->F || P->ldF < P->rows || !P->c) return RAC_ERR_ARG;
+  if (P->n > (int64_t)INT32_MAX) return RAC_ERR_ARG;
+  if (dtype_size(P->F_dtype) == 0) return RAC_ERR_ARG;
+  if (P->prox < RAC_PROX_NONE || P->prox > RAC_PROX_BOX) return RAC_ERR_ARG;
+  if (!is_fin(P->Ns) || !(P->Ns > 0.0) || !is_fin(P->b) || !is_fin(P->obj_const)) return RAC_ERR_ARG;
+  if (P->prox == RAC_PROX_ELASTIC_NET &&
+      (!is_fin(P->lambda) || P->lambda < 0.0 || !is_fin(P->alpha) || P->alpha < 0.0 || P->alpha > 1.0))
+    return RAC_ERR_ARG;
+  if (P->prox == RAC_PROX_BOX && (!is_fin(P->lo) || !is_fin(P->hi) || P->lo > P->hi)) return RAC_ERR_ARG;
+  return RAC_OK;
+}
+
+int padded(int64_t s) { return (int)((s + 15) / 16 * 16); }
+
+struct Buffers {
+  std::vector<void*> owned;
+  template <typename T> rac_status alloc(T** p, size_t count) {
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, sizeof(T) * count) != hipSuccess) return RAC_ERR_NOMEM;
+    owned.push_back(q);
+    *p = (T*)q;
+    return RAC_OK;
+  }
+  void release() {
+    for (void* q : owned) (void)hipFree(q);
+    owned.clear();
+  }
+};
+
+#define ALLOC(buf, ptr, count)                    \
+  do {                                            \
+    rac_status r_ = (buf).alloc(&(ptr), (count)); \
+    if (r_ != RAC_OK) return r_;                  \
+  } while (0)
+
+rac_status alloc_perm_work(Buffers& B, int64_t T, int64_t n, PermWork* w, int32_t** perm) {
+  int64_t nb = 1;
+  int lg = 0;
+  while (nb < n) { nb <<= 1; ++lg; }
+  w->nb = nb;
+  w->log2nb = lg;
+  ALLOC(B, w->keys, (size_t)(T * n));
+  ALLOC(B, w->count, (size_t)(T * nb));
+  ALLOC(B, w->offset, (size_t)(T * (nb + 1)));
+  ALLOC(B, w->fill, (size_t)(T * nb));
+  ALLOC(B, w->members, (size_t)(T * n));
+  ALLOC(B, *perm, (size_t)(T * n));
+  HIPCHK(hipMemset(w->count, 0, sizeof(uint32_t) * T * nb));
+  HIPCHK(hipMemset(w->fill, 0, sizeof(uint32_t) * T * nb));
+  return RAC_OK;
+}
+
+int auto_sweep_groups(int64_t rows) {
+  int64_t K = rows / 320;
+  if (K < 1) K = 1;
+  if (K > 64) K = 64;
+  return (int)K;
+}
+
+int auto_row_chunks(int64_t p, int64_t rows) {
+  int64_t R = (512 + p - 1) / p;
+  int64_t rmax = rows / 128;
+  if (rmax < 1) rmax = 1;
+  if (R > rmax) R = rmax;
+  if (R < 1) R = 1;
+  return (int)R;
+}
+
+int matvec_parts(int64_t n) {
+  int64_t q = (n + 255) / 256;
+  return (int)(q < 1 ? 1 : (q > 64 ? 64 : q));
+}
+
+}  // namespace
+
+struct rac_solver_s {
+  rac_problem P{};
+  rac_opts O{};
+  int64_t n = 0, rows = 0, p = 0, T = 1;
+  int sp = 16, R = 1, K = 1;
+  Buffers buf;
+  int32_t* perm = nullptr;
+  PermWork pw{};
+  double* partial = nullptr;
+  double* Minv = nullptr;
+  double *x = nullptr, *z = nullptr, *xi = nullptr, *zprev = nullptr, *u = nullptr;
+  DevScalars* sc = nullptr;
+  double* sweep_part = nullptr;
+  uint64_t* flags = nullptr;
+  uint64_t epoch = 0;
+  double* red = nullptr;
+  uint32_t* done = nullptr;
+  double* kkt_out = nullptr;
+  double* obj_out = nullptr;
+  double* hist = nullptr;
+  int64_t hist_cap = 0, hist_count = 0;
+  double* d_sched = nullptr;
+  double* mv_part = nullptr;
+  int mv_nparts = 1;
+  double* uz = nullptr;     // F z for the objective
+  DevScalars hsc{};
+};
+
+namespace {
+
+DevScalars fresh_scalars(double beta) {
+  DevScalars s{};
+  s.t = 0.0;
+  s.mu = 0.0;
+  s.beta = beta;
+  s.kkt = NAN;
+  s.kkt_prev = -1.0;
+  s.last_l10 = 0.0;
+  s.rp_first = -1.0;
+  s.rp = s.rd = s.rp_win = s.rd_win = 0.0;
+  s.objective = NAN;
+  s.k = 0;
+  s.decisions = 0;
+  s.fail_key = ~0ULL;
+  s.status = 0;
+  return s;
+}
+
+rac_status fx_into_u(rac_solver s, const double* x, double* u, hipStream_t st) {
+  HIPCHK(launch_matvec_F_parts(s->P.F, s->P.F_dtype, s->P.ldF, s->rows, s->n, x, u, s->mv_part,
+                               s->mv_nparts, st));
+  return RAC_OK;
+}
+
+rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
+  const rac_problem& P = s->P;
+  const int64_t k0 = s->hsc.k;
+  HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
+  const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
+  for (int64_t t = 0; t < Tc; ++t) {
+    const int32_t* perm = s->perm + t * s->n;
+    GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
+               s->partial};
+    HIPCHK(launch_gram(g, st));
+    FactorArgs f{};
+    f.partial = s->partial; f.R = s->R; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
+    f.Ns = P.Ns; f.h = P.h; f.a = P.a;
+    f.beta_ptr = sched ? s->d_sched + (run_offset + t) : &s->sc->beta;
+    f.beta_val = 0.0; f.Minv = s->Minv; f.write_matrix = 0; f.sc = s->sc;
+    f.iter_global = k0 + t; f.publish_beta = sched ? 1 : 0;
+    HIPCHK(launch_factor(f, st));
+    SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->Minv, s->sp, P.c, P.h, P.a,
+                P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K};
+    HIPCHK(launch_sweep(w, st));
+    s->epoch += (uint64_t)s->p;
+    UpdateArgs za{};
+    za.n = s->n; za.prox = P.prox; za.lam = P.lambda; za.alpha = P.alpha; za.lo = P.lo; za.hi = P.hi;
+    za.b = P.b; za.has_eq = P.a ? 1 : 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
+    za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
+    za.hist_base = k0 - run_offset; za.T = s->T;
+    HIPCHK(launch_zdual(za, st));
+  }
+  KKTArgs ka{};
+  ka.F = P.F; ka.dtype = P.F_dtype; ka.ldF = P.ldF; ka.rows = s->rows; ka.n = s->n; ka.Ns = P.Ns;
+  ka.h = P.h; ka.c = P.c; ka.a = P.a; ka.b = P.b; ka.prox = P.prox; ka.lam = P.lambda;
+  ka.alpha = P.alpha; ka.lo = P.lo; ka.hi = P.hi; ka.x = s->x; ka.z = s->z; ka.xi = s->xi;
+  ka.u = s->u; ka.mu_ptr = &s->sc->mu; ka.mu_val = 0.0; ka.red = s->red; ka.done = s->done;
+  ka.out = s->kkt_out;
+  HIPCHK(launch_kkt(ka, st));
+  ControlArgs ca{};
+  ca.sc = s->sc; ca.kkt_out = s->kkt_out; ca.beta_mode = s->O.beta_mode; ca.rb_mu = s->O.rb_mu;
+  ca.rb_tau = s->O.rb_tau; ca.tol = s->O.tol; ca.mlp_w = s->O.mlp_weights; ca.mlp_ymax = s->O.mlp_ymax;
+  ca.decide = ((k0 + Tc) % s->T == 0) ? 1 : 0; ca.hist = s->hist; ca.hist_cap = s->hist_cap;
+  ca.hist_base = k0 - run_offset;
+  HIPCHK(launch_control(ca, st));
+  return RAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rac_status_str(rac_status s) {
+  switch (s) {
+    case RAC_OK: return "ok";
+    case RAC_ERR_ARG: return "invalid argument";
+    case RAC_ERR_NOT_PD: return "block matrix not positive definite (Assumption 2.1)";
+    case RAC_ERR_DEVICE: return "HIP device error";
+    case RAC_ERR_NOMEM: return "out of device memory";
+    case RAC_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_solver* out) {
+  if (!out || !opts) return RAC_ERR_ARG;
+  *out = nullptr;
+  rac_status v = validate_problem(prob);
+  if (v != RAC_OK) return v;
+  rac_opts O = *opts;
+  const int64_t n = prob->n;
+  if (O.num_blocks < 1 || O.num_blocks > n) return RAC_ERR_ARG;
+  const int64_t smax = (n + O.num_blocks - 1) / O.num_blocks;
+  if (smax > RAC_MAX_BLOCK) return RAC_ERR_ARG;
+  if (!is_fin(O.beta0) || !(O.beta0 > 0.0)) return RAC_ERR_ARG;
+  if (O.check_every < 1 || O.max_iter < 0 || !is_fin(O.tol) || O.tol < 0.0) return RAC_ERR_ARG;
+  if (O.precision != RAC_PREC_FP64 && O.precision != RAC_PREC_MIXED) return RAC_ERR_ARG;
+  if (O.beta_mode < RAC_BETA_FIXED || O.beta_mode > RAC_BETA_SCHEDULE) return RAC_ERR_ARG;
+  if (O.rb_mu <= 0.0) O.rb_mu = 10.0;
+  if (O.rb_tau <= 0.0) O.rb_tau = 2.0;
+  if (!is_fin(O.rb_mu) || !is_fin(O.rb_tau) || O.rb_tau < 1.0) return RAC_ERR_ARG;
+  if (!(O.mlp_ymax > 0.0)) O.mlp_ymax = std::log(10.0);
+  if (O.beta_mode == RAC_BETA_MLP && !O.mlp_weights) return RAC_ERR_ARG;
+  if (O.beta_mode == RAC_BETA_SCHEDULE) {
+    if (!O.beta_schedule) return RAC_ERR_ARG;
+    for (int64_t i = 0; i < O.max_iter; ++i)
+      if (!is_fin(O.beta_schedule[i]) || !(O.beta_schedule[i] > 0.0)) return RAC_ERR_ARG;
+  }
+  if (O.sweep_groups < 0 || O.sweep_groups > 256 || O.row_chunks < 0) return RAC_ERR_ARG;
+
+  rac_solver s = new (std::nothrow) rac_solver_s();
+  if (!s) return RAC_ERR_NOMEM;
+  s->P = *prob;
+  s->O = O;
+  s->n = n;
+  s->rows = prob->rows;
+  s->p = O.num_blocks;
+  s->T = O.check_every;
+  s->sp = padded(smax);
+  s->K = O.sweep_groups > 0 ? O.sweep_groups : auto_sweep_groups(prob->rows);
+  if (s->K > s->rows) s->K = (int)s->rows;
+  s->R = O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows);
+  if (s->R > s->rows) s->R = (int)s->rows;
+  s->mv_nparts = matvec_parts(n);
+
+  auto fail = [&](rac_status r) {
+    s->buf.release();
+    delete s;
+    return r;
+  };
+  rac_status r;
+  if ((r = alloc_perm_work(s->buf, s->T, n, &s->pw, &s->perm)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->partial, (size_t)(s->p * s->R) * s->sp * s->sp)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->Minv, (size_t)s->p * s->sp * s->sp)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->x, (size_t)n)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->z, (size_t)n)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->xi, (size_t)n)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->zprev, (size_t)n)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->u, (size_t)s->rows)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->sc, 1)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->sweep_part, (size_t)2 * s->K * kMaxBlock)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->flags, (size_t)s->K * kFlagStride)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->red, (size_t)kRedSlots)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->done, 4)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->kkt_out, 4)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->obj_out, 1)) != RAC_OK) return fail(r);
+  s->hist_cap = O.max_iter > 0 ? O.max_iter : 1;
+  if ((r = s->buf.alloc(&s->hist, (size_t)s->hist_cap * 4)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->mv_part, (size_t)s->mv_nparts * s->rows)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->uz, (size_t)s->rows)) != RAC_OK) return fail(r);
+  if (O.beta_mode == RAC_BETA_SCHEDULE) {
+    if ((r = s->buf.alloc(&s->d_sched, (size_t)(O.max_iter > 0 ? O.max_iter : 1))) != RAC_OK) return fail(r);
+    if (O.max_iter > 0 &&
+        hipMemcpy(s->d_sched, O.beta_schedule, sizeof(double) * O.max_iter, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RAC_ERR_DEVICE);
+    s->O.beta_schedule = nullptr;   // the host array is not kept
+  }
+  if (hipMemset(s->x, 0, sizeof(double) * n) != hipSuccess ||
+      hipMemset(s->z, 0, sizeof(double) * n) != hipSuccess ||
+      hipMemset(s->xi, 0, sizeof(double) * n) != hipSuccess ||
+      hipMemset(s->zprev, 0, sizeof(double) * n) != hipSuccess ||
+      hipMemset(s->u, 0, sizeof(double) * s->rows) != hipSuccess ||
+      hipMemset(s->flags, 0, sizeof(uint64_t) * s->K * kFlagStride) != hipSuccess ||
+      hipMemset(s->done, 0, sizeof(uint32_t) * 4) != hipSuccess)
+    return fail(RAC_ERR_DEVICE);
+  s->hsc = fresh_scalars(O.beta0);
+  if (hipMemcpy(s->sc, &s->hsc, sizeof(DevScalars), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(RAC_ERR_DEVICE);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(RAC_ERR_DEVICE);
+  *out = s;
+  return RAC_OK;
+}
+
+rac_status rac_solver_destroy(rac_solver s) {
+  if (!s) return RAC_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  s->buf.release();
+  delete s;
+  return RAC_OK;
+}
+
+rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
+  if (!s || !res) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  std::memset(res, 0, sizeof(*res));
+  res->fail_iter = -1;
+  res->fail_block = -1;
+  s->hsc.status = 0;
+  s->hsc.fail_key = ~0ULL;
+  HIPCHK(hipMemcpyAsync(&s->sc->status, &s->hsc.status, sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(&s->sc->fail_key, &s->hsc.fail_key, sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  const int64_t budget = s->O.max_iter;
+  const int64_t k_start = s->hsc.k;
+  int64_t done_iters = 0;
+  rac_status rc = RAC_OK;
+  int32_t run_status = RAC_RUN_MAX_ITER;
+  while (done_iters < budget) {
+    const int64_t k = s->hsc.k;
+    int64_t Tc = s->T - (k % s->T);
+    if (Tc > budget - done_iters) Tc = budget - done_iters;
+    rac_status e = enqueue_iteration_chunk(s, Tc, done_iters, st);
+    if (e != RAC_OK) return e;
+    HIPCHK(hipMemcpyAsync(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    done_iters += Tc;
+    if (s->hsc.fail_key != ~0ULL) {
+      res->fail_iter = (int64_t)(s->hsc.fail_key >> 32);
+      res->fail_block = (int64_t)(s->hsc.fail_key & 0xffffffffULL);
+      rc = RAC_ERR_NOT_PD;
+      break;
+    }
+    if (s->hsc.status == 1) { run_status = RAC_RUN_CONVERGED; break; }
+    if (s->hsc.status == 2) { run_status = RAC_RUN_DIVERGED; break; }
+  }
+  s->hist_count = s->hsc.k - k_start;
+  // objective at z
+  rac_status e = fx_into_u(s, s->z, s->uz, st);
+  if (e != RAC_OK) return e;
+  HIPCHK(launch_objective_red(s->rows, s->n, s->P.Ns, s->P.h, s->P.c, s->P.prox, s->P.lambda,
+                              s->P.alpha, s->P.obj_const, s->z, s->uz, s->red, s->done, s->obj_out, st));
+  double obj = NAN;
+  HIPCHK(hipMemcpyAsync(&obj, s->obj_out, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  res->iters = s->hist_count;
+  res->status = run_status;
+  res->kkt = s->hsc.kkt;
+  res->beta = s->hsc.beta;
+  res->objective = obj;
+  return rc;
+}
+
+rac_status rac_solver_set_state(rac_solver s, const double* x, const double* z, const double* xi,
+                                double mu, double beta, int64_t iter, void* stream) {
+  if (!s || !x || !z || !xi || !is_fin(mu) || !is_fin(beta) || !(beta > 0.0) || iter < 0)
+    return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nb = sizeof(double) * s->n;
+  HIPCHK(hipMemcpyAsync(s->x, x, nb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->z, z, nb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->xi, xi, nb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(s->zprev, z, nb, hipMemcpyDeviceToDevice, st));
+  rac_status e = fx_into_u(s, s->x, s->u, st);
+  if (e != RAC_OK) return e;
+  s->hsc = fresh_scalars(beta);
+  s->hsc.mu = mu;
+  s->hsc.k = iter;
+  HIPCHK(hipMemcpyAsync(s->sc, &s->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, st));
+  if (s->P.a) HIPCHK(launch_dot_red(s->P.a, s->x, s->n, s->red, s->done, &s->sc->t, st));
+  HIPCHK(hipMemcpyAsync(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
+}
+
+rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, double* mu,
+                                double* beta, int64_t* iter, void* stream) {
+  if (!s) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nb = sizeof(double) * s->n;
+  if (x) HIPCHK(hipMemcpyAsync(x, s->x, nb, hipMemcpyDeviceToDevice, st));
+  if (z) HIPCHK(hipMemcpyAsync(z, s->z, nb, hipMemcpyDeviceToDevice, st));
+  if (xi) HIPCHK(hipMemcpyAsync(xi, s->xi, nb, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (mu) *mu = s->hsc.mu;
+  if (beta) *beta = s->hsc.beta;
+  if (iter) *iter = s->hsc.k;
+  return RAC_OK;
+}
+
+rac_status rac_solver_history(rac_solver s, double* out, int64_t capacity, int64_t* count) {
+  if (!s || !out || capacity < 0) return RAC_ERR_ARG;
+  int64_t c = s->hist_count < s->hist_cap ? s->hist_count : s->hist_cap;
+  if (c > capacity) c = capacity;
+  if (c > 0) HIPCHK(hipMemcpy(out, s->hist, sizeof(double) * 4 * c, hipMemcpyDeviceToHost));
+  if (count) *count = c;
+  return RAC_OK;
+}
+
+namespace {
+struct StateHeader {
+  uint64_t magic;
+  int64_t n, rows;
+  uint64_t scalars_bytes;
+  uint64_t epoch_unused;
+};
+constexpr uint64_t kStateMagic = 0x52414353544154ULL;  // "RACSTAT"
+}  // namespace
+
+rac_status rac_state_export(rac_solver s, void* buf, size_t* bytes) {
+  if (!s || !bytes) return RAC_ERR_ARG;
+  const size_t need = sizeof(StateHeader) + sizeof(DevScalars) + sizeof(double) * (4 * s->n + s->rows);
+  if (!buf) {
+    *bytes = need;
+    return RAC_OK;
+  }
+  if (*bytes < need) return RAC_ERR_ARG;
+  char* p = (char*)buf;
+  StateHeader h{kStateMagic, s->n, s->rows, sizeof(DevScalars), 0};
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  HIPCHK(hipMemcpy(p, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
+  p += sizeof(DevScalars);
+  const size_t nb = sizeof(double) * s->n;
+  HIPCHK(hipMemcpy(p, s->x, nb, hipMemcpyDeviceToHost)); p += nb;
+  HIPCHK(hipMemcpy(p, s->z, nb, hipMemcpyDeviceToHost)); p += nb;
+  HIPCHK(hipMemcpy(p, s->xi, nb, hipMemcpyDeviceToHost)); p += nb;
+  HIPCHK(hipMemcpy(p, s->zprev, nb, hipMemcpyDeviceToHost)); p += nb;
+  HIPCHK(hipMemcpy(p, s->u, sizeof(double) * s->rows, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return RAC_OK;
+}
+
+rac_status rac_state_import(rac_solver s, const void* buf, size_t bytes) {
+  if (!s || !buf) return RAC_ERR_ARG;
+  const size_t need = sizeof(StateHeader) + sizeof(DevScalars) + sizeof(double) * (4 * s->n + s->rows);
+  if (bytes < need) return RAC_ERR_ARG;
+  const char* p = (const char*)buf;
+  StateHeader h;
+  std::memcpy(&h, p, sizeof(h));
+  if (h.magic != kStateMagic || h.n != s->n || h.rows != s->rows || h.scalars_bytes != sizeof(DevScalars))
+    return RAC_ERR_ARG;
+  p += sizeof(h);
+  std::memcpy(&s->hsc, p, sizeof(DevScalars));
+  HIPCHK(hipMemcpy(s->sc, p, sizeof(DevScalars), hipMemcpyHostToDevice));
+  p += sizeof(DevScalars);
+  const size_t nb = sizeof(double) * s->n;
+  HIPCHK(hipMemcpy(s->x, p, nb, hipMemcpyHostToDevice)); p += nb;
+  HIPCHK(hipMemcpy(s->z, p, nb, hipMemcpyHostToDevice)); p += nb;
+  HIPCHK(hipMemcpy(s->xi, p, nb, hipMemcpyHostToDevice)); p += nb;
+  HIPCHK(hipMemcpy(s->zprev, p, nb, hipMemcpyHostToDevice)); p += nb;
+  HIPCHK(hipMemcpy(s->u, p, sizeof(double) * s->rows, hipMemcpyHostToDevice));
+  return RAC_OK;
+}
+
+rac_status rac_permutation(uint64_t seed, uint64_t instance, int64_t iter, int64_t n, int32_t* perm,
+                           void* stream) {
+  if (n < 1 || n > (int64_t)INT32_MAX || !perm || iter < 0) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  Buffers B;
+  PermWork w{};
+  int32_t* tmp = nullptr;
+  rac_status r = alloc_perm_work(B, 1, n, &w, &tmp);
+  if (r != RAC_OK) { B.release(); return r; }
+  hipError_t e = launch_permutations(seed, instance, iter, 1, n, w, tmp, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(perm, tmp, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  B.release();
+  return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
+rac_status rac_kkt(const rac_problem* prob, const double* x, const double* z, const double* xi,
+                   double mu, void* stream, double* out) {
+  rac_status v = validate_problem(prob);
+  if (v != RAC_OK) return v;
+  if (!x || !z || !xi || !out || !is_fin(mu)) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  Buffers B;
+  double *u = nullptr, *part = nullptr, *red = nullptr, *o = nullptr;
+  uint32_t* done = nullptr;
+  const int np = matvec_parts(prob->n);
+  rac_status r;
+  if ((r = B.alloc(&u, (size_t)prob->rows)) != RAC_OK || (r = B.alloc(&part, (size_t)np * prob->rows)) != RAC_OK ||
+      (r = B.alloc(&red, (size_t)kRedSlots)) != RAC_OK || (r = B.alloc(&o, 4)) != RAC_OK ||
+      (r = B.alloc(&done, 4)) != RAC_OK) {
+    B.release();
+    return r;
+  }
+  hipError_t e = hipMemsetAsync(done, 0, 4 * sizeof(uint32_t), st);
+  if (e == hipSuccess)
+    e = launch_matvec_F_parts(prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, x, u, part, np, st);
+  if (e == hipSuccess) {
+    KKTArgs ka{};
+    ka.F = prob->F; ka.dtype = prob->F_dtype; ka.ldF = prob->ldF; ka.rows = prob->rows; ka.n = prob->n;
+    ka.Ns = prob->Ns; ka.h = prob->h; ka.c = prob->c; ka.a = prob->a; ka.b = prob->b;
+    ka.prox = prob->prox; ka.lam = prob->lambda; ka.alpha = prob->alpha; ka.lo = prob->lo;
+    ka.hi = prob->hi; ka.x = x; ka.z = z; ka.xi = xi; ka.u = u; ka.mu_ptr = nullptr; ka.mu_val = mu;
+    ka.red = red; ka.done = done; ka.out = o;
+    e = launch_kkt(ka, st);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, o, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  B.release();
+  return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
+rac_status rac_objective(const rac_problem* prob, const double* z, void* stream, double* out) {
+  rac_status v = validate_problem(prob);
+  if (v != RAC_OK) return v;
+  if (!z || !out) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  Buffers B;
+  double *u = nullptr, *part = nullptr, *red = nullptr, *o = nullptr;
+  uint32_t* done = nullptr;
+  const int np = matvec_parts(prob->n);
+  rac_status r;
+  if ((r = B.alloc(&u, (size_t)prob->rows)) != RAC_OK || (r = B.alloc(&part, (size_t)np * prob->rows)) != RAC_OK ||
+      (r = B.alloc(&red, (size_t)kRedSlots)) != RAC_OK || (r = B.alloc(&o, 1)) != RAC_OK ||
+      (r = B.alloc(&done, 4)) != RAC_OK) {
+    B.release();
+    return r;
+  }
+  hipError_t e = hipMemsetAsync(done, 0, 4 * sizeof(uint32_t), st);
+  if (e == hipSuccess)
+    e = launch_matvec_F_parts(prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, z, u, part, np, st);
+  if (e == hipSuccess)
+    e = launch_objective_red(prob->rows, prob->n, prob->Ns, prob->h, prob->c, prob->prox, prob->lambda,
+                             prob->alpha, prob->obj_const, z, u, red, done, o, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, o, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  B.release();
+  return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
+rac_status rac_regression_c(const void* F, int32_t F_dtype, int64_t rows, int64_t n, int64_t ldF, double Ns,
+                            const double* y, double* c, void* stream) {
+  if (!F || !y || !c || rows < 1 || n < 1 || ldF < rows || dtype_size(F_dtype) == 0 || !is_fin(Ns) ||
+      !(Ns > 0.0))
+    return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_matvec_Ft(F, F_dtype, ldF, rows, n, y, -1.0 / Ns, c, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
+}
+
+rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed, uint64_t instance, int64_t iter,
+                              double beta, int32_t precision, double* out, int64_t* sp_out, void* stream) {
+  rac_status v = validate_problem(prob);
+  if (v != RAC_OK) return v;
+  if (p < 1 || p > prob->n || !out || iter < 0 || !is_fin(beta) || !(beta > 0.0)) return RAC_ERR_ARG;
+  if (precision != RAC_PREC_FP64 && precision != RAC_PREC_MIXED) return RAC_ERR_ARG;
+  const int64_t smax = (prob->n + p - 1) / p;
+  if (smax > RAC_MAX_BLOCK) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int sp = padded(smax);
+  const int R = auto_row_chunks(p, prob->rows);
+  Buffers B;
+  PermWork w{};
+  int32_t* perm = nullptr;
+  double* partial = nullptr;
+  rac_status r = alloc_perm_work(B, 1, prob->n, &w, &perm);
+  if (r == RAC_OK) r = B.alloc(&partial, (size_t)p * R * sp * sp);
+  if (r != RAC_OK) { B.release(); return r; }
+  hipError_t e = launch_permutations(seed, instance, iter, 1, prob->n, w, perm, st);
+  if (e == hipSuccess) {
+    GramArgs g{prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, p, perm, precision, R, sp, partial};
+    e = launch_gram(g, st);
+  }
+  if (e == hipSuccess) {
+    FactorArgs f{};
+    f.partial = partial; f.R = R; f.sp = sp; f.n = prob->n; f.p = p; f.perm = perm; f.Ns = prob->Ns;
+    f.h = prob->h; f.a = prob->a; f.beta_ptr = nullptr; f.beta_val = beta; f.Minv = out;
+    f.write_matrix = 1; f.sc = nullptr; f.iter_global = iter; f.publish_beta = 0;
+    e = launch_factor(f, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  B.release();
+  if (sp_out) *sp_out = sp;
+  return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
+rac_status rac_mlp_forward(const float* w, const float* feats, int64_t batch, float ymax, float* y, void* stream) {
+  if (!w || !feats || !y || batch < 0 || !(ymax > 0.0f)) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_mlp_forward(w, feats, batch, ymax, y, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
+}
+
+rac_status rac_mlp_loss_grad(const float* w, const float* feats, const float* target, int64_t batch, float ymax,
+                             float* grad, double* loss, void* stream) {
+  if (!w || !feats || !target || !grad || batch < 1 || !(ymax > 0.0f)) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  int nparts = (int)(batch < 256 ? batch : 256);
+  Buffers B;
+  float *part = nullptr, *lp = nullptr;
+  rac_status r = B.alloc(&part, (size_t)nparts * RAC_MLP_NPARAM);
+  if (r == RAC_OK) r = B.alloc(&lp, (size_t)nparts + 1);
+  if (r != RAC_OK) { B.release(); return r; }
+  hipError_t e = launch_mlp_loss_grad(w, feats, target, batch, ymax, grad, part, lp, nparts, st);
+  float l = 0.f;
+  if (e == hipSuccess) e = hipMemcpyAsync(&l, lp + nparts, sizeof(float), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  B.release();
+  if (loss) *loss = (double)l;
+  return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
+rac_status rac_mlp_adam(float* w, const float* grad, float* m, float* v, int64_t t, float lr, float b1, float b2,
+                        float eps, void* stream) {
+  if (!w || !grad || !m || !v || t < 1) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_mlp_adam(w, grad, m, v, t, lr, b1, b2, eps, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,460 @@
+// update.hip -- the z block, the dual step, residual norms, the KKT residual,
+// the penalty controller, and the small set-up products.
+//
+// z block (solved as one block after all x blocks, Sec.3.1):
+//   elastic net: z = soft(beta x - xi, lambda alpha) / (beta + lambda (1 - alpha))
+//   box:         z = clip(x - xi/beta, lo, hi)
+//   none:        z = x - xi/beta
+// dual step (Eq.(3)): xi <- xi - beta (x - z), mu <- mu - beta (a'x - b).
+// Norms r_p = |(x - z, a'x - b)|_2, r_d = beta |z - z_prev|_2 in FP64 with a
+// fixed-order two-level reduction (per-workgroup partials, summed in workgroup
+// order by the last workgroup to finish), so results do not depend on timing.
+#include "rac_internal.h"
+
+namespace rac {
+namespace {
+
+constexpr int kRedBlocks = 256;
+
+__device__ __forceinline__ double soft(double v, double t) {
+  return v > t ? v - t : (v < -t ? v + t : 0.0);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  return s;
+}
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, sh[w]);
+  return s;
+}
+
+// Returns true in exactly one workgroup: the last one to finish its partials.
+__device__ __forceinline__ bool last_block(uint32_t* done) {
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t prev = atomicAdd(done, 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (is_last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  return is_last;
+}
+
+__global__ void __launch_bounds__(256) k_zdual(int64_t n, int32_t prox, double lam, double alpha,
+                                               double lo, double hi, double b, int has_eq,
+                                               const double* __restrict__ x, double* z, double* xi,
+                                               double* zprev, DevScalars* sc, double* red,
+                                               uint32_t* done, double* hist, int64_t hist_cap,
+                                               int64_t hist_base, int64_t T) {
+  __shared__ double sh[4];
+  const double beta = sc->beta;
+  double rp2 = 0.0, rd2 = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    const double xj = x[j], xij = xi[j], zo = z[j];
+    double zn;
+    if (prox == RAC_PROX_ELASTIC_NET) zn = soft(beta * xj - xij, lam * alpha) / (beta + lam * (1.0 - alpha));
+    else if (prox == RAC_PROX_BOX) zn = fmin(fmax(xj - xij / beta, lo), hi);
+    else zn = xj - xij / beta;
+    const double r = xj - zn, dz = zn - zo;
+    xi[j] = xij - beta * r;
+    z[j] = zn;
+    zprev[j] = zo;
+    rp2 += r * r;
+    rd2 += dz * dz;
+  }
+  rp2 = block_sum(rp2, sh);
+  rd2 = block_sum(rd2, sh);
+  if (threadIdx.x == 0) { red[2 * blockIdx.x] = rp2; red[2 * blockIdx.x + 1] = rd2; }
+  if (!last_block(done)) return;
+  if (threadIdx.x != 0) return;
+  double P = 0.0, D = 0.0;
+  for (unsigned q = 0; q < gridDim.x; ++q) { P += red[2 * q]; D += red[2 * q + 1]; }
+  *done = 0u;
+  if (has_eq) {
+    const double e = sc->t - b;
+    sc->mu -= beta * e;
+    P += e * e;
+  }
+  const double rp = sqrt(P), rd = beta * sqrt(D);
+  const int64_t k = sc->k;
+  sc->rp = rp;
+  sc->rd = rd;
+  if (k % T == 0) { sc->rp_win = rp; sc->rd_win = rd; }
+  if (sc->rp_first < 0.0) sc->rp_first = rp;
+  if (!isfinite(rp) || !isfinite(rd) || (sc->rp_first > 0.0 && rp > 1e12 * sc->rp_first))
+    sc->status = 2;
+  const int64_t hi_ = k - hist_base;
+  if (hist && hi_ >= 0 && hi_ < hist_cap) {
+    hist[4 * hi_ + 0] = rp;
+    hist[4 * hi_ + 1] = rd;
+    hist[4 * hi_ + 2] = beta;
+    hist[4 * hi_ + 3] = __builtin_nan("");
+  }
+  sc->k = k + 1;
+}
+
+// ---------------------------------------------------------------------------
+// KKT residual: one pass over F for grad f(x) = F'u/Ns + h.x + c (one wavefront
+// per column, lanes over rows), per-column terms reduced to maxima; t = a'x is
+// re-summed from x.  red holds 10 values per workgroup:
+//   0 |Hx|, 1 |c|, 2 |xi|, 3 |x|, 4 |z|, 5 |x-z|, 6 |grad f - xi - mu a|,
+//   7 dist(-xi, dP(z)), 8 |a|, 9 sum a.x
+template <typename T>
+__global__ void __launch_bounds__(256) k_kkt(const T* __restrict__ F, int64_t ldF, int64_t rows,
+                                             int64_t n, double Ns, const double* __restrict__ h,
+                                             const double* __restrict__ c, const double* __restrict__ a,
+                                             double b, int32_t prox, double lam, double alpha, double lo,
+                                             double hi, const double* __restrict__ x,
+                                             const double* __restrict__ z, const double* __restrict__ xi,
+                                             const double* __restrict__ u, const double* mu_ptr,
+                                             double mu_val, double* red, uint32_t* done, double* out) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double mu = mu_ptr ? *mu_ptr : mu_val;
+  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t j = (int64_t)blockIdx.x * 4 + wave; j < n; j += (int64_t)gridDim.x * 4) {
+    const T* col = F + j * ldF;
+    double acc = 0.0;
+    for (int64_t r = lane; r < rows; r += 64) acc += ld_f64(col, r) * u[r];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const double xj = x[j], zj = z[j], xij = xi[j], cj = c[j];
+      const double aj = a ? a[j] : 0.0;
+      const double hx = acc / Ns + (h ? h[j] * xj : 0.0);
+      const double g = hx + cj - xij - mu * aj;
+      double d;
+      if (prox == RAC_PROX_NONE) {
+        d = fabs(xij);
+      } else if (prox == RAC_PROX_ELASTIC_NET) {
+        const double la = lam * alpha, l2 = lam * (1.0 - alpha);
+        if (zj > 0) d = fabs(-xij - (la + l2 * zj));
+        else if (zj < 0) d = fabs(-xij - (-la + l2 * zj));
+        else d = fabs(xij) > la ? fabs(xij) - la : 0.0;
+      } else {
+        const double w = -xij;
+        const bool at_lo = zj <= lo, at_hi = zj >= hi;
+        if (at_lo && at_hi) d = 0.0;
+        else if (at_lo) d = w > 0 ? w : 0.0;
+        else if (at_hi) d = w < 0 ? -w : 0.0;
+        else d = fabs(w);
+      }
+      m[0] = fmax(m[0], fabs(hx));
+      m[1] = fmax(m[1], fabs(cj));
+      m[2] = fmax(m[2], fabs(xij));
+      m[3] = fmax(m[3], fabs(xj));
+      m[4] = fmax(m[4], fabs(zj));
+      m[5] = fmax(m[5], fabs(xj - zj));
+      m[6] = fmax(m[6], fabs(g));
+      m[7] = fmax(m[7], d);
+      m[8] = fmax(m[8], fabs(aj));
+      m[9] += aj * xj;
+    }
+  }
+  for (int q = 0; q < 9; ++q) {
+    double v = block_max(m[q], sh);
+    if (threadIdx.x == 0) red[10 * blockIdx.x + q] = v;
+  }
+  {
+    double v = block_sum(m[9], sh);
+    if (threadIdx.x == 0) red[10 * blockIdx.x + 9] = v;
+  }
+  if (!last_block(done)) return;
+  if (threadIdx.x != 0) return;
+  double M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (unsigned q = 0; q < gridDim.x; ++q) {
+    for (int e = 0; e < 9; ++e) M[e] = fmax(M[e], red[10 * q + e]);
+    M[9] += red[10 * q + 9];
+  }
+  *done = 0u;
+  double feas = M[5] / (1.0 + fmax(M[3], M[4]));
+  if (a) feas = fmax(feas, fabs(M[9] - b) / (1.0 + fabs(b) + M[8] * M[3]));
+  double scale = fmax(fmax(M[0], M[1]), M[2]);
+  if (a) scale = fmax(scale, fabs(mu) * M[8]);
+  if (scale < 1e-300) scale = 1e-300;
+  const double stat = M[6] / scale, dual = M[7] / scale;
+  out[1] = feas;
+  out[2] = stat;
+  out[3] = dual;
+  out[0] = fmax(feas, fmax(stat, dual));
+}
+
+// ---------------------------------------------------------------------------
+// Penalty controller (runs once per check, one workgroup of 64 threads).
+//   residual balancing: beta *= tau if r_p > mu_rb r_d; beta /= tau if r_d > mu_rb r_p
+//   network: features -> 8-64-64-1 tanh perceptron -> beta *= exp(ymax tanh(o));
+//   a non-finite network output falls back to residual balancing.
+__device__ __forceinline__ double lg10c(double v) { return log10(v > 1e-300 ? v : 1e-300); }
+__device__ __forceinline__ double clip4(double v) { return v < -4.0 ? -4.0 : (v > 4.0 ? 4.0 : v); }
+
+__global__ void __launch_bounds__(64) k_control(DevScalars* sc, const double* kkt_out,
+                                                int32_t beta_mode, double rb_mu, double rb_tau,
+                                                double tol, const float* __restrict__ w,
+                                                double ymax, int decide, double* hist,
+                                                int64_t hist_cap, int64_t hist_base) {
+  __shared__ float f[RAC_MLP_IN];
+  __shared__ float h1[RAC_MLP_HIDDEN];
+  __shared__ float h2[RAC_MLP_HIDDEN];
+  __shared__ double mult_sh;
+  const int tid = threadIdx.x;
+  const double kkt = kkt_out[0];
+  const double rp = sc->rp, rd = sc->rd;
+  const int status0 = sc->status;
+  const bool conv = status0 == 0 && kkt <= tol;
+  __syncthreads();   // every thread has read the scalars before thread 0 updates them
+  if (tid == 0) {
+    sc->kkt = kkt;
+    const int64_t hi_ = sc->k - 1 - hist_base;
+    if (hist && hi_ >= 0 && hi_ < hist_cap) hist[4 * hi_ + 3] = kkt;
+    if (conv) sc->status = 1;
+  }
+  const bool act = decide && status0 == 0 && !conv &&
+                   (beta_mode == RAC_BETA_RESBAL || beta_mode == RAC_BETA_MLP);
+  if (act) {
+    double rb = 1.0;
+    if (rp > rb_mu * rd) rb = rb_tau;
+    else if (rd > rb_mu * rp) rb = 1.0 / rb_tau;
+    if (beta_mode == RAC_BETA_RESBAL) {
+      if (tid == 0) mult_sh = rb;
+    } else {
+      if (tid == 0) {
+        const double rpo = sc->rp_win, rdo = sc->rd_win, kp = sc->kkt_prev;
+        f[0] = (float)clip4(0.5 * (lg10c(rp) - lg10c(rd)));
+        f[1] = (float)clip4(0.5 * (lg10c(rpo) - lg10c(rdo)));
+        f[2] = (float)clip4(lg10c(rp) - lg10c(rpo));
+        f[3] = (float)clip4(lg10c(rd) - lg10c(rdo));
+        f[4] = (float)clip4(kp > 0.0 ? lg10c(kkt) - lg10c(kp) : 0.0);
+        f[5] = (float)clip4(sc->last_l10);
+        f[6] = (float)clip4((lg10c(kkt) + 6.0) / 3.0);
+        f[7] = (float)clip4((double)sc->decisions / 10.0);
+      }
+      __syncthreads();
+      const float* W1 = w;
+      const float* B1 = W1 + RAC_MLP_HIDDEN * RAC_MLP_IN;
+      const float* W2 = B1 + RAC_MLP_HIDDEN;
+      const float* B2 = W2 + RAC_MLP_HIDDEN * RAC_MLP_HIDDEN;
+      const float* W3 = B2 + RAC_MLP_HIDDEN;
+      const float* B3 = W3 + RAC_MLP_HIDDEN;
+      float s = B1[tid];
+      for (int k = 0; k < RAC_MLP_IN; ++k) s += W1[tid * RAC_MLP_IN + k] * f[k];
+      h1[tid] = tanhf(s);
+      __syncthreads();
+      s = B2[tid];
+      for (int k = 0; k < RAC_MLP_HIDDEN; ++k) s += W2[tid * RAC_MLP_HIDDEN + k] * h1[k];
+      h2[tid] = tanhf(s);
+      __syncthreads();
+      float o = W3[tid] * h2[tid];
+      for (int off = 32; off >= 1; off >>= 1) o += __shfl_xor(o, off, 64);
+      if (tid == 0) {
+        const double y = ymax * tanh((double)(o + B3[0]));
+        mult_sh = isfinite(y) ? exp(y) : rb;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      sc->beta *= mult_sh;
+      sc->last_l10 = log10(mult_sh);
+      sc->decisions += 1;
+    }
+  }
+  if (tid == 0) sc->kkt_prev = kkt;
+}
+
+// ---------------------------------------------------------------------------
+// u = F x: partial sums over column chunks, then a fixed-order combination.
+template <typename T>
+__global__ void __launch_bounds__(256) k_matvec_F_part(const T* __restrict__ F, int64_t ldF,
+                                                       int64_t rows, int64_t n, int64_t cpc,
+                                                       const double* __restrict__ x, double* part) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.y * cpc;
+  const int64_t j1 = j0 + cpc < n ? j0 + cpc : n;
+  if (r >= rows) return;
+  double acc = 0.0;
+  for (int64_t j = j0; j < j1; ++j) acc += ld_f64(F + j * ldF, r) * x[j];
+  part[(int64_t)blockIdx.y * rows + r] = acc;
+}
+__global__ void __launch_bounds__(256) k_sum_parts(int64_t rows, int nparts, const double* part,
+                                                   double* u) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int q = 0; q < nparts; ++q) s += part[(int64_t)q * rows + r];
+  u[r] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_matvec_Ft(const T* __restrict__ F, int64_t ldF, int64_t rows,
+                                                   int64_t n, const double* __restrict__ u,
+                                                   double scale, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t j = (int64_t)blockIdx.x * 4 + wave; j < n; j += (int64_t)gridDim.x * 4) {
+    const T* col = F + j * ldF;
+    double acc = 0.0;
+    for (int64_t r = lane; r < rows; r += 64) acc += ld_f64(col, r) * u[r];
+    acc = wave_sum(acc);
+    if (lane == 0) out[j] = scale * acc;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_dot(const double* __restrict__ a, const double* __restrict__ x,
+                                             int64_t n, double* red, uint32_t* done, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+    s += a[j] * x[j];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = s;
+  if (!last_block(done)) return;
+  if (threadIdx.x != 0) return;
+  double t = 0.0;
+  for (unsigned q = 0; q < gridDim.x; ++q) t += red[q];
+  *done = 0u;
+  *out = t;
+}
+
+// objective = 1/2 (|u|^2/Ns + sum h z^2) + c'z + P(z) + const, with u = F z given.
+__global__ void __launch_bounds__(256) k_objective(int64_t rows, int64_t n, double Ns,
+                                                   const double* __restrict__ h,
+                                                   const double* __restrict__ c, int32_t prox,
+                                                   double lam, double alpha, double cst,
+                                                   const double* __restrict__ z,
+                                                   const double* __restrict__ u, double* red,
+                                                   uint32_t* done, double* out) {
+  __shared__ double sh[4];
+  double q = 0.0, rest = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += stride) q += u[r] * u[r];
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += stride) {
+    const double zj = z[j];
+    double v = c[j] * zj;
+    if (h) v += 0.5 * h[j] * zj * zj;
+    if (prox == RAC_PROX_ELASTIC_NET) v += lam * (alpha * fabs(zj) + 0.5 * (1.0 - alpha) * zj * zj);
+    rest += v;
+  }
+  q = block_sum(q, sh);
+  rest = block_sum(rest, sh);
+  if (threadIdx.x == 0) { red[2 * blockIdx.x] = q; red[2 * blockIdx.x + 1] = rest; }
+  if (!last_block(done)) return;
+  if (threadIdx.x != 0) return;
+  double Q = 0.0, S = 0.0;
+  for (unsigned e = 0; e < gridDim.x; ++e) { Q += red[2 * e]; S += red[2 * e + 1]; }
+  *done = 0u;
+  *out = 0.5 * Q / Ns + S + cst;
+}
+
+template <typename T>
+hipError_t kkt_launch(const KKTArgs& k, hipStream_t st) {
+  int64_t blocks = (k.n + 3) / 4;
+  if (blocks > kRedBlocks) blocks = kRedBlocks;
+  k_kkt<T><<<(unsigned)blocks, 256, 0, st>>>((const T*)k.F, k.ldF, k.rows, k.n, k.Ns, k.h, k.c, k.a,
+                                              k.b, k.prox, k.lam, k.alpha, k.lo, k.hi, k.x, k.z,
+                                              k.xi, k.u, k.mu_ptr, k.mu_val, k.red, k.done, k.out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t matvec_F_launch(const void* F, int64_t ldF, int64_t rows, int64_t n, const double* x,
+                           double* u, double* part, int nparts, int64_t cpc, hipStream_t st) {
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nparts);
+  k_matvec_F_part<T><<<grid, 256, 0, st>>>((const T*)F, ldF, rows, n, cpc, x, part);
+  k_sum_parts<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(rows, nparts, part, u);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_zdual(const UpdateArgs& z, hipStream_t st) {
+  int64_t blocks = (z.n + 255) / 256;
+  if (blocks > kRedBlocks) blocks = kRedBlocks;
+  k_zdual<<<(unsigned)blocks, 256, 0, st>>>(z.n, z.prox, z.lam, z.alpha, z.lo, z.hi, z.b, z.has_eq,
+                                            z.x, z.z, z.xi, z.zprev, z.sc, z.red, z.done, z.hist,
+                                            z.hist_cap, z.hist_base, z.T);
+  return hipGetLastError();
+}
+
+hipError_t launch_kkt(const KKTArgs& k, hipStream_t st) {
+  switch (k.dtype) {
+    case RAC_DT_F64: return kkt_launch<double>(k, st);
+    case RAC_DT_F32: return kkt_launch<float>(k, st);
+    case RAC_DT_BF16: return kkt_launch<uint16_t>(k, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_control(const ControlArgs& c, hipStream_t st) {
+  k_control<<<1, 64, 0, st>>>(c.sc, c.kkt_out, c.beta_mode, c.rb_mu, c.rb_tau, c.tol, c.mlp_w,
+                              c.mlp_ymax, c.decide, c.hist, c.hist_cap, c.hist_base);
+  return hipGetLastError();
+}
+
+// u = F x needs a scratch of nparts*rows doubles: the caller passes `u` of size
+// rows and this routine allocates nothing, so the partials go through a
+// temporary provided by the caller inside `u_part`.
+hipError_t launch_matvec_F_parts(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,
+                                 const double* x, double* u, double* part, int nparts,
+                                 hipStream_t st) {
+  const int64_t cpc = (n + nparts - 1) / nparts;
+  switch (dtype) {
+    case RAC_DT_F64: return matvec_F_launch<double>(F, ldF, rows, n, x, u, part, nparts, cpc, st);
+    case RAC_DT_F32: return matvec_F_launch<float>(F, ldF, rows, n, x, u, part, nparts, cpc, st);
+    case RAC_DT_BF16: return matvec_F_launch<uint16_t>(F, ldF, rows, n, x, u, part, nparts, cpc, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_matvec_Ft(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,
+                            const double* u, double scale, double* out, hipStream_t st) {
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  switch (dtype) {
+    case RAC_DT_F64:
+      k_matvec_Ft<double><<<(unsigned)blocks, 256, 0, st>>>((const double*)F, ldF, rows, n, u, scale, out);
+      break;
+    case RAC_DT_F32:
+      k_matvec_Ft<float><<<(unsigned)blocks, 256, 0, st>>>((const float*)F, ldF, rows, n, u, scale, out);
+      break;
+    case RAC_DT_BF16:
+      k_matvec_Ft<uint16_t><<<(unsigned)blocks, 256, 0, st>>>((const uint16_t*)F, ldF, rows, n, u, scale,
+                                                               out);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_red(const double* a, const double* x, int64_t n, double* red, uint32_t* done,
+                          double* out, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > kRedBlocks) blocks = kRedBlocks;
+  k_dot<<<(unsigned)blocks, 256, 0, st>>>(a, x, n, red, done, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective_red(int64_t rows, int64_t n, double Ns, const double* h, const double* c,
+                                int32_t prox, double lam, double alpha, double cst, const double* z,
+                                const double* u, double* red, uint32_t* done, double* out,
+                                hipStream_t st) {
+  int64_t m = rows > n ? rows : n;
+  int64_t blocks = (m + 255) / 256;
+  if (blocks > kRedBlocks) blocks = kRedBlocks;
+  k_objective<<<(unsigned)blocks, 256, 0, st>>>(rows, n, Ns, h, c, prox, lam, alpha, cst, z, u, red,
+                                                done, out);
+  return hipGetLastError();
+}
+
+}  // namespace rac

@@ -1,0 +1,375 @@
+"""ctypes binding of libracmb.so (the gfx950 RAC-MBADMM library, include/racmb.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Device memory comes from torch tensors on ``cuda`` (ROCm) and the work
+is enqueued on torch's current stream.  If the shared library has not been
+built, importing works but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libracmb.so")
+
+RAC_OK, RAC_ERR_ARG, RAC_ERR_NOT_PD, RAC_ERR_DEVICE, RAC_ERR_NOMEM, RAC_ERR_UNSUPPORTED = range(6)
+RUN_CONVERGED, RUN_MAX_ITER, RUN_DIVERGED = 0, 1, 2
+PROX_NONE, PROX_EN, PROX_BOX = 0, 1, 2
+DT_F64, DT_F32, DT_BF16 = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+BETA_FIXED, BETA_RESBAL, BETA_MLP, BETA_SCHEDULE = 0, 1, 2, 3
+MAX_BLOCK = 128
+MLP_IN, MLP_HIDDEN = 8, 64
+MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+
+EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_solver_set_state",
+            "rac_solver_get_state", "rac_solver_history", "rac_state_export", "rac_state_import",
+            "rac_permutation", "rac_kkt", "rac_objective", "rac_regression_c", "rac_block_matrices",
+            "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_status_str"]
+
+
+class RacError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, status_str(code), code))
+
+
+class Problem_(C.Structure):
+    _fields_ = [("n", C.c_int64), ("rows", C.c_int64), ("F", C.c_void_p), ("ldF", C.c_int64),
+                ("F_dtype", C.c_int32), ("prox", C.c_int32), ("Ns", C.c_double),
+                ("h", C.c_void_p), ("c", C.c_void_p), ("a", C.c_void_p), ("b", C.c_double),
+                ("lam", C.c_double), ("alpha", C.c_double), ("lo", C.c_double),
+                ("hi", C.c_double), ("obj_const", C.c_double)]
+
+
+class Opts_(C.Structure):
+    _fields_ = [("num_blocks", C.c_int64), ("seed", C.c_uint64), ("instance", C.c_uint64),
+                ("precision", C.c_int32), ("beta_mode", C.c_int32), ("beta0", C.c_double),
+                ("rb_mu", C.c_double), ("rb_tau", C.c_double),
+                ("beta_schedule", C.POINTER(C.c_double)), ("mlp_weights", C.c_void_p),
+                ("mlp_ymax", C.c_double), ("check_every", C.c_int64), ("max_iter", C.c_int64),
+                ("tol", C.c_double), ("sweep_groups", C.c_int32), ("row_chunks", C.c_int32)]
+
+
+class Result_(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("status", C.c_int32), ("pad0", C.c_int32),
+                ("kkt", C.c_double), ("beta", C.c_double), ("objective", C.c_double),
+                ("fail_iter", C.c_int64), ("fail_block", C.c_int64)]
+
+
+_lib = None
+
+
+def lib_available() -> bool:
+    return os.path.exists(LIB_PATH)
+
+
+def load():
+    """Load the in-tree libracmb.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libracmb.so is not built: run `python -c 'import __graft_entry__ as g; "
+                           "g.build()'` (hipcc, gfx950) first; there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, u64, dp = C.c_void_p, C.c_int64, C.c_uint64, C.POINTER(C.c_double)
+    sig = {
+        "rac_solver_create": [C.POINTER(Problem_), C.POINTER(Opts_), C.POINTER(vp)],
+        "rac_solver_destroy": [vp],
+        "rac_solver_run": [vp, vp, C.POINTER(Result_)],
+        "rac_solver_set_state": [vp, vp, vp, vp, C.c_double, C.c_double, i64, vp],
+        "rac_solver_get_state": [vp, vp, vp, vp, dp, dp, C.POINTER(i64), vp],
+        "rac_solver_history": [vp, dp, i64, C.POINTER(i64)],
+        "rac_state_export": [vp, vp, C.POINTER(C.c_size_t)],
+        "rac_state_import": [vp, vp, C.c_size_t],
+        "rac_permutation": [u64, u64, i64, i64, vp, vp],
+        "rac_kkt": [C.POINTER(Problem_), vp, vp, vp, C.c_double, vp, dp],
+        "rac_objective": [C.POINTER(Problem_), vp, vp, dp],
+        "rac_regression_c": [vp, C.c_int32, i64, i64, i64, C.c_double, vp, vp, vp],
+        "rac_block_matrices": [C.POINTER(Problem_), i64, u64, u64, i64, C.c_double, C.c_int32, vp,
+                               C.POINTER(i64), vp],
+        "rac_mlp_forward": [vp, vp, i64, C.c_float, vp, vp],
+        "rac_mlp_loss_grad": [vp, vp, vp, i64, C.c_float, vp, dp, vp],
+        "rac_mlp_adam": [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.rac_status_str.argtypes = [C.c_int]
+    lib.rac_status_str.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_str(code) -> str:
+    try:
+        return load().rac_status_str(int(code)).decode()
+    except RuntimeError:
+        return "status %d" % int(code)
+
+
+def _check(code, what):
+    if code != RAC_OK:
+        raise RacError(code, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+_DT = {"f64": DT_F64, "f32": DT_F32, "bf16": DT_BF16}
+
+
+def _torch_dtype(storage):
+    torch = _torch()
+    return {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[storage]
+
+
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Problem:
+    """Device-resident problem (torch tensors keep the memory alive)."""
+    F: object            # torch tensor (n, rows) contiguous == column-major rows x n
+    storage: str
+    rows: int
+    n: int
+    Ns: float
+    c: object
+    h: object = None
+    a: object = None
+    b: float = 0.0
+    prox: int = PROX_NONE
+    lam: float = 0.0
+    alpha: float = 1.0
+    lo: float = 0.0
+    hi: float = 0.0
+    obj_const: float = 0.0
+
+    def struct(self) -> Problem_:
+        return Problem_(self.n, self.rows, self.F.data_ptr(), self.rows, _DT[self.storage], self.prox,
+                        self.Ns, None if self.h is None else self.h.data_ptr(), self.c.data_ptr(),
+                        None if self.a is None else self.a.data_ptr(), self.b, self.lam, self.alpha,
+                        self.lo, self.hi, self.obj_const)
+
+
+def upload_columns(D, storage, device="cuda"):
+    """Column-major rows x n data (numpy, values exact in `storage`) -> device tensor (n, rows)."""
+    torch = _torch()
+    Dt = np.ascontiguousarray(np.asarray(D).T)
+    if storage == "f64":
+        t = torch.from_numpy(Dt.astype(np.float64))
+    elif storage == "f32":
+        t = torch.from_numpy(Dt.astype(np.float32))
+    else:  # bf16: values are exactly representable, so the conversion is exact
+        t = torch.from_numpy(Dt.astype(np.float32)).to(torch.bfloat16)
+    return t.to(device).contiguous()
+
+
+def regression_problem(D, y, lam=0.0, alpha=1.0, storage="f64", h=None, device="cuda") -> Problem:
+    """Elastic net (Sec.3.1): H = D'D/N, c = -D'y/N computed on the device."""
+    torch = _torch()
+    load()
+    N, n = D.shape
+    F = upload_columns(D, storage, device)
+    yt = torch.as_tensor(np.asarray(y, dtype=np.float64), device=device)
+    c = torch.empty(n, dtype=torch.float64, device=device)
+    _check(load().rac_regression_c(C.c_void_p(F.data_ptr()), _DT[storage], N, n, N, float(N),
+                                   _ptr(yt), _ptr(c), _stream()), "rac_regression_c")
+    ht = None if h is None else torch.as_tensor(np.asarray(h, dtype=np.float64), device=device)
+    yy = float(np.dot(np.asarray(y, dtype=np.float64), np.asarray(y, dtype=np.float64)))
+    return Problem(F=F, storage=storage, rows=N, n=n, Ns=float(N), c=c, h=ht,
+                   prox=PROX_EN if lam > 0 else PROX_NONE, lam=float(lam), alpha=float(alpha),
+                   obj_const=yy / (2.0 * N))
+
+
+def svm_problem(X, labels, Cbox, storage="f32", device="cuda") -> Problem:
+    """C-SVC dual (Sec.3.2), linear kernel: F = G' with G = diag(y) X, c = -e, a = y, box [0, C]."""
+    torch = _torch()
+    X = np.asarray(X)
+    yl = np.asarray(labels, dtype=np.float64)
+    n, r = X.shape
+    G = X * yl[:, None].astype(X.dtype)        # a sign flip: exact in any precision
+    F = upload_columns(G.T, storage, device)   # column j of F is row j of G
+    c = torch.full((n,), -1.0, dtype=torch.float64, device=device)
+    a = torch.as_tensor(yl, device=device)
+    return Problem(F=F, storage=storage, rows=r, n=n, Ns=1.0, c=c, a=a, b=0.0, prox=PROX_BOX,
+                   lo=0.0, hi=float(Cbox))
+
+
+@dataclass
+class Result:
+    iters: int
+    status: int
+    kkt: float
+    beta: float
+    objective: float
+    fail_iter: int
+    fail_block: int
+
+
+class Solver:
+    """Handle around rac_solver: create once, run many times."""
+
+    def __init__(self, prob: Problem, *, p=None, s=None, seed=0, instance=0, precision=PREC_FP64,
+                 beta0=1.0, beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0, beta_schedule=None,
+                 mlp_weights=None, mlp_ymax=float(np.log(10.0)), check_every=10, max_iter=100,
+                 tol=0.0, sweep_groups=0, row_chunks=0):
+        self.lib = load()
+        self.prob = prob
+        if p is None:
+            p = -(-prob.n // int(s))
+        self.p = int(p)
+        self._sched = None
+        sched_ptr = None
+        if beta_schedule is not None:
+            self._sched = np.ascontiguousarray(beta_schedule, dtype=np.float64)
+            sched_ptr = self._sched.ctypes.data_as(C.POINTER(C.c_double))
+        self._w = mlp_weights
+        self.opts = Opts_(self.p, int(seed), int(instance), int(precision), int(beta_mode), float(beta0),
+                          float(rb_mu), float(rb_tau), sched_ptr,
+                          None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax),
+                          int(check_every), int(max_iter), float(tol), int(sweep_groups), int(row_chunks))
+        self._ps = prob.struct()
+        h = C.c_void_p()
+        _check(self.lib.rac_solver_create(C.byref(self._ps), C.byref(self.opts), C.byref(h)),
+               "rac_solver_create")
+        self.h = h
+        self.max_iter = int(max_iter)
+
+    def close(self):
+        if self.h:
+            self.lib.rac_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, allow_not_pd=False) -> Result:
+        r = Result_()
+        code = self.lib.rac_solver_run(self.h, _stream(), C.byref(r))
+        if code != RAC_OK and not (allow_not_pd and code == RAC_ERR_NOT_PD):
+            raise RacError(code, "rac_solver_run")
+        self.last_code = code
+        return Result(r.iters, r.status, r.kkt, r.beta, r.objective, r.fail_iter, r.fail_block)
+
+    def set_state(self, x, z, xi, mu=0.0, beta=None, iteration=0):
+        torch = _torch()
+        dev = self.prob.c.device
+        xs = [torch.as_tensor(np.asarray(v, dtype=np.float64), device=dev) if not hasattr(v, "data_ptr")
+              else v.to(dev, torch.float64).contiguous() for v in (x, z, xi)]
+        b = self.opts.beta0 if beta is None else beta
+        _check(self.lib.rac_solver_set_state(self.h, _ptr(xs[0]), _ptr(xs[1]), _ptr(xs[2]), float(mu),
+                                             float(b), int(iteration), _stream()), "rac_solver_set_state")
+
+    def state(self):
+        """(x, z, xi, mu, beta, iteration) with vectors as numpy float64."""
+        torch = _torch()
+        dev = self.prob.c.device
+        x, z, xi = (torch.empty(self.prob.n, dtype=torch.float64, device=dev) for _ in range(3))
+        mu, beta, it = C.c_double(), C.c_double(), C.c_int64()
+        _check(self.lib.rac_solver_get_state(self.h, _ptr(x), _ptr(z), _ptr(xi), C.byref(mu), C.byref(beta),
+                                             C.byref(it), _stream()), "rac_solver_get_state")
+        return x.cpu().numpy(), z.cpu().numpy(), xi.cpu().numpy(), mu.value, beta.value, it.value
+
+    def history(self):
+        out = np.zeros((max(self.max_iter, 1), 4))
+        cnt = C.c_int64()
+        _check(self.lib.rac_solver_history(self.h, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                           out.shape[0], C.byref(cnt)), "rac_solver_history")
+        return out[:cnt.value]
+
+    def export_state(self) -> bytes:
+        nb = C.c_size_t()
+        _check(self.lib.rac_state_export(self.h, None, C.byref(nb)), "rac_state_export")
+        buf = C.create_string_buffer(nb.value)
+        _check(self.lib.rac_state_export(self.h, buf, C.byref(nb)), "rac_state_export")
+        return buf.raw[:nb.value]
+
+    def import_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(self.lib.rac_state_import(self.h, buf, len(blob)), "rac_state_import")
+
+
+# ---------------------------------------------------------------------------
+
+def permutation(seed, instance, it, n, device="cuda"):
+    torch = _torch()
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    _check(load().rac_permutation(int(seed), int(instance), int(it), int(n), _ptr(out), _stream()),
+           "rac_permutation")
+    return out
+
+
+def kkt(prob: Problem, x, z, xi, mu=0.0):
+    torch = _torch()
+    dev = prob.c.device
+    ts = [torch.as_tensor(np.asarray(v, dtype=np.float64), device=dev) for v in (x, z, xi)]
+    out = np.zeros(4)
+    ps = prob.struct()
+    _check(load().rac_kkt(C.byref(ps), _ptr(ts[0]), _ptr(ts[1]), _ptr(ts[2]), float(mu), _stream(),
+                          out.ctypes.data_as(C.POINTER(C.c_double))), "rac_kkt")
+    return out
+
+
+def objective(prob: Problem, z):
+    torch = _torch()
+    zt = torch.as_tensor(np.asarray(z, dtype=np.float64), device=prob.c.device)
+    out = C.c_double()
+    ps = prob.struct()
+    _check(load().rac_objective(C.byref(ps), _ptr(zt), _stream(), C.byref(out)), "rac_objective")
+    return out.value
+
+
+def block_matrices(prob: Problem, p, seed, instance, it, beta, precision=PREC_FP64):
+    torch = _torch()
+    smax = -(-prob.n // p)
+    sp = (smax + 15) // 16 * 16
+    out = torch.zeros(p * sp * sp, dtype=torch.float64, device=prob.c.device)
+    spo = C.c_int64()
+    ps = prob.struct()
+    _check(load().rac_block_matrices(C.byref(ps), int(p), int(seed), int(instance), int(it), float(beta),
+                                     int(precision), _ptr(out), C.byref(spo), _stream()),
+           "rac_block_matrices")
+    return out.cpu().numpy().reshape(p, sp, sp), sp
+
+
+def mlp_forward(w, feats, ymax=float(np.log(10.0))):
+    torch = _torch()
+    y = torch.empty(feats.shape[0], dtype=torch.float32, device=w.device)
+    _check(load().rac_mlp_forward(_ptr(w), _ptr(feats), feats.shape[0], float(ymax), _ptr(y), _stream()),
+           "rac_mlp_forward")
+    return y
+
+
+def mlp_loss_grad(w, feats, target, ymax=float(np.log(10.0))):
+    torch = _torch()
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=w.device)
+    loss = C.c_double()
+    _check(load().rac_mlp_loss_grad(_ptr(w), _ptr(feats), _ptr(target), feats.shape[0], float(ymax),
+                                    _ptr(g), C.byref(loss), _stream()), "rac_mlp_loss_grad")
+    return loss.value, g
+
+
+def mlp_adam(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    _check(load().rac_mlp_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), int(t), float(lr), float(b1),
+                               float(b2), float(eps), _stream()), "rac_mlp_adam")
