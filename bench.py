@@ -1,0 +1,195 @@
+"""Benchmark of the RAC-MBADMM hot path on one MI355X.
+
+Workload (default): LASSO, D 20000 x 2000 iid N(0,1) with unit-norm columns,
+stored in FP32; x_true with 5% non-zeros of magnitude U(1,3); noise 0.05;
+lambda = 0.1 lambda_max; blocks of 64 variables (p = 32); synthetic data.
+
+A "step" is one RAC-MBADMM iteration (partition draw, all block Grams and
+factors, the Gauss-Seidel sweep, z block, dual step, and every T = 10
+iterations the KKT check and the penalty decision) of the candidate solver:
+mixed precision (FP32 block Grams on the matrix cores, FP64 everything else)
+with the learned penalty controller when trained weights are present, else
+residual balancing.  `value` is iterations per second with the data already in
+HBM.  The line also reports, on the same data:
+  time_to_tol  -- wall time to the first KKT check <= 1e-6 for the candidate
+                  and for the plain FP64 fixed-beta solver (FP64 data, FP64
+                  Grams, beta = 0.1 lambda as in Sec.3.1),
+  roofline     -- the dominant kernel's achieved rate from HIP events recorded
+                  around each launch inside the timed region,
+  cpu_baseline -- the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+MFMA_PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
+METRIC = "time-to-1e-6 KKT residual & ADMM iters/s: learned-β batched vs plain FP64"
+WEIGHTS = os.path.join(ROOT, "paper_1907_01995_amd", "controller_weights.npy")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic(phase, N, n, p, bA):
+    """Algorithmic bytes and flops of one launch of a phase (one read of the data)."""
+    sizes = np.diff((np.arange(p + 1) * n) // p)
+    if phase == "sweep":
+        return N * n * bA + 6 * n * 8, 4.0 * N * n
+    if phase == "gram":
+        return N * n * bA, float(np.sum(N * sizes * (sizes + 1)))
+    if phase == "factor":
+        return float(np.sum(sizes * sizes * 8)), float(np.sum(sizes ** 3))
+    if phase == "check":
+        return N * n * bA + 8 * n * 8, 2.0 * N * n
+    return 0.0, 0.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-to-tol", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(see DESIGN.md for how the path would shard)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1907_01995_amd import racmb, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t_gen = time.time()
+    w = W.lasso_20000x2000("f32")
+    log("workload generated in %.1fs" % (time.time() - t_gen))
+    N, n, s = w.N, w.n, w.block_size
+    p = -(-n // s)
+
+    prob32 = racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=1.0, storage="f32")
+    weights = None
+    beta_mode = racmb.BETA_RESBAL
+    if os.path.exists(WEIGHTS):
+        weights = torch.as_tensor(np.load(WEIGHTS).astype(np.float32), device="cuda")
+        beta_mode = racmb.BETA_MLP
+    cand_kw = dict(s=s, precision=racmb.PREC_MIXED, beta0=w.beta0, beta_mode=beta_mode,
+                   mlp_weights=weights, check_every=10)
+
+    # ---- throughput: K timed iterations after W warm-up iterations ----------
+    sol = racmb.Solver(prob32, max_iter=args.steps, tol=0.0, **cand_kw)
+    warm = racmb.Solver(prob32, max_iter=max(args.warmup, 1), tol=0.0, **cand_kw)
+    if args.warmup > 0:
+        warm.run()
+    warm.close()
+    sol.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = sol.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    phases = sol.timing()
+    info = sol.info()
+    ips = res.iters / elapsed
+    log("throughput: %d iterations in %.4fs -> %.1f it/s; phases %s" % (res.iters, elapsed, ips, phases))
+
+    # ---- roofline of the dominant kernel --------------------------------------
+    dom = max(phases, key=lambda k: phases[k][0])
+    rows = {}
+    for ph, (ms, cnt) in phases.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt / 1e3
+        by, fl = algorithmic(ph, N, n, p, 4)
+        rows[ph] = dict(avg_us=avg * 1e6, launches=cnt, GBps=by / avg / 1e9, TFLOPs=fl / avg / 1e12)
+    by, fl = algorithmic(dom, N, n, p, 4)
+    avg = phases[dom][0] / phases[dom][1] / 1e3
+    t_hbm, t_mfma = by / HBM_PEAK, fl / MFMA_PEAK["f32"]
+    if dom == "gram" and t_mfma > t_hbm:
+        roof = {"bound": "mfma", "achieved": fl / avg / 1e12, "peak": MFMA_PEAK["f32"] / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = {"sweep": "k_sweep", "gram": "k_gram", "factor": "k_factor",
+                      "zdual": "k_zdual", "check": "k_kkt+k_control", "partition": "k_perm_*"}[dom]
+    roof["avg_launch_us"] = avg * 1e6
+
+    out = {"metric": METRIC, "value": ips, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / max(res.iters, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "lasso_20000x2000", "N": N, "n": n, "block_size": s, "p": p,
+                      "data_storage": "f32", "precision": "mixed (f32 MFMA Gram, f64 rest)",
+                      "beta_mode": "mlp" if weights is not None else "residual_balancing",
+                      "check_every": 10, "sweep_groups": info["K"], "gram_row_chunks": info["R"]},
+           "roofline": roof, "phases": rows}
+
+    # ---- time to KKT <= 1e-6: candidate vs plain FP64 fixed beta ----------------
+    if not args.no_time_to_tol:
+        tt = {}
+        prob64 = racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=1.0, storage="f64")
+        cfgs = {"candidate": (prob32, dict(cand_kw, max_iter=5000)),
+                "plain_fp64_fixed_beta": (prob64, dict(s=s, precision=racmb.PREC_FP64, beta0=w.beta0,
+                                                       beta_mode=racmb.BETA_FIXED, check_every=10,
+                                                       max_iter=20000))}
+        sols = {}
+        for name, (pr, kw) in cfgs.items():
+            times = []
+            for rep in range(2):
+                so = racmb.Solver(pr, tol=1e-6, **kw)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                r = so.run()
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - a)
+                if rep == 1:
+                    sols[name] = so.state()
+                    tt[name] = {"seconds": min(times), "iters": r.iters, "kkt": r.kkt,
+                                "converged": r.status == racmb.RUN_CONVERGED, "objective": r.objective}
+                so.close()
+            log("time-to-tol %s: %s" % (name, tt[name]))
+        zc, zp = sols["candidate"][1], sols["plain_fp64_fixed_beta"][1]
+        tt["speedup"] = tt["plain_fp64_fixed_beta"]["seconds"] / tt["candidate"]["seconds"]
+        tt["candidate_vs_plain_rel_z"] = float(np.max(np.abs(zc - zp)) / np.max(np.abs(zp)))
+        out["time_to_tol"] = tt
+        del prob64
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ----------------------
+    if not args.no_cpu_baseline:
+        import oracle as O
+        op = O.en_problem(w.D.astype(np.float64), w.y, lam=w.lam, alpha=1.0)
+        k = args.cpu_iters
+        a = time.perf_counter()
+        ro = O.solve(op, s=s, beta0=w.beta0, beta_mode=O.BETA_RESBAL, max_iter=k, check_every=10)
+        dt = time.perf_counter() - a
+        out["cpu_baseline"] = {"value": ro.iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d iterations of lasso_20000x2000 (FP64 oracle, one thread, "
+                                         "%.1f s)" % (ro.iters, dt)}
+        if "time_to_tol" in out:
+            xc = sols["candidate"]
+            out["time_to_tol"]["oracle_kkt_of_candidate"] = O.kkt(op, xc[0], xc[1], xc[2], xc[3])
+            out["time_to_tol"]["oracle_objective_rel_err"] = abs(
+                O.objective(op, xc[1]) - out["time_to_tol"]["candidate"]["objective"]) / abs(
+                O.objective(op, xc[1]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,6 +140,20 @@ rac_status rac_solver_set_state(rac_solver s, const double* x, const double* z, 
 rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, double* mu,
                                 double* beta, int64_t* iter, void* stream);
 
+/* Phase timing (HIP events on the run's stream, accumulated over runs until the
+ * next rac_solver_set_timing call).  Phases, in order: partition draw, block Gram,
+ * block factor, sweep, z/dual step, KKT check + penalty rule. */
+#define RAC_NUM_PHASES 6
+enum { RAC_PHASE_PARTITION = 0, RAC_PHASE_GRAM = 1, RAC_PHASE_FACTOR = 2, RAC_PHASE_SWEEP = 3,
+       RAC_PHASE_ZDUAL = 4, RAC_PHASE_CHECK = 5 };
+rac_status rac_solver_set_timing(rac_solver s, int32_t enable);   /* also clears the totals */
+/* ms (host, RAC_NUM_PHASES) receives the summed milliseconds per phase, launches
+ * (host, RAC_NUM_PHASES or NULL) the number of timed launches per phase. */
+rac_status rac_solver_timing(rac_solver s, double* ms, int64_t* launches);
+/* info (host, 7 int64): p, padded block size, sweep workgroups K, Gram row chunks R, T,
+ * sweep register tile (rows per lane A, columns per wavefront B; 0 = streaming sweep). */
+rac_status rac_solver_info(rac_solver s, int64_t* info);
+
 /* Per-iteration history of the last run: 4 doubles per iteration, (r_p, r_d,
  * beta, KKT or NaN), copied to host memory `out` (capacity max_iter*4). */
 rac_status rac_solver_history(rac_solver s, double* out, int64_t capacity, int64_t* count);
@@ -174,8 +188,8 @@ rac_status rac_regression_c(const void* F, int32_t F_dtype, int64_t rows, int64_
                             double Ns, const double* y, double* c, void* stream);
 
 /* Block matrices of one iteration, for inspection: writes, for each block i,
- * H_BB + beta(I + a_B a_B') (lower triangle valid, padded stride sp = block
- * size rounded up to 16) to out (device, p*sp*sp doubles). */
+ * H_BB + beta(I + a_B a_B') (lower triangle valid, padded stride sp = the block
+ * size rounded up to 16, 32, 64 or 128) to out (device, p*sp*sp doubles). */
 rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed, uint64_t instance,
                               int64_t iter, double beta, int32_t precision, double* out,
                               int64_t* sp_out, void* stream);

@@ -30,66 +30,60 @@ typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 
 enum GramMode { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
 
+// LDS element type and MFMA of each mode.
 template <int MODE> struct GramTraits;
-template <> struct GramTraits<G_F64> {
-  typedef double E; typedef f64x4 Acc; static constexpr int KT = 16; static constexpr int PAD = 1;
-};
-template <> struct GramTraits<G_F32> {
-  typedef float E; typedef f32x4 Acc; static constexpr int KT = 32; static constexpr int PAD = 1;
-};
-template <> struct GramTraits<G_BF16> {
-  typedef uint16_t E; typedef f32x4 Acc; static constexpr int KT = 64; static constexpr int PAD = 8;
-};
+template <> struct GramTraits<G_F64> { typedef double E; typedef f64x4 Acc; static constexpr int PAD = 2; };
+template <> struct GramTraits<G_F32> { typedef float E; typedef f32x4 Acc; static constexpr int PAD = 4; };
+template <> struct GramTraits<G_BF16> { typedef uint16_t E; typedef f32x4 Acc; static constexpr int PAD = 8; };
 
-template <typename E> __device__ __forceinline__ E to_lds(double v);
-template <> __device__ __forceinline__ double to_lds<double>(double v) { return v; }
-template <> __device__ __forceinline__ float to_lds<float>(double v) { return (float)v; }
-
-// Raw element -> LDS element.  BF16 data stays as its bit pattern; FP32 data stays FP32.
-template <typename T, int MODE> struct Loader;
-template <typename T> struct Loader<T, G_F64> {
-  __device__ static double get(const T* F, int64_t i) { return ld_f64(F, i); }
-};
-template <> struct Loader<float, G_F32> {
-  __device__ static float get(const float* F, int64_t i) { return F[i]; }
-};
-template <> struct Loader<uint16_t, G_BF16> {
-  __device__ static uint16_t get(const uint16_t* F, int64_t i) { return F[i]; }
-};
-
-template <int MODE> struct Zero;
-template <> struct Zero<G_F64> { __device__ static double v() { return 0.0; } };
-template <> struct Zero<G_F32> { __device__ static float v() { return 0.f; } };
-template <> struct Zero<G_BF16> { __device__ static uint16_t v() { return (uint16_t)0; } };
+// Raw data element (bits) -> LDS element: exact conversions only.
+template <typename T, int MODE> __device__ __forceinline__ typename GramTraits<MODE>::E to_lds(T v);
+template <> __device__ __forceinline__ double to_lds<double, G_F64>(double v) { return v; }
+template <> __device__ __forceinline__ double to_lds<float, G_F64>(float v) { return (double)v; }
+template <> __device__ __forceinline__ double to_lds<uint16_t, G_F64>(uint16_t v) {
+  return (double)__uint_as_float(((uint32_t)v) << 16);
+}
+template <> __device__ __forceinline__ float to_lds<float, G_F32>(float v) { return v; }
+template <> __device__ __forceinline__ uint16_t to_lds<uint16_t, G_BF16>(uint16_t v) { return v; }
 
 constexpr int kMaxPairsPerWave = 9;   // 36 lower tiles of a 128x128 block over 4 waves
+constexpr int KT = 64;                // rows per LDS tile
 
-template <typename T, int MODE>
+// One workgroup: block `blk`, rows [rb, re).  Data move as 16-byte vectors of
+// VE = 16/sizeof(T) consecutive rows of one column; the next 64-row tile is
+// loaded into registers while the matrix cores work on the current one.
+template <typename T, int MODE, int SP>
 __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t ldF, int64_t rows,
                                               int64_t n, int64_t p, const int32_t* __restrict__ perm,
-                                              int R, int sp, double* __restrict__ partial) {
+                                              int R, int vec, double* __restrict__ partial) {
   typedef GramTraits<MODE> Tr;
   typedef typename Tr::E E;
   typedef typename Tr::Acc Acc;
-  constexpr int KT = Tr::KT;
+  constexpr int VE = 16 / sizeof(T);            // elements per 16-byte vector
+  constexpr int VPC = KT / VE;                  // vectors per column per tile
+  constexpr int NVEC = SP * VPC;
+  constexpr int NV = (NVEC + 255) / 256;        // vectors per thread per tile
   constexpr int LD = KT + Tr::PAD;              // LDS row stride of the column-major tile
-  __shared__ E tile[kMaxBlock * LD];            // tile[m * LD + k] = F[r0 + k, col_m]
-  __shared__ int64_t colbase[kMaxBlock];
+  constexpr int NT = SP / 16, NPAIR = NT * (NT + 1) / 2;
+  constexpr int MAXP = (NPAIR + 3) / 4;
+  __shared__ __attribute__((aligned(16))) E tile[SP * LD];   // tile[m * LD + k] = F[r0 + k, col_m]
+  __shared__ int64_t colbase[SP];
 
   const int blk = blockIdx.x, chunk = blockIdx.y;
   const int64_t s0 = block_start(blk, n, p);
   const int sb = (int)(block_start(blk + 1, n, p) - s0);
-  const int64_t rb = block_start(chunk, rows, R), re = block_start(chunk + 1, rows, R);
+  // row chunks are whole tiles except the last
+  const int64_t ntiles = (rows + KT - 1) / KT;
+  const int64_t rb = block_start(chunk, ntiles, R) * KT;
+  const int64_t re_t = block_start(chunk + 1, ntiles, R) * KT;
+  const int64_t re = re_t < rows ? re_t : rows;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int NT = sp / 16;
-  const int npairs = NT * (NT + 1) / 2;
+  for (int m = tid; m < SP; m += 256) colbase[m] = m < sb ? (int64_t)perm[s0 + m] * ldF : -1;
 
-  for (int m = tid; m < sp; m += 256) colbase[m] = m < sb ? (int64_t)perm[s0 + m] * ldF : -1;
-
-  Acc acc[kMaxPairsPerWave];
-  int pti[kMaxPairsPerWave], ptj[kMaxPairsPerWave];
+  Acc acc[MAXP];
+  int pti[MAXP], ptj[MAXP];
 #pragma unroll
-  for (int q = 0; q < kMaxPairsPerWave; ++q) {
+  for (int q = 0; q < MAXP; ++q) {
     acc[q] = Acc{0, 0, 0, 0};
     int pr = wave + 4 * q;               // pair index -> (ti >= tj), row-major over the lower triangle
     int ti = 0;
@@ -99,20 +93,45 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
   }
   __syncthreads();
 
-  for (int64_t r0 = rb; r0 < re; r0 += KT) {
-    const int kn = (int)((re - r0) < KT ? (re - r0) : KT);
-    // gather: consecutive threads take consecutive rows of one column (contiguous in memory)
-    for (int e = tid; e < sp * KT; e += 256) {
-      const int m = e / KT, k = e - m * KT;
-      const int64_t cb = colbase[m];
-      E v = Zero<MODE>::v();
-      if (cb >= 0 && k < kn) v = Loader<T, MODE>::get(F, cb + r0 + k);
-      tile[m * LD + k] = v;
-    }
-    __syncthreads();
+  T stage[NV][VE];
+  auto load = [&](int64_t r0) {
 #pragma unroll
-    for (int q = 0; q < kMaxPairsPerWave; ++q) {
-      if (wave + 4 * q < npairs) {
+    for (int q = 0; q < NV; ++q) {
+      const int v = tid + 256 * q;
+      const int m = v / VPC, seg = v % VPC;
+      const int64_t cb = (v < NVEC) ? colbase[m] : -1;
+      const int64_t r = r0 + seg * VE;
+      if (cb >= 0 && vec && r + VE <= re) {
+        const uint4 raw = *reinterpret_cast<const uint4*>(F + cb + r);
+        const T* e = reinterpret_cast<const T*>(&raw);
+#pragma unroll
+        for (int u = 0; u < VE; ++u) stage[q][u] = e[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < VE; ++u) stage[q][u] = (cb >= 0 && r + u < re) ? F[cb + r + u] : (T)0;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int v = tid + 256 * q;
+      if (v < NVEC) {
+        const int m = v / VPC, seg = v % VPC;
+#pragma unroll
+        for (int u = 0; u < VE; ++u) tile[m * LD + seg * VE + u] = to_lds<T, MODE>(stage[q][u]);
+      }
+    }
+  };
+
+  if (rb < re) load(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += KT) {
+    store();
+    __syncthreads();
+    if (r0 + KT < re) load(r0 + KT);     // next tile in flight during the MFMAs
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q) {
+      if (wave + 4 * q < NPAIR) {
         const int am = pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
         if constexpr (MODE == G_F64) {
 #pragma unroll
@@ -131,12 +150,8 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
         } else {
 #pragma unroll
           for (int kk = 0; kk < KT; kk += 32) {
-            bf16x8 av, bv;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              av[e] = (short)tile[am * LD + kk + 8 * (lane >> 4) + e];
-              bv[e] = (short)tile[bn * LD + kk + 8 * (lane >> 4) + e];
-            }
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[am * LD + kk + 8 * (lane >> 4)]);
+            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&tile[bn * LD + kk + 8 * (lane >> 4)]);
             acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, av),
                                                              __builtin_bit_cast(bf16x8v, bv),
                                                              acc[q], 0, 0, 0);
@@ -147,139 +162,191 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
     __syncthreads();
   }
   // write the partial lower tiles in FP64
-  double* out = partial + ((int64_t)blk * R + chunk) * (int64_t)sp * sp;
+  double* out = partial + ((int64_t)blk * R + chunk) * (int64_t)SP * SP;
 #pragma unroll
-  for (int q = 0; q < kMaxPairsPerWave; ++q) {
-    if (wave + 4 * q < npairs) {
+  for (int q = 0; q < MAXP; ++q) {
+    if (wave + 4 * q < NPAIR) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         int row, col = ptj[q] * 16 + (lane & 15);
         if constexpr (MODE == G_F64) row = pti[q] * 16 + 4 * i + (lane >> 4);   // f64 output layout
         else row = pti[q] * 16 + 4 * (lane >> 4) + i;                           // f32 output layout
-        out[(int64_t)row * sp + col] = (double)acc[q][i];
+        out[(int64_t)row * SP + col] = (double)acc[q][i];
       }
     }
   }
 }
 
-// Sum the partial Grams, add the diagonal and penalty terms, Cholesky, inverse.
-__global__ void __launch_bounds__(256) k_factor(const double* __restrict__ partial, int R, int sp,
-                                                int64_t n, int64_t p, const int32_t* __restrict__ perm,
-                                                double Ns, const double* __restrict__ h,
-                                                const double* __restrict__ a, const double* beta_ptr,
-                                                double beta_val, double* __restrict__ out,
-                                                int write_matrix, DevScalars* sc, int64_t iter_global,
-                                                int publish_beta) {
-  extern __shared__ double smem[];
-  const int LDM = sp + 1;
-  double* M = smem;                  // M[i * LDM + j], lower triangle
-  double* colj = smem + sp * LDM;    // one saved column
-  __shared__ int32_t cols[kMaxBlock];
-  __shared__ int failed;
-  const int blk = blockIdx.x, tid = threadIdx.x;
+// Sum the partial Grams, add the diagonal and penalty terms, then invert the
+// block matrix by Gauss-Jordan elimination without pivoting.  For a symmetric
+// positive definite matrix the k-th pivot is the k-th diagonal entry of the
+// Schur complement, i.e. the square of the k-th Cholesky pivot, so Assumption
+// 2.1 is checked exactly as a Cholesky factorisation would check it (a pivot
+// that is not positive is reported with its iteration and block).
+//
+// The SP x SP matrix lives in registers: thread (ti, tj) of a 16 x 16 grid owns
+// rows ti + 16a and columns tj + 16b (a, b < SP/16).  At pivot k only row k and
+// column k travel through LDS (double-buffered by the parity of k, one barrier
+// per step); every owned entry is then updated independently.
+// The same kernel writes the iterate-independent part of every gradient of the
+// block, gbase = c - xi + beta (x - z) + h.x - mu a, in permuted order.
+template <int SP>
+__global__ void __launch_bounds__(256) k_factor(const double* __restrict__ partial, int R, int64_t n,
+                                                int64_t p, const int32_t* __restrict__ perm, double Ns,
+                                                const double* __restrict__ h, const double* __restrict__ a,
+                                                const double* beta_ptr, double beta_val,
+                                                double* __restrict__ out, int write_matrix, DevScalars* sc,
+                                                int64_t iter_global, int publish_beta,
+                                                const double* __restrict__ c, const double* __restrict__ x,
+                                                const double* __restrict__ z, const double* __restrict__ xi,
+                                                double* __restrict__ gbase) {
+  constexpr int NA = SP / 16;
+  __shared__ double rowk[2][SP];
+  __shared__ double colk[2][SP];
+  __shared__ int32_t cols[SP];
+  const int blk = blockIdx.x, tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
   const int64_t s0 = block_start(blk, n, p);
   const int sb = (int)(block_start(blk + 1, n, p) - s0);
   const double beta = beta_ptr ? *beta_ptr : beta_val;
-  for (int m = tid; m < sp; m += 256) cols[m] = m < sb ? perm[s0 + m] : -1;
-  if (tid == 0) failed = 0;
+  for (int m = tid; m < SP; m += 256) cols[m] = m < sb ? perm[s0 + m] : -1;
   if (publish_beta && sc && blk == 0 && tid == 0) sc->beta = beta;
   __syncthreads();
 
-  const double* part = partial + (int64_t)blk * R * sp * sp;
-  for (int e = tid; e < sp * sp; e += 256) {
-    const int i = e / sp, j = e - i * sp;
-    if (j > i) continue;
-    double v;
-    if (i < sb && j < sb) {
-      double s = 0.0;
-      for (int r = 0; r < R; ++r) s += part[(int64_t)r * sp * sp + e];
-      v = s / Ns;
-      if (i == j) v += beta + (h ? h[cols[i]] : 0.0);
-      if (a) v += beta * a[cols[i]] * a[cols[j]];
-    } else {
-      v = (i == j) ? 1.0 : 0.0;   // padding: an identity block, decoupled from the real one
-    }
-    M[i * LDM + j] = v;
+  if (gbase && sc && tid < sb) {
+    const int col = cols[tid];
+    double v = c[col] - xi[col] + beta * (x[col] - z[col]);
+    if (h) v += h[col] * x[col];
+    if (a) v -= sc->mu * a[col];
+    gbase[s0 + tid] = v;
   }
-  __syncthreads();
 
-  double* dst = out + (int64_t)blk * sp * sp;
-  if (write_matrix) {
-    for (int e = tid; e < sp * sp; e += 256) {
-      const int i = e / sp, j = e - i * sp;
-      dst[e] = (j <= i && i < sb) ? M[i * LDM + j] : 0.0;
+  // gather: entry (i, j) is the lower-triangle partial (max, min); R partials summed in order
+  const double* part = partial + (int64_t)blk * R * SP * SP;
+  double Mr[NA][NA];
+#pragma unroll
+  for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < NA; ++bb) Mr[aa][bb] = 0.0;
+  for (int r = 0; r < R; ++r) {
+    const double* pr = part + (int64_t)r * SP * SP;
+    double v[NA][NA];
+#pragma unroll
+    for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < NA; ++bb) {
+        const int i = ti + 16 * aa, j = tj + 16 * bb;
+        v[aa][bb] = (i < sb && j < sb) ? pr[i >= j ? i * SP + j : j * SP + i] : 0.0;
+      }
+#pragma unroll
+    for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < NA; ++bb) Mr[aa][bb] += v[aa][bb];
+  }
+#pragma unroll
+  for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < NA; ++bb) {
+      const int i = ti + 16 * aa, j = tj + 16 * bb;
+      double v;
+      if (i < sb && j < sb) {
+        v = Mr[aa][bb] / Ns;
+        if (i == j) v += beta + (h ? h[cols[i]] : 0.0);
+        if (a) v += beta * a[cols[i]] * a[cols[j]];
+      } else {
+        v = (i == j) ? 1.0 : 0.0;   // padding: an identity block, decoupled from the real one
+      }
+      Mr[aa][bb] = v;
     }
+
+  double* dst = out + (int64_t)blk * SP * SP;
+  if (write_matrix) {
+#pragma unroll
+    for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < NA; ++bb) {
+        const int i = ti + 16 * aa, j = tj + 16 * bb;
+        dst[i * SP + j] = (j <= i && i < sb) ? Mr[aa][bb] : 0.0;
+      }
     return;
   }
 
-  // right-looking Cholesky, lower triangle in place
-  for (int k = 0; k < sp; ++k) {
-    const double d = M[k * LDM + k];
-    if (!(d > 0.0) || !isfinite(d)) {          // same value seen by every thread
-      if (tid == 0) {
-        failed = 1;
-        if (sc) {
-          unsigned long long key = ((unsigned long long)iter_global << 32) | (unsigned)blk;
-          atomicMin((unsigned long long*)&sc->fail_key, key);
-        }
+  bool failed = false;
+  for (int k = 0; k < sb; ++k) {
+    const int buf = k & 1;
+    const int ka = k >> 4, kr = k & 15;
+    // owners of row k and column k publish them
+    if (ti == kr) {
+#pragma unroll
+      for (int aa = 0; aa < NA; ++aa)
+        if (aa == ka)
+#pragma unroll
+          for (int bb = 0; bb < NA; ++bb) rowk[buf][tj + 16 * bb] = Mr[aa][bb];
+    }
+    if (tj == kr) {
+#pragma unroll
+      for (int bb = 0; bb < NA; ++bb)
+        if (bb == ka)
+#pragma unroll
+          for (int aa = 0; aa < NA; ++aa) colk[buf][ti + 16 * aa] = Mr[aa][bb];
+    }
+    __syncthreads();
+    const double piv = rowk[buf][k];           // the same value in every thread
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (tid == 0 && sc) {
+        unsigned long long key = ((unsigned long long)iter_global << 32) | (unsigned)blk;
+        atomicMin((unsigned long long*)&sc->fail_key, key);
       }
+      failed = true;
       break;
     }
-    const double piv = sqrt(d);
-    __syncthreads();
-    for (int i = k + 1 + tid; i < sp; i += 256) M[i * LDM + k] /= piv;
-    if (tid == 0) M[k * LDM + k] = piv;
-    __syncthreads();
-    const int mm = sp - k - 1;
-    for (int e = tid; e < mm * mm; e += 256) {
-      const int ii = e / mm, jj = e - ii * mm;
-      if (jj <= ii) {
-        const int i = k + 1 + ii, j = k + 1 + jj;
-        M[i * LDM + j] -= M[i * LDM + k] * M[j * LDM + k];
+    const double ip = 1.0 / piv;
+    double rk[NA], ck[NA];
+#pragma unroll
+    for (int bb = 0; bb < NA; ++bb) rk[bb] = rowk[buf][tj + 16 * bb] * ip;
+#pragma unroll
+    for (int aa = 0; aa < NA; ++aa) ck[aa] = colk[buf][ti + 16 * aa];
+#pragma unroll
+    for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < NA; ++bb) {
+        const bool ri = (ti + 16 * aa) == k, cj = (tj + 16 * bb) == k;
+        double v;
+        if (ri) v = cj ? ip : rk[bb];
+        else if (cj) v = -ck[aa] * ip;
+        else v = Mr[aa][bb] - ck[aa] * rk[bb];
+        Mr[aa][bb] = v;
       }
-    }
-    __syncthreads();
   }
-  __syncthreads();
   if (failed) {
-    for (int e = tid; e < sp * sp; e += 256) dst[e] = 0.0;   // zero step for a failed block
+#pragma unroll
+    for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < NA; ++bb) dst[(ti + 16 * aa) * SP + tj + 16 * bb] = 0.0;   // zero step
     return;
   }
-
-  // X = L^{-1} in place, columns from last to first:
-  //   X_jj = 1/L_jj,  X_ij = -(sum_{k=j+1..i} X_ik L_kj) / L_jj  (i > j)
-  for (int j = sp - 1; j >= 0; --j) {
-    for (int i = j + tid; i < sp; i += 256) colj[i] = M[i * LDM + j];
-    __syncthreads();
-    for (int i = j + tid; i < sp; i += 256) {
-      if (i == j) {
-        M[j * LDM + j] = 1.0 / colj[j];
-      } else {
-        double s = 0.0;
-        for (int k = j + 1; k <= i; ++k) s += M[i * LDM + k] * colj[k];
-        M[i * LDM + j] = -s / colj[j];
-      }
+#pragma unroll
+  for (int aa = 0; aa < NA; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < NA; ++bb) {
+      const int i = ti + 16 * aa, j = tj + 16 * bb;
+      dst[i * SP + j] = (i < sb && j < sb) ? Mr[aa][bb] : 0.0;
     }
-    __syncthreads();
-  }
-  // M^{-1} = X'X:  (i, j) = sum_{k >= max(i,j)} X_ki X_kj  (symmetric, written in full)
-  for (int e = tid; e < sp * sp; e += 256) {
-    const int i = e / sp, j = e - i * sp;
-    double v = 0.0;
-    if (i < sb && j < sb) {
-      const int k0 = i > j ? i : j;
-      for (int k = k0; k < sb; ++k) v += M[k * LDM + i] * M[k * LDM + j];
-    }
-    dst[e] = v;
-  }
 }
 
 template <typename T, int MODE>
 hipError_t gram_launch(const GramArgs& g, hipStream_t st) {
   dim3 grid((unsigned)g.p, (unsigned)g.R);
-  k_gram<T, MODE><<<grid, 256, 0, st>>>((const T*)g.F, g.ldF, g.rows, g.n, g.p, g.perm, g.R, g.sp,
-                                        g.partial);
-  return hipGetLastError();
+  const int vec = (g.ldF % (16 / (int)sizeof(T)) == 0) && ((uintptr_t)g.F % 16 == 0);
+  const T* F = (const T*)g.F;
+#define RAC_GRAM(SPV)                                                                          \
+  if (g.sp == SPV) {                                                                           \
+    k_gram<T, MODE, SPV><<<grid, 256, 0, st>>>(F, g.ldF, g.rows, g.n, g.p, g.perm, g.R, vec,   \
+                                               g.partial);                                    \
+    return hipGetLastError();                                                                 \
+  }
+  RAC_GRAM(16) RAC_GRAM(32) RAC_GRAM(64) RAC_GRAM(128)
+#undef RAC_GRAM
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -296,19 +363,17 @@ hipError_t launch_gram(const GramArgs& g, hipStream_t st) {
 }
 
 hipError_t launch_factor(const FactorArgs& f, hipStream_t st) {
-  size_t lds = sizeof(double) * ((size_t)f.sp * (f.sp + 1) + f.sp);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_factor,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * (kMaxBlock * (kMaxBlock + 1) + kMaxBlock)));
-    if (e != hipSuccess) return e;
-    attr_set = true;
+#define RAC_FACTOR(SPV)                                                                              \
+  if (f.sp == SPV) {                                                                                 \
+    k_factor<SPV><<<(unsigned)f.p, 256, 0, st>>>(f.partial, f.R, f.n, f.p, f.perm, f.Ns, f.h, f.a,     \
+                                                  f.beta_ptr, f.beta_val, f.Minv, f.write_matrix, f.sc, \
+                                                  f.iter_global, f.publish_beta, f.c, f.x, f.z, f.xi,   \
+                                                  f.gbase);                                             \
+    return hipGetLastError();                                                                        \
   }
-  k_factor<<<(unsigned)f.p, 256, lds, st>>>(f.partial, f.R, f.sp, f.n, f.p, f.perm, f.Ns, f.h, f.a,
-                                            f.beta_ptr, f.beta_val, f.Minv, f.write_matrix, f.sc,
-                                            f.iter_global, f.publish_beta);
-  return hipGetLastError();
+  RAC_FACTOR(16) RAC_FACTOR(32) RAC_FACTOR(64) RAC_FACTOR(128)
+#undef RAC_FACTOR
+  return hipErrorInvalidValue;
 }
 
 }  // namespace rac

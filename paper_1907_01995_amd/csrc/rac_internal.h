@@ -94,6 +94,9 @@ struct FactorArgs {
   DevScalars* sc;          // failure reporting (may be null)
   int64_t iter_global;
   int publish_beta;        // write the beta used into sc->beta (given schedules)
+  // iterate-independent part of each block's gradient, in permuted order (may be null):
+  //   gbase = c - xi + beta (x - z) + h.x - mu a
+  const double* c; const double* x; const double* z; const double* xi; double* gbase;
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 
@@ -107,7 +110,11 @@ struct SweepArgs {
   uint64_t* flags;         // [K * kFlagStride], monotone epochs
   uint64_t epoch_base;
   int K;
+  const double* gbase;     // iterate-independent gradient terms, permuted order (register path)
+  int tileA, tileB;        // register tile: rows per lane, columns per wavefront (0: streaming path)
 };
+// Register-tile shapes with a compiled sweep kernel (A rows per lane, B columns per wavefront).
+bool sweep_tile_supported(int32_t dtype, int A, int B);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
 
 struct UpdateArgs {

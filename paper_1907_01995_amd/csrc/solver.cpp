@@ -59,7 +59,7 @@ rac_status validate_problem(const rac_problem* P) {
   return RAC_OK;
 }
 
-int padded(int64_t s) { return (int)((s + 15) / 16 * 16); }
+int padded(int64_t s) { return s <= 16 ? 16 : (s <= 32 ? 32 : (s <= 64 ? 64 : 128)); }  // 16..128, power of two
 
 struct Buffers {
   std::vector<void*> owned;
@@ -100,6 +100,37 @@ rac_status alloc_perm_work(Buffers& B, int64_t T, int64_t n, PermWork* w, int32_
   return RAC_OK;
 }
 
+// Register-tile shape of the sweep: B columns per wavefront covers the largest
+// block; A rows per lane is the smallest shape that keeps the number of
+// cooperating groups K = ceil(rows / 64A) at or below 128 (the all-to-all
+// exchange of partials grows with K), else the largest compiled shape with
+// K <= 256 (one group per compute unit).  Returns false when no register shape
+// fits; the streaming sweep is used then.
+bool choose_tile(int32_t dtype, int64_t rows, int64_t smax, int forced_K, int* A_out, int* B_out, int* K_out) {
+  const int B = smax <= 32 ? 8 : (smax <= 64 ? 16 : 32);
+  const int As[3] = {1, 2, 4};
+  if (forced_K > 0) {
+    const int64_t per = (rows + forced_K - 1) / forced_K;
+    for (int A : As)
+      if (per <= 64 * A && sweep_tile_supported(dtype, A, B)) {
+        *A_out = A; *B_out = B; *K_out = forced_K;
+        return true;
+      }
+    return false;
+  }
+  for (int lim : {128, 256}) {
+    for (int A : As) {
+      if (!sweep_tile_supported(dtype, A, B)) continue;
+      const int64_t K = (rows + 64 * A - 1) / (64 * A);
+      if (K <= lim) {
+        *A_out = A; *B_out = B; *K_out = (int)K;
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
 int auto_sweep_groups(int64_t rows) {
   int64_t K = rows / 320;
   if (K < 1) K = 1;
@@ -108,8 +139,8 @@ int auto_sweep_groups(int64_t rows) {
 }
 
 int auto_row_chunks(int64_t p, int64_t rows) {
-  int64_t R = (512 + p - 1) / p;
-  int64_t rmax = rows / 128;
+  int64_t R = (256 + p - 1) / p;
+  int64_t rmax = rows / 256;
   if (rmax < 1) rmax = 1;
   if (R > rmax) R = rmax;
   if (R < 1) R = 1;
@@ -148,7 +179,15 @@ struct rac_solver_s {
   double* mv_part = nullptr;
   int mv_nparts = 1;
   double* uz = nullptr;     // F z for the objective
+  double* gbase = nullptr;  // iterate-independent gradient terms, permuted order
+  int tileA = 0, tileB = 0; // register tile of the sweep (0: streaming sweep)
   DevScalars hsc{};
+  // optional per-phase timing with HIP events on the run's stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev;            // pool, two per timed launch
+  std::vector<int> ev_phase;             // phase of each recorded pair in the current chunk
+  double phase_ms[RAC_NUM_PHASES] = {0};
+  int64_t phase_count[RAC_NUM_PHASES] = {0};
 };
 
 namespace {
@@ -177,33 +216,82 @@ rac_status fx_into_u(rac_solver s, const double* x, double* u, hipStream_t st) {
   return RAC_OK;
 }
 
+// Event pairs around timed launches: begin() records the start event of the
+// next pair, end() its stop event and remembers the phase.
+struct PhaseTimer {
+  rac_solver s;
+  hipStream_t st;
+  hipError_t begin() {
+    if (!s->timing) return hipSuccess;
+    const size_t i = 2 * s->ev_phase.size();
+    while (s->ev.size() < i + 2) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      s->ev.push_back(e);
+    }
+    return hipEventRecord(s->ev[i], st);
+  }
+  hipError_t end(int phase) {
+    if (!s->timing) return hipSuccess;
+    const size_t i = 2 * s->ev_phase.size();
+    s->ev_phase.push_back(phase);
+    return hipEventRecord(s->ev[i + 1], st);
+  }
+};
+
+rac_status collect_timing(rac_solver s) {
+  if (!s->timing) return RAC_OK;
+  for (size_t q = 0; q < s->ev_phase.size(); ++q) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev[2 * q], s->ev[2 * q + 1]));
+    s->phase_ms[s->ev_phase[q]] += ms;
+    s->phase_count[s->ev_phase[q]] += 1;
+  }
+  s->ev_phase.clear();
+  return RAC_OK;
+}
+
 rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
   const rac_problem& P = s->P;
+  PhaseTimer tm{s, st};
   const int64_t k0 = s->hsc.k;
+  HIPCHK(tm.begin());
   HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
+  HIPCHK(tm.end(RAC_PHASE_PARTITION));
   const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
   for (int64_t t = 0; t < Tc; ++t) {
     const int32_t* perm = s->perm + t * s->n;
     GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
                s->partial};
+    HIPCHK(tm.begin());
     HIPCHK(launch_gram(g, st));
+    HIPCHK(tm.end(RAC_PHASE_GRAM));
     FactorArgs f{};
     f.partial = s->partial; f.R = s->R; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
     f.Ns = P.Ns; f.h = P.h; f.a = P.a;
     f.beta_ptr = sched ? s->d_sched + (run_offset + t) : &s->sc->beta;
     f.beta_val = 0.0; f.Minv = s->Minv; f.write_matrix = 0; f.sc = s->sc;
     f.iter_global = k0 + t; f.publish_beta = sched ? 1 : 0;
+    f.c = P.c; f.x = s->x; f.z = s->z; f.xi = s->xi; f.gbase = s->gbase;
+    HIPCHK(tm.begin());
     HIPCHK(launch_factor(f, st));
+    HIPCHK(tm.end(RAC_PHASE_FACTOR));
     SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->Minv, s->sp, P.c, P.h, P.a,
-                P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K};
+                P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
+                s->gbase, s->tileA, s->tileB};
+    HIPCHK(tm.begin());
     HIPCHK(launch_sweep(w, st));
+    HIPCHK(tm.end(RAC_PHASE_SWEEP));
     s->epoch += (uint64_t)s->p;
     UpdateArgs za{};
     za.n = s->n; za.prox = P.prox; za.lam = P.lambda; za.alpha = P.alpha; za.lo = P.lo; za.hi = P.hi;
     za.b = P.b; za.has_eq = P.a ? 1 : 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
     za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
     za.hist_base = k0 - run_offset; za.T = s->T;
+    HIPCHK(tm.begin());
     HIPCHK(launch_zdual(za, st));
+    HIPCHK(tm.end(RAC_PHASE_ZDUAL));
   }
   KKTArgs ka{};
   ka.F = P.F; ka.dtype = P.F_dtype; ka.ldF = P.ldF; ka.rows = s->rows; ka.n = s->n; ka.Ns = P.Ns;
@@ -211,6 +299,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   ka.alpha = P.alpha; ka.lo = P.lo; ka.hi = P.hi; ka.x = s->x; ka.z = s->z; ka.xi = s->xi;
   ka.u = s->u; ka.mu_ptr = &s->sc->mu; ka.mu_val = 0.0; ka.red = s->red; ka.done = s->done;
   ka.out = s->kkt_out;
+  HIPCHK(tm.begin());
   HIPCHK(launch_kkt(ka, st));
   ControlArgs ca{};
   ca.sc = s->sc; ca.kkt_out = s->kkt_out; ca.beta_mode = s->O.beta_mode; ca.rb_mu = s->O.rb_mu;
@@ -218,6 +307,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   ca.decide = ((k0 + Tc) % s->T == 0) ? 1 : 0; ca.hist = s->hist; ca.hist_cap = s->hist_cap;
   ca.hist_base = k0 - run_offset;
   HIPCHK(launch_control(ca, st));
+  HIPCHK(tm.end(RAC_PHASE_CHECK));
   return RAC_OK;
 }
 
@@ -272,7 +362,15 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   s->p = O.num_blocks;
   s->T = O.check_every;
   s->sp = padded(smax);
-  s->K = O.sweep_groups > 0 ? O.sweep_groups : auto_sweep_groups(prob->rows);
+  {
+    int A = 0, B = 0, K = 0;
+    if (choose_tile(prob->F_dtype, prob->rows, smax, O.sweep_groups, &A, &B, &K)) {
+      s->tileA = A; s->tileB = B; s->K = K;
+    } else {
+      s->tileA = s->tileB = 0;
+      s->K = O.sweep_groups > 0 ? O.sweep_groups : auto_sweep_groups(prob->rows);
+    }
+  }
   if (s->K > s->rows) s->K = (int)s->rows;
   s->R = O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows);
   if (s->R > s->rows) s->R = (int)s->rows;
@@ -303,6 +401,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->hist, (size_t)s->hist_cap * 4)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->mv_part, (size_t)s->mv_nparts * s->rows)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->uz, (size_t)s->rows)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->gbase, (size_t)n)) != RAC_OK) return fail(r);
   if (O.beta_mode == RAC_BETA_SCHEDULE) {
     if ((r = s->buf.alloc(&s->d_sched, (size_t)(O.max_iter > 0 ? O.max_iter : 1))) != RAC_OK) return fail(r);
     if (O.max_iter > 0 &&
@@ -329,6 +428,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
 rac_status rac_solver_destroy(rac_solver s) {
   if (!s) return RAC_ERR_ARG;
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   s->buf.release();
   delete s;
   return RAC_OK;
@@ -349,14 +449,16 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
   int64_t done_iters = 0;
   rac_status rc = RAC_OK;
   int32_t run_status = RAC_RUN_MAX_ITER;
+  rac_status e = RAC_OK;
   while (done_iters < budget) {
     const int64_t k = s->hsc.k;
     int64_t Tc = s->T - (k % s->T);
     if (Tc > budget - done_iters) Tc = budget - done_iters;
-    rac_status e = enqueue_iteration_chunk(s, Tc, done_iters, st);
+    e = enqueue_iteration_chunk(s, Tc, done_iters, st);
     if (e != RAC_OK) return e;
     HIPCHK(hipMemcpyAsync(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if ((e = collect_timing(s)) != RAC_OK) return e;
     done_iters += Tc;
     if (s->hsc.fail_key != ~0ULL) {
       res->fail_iter = (int64_t)(s->hsc.fail_key >> 32);
@@ -369,7 +471,7 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
   }
   s->hist_count = s->hsc.k - k_start;
   // objective at z
-  rac_status e = fx_into_u(s, s->z, s->uz, st);
+  e = fx_into_u(s, s->z, s->uz, st);
   if (e != RAC_OK) return e;
   HIPCHK(launch_objective_red(s->rows, s->n, s->P.Ns, s->P.h, s->P.c, s->P.prox, s->P.lambda,
                               s->P.alpha, s->P.obj_const, s->z, s->uz, s->red, s->done, s->obj_out, st));
@@ -419,6 +521,35 @@ rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, 
   if (mu) *mu = s->hsc.mu;
   if (beta) *beta = s->hsc.beta;
   if (iter) *iter = s->hsc.k;
+  return RAC_OK;
+}
+
+rac_status rac_solver_set_timing(rac_solver s, int32_t enable) {
+  if (!s) return RAC_ERR_ARG;
+  s->timing = enable != 0;
+  for (int q = 0; q < RAC_NUM_PHASES; ++q) { s->phase_ms[q] = 0.0; s->phase_count[q] = 0; }
+  s->ev_phase.clear();
+  return RAC_OK;
+}
+
+rac_status rac_solver_timing(rac_solver s, double* ms, int64_t* launches) {
+  if (!s || !ms) return RAC_ERR_ARG;
+  for (int q = 0; q < RAC_NUM_PHASES; ++q) {
+    ms[q] = s->phase_ms[q];
+    if (launches) launches[q] = s->phase_count[q];
+  }
+  return RAC_OK;
+}
+
+rac_status rac_solver_info(rac_solver s, int64_t* info) {
+  if (!s || !info) return RAC_ERR_ARG;
+  info[0] = s->p;
+  info[1] = s->sp;
+  info[2] = s->K;
+  info[3] = s->R;
+  info[4] = s->T;
+  info[5] = s->tileA;
+  info[6] = s->tileB;
   return RAC_OK;
 }
 
@@ -605,6 +736,7 @@ rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed,
     f.partial = partial; f.R = R; f.sp = sp; f.n = prob->n; f.p = p; f.perm = perm; f.Ns = prob->Ns;
     f.h = prob->h; f.a = prob->a; f.beta_ptr = nullptr; f.beta_val = beta; f.Minv = out;
     f.write_matrix = 1; f.sc = nullptr; f.iter_global = iter; f.publish_beta = 0;
+    f.c = nullptr; f.x = nullptr; f.z = nullptr; f.xi = nullptr; f.gbase = nullptr;
     e = launch_factor(f, st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -5,16 +5,25 @@
 //   x_B <- x_B - M_B^{-1} g_B,
 //   g_B = F_B'u/Ns + h_B.x_B + c_B - xi_B + beta(x_B - z_B) - mu a_B + beta a_B (t - b),
 // where u = F x and t = a'x are maintained through the sweep (u += F_B d, t += a_B'd).
+// Everything in g_B except F_B'u and the t term is fixed before the sweep; the
+// factor kernel precomputes it per block (gbase).
 //
-// Work split: K cooperating workgroups each own a contiguous range of the rows
-// of F, and hence of u, which never leaves its owner.  Per block:
-//   1. every workgroup forms its partial F_B'u over its rows (FP64 accumulation,
-//      wavefront-shuffle reductions) and publishes it;
-//   2. one flag per workgroup (no contended counter) tells the others it is ready;
-//   3. every workgroup sums the K partials in the same fixed order, adds the
-//      remaining terms and applies M_B^{-1}, so all of them hold the identical
-//      step d without a second exchange;
-//   4. each updates its own rows of u; workgroup 0 writes x_B.
+// Work split: K cooperating workgroups each own a contiguous range of at most
+// 64*A rows of F, and hence of u, which never leaves its owner (registers).
+// Lane l of every wavefront holds rows l, l+64, ...; wavefront w holds block
+// columns w, w+4, ... (B of them).  Per block:
+//   1. the block's tile of F (rows x columns) is already in registers: it was
+//      prefetched while the previous block was being exchanged, so each element
+//      of F is read from HBM once per sweep and serves both products below;
+//   2. partial F_B'u over the group's rows (FP64 accumulation, wavefront
+//      shuffles), published with agent-scope relaxed atomic stores, then one
+//      flag per group (a monotone epoch, no contended counter);
+//   3. the next block's tile and gbase are loaded while the flags are awaited;
+//   4. every group sums the K partials in the same fixed order, applies M_B^{-1}
+//      (precomputed by the factor kernel) and so holds the identical step d;
+//   5. its rows of u are updated from the register tile; group 0 writes x_B.
+// Cross-group traffic uses only sc1 (device-coherent) loads and stores and an
+// s_waitcnt before the flag store -- no cache write-back or invalidation.
 // Partials are double-buffered by block parity, so one exchange per block suffices.
 #include "rac_internal.h"
 
@@ -114,6 +123,291 @@ __global__ void __launch_bounds__(256) k_sweep(const T* __restrict__ F, int64_t 
   if (g == 0 && tid == 0) sc->t = t;
 }
 
+// ---------------------------------------------------------------------------
+// Register-tiled sweep (the default path).
+
+template <typename T> struct RegT { typedef float type; };
+template <> struct RegT<double> { typedef double type; };
+__device__ __forceinline__ float ld_reg(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ld_reg(const uint16_t* p, int64_t i) {
+  return __uint_as_float(((uint32_t)p[i]) << 16);
+}
+__device__ __forceinline__ double ld_reg(const double* p, int64_t i) { return p[i]; }
+
+__device__ __forceinline__ void st_coherent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coherent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct Sweep2Args {
+  const void* F; int64_t ldF; int64_t rows; int64_t n; int64_t p;
+  const int32_t* perm; const double* Minv; int sp; const double* gbase;
+  const double* a; double b; double Ns;
+  double* x; double* u; DevScalars* sc; double* partials; uint64_t* flags; uint64_t epoch_base;
+  int64_t RW;              // rows per group (a multiple of A, at most 64A)
+  int vec;                 // column starts allow A-element vector loads
+};
+
+// Lane l holds rows r0 + A l + a (a < A) of the group's range: A consecutive
+// rows of a column form one vector load when the data are aligned.
+template <typename T, int A, int B>
+__device__ __forceinline__ void load_tile(const T* __restrict__ F, int64_t ldF, int64_t r0, int64_t r1,
+                                          const int32_t* cols, int sb, int lane, int wave, int vec,
+                                          typename RegT<T>::type (&tile)[A][B]) {
+  typedef typename RegT<T>::type R;
+  const int64_t rl = r0 + (int64_t)A * lane;
+#pragma unroll
+  for (int bb = 0; bb < B; ++bb) {
+    const int j = wave + 4 * bb;
+    if (j < sb) {
+      const T* colp = F + (int64_t)cols[j] * ldF;
+      if constexpr (A > 1) {
+        if (vec && rl + A <= r1) {
+          typedef T VT __attribute__((ext_vector_type(A)));
+          const VT v = *reinterpret_cast<const VT*>(colp + rl);
+#pragma unroll
+          for (int aa = 0; aa < A; ++aa) tile[aa][bb] = ld_reg(reinterpret_cast<const T*>(&v), aa);
+          continue;
+        }
+      }
+#pragma unroll
+      for (int aa = 0; aa < A; ++aa) tile[aa][bb] = (rl + aa < r1) ? ld_reg(colp, rl + aa) : (R)0;
+    } else {
+#pragma unroll
+      for (int aa = 0; aa < A; ++aa) tile[aa][bb] = (R)0;
+    }
+  }
+}
+
+// Sum B per-lane values across the 64 lanes, transposed: B-1 halving exchanges
+// leave lane l with one column's partial over a lane subset, then full
+// reductions over the remaining lane bits.  Lane l ends with the total of
+// column index c(l) (bits 5, 4, ... of l, most significant first); it is
+// returned together with c.  The summation pattern is fixed.
+template <int B>
+__device__ __forceinline__ double transpose_sum(double (&v)[B], int lane, int& c) {
+  int half = B / 2, o = 32;
+#pragma unroll
+  for (; half >= 1; half >>= 1, o >>= 1) {
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int q = 0; q < half; ++q) {
+      const double send = upper ? v[q] : v[q + half];
+      const double keep = upper ? v[q + half] : v[q];
+      v[q] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  double r = v[0];
+#pragma unroll
+  for (; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  int cc = 0, bit = 32;
+#pragma unroll
+  for (int t = B; t > 1; t >>= 1, bit >>= 1) cc = (cc << 1) | ((lane & bit) ? 1 : 0);
+  c = cc;
+  return r;
+}
+
+template <typename T, int A, int B>
+__global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
+  typedef typename RegT<T>::type R;
+  constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
+  constexpr int KM = (NC + P - 1) / P;            // Minv entries per thread
+  constexpr bool MREG = KM <= 16;                 // keep the next block's inverse in registers
+  const int K = gridDim.x, g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jc = tid % NC, part = tid / NC;
+  const int64_t r0 = (int64_t)g * s.RW;
+  const int64_t r1 = r0 + s.RW < s.rows ? r0 + s.RW : s.rows;
+  const T* F = (const T*)s.F;
+  __shared__ double sh_g[kMaxBlock];
+  __shared__ double sh_d[kMaxBlock];
+  __shared__ double sh_pg[256];
+  __shared__ double sh_red[4 * 64 * A];
+  __shared__ int32_t sh_cols[2][kMaxBlock];
+  const double beta = s.sc->beta;
+  double t = s.sc->t;
+  double ureg[A];
+#pragma unroll
+  for (int aa = 0; aa < A; ++aa) {
+    const int64_t r = r0 + (int64_t)A * lane + aa;
+    ureg[aa] = r < r1 ? s.u[r] : 0.0;
+  }
+  R ta[A][B], tb[A][B];
+  double mreg[MREG ? KM : 1];
+  auto load_minv = [&](int64_t i, int sbi) {
+    if constexpr (MREG) {
+      const double* Mi = s.Minv + i * (int64_t)s.sp * s.sp;
+#pragma unroll
+      for (int e = 0; e < KM; ++e) {
+        const int k = part + P * e;
+        mreg[e] = (jc < sbi && k < sbi) ? Mi[(int64_t)k * s.sp + jc] : 0.0;
+      }
+    }
+  };
+  {
+    const int sb0 = (int)block_start(1, s.n, s.p);
+    if (tid < sb0) sh_cols[0][tid] = s.perm[tid];
+    __syncthreads();
+    load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[0], sb0, lane, wave, s.vec, ta);
+    load_minv(0, sb0);
+  }
+  double gb = tid < (int)block_start(1, s.n, s.p) ? s.gbase[tid] : 0.0;
+
+  auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B]) {
+    const int64_t s0 = block_start(i, s.n, s.p);
+    const int sb = (int)(block_start(i + 1, s.n, s.p) - s0);
+    const int32_t* cols = sh_cols[i & 1];
+    const bool more = i + 1 < s.p;
+    const int64_t s1 = block_start(i + 1, s.n, s.p);
+    const int sb1 = more ? (int)(block_start(i + 2, s.n, s.p) - s1) : 0;
+    if (tid < sb1) sh_cols[(i + 1) & 1][tid] = s.perm[s1 + tid];   // indices of the next block
+    // partial F_B'u over this group's rows, transposed across lanes
+    double* buf = s.partials + (int64_t)(i & 1) * K * kMaxBlock;
+    {
+      double v[B];
+#pragma unroll
+      for (int bb = 0; bb < B; ++bb) {
+        double acc = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < A; ++aa) acc += (double)cur[aa][bb] * ureg[aa];
+        v[bb] = acc;
+      }
+      int c;
+      const double tot = transpose_sum<B>(v, lane, c);
+      const int j = wave + 4 * c;
+      if ((lane & (64 / B - 1)) == 0 && j < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + j], tot);
+    }
+    const uint64_t epoch = s.epoch_base + (uint64_t)i + 1;
+    __builtin_amdgcn_s_waitcnt(0);   // partial stores complete at device scope; next indices landed
+    __syncthreads();
+    if (K > 1 && tid == 0)
+      __hip_atomic_store(&s.flags[(int64_t)g * kFlagStride], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // prefetch the next block's tile and gbase while the other groups finish
+    double gb_next = 0.0;
+    if (more) {
+      load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(i + 1) & 1], sb1, lane, wave, s.vec, nxt);
+      if (tid < sb1) gb_next = s.gbase[s1 + tid];
+    }
+    if (K > 1 && wave == 0) {
+      for (int q = lane; q < K; q += 64)
+        while (__hip_atomic_load(&s.flags[(int64_t)q * kFlagStride], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) < epoch)
+          __builtin_amdgcn_s_sleep(1);
+    }
+    __syncthreads();
+    // full gradient: P threads per column, every P-th group, sixteen loads in flight
+    {
+      double acc = 0.0;
+      if (jc < sb) {
+        int q = part;
+        for (; q < K; q += 16 * P) {
+          double v[16];
+#pragma unroll
+          for (int e = 0; e < 16; ++e)
+            v[e] = (q + e * P < K) ? ld_coherent(&buf[(int64_t)(q + e * P) * kMaxBlock + jc]) : 0.0;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) acc += v[e];
+        }
+      }
+      sh_pg[part * NC + jc] = acc;
+    }
+    __syncthreads();
+    if (tid < sb) {
+      double tot = 0.0;
+#pragma unroll
+      for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
+      double v = tot / s.Ns + gb;
+      if (s.a) v += beta * s.a[cols[tid]] * (t - s.b);
+      sh_g[tid] = v;
+    }
+    __syncthreads();
+    // step d = -M^{-1} g, P threads per column, combined in order
+    {
+      double acc = 0.0;
+      if constexpr (MREG) {
+#pragma unroll
+        for (int e = 0; e < KM; ++e) {
+          const int k = part + P * e;
+          acc += mreg[e] * sh_g[k < sb ? k : 0] * (k < sb ? 1.0 : 0.0);
+        }
+      } else {
+        const double* Mi = s.Minv + i * (int64_t)s.sp * s.sp;
+        if (jc < sb) {
+#pragma unroll 16
+          for (int k = part; k < sb; k += P) acc += Mi[(int64_t)k * s.sp + jc] * sh_g[k];
+        }
+      }
+      sh_pg[part * NC + jc] = acc;
+    }
+    __syncthreads();
+    if (tid < NC) {
+      double tot = 0.0;
+#pragma unroll
+      for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
+      sh_d[tid] = tid < sb ? -tot : 0.0;
+    }
+    if (more) load_minv(i + 1, sb1);   // the next inverse arrives during the update below
+    __syncthreads();
+    if (s.a) {
+      double dt = 0.0;
+      for (int j = 0; j < sb; ++j) dt += s.a[cols[j]] * sh_d[j];
+      t += dt;   // every thread forms the same sum in the same order
+    }
+    // rows of u from the register tile, summed over the four wavefronts in order
+#pragma unroll
+    for (int aa = 0; aa < A; ++aa) {
+      double v = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < B; ++bb) v += (double)cur[aa][bb] * sh_d[wave + 4 * bb];
+      sh_red[wave * 64 * A + 64 * aa + lane] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int aa = 0; aa < A; ++aa) {
+      const int q = 64 * aa + lane;
+      ureg[aa] += ((sh_red[q] + sh_red[64 * A + q]) + sh_red[2 * 64 * A + q]) + sh_red[3 * 64 * A + q];
+    }
+    if (g == 0 && tid < sb) s.x[cols[tid]] += sh_d[tid];
+    gb = gb_next;
+    __syncthreads();
+  };
+
+  for (int64_t i = 0; i < s.p; i += 2) {
+    block(i, ta, tb);
+    if (i + 1 < s.p) block(i + 1, tb, ta);
+  }
+#pragma unroll
+  for (int aa = 0; aa < A; ++aa) {
+    const int64_t r = r0 + (int64_t)A * lane + aa;
+    if (r < r1) s.u[r] = ureg[aa];
+  }
+  if (g == 0 && tid == 0) s.sc->t = t;
+}
+
+template <typename T, int A, int B>
+hipError_t sweep2_launch(const Sweep2Args& a, int K, hipStream_t st) {
+  if (K == 1) {
+    k_sweep2<T, A, B><<<1, 256, 0, st>>>(a);
+    return hipGetLastError();
+  }
+  Sweep2Args c = a;
+  void* args[] = {(void*)&c};
+  return hipLaunchCooperativeKernel((const void*)k_sweep2<T, A, B>, dim3((unsigned)K), dim3(256), args, 0, st);
+}
+
+template <typename T>
+hipError_t sweep2_dispatch(const Sweep2Args& a, int K, int A, int B, hipStream_t st) {
+#define RAC_SW(AA, BB) if (A == AA && B == BB) return sweep2_launch<T, AA, BB>(a, K, st)
+  RAC_SW(1, 8); RAC_SW(2, 8); RAC_SW(4, 8);
+  RAC_SW(1, 16); RAC_SW(2, 16);
+  RAC_SW(1, 32);
+  if constexpr (sizeof(T) < 8) { RAC_SW(4, 16); RAC_SW(2, 32); }
+#undef RAC_SW
+  return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t sweep_launch(const SweepArgs& s, hipStream_t st) {
   const T* F = (const T*)s.F;
@@ -136,6 +430,22 @@ hipError_t sweep_launch(const SweepArgs& s, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
+  if (s.tileA > 0) {
+    Sweep2Args a{s.F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.gbase, s.a, s.b, s.Ns,
+                 s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0};
+    int64_t rw = (s.rows + s.K - 1) / s.K;
+    rw = (rw + s.tileA - 1) / s.tileA * s.tileA;
+    if (rw > 64 * s.tileA) return hipErrorInvalidValue;
+    a.RW = rw;
+    const int esz = s.dtype == RAC_DT_F64 ? 8 : (s.dtype == RAC_DT_F32 ? 4 : 2);
+    a.vec = (s.ldF % s.tileA == 0) && ((uintptr_t)s.F % (size_t)(esz * s.tileA) == 0);
+    switch (s.dtype) {
+      case RAC_DT_F64: return sweep2_dispatch<double>(a, s.K, s.tileA, s.tileB, st);
+      case RAC_DT_F32: return sweep2_dispatch<float>(a, s.K, s.tileA, s.tileB, st);
+      case RAC_DT_BF16: return sweep2_dispatch<uint16_t>(a, s.K, s.tileA, s.tileB, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (s.dtype) {
     case RAC_DT_F64: return sweep_launch<double>(s, st);
     case RAC_DT_F32: return sweep_launch<float>(s, st);
@@ -144,4 +454,14 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
   }
 }
 
+}  // namespace rac
+
+namespace rac {
+bool sweep_tile_supported(int32_t dtype, int A, int B) {
+  const bool small = dtype != RAC_DT_F64;
+  if (B == 8) return A == 1 || A == 2 || A == 4;
+  if (B == 16) return A == 1 || A == 2 || (A == 4 && small);
+  if (B == 32) return A == 1 || (A == 2 && small);
+  return false;
+}
 }  // namespace rac

@@ -27,7 +27,8 @@ MLP_IN, MLP_HIDDEN = 8, 64
 MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
 EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_solver_set_state",
-            "rac_solver_get_state", "rac_solver_history", "rac_state_export", "rac_state_import",
+            "rac_solver_get_state", "rac_solver_history", "rac_solver_set_timing", "rac_solver_timing",
+            "rac_solver_info", "rac_state_export", "rac_state_import",
             "rac_permutation", "rac_kkt", "rac_objective", "rac_regression_c", "rac_block_matrices",
             "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_status_str"]
 
@@ -85,6 +86,9 @@ def load():
         "rac_solver_set_state": [vp, vp, vp, vp, C.c_double, C.c_double, i64, vp],
         "rac_solver_get_state": [vp, vp, vp, vp, dp, dp, C.POINTER(i64), vp],
         "rac_solver_history": [vp, dp, i64, C.POINTER(i64)],
+        "rac_solver_set_timing": [vp, C.c_int32],
+        "rac_solver_timing": [vp, dp, C.POINTER(i64)],
+        "rac_solver_info": [vp, C.POINTER(i64)],
         "rac_state_export": [vp, vp, C.POINTER(C.c_size_t)],
         "rac_state_import": [vp, vp, C.c_size_t],
         "rac_permutation": [u64, u64, i64, i64, vp, vp],
@@ -291,6 +295,29 @@ class Solver:
                                              C.byref(it), _stream()), "rac_solver_get_state")
         return x.cpu().numpy(), z.cpu().numpy(), xi.cpu().numpy(), mu.value, beta.value, it.value
 
+    PHASES = ("partition", "gram", "factor", "sweep", "zdual", "check")
+
+    def set_timing(self, enable=True):
+        _check(self.lib.rac_solver_set_timing(self.h, 1 if enable else 0), "rac_solver_set_timing")
+
+    def timing(self):
+        """{phase: (total ms, launches)} accumulated since set_timing."""
+        ms = np.zeros(6)
+        cnt = (C.c_int64 * 6)()
+        _check(self.lib.rac_solver_timing(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)), cnt),
+               "rac_solver_timing")
+        return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(self.PHASES)}
+
+    def info(self):
+        v = (C.c_int64 * 7)()
+        _check(self.lib.rac_solver_info(self.h, v), "rac_solver_info")
+        return dict(p=v[0], sp=v[1], K=v[2], R=v[3], T=v[4], tileA=v[5], tileB=v[6])
+
+    def reset(self, beta=None):
+        """Zero state (cold start) at iteration 0."""
+        z = np.zeros(self.prob.n)
+        self.set_state(z, z, z, 0.0, beta, 0)
+
     def history(self):
         out = np.zeros((max(self.max_iter, 1), 4))
         cnt = C.c_int64()
@@ -343,13 +370,16 @@ def objective(prob: Problem, z):
 def block_matrices(prob: Problem, p, seed, instance, it, beta, precision=PREC_FP64):
     torch = _torch()
     smax = -(-prob.n // p)
-    sp = (smax + 15) // 16 * 16
+    sp = 16
+    while sp < smax:
+        sp *= 2
     out = torch.zeros(p * sp * sp, dtype=torch.float64, device=prob.c.device)
     spo = C.c_int64()
     ps = prob.struct()
     _check(load().rac_block_matrices(C.byref(ps), int(p), int(seed), int(instance), int(it), float(beta),
                                      int(precision), _ptr(out), C.byref(spo), _stream()),
            "rac_block_matrices")
+    assert spo.value == sp
     return out.cpu().numpy().reshape(p, sp, sp), sp
 
 
