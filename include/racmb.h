@@ -105,6 +105,11 @@ typedef struct {
   double tol;           /* stop at the first check with KKT residual <= tol */
   int32_t sweep_groups; /* workgroups cooperating in the sweep (0 = automatic) */
   int32_t row_chunks;   /* row chunks of the block Gram contraction (0 = automatic) */
+  int32_t overlap;      /* 0 (default): build the next iteration's block matrices on a second
+                           stream during the sweep when all sweep groups fit on the device;
+                           negative: one stream.  Overlapped solvers assume no other solver's
+                           sweep runs on the device at the same time. */
+  int32_t pad0;
 } rac_opts;
 
 typedef struct {
@@ -150,8 +155,9 @@ rac_status rac_solver_set_timing(rac_solver s, int32_t enable);   /* also clears
 /* ms (host, RAC_NUM_PHASES) receives the summed milliseconds per phase, launches
  * (host, RAC_NUM_PHASES or NULL) the number of timed launches per phase. */
 rac_status rac_solver_timing(rac_solver s, double* ms, int64_t* launches);
-/* info (host, 7 int64): p, padded block size, sweep workgroups K, Gram row chunks R, T,
- * sweep register tile (rows per lane A, columns per wavefront B; 0 = streaming sweep). */
+/* info (host, 8 int64): p, padded block size, sweep workgroups K, Gram row chunks R, T,
+ * sweep register tile (rows per lane A, columns per wavefront B; 0 = streaming sweep),
+ * and 1 if the assemble phase overlaps the sweep. */
 rac_status rac_solver_info(rac_solver s, int64_t* info);
 
 /* Per-iteration history of the last run: 4 doubles per iteration, (r_p, r_d,

@@ -188,18 +188,13 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
 // rows ti + 16a and columns tj + 16b (a, b < SP/16).  At pivot k only row k and
 // column k travel through LDS (double-buffered by the parity of k, one barrier
 // per step); every owned entry is then updated independently.
-// The same kernel writes the iterate-independent part of every gradient of the
-// block, gbase = c - xi + beta (x - z) + h.x - mu a, in permuted order.
 template <int SP>
 __global__ void __launch_bounds__(256) k_factor(const double* __restrict__ partial, int R, int64_t n,
                                                 int64_t p, const int32_t* __restrict__ perm, double Ns,
                                                 const double* __restrict__ h, const double* __restrict__ a,
                                                 const double* beta_ptr, double beta_val,
                                                 double* __restrict__ out, int write_matrix, DevScalars* sc,
-                                                int64_t iter_global, int publish_beta,
-                                                const double* __restrict__ c, const double* __restrict__ x,
-                                                const double* __restrict__ z, const double* __restrict__ xi,
-                                                double* __restrict__ gbase) {
+                                                int64_t iter_global) {
   constexpr int NA = SP / 16;
   __shared__ double rowk[2][SP];
   __shared__ double colk[2][SP];
@@ -209,16 +204,7 @@ __global__ void __launch_bounds__(256) k_factor(const double* __restrict__ parti
   const int sb = (int)(block_start(blk + 1, n, p) - s0);
   const double beta = beta_ptr ? *beta_ptr : beta_val;
   for (int m = tid; m < SP; m += 256) cols[m] = m < sb ? perm[s0 + m] : -1;
-  if (publish_beta && sc && blk == 0 && tid == 0) sc->beta = beta;
   __syncthreads();
-
-  if (gbase && sc && tid < sb) {
-    const int col = cols[tid];
-    double v = c[col] - xi[col] + beta * (x[col] - z[col]);
-    if (h) v += h[col] * x[col];
-    if (a) v -= sc->mu * a[col];
-    gbase[s0 + tid] = v;
-  }
 
   // gather: entry (i, j) is the lower-triangle partial (max, min); R partials summed in order
   const double* part = partial + (int64_t)blk * R * SP * SP;
@@ -367,8 +353,7 @@ hipError_t launch_factor(const FactorArgs& f, hipStream_t st) {
   if (f.sp == SPV) {                                                                                 \
     k_factor<SPV><<<(unsigned)f.p, 256, 0, st>>>(f.partial, f.R, f.n, f.p, f.perm, f.Ns, f.h, f.a,     \
                                                   f.beta_ptr, f.beta_val, f.Minv, f.write_matrix, f.sc, \
-                                                  f.iter_global, f.publish_beta, f.c, f.x, f.z, f.xi,   \
-                                                  f.gbase);                                             \
+                                                  f.iter_global);                                       \
     return hipGetLastError();                                                                        \
   }
   RAC_FACTOR(16) RAC_FACTOR(32) RAC_FACTOR(64) RAC_FACTOR(128)

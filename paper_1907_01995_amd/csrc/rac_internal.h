@@ -93,10 +93,6 @@ struct FactorArgs {
   int write_matrix;        //  themselves when write_matrix != 0)
   DevScalars* sc;          // failure reporting (may be null)
   int64_t iter_global;
-  int publish_beta;        // write the beta used into sc->beta (given schedules)
-  // iterate-independent part of each block's gradient, in permuted order (may be null):
-  //   gbase = c - xi + beta (x - z) + h.x - mu a
-  const double* c; const double* x; const double* z; const double* xi; double* gbase;
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 
@@ -110,9 +106,12 @@ struct SweepArgs {
   uint64_t* flags;         // [K * kFlagStride], monotone epochs
   uint64_t epoch_base;
   int K;
-  const double* gbase;     // iterate-independent gradient terms, permuted order (register path)
+  const double* beta_ptr;  // penalty of this iteration
   int tileA, tileB;        // register tile: rows per lane, columns per wavefront (0: streaming path)
+  int cooperative;         // launch with the cooperative API (else a plain launch, K <= resident limit)
 };
+// Largest number of sweep workgroups that can be resident at once for a tile shape.
+int sweep_max_resident(int32_t dtype, int A, int B);
 // Register-tile shapes with a compiled sweep kernel (A rows per lane, B columns per wavefront).
 bool sweep_tile_supported(int32_t dtype, int A, int B);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
@@ -127,6 +126,8 @@ struct UpdateArgs {
   int64_t hist_cap;
   int64_t hist_base;       // global iteration index of this run's first iteration
   int64_t T;               // check period (window start bookkeeping)
+  const double* beta_ptr;  // penalty of this iteration
+  int publish_beta;        // copy *beta_ptr into sc->beta (given schedules)
 };
 hipError_t launch_zdual(const UpdateArgs& a, hipStream_t st);
 

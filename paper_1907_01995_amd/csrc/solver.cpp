@@ -1,18 +1,22 @@
 // solver.cpp -- host side of the library: argument validation, workspace,
 // the per-chunk launch sequence of RAC-MBADMM, and the C ABI of racmb.h.
 //
-// One iteration (Eq.(3)) is four device phases, all enqueued on the caller's
-// stream with no host round trip:
+// One iteration (Eq.(3)) is four device phases with no host round trip:
 //   assemble  k_gram + k_factor : every block matrix of the drawn partition and
 //                                 its inverse, all blocks in parallel;
-//   sweep     k_sweep           : the sequential Gauss-Seidel pass (one
-//                                 cooperative persistent launch);
+//   sweep     k_sweep2          : the sequential Gauss-Seidel pass (one
+//                                 persistent launch of K cooperating groups);
 //   z + dual  k_zdual           : z block, dual step, residual norms, history.
 // The partitions of a whole chunk of T iterations are drawn by one set of
 // sort launches up front (they depend only on the seed and the iteration
-// index).  After the chunk, k_kkt evaluates the KKT residual and k_control
-// applies the stopping test and the penalty rule; the host then reads the
-// 144-byte scalar block once to decide whether to continue.
+// index).  The block matrices of an iteration depend only on the data, the
+// partition and beta, so they are built on a second stream while the previous
+// iteration's sweep runs on the compute units it leaves idle; the inverses are
+// double-buffered by iteration parity and events order the two streams.  After
+// the chunk, k_kkt evaluates the KKT residual and k_control applies the
+// stopping test and the penalty rule (beta changes only there, so the second
+// stream waits for it at chunk boundaries); the host then reads the scalar
+// block once to decide whether to continue.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -179,8 +183,10 @@ struct rac_solver_s {
   double* mv_part = nullptr;
   int mv_nparts = 1;
   double* uz = nullptr;     // F z for the objective
-  double* gbase = nullptr;  // iterate-independent gradient terms, permuted order
   int tileA = 0, tileB = 0; // register tile of the sweep (0: streaming sweep)
+  bool overlap = false;     // assemble on a second stream during the previous sweep
+  hipStream_t sB = nullptr;
+  hipEvent_t ev_start = nullptr, ev_fac[2] = {nullptr, nullptr}, ev_sweep[2] = {nullptr, nullptr};
   DevScalars hsc{};
   // optional per-phase timing with HIP events on the run's stream
   bool timing = false;
@@ -221,6 +227,7 @@ rac_status fx_into_u(rac_solver s, const double* x, double* u, hipStream_t st) {
 struct PhaseTimer {
   rac_solver s;
   hipStream_t st;
+  hipError_t begin(hipStream_t on) { st = on; return begin(); }
   hipError_t begin() {
     if (!s->timing) return hipSuccess;
     const size_t i = 2 * s->ev_phase.size();
@@ -260,36 +267,49 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
   HIPCHK(tm.end(RAC_PHASE_PARTITION));
   const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
+  hipStream_t sa = s->overlap ? s->sB : st;   // stream of the assemble phase
+  if (s->overlap) {
+    HIPCHK(hipEventRecord(s->ev_start, st));   // partitions drawn, previous chunk's penalty final
+    HIPCHK(hipStreamWaitEvent(sa, s->ev_start, 0));
+  }
+  const size_t mstride = (size_t)s->p * s->sp * s->sp;
   for (int64_t t = 0; t < Tc; ++t) {
     const int32_t* perm = s->perm + t * s->n;
+    const int par = (int)((k0 + t) & 1);
+    double* Minv = s->Minv + par * mstride;
+    const double* beta_ptr = sched ? s->d_sched + (run_offset + t) : &s->sc->beta;
+    // assemble: the inverse buffer of this parity was last read by the sweep two iterations ago
+    if (s->overlap && t >= 2) HIPCHK(hipStreamWaitEvent(sa, s->ev_sweep[par], 0));
     GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
                s->partial};
-    HIPCHK(tm.begin());
-    HIPCHK(launch_gram(g, st));
+    HIPCHK(tm.begin(sa));
+    HIPCHK(launch_gram(g, sa));
     HIPCHK(tm.end(RAC_PHASE_GRAM));
     FactorArgs f{};
     f.partial = s->partial; f.R = s->R; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
-    f.Ns = P.Ns; f.h = P.h; f.a = P.a;
-    f.beta_ptr = sched ? s->d_sched + (run_offset + t) : &s->sc->beta;
-    f.beta_val = 0.0; f.Minv = s->Minv; f.write_matrix = 0; f.sc = s->sc;
-    f.iter_global = k0 + t; f.publish_beta = sched ? 1 : 0;
-    f.c = P.c; f.x = s->x; f.z = s->z; f.xi = s->xi; f.gbase = s->gbase;
-    HIPCHK(tm.begin());
-    HIPCHK(launch_factor(f, st));
+    f.Ns = P.Ns; f.h = P.h; f.a = P.a; f.beta_ptr = beta_ptr; f.beta_val = 0.0; f.Minv = Minv;
+    f.write_matrix = 0; f.sc = s->sc; f.iter_global = k0 + t;
+    HIPCHK(tm.begin(sa));
+    HIPCHK(launch_factor(f, sa));
     HIPCHK(tm.end(RAC_PHASE_FACTOR));
-    SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->Minv, s->sp, P.c, P.h, P.a,
+    if (s->overlap) {
+      HIPCHK(hipEventRecord(s->ev_fac[par], sa));
+      HIPCHK(hipStreamWaitEvent(st, s->ev_fac[par], 0));
+    }
+    SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, Minv, s->sp, P.c, P.h, P.a,
                 P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
-                s->gbase, s->tileA, s->tileB};
-    HIPCHK(tm.begin());
+                beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1};
+    HIPCHK(tm.begin(st));
     HIPCHK(launch_sweep(w, st));
     HIPCHK(tm.end(RAC_PHASE_SWEEP));
+    if (s->overlap) HIPCHK(hipEventRecord(s->ev_sweep[par], st));
     s->epoch += (uint64_t)s->p;
     UpdateArgs za{};
     za.n = s->n; za.prox = P.prox; za.lam = P.lambda; za.alpha = P.alpha; za.lo = P.lo; za.hi = P.hi;
     za.b = P.b; za.has_eq = P.a ? 1 : 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
     za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
-    za.hist_base = k0 - run_offset; za.T = s->T;
-    HIPCHK(tm.begin());
+    za.hist_base = k0 - run_offset; za.T = s->T; za.beta_ptr = beta_ptr; za.publish_beta = sched ? 1 : 0;
+    HIPCHK(tm.begin(st));
     HIPCHK(launch_zdual(za, st));
     HIPCHK(tm.end(RAC_PHASE_ZDUAL));
   }
@@ -299,7 +319,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   ka.alpha = P.alpha; ka.lo = P.lo; ka.hi = P.hi; ka.x = s->x; ka.z = s->z; ka.xi = s->xi;
   ka.u = s->u; ka.mu_ptr = &s->sc->mu; ka.mu_val = 0.0; ka.red = s->red; ka.done = s->done;
   ka.out = s->kkt_out;
-  HIPCHK(tm.begin());
+  HIPCHK(tm.begin(st));
   HIPCHK(launch_kkt(ka, st));
   ControlArgs ca{};
   ca.sc = s->sc; ca.kkt_out = s->kkt_out; ca.beta_mode = s->O.beta_mode; ca.rb_mu = s->O.rb_mu;
@@ -378,13 +398,19 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
 
   auto fail = [&](rac_status r) {
     s->buf.release();
+    if (s->ev_start) (void)hipEventDestroy(s->ev_start);
+    for (int q = 0; q < 2; ++q) {
+      if (s->ev_fac[q]) (void)hipEventDestroy(s->ev_fac[q]);
+      if (s->ev_sweep[q]) (void)hipEventDestroy(s->ev_sweep[q]);
+    }
+    if (s->sB) (void)hipStreamDestroy(s->sB);
     delete s;
     return r;
   };
   rac_status r;
   if ((r = alloc_perm_work(s->buf, s->T, n, &s->pw, &s->perm)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->partial, (size_t)(s->p * s->R) * s->sp * s->sp)) != RAC_OK) return fail(r);
-  if ((r = s->buf.alloc(&s->Minv, (size_t)s->p * s->sp * s->sp)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->Minv, (size_t)2 * s->p * s->sp * s->sp)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->x, (size_t)n)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->z, (size_t)n)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->xi, (size_t)n)) != RAC_OK) return fail(r);
@@ -401,7 +427,17 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->hist, (size_t)s->hist_cap * 4)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->mv_part, (size_t)s->mv_nparts * s->rows)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->uz, (size_t)s->rows)) != RAC_OK) return fail(r);
-  if ((r = s->buf.alloc(&s->gbase, (size_t)n)) != RAC_OK) return fail(r);
+  // overlap the assemble phase with the sweep when all sweep groups fit on the device at once
+  if (s->tileA > 0 && s->K > 1 && s->K <= sweep_max_resident(prob->F_dtype, s->tileA, s->tileB) &&
+      O.overlap >= 0) {
+    if (hipStreamCreateWithFlags(&s->sB, hipStreamNonBlocking) != hipSuccess) return fail(RAC_ERR_DEVICE);
+    bool ok = hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming) == hipSuccess;
+    for (int q = 0; q < 2 && ok; ++q)
+      ok = hipEventCreateWithFlags(&s->ev_fac[q], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&s->ev_sweep[q], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return fail(RAC_ERR_DEVICE);
+    s->overlap = true;
+  }
   if (O.beta_mode == RAC_BETA_SCHEDULE) {
     if ((r = s->buf.alloc(&s->d_sched, (size_t)(O.max_iter > 0 ? O.max_iter : 1))) != RAC_OK) return fail(r);
     if (O.max_iter > 0 &&
@@ -429,6 +465,12 @@ rac_status rac_solver_destroy(rac_solver s) {
   if (!s) return RAC_ERR_ARG;
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  if (s->ev_start) (void)hipEventDestroy(s->ev_start);
+  for (int q = 0; q < 2; ++q) {
+    if (s->ev_fac[q]) (void)hipEventDestroy(s->ev_fac[q]);
+    if (s->ev_sweep[q]) (void)hipEventDestroy(s->ev_sweep[q]);
+  }
+  if (s->sB) (void)hipStreamDestroy(s->sB);
   s->buf.release();
   delete s;
   return RAC_OK;
@@ -550,6 +592,7 @@ rac_status rac_solver_info(rac_solver s, int64_t* info) {
   info[4] = s->T;
   info[5] = s->tileA;
   info[6] = s->tileB;
+  info[7] = s->overlap ? 1 : 0;
   return RAC_OK;
 }
 
@@ -735,8 +778,7 @@ rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed,
     FactorArgs f{};
     f.partial = partial; f.R = R; f.sp = sp; f.n = prob->n; f.p = p; f.perm = perm; f.Ns = prob->Ns;
     f.h = prob->h; f.a = prob->a; f.beta_ptr = nullptr; f.beta_val = beta; f.Minv = out;
-    f.write_matrix = 1; f.sc = nullptr; f.iter_global = iter; f.publish_beta = 0;
-    f.c = nullptr; f.x = nullptr; f.z = nullptr; f.xi = nullptr; f.gbase = nullptr;
+    f.write_matrix = 1; f.sc = nullptr; f.iter_global = iter;
     e = launch_factor(f, st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -5,8 +5,9 @@
 //   x_B <- x_B - M_B^{-1} g_B,
 //   g_B = F_B'u/Ns + h_B.x_B + c_B - xi_B + beta(x_B - z_B) - mu a_B + beta a_B (t - b),
 // where u = F x and t = a'x are maintained through the sweep (u += F_B d, t += a_B'd).
-// Everything in g_B except F_B'u and the t term is fixed before the sweep; the
-// factor kernel precomputes it per block (gbase).
+// Everything in g_B except F_B'u and the t term is fixed before the block is
+// reached (x_B changes only when B itself is solved), so it is gathered while
+// the previous block is still being exchanged.
 //
 // Work split: K cooperating workgroups each own a contiguous range of at most
 // 64*A rows of F, and hence of u, which never leaves its owner (registers).
@@ -17,7 +18,8 @@
 //      of F is read from HBM once per sweep and serves both products below;
 //   2. partial F_B'u over the group's rows (FP64 accumulation, wavefront
 //      shuffles), published with agent-scope relaxed atomic stores, then one
-//      flag per group (a monotone epoch, no contended counter);
+//      flag per group (a monotone epoch, no contended counter); the flags are
+//      packed densely so that a poll of all of them is a few cache lines;
 //   3. the next block's tile and gbase are loaded while the flags are awaited;
 //   4. every group sums the K partials in the same fixed order, applies M_B^{-1}
 //      (precomputed by the factor kernel) and so holds the identical step d;
@@ -143,7 +145,8 @@ __device__ __forceinline__ double ld_coherent(const double* p) {
 
 struct Sweep2Args {
   const void* F; int64_t ldF; int64_t rows; int64_t n; int64_t p;
-  const int32_t* perm; const double* Minv; int sp; const double* gbase;
+  const int32_t* perm; const double* Minv; int sp;
+  const double* c; const double* h; const double* xi; const double* z; const double* beta_ptr;
   const double* a; double b; double Ns;
   double* x; double* u; DevScalars* sc; double* partials; uint64_t* flags; uint64_t epoch_base;
   int64_t RW;              // rows per group (a multiple of A, at most 64A)
@@ -226,8 +229,17 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   __shared__ double sh_pg[256];
   __shared__ double sh_red[4 * 64 * A];
   __shared__ int32_t sh_cols[2][kMaxBlock];
-  const double beta = s.sc->beta;
+  const double beta = *s.beta_ptr;
+  const double mu = s.sc->mu;
   double t = s.sc->t;
+  // iterate-independent gradient terms of one column: c - xi + beta (x - z) + h x - mu a
+  auto gbase = [&](int col) {
+    const double xc = s.x[col];
+    double v = s.c[col] - s.xi[col] + beta * (xc - s.z[col]);
+    if (s.h) v += s.h[col] * xc;
+    if (s.a) v -= mu * s.a[col];
+    return v;
+  };
   double ureg[A];
 #pragma unroll
   for (int aa = 0; aa < A; ++aa) {
@@ -253,7 +265,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[0], sb0, lane, wave, s.vec, ta);
     load_minv(0, sb0);
   }
-  double gb = tid < (int)block_start(1, s.n, s.p) ? s.gbase[tid] : 0.0;
+  double gb = tid < (int)block_start(1, s.n, s.p) ? gbase(sh_cols[0][tid]) : 0.0;
 
   auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B]) {
     const int64_t s0 = block_start(i, s.n, s.p);
@@ -283,32 +295,41 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     __builtin_amdgcn_s_waitcnt(0);   // partial stores complete at device scope; next indices landed
     __syncthreads();
     if (K > 1 && tid == 0)
-      __hip_atomic_store(&s.flags[(int64_t)g * kFlagStride], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // prefetch the next block's tile and gbase while the other groups finish
+      __hip_atomic_store(&s.flags[g], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // prefetch the next block's tile and gbase while the other groups finish.
+    // Wavefront 0 polls the flags first: a poll waits on all of its wavefront's
+    // outstanding loads, so its share of the prefetch is issued after the flags.
     double gb_next = 0.0;
-    if (more) {
+    if (more && wave != 0) {
       load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(i + 1) & 1], sb1, lane, wave, s.vec, nxt);
-      if (tid < sb1) gb_next = s.gbase[s1 + tid];
     }
-    if (K > 1 && wave == 0) {
-      for (int q = lane; q < K; q += 64)
-        while (__hip_atomic_load(&s.flags[(int64_t)q * kFlagStride], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT) < epoch)
+    if (wave == 0) {
+      if (K > 1) {
+        // every lane checks its flags each round; the wavefront leaves when all are raised
+        while (true) {
+          bool ok = true;
+          for (int q = lane; q < K; q += 64)
+            ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+          if (__all(ok)) break;
           __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      if (more) load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(i + 1) & 1], sb1, lane, wave, s.vec, nxt);
     }
+    if (more && tid < sb1) gb_next = gbase(sh_cols[(i + 1) & 1][tid]);
     __syncthreads();
-    // full gradient: P threads per column, every P-th group, sixteen loads in flight
+    // full gradient: P threads per column, every P-th group, all loads in flight at once
     {
+      constexpr int NL = 128 / P;        // enough for K <= 128 in one batch
       double acc = 0.0;
       if (jc < sb) {
-        int q = part;
-        for (; q < K; q += 16 * P) {
-          double v[16];
+        for (int q = part; q < K; q += NL * P) {
+          double v[NL];
 #pragma unroll
-          for (int e = 0; e < 16; ++e)
+          for (int e = 0; e < NL; ++e)
             v[e] = (q + e * P < K) ? ld_coherent(&buf[(int64_t)(q + e * P) * kMaxBlock + jc]) : 0.0;
 #pragma unroll
-          for (int e = 0; e < 16; ++e) acc += v[e];
+          for (int e = 0; e < NL; ++e) acc += v[e];
         }
       }
       sh_pg[part * NC + jc] = acc;
@@ -386,10 +407,13 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   if (g == 0 && tid == 0) s.sc->t = t;
 }
 
+// A plain launch is used only when the caller has checked that all K groups can
+// be resident together (every other kernel that may run beside the sweep
+// finishes without waiting on it, so the late groups are always scheduled).
 template <typename T, int A, int B>
-hipError_t sweep2_launch(const Sweep2Args& a, int K, hipStream_t st) {
-  if (K == 1) {
-    k_sweep2<T, A, B><<<1, 256, 0, st>>>(a);
+hipError_t sweep2_launch(const Sweep2Args& a, int K, int coop, hipStream_t st) {
+  if (K == 1 || !coop) {
+    k_sweep2<T, A, B><<<(unsigned)K, 256, 0, st>>>(a);
     return hipGetLastError();
   }
   Sweep2Args c = a;
@@ -397,9 +421,30 @@ hipError_t sweep2_launch(const Sweep2Args& a, int K, hipStream_t st) {
   return hipLaunchCooperativeKernel((const void*)k_sweep2<T, A, B>, dim3((unsigned)K), dim3(256), args, 0, st);
 }
 
+template <typename T, int A, int B>
+int sweep2_resident() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_sweep2<T, A, B>, 256, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
+
 template <typename T>
-hipError_t sweep2_dispatch(const Sweep2Args& a, int K, int A, int B, hipStream_t st) {
-#define RAC_SW(AA, BB) if (A == AA && B == BB) return sweep2_launch<T, AA, BB>(a, K, st)
+int sweep2_resident_dispatch(int A, int B) {
+#define RAC_SR(AA, BB) if (A == AA && B == BB) return sweep2_resident<T, AA, BB>()
+  RAC_SR(1, 8); RAC_SR(2, 8); RAC_SR(4, 8);
+  RAC_SR(1, 16); RAC_SR(2, 16);
+  RAC_SR(1, 32);
+  if constexpr (sizeof(T) < 8) { RAC_SR(4, 16); RAC_SR(2, 32); }
+#undef RAC_SR
+  return 0;
+}
+
+template <typename T>
+hipError_t sweep2_dispatch(const Sweep2Args& a, int K, int A, int B, int coop, hipStream_t st) {
+#define RAC_SW(AA, BB) if (A == AA && B == BB) return sweep2_launch<T, AA, BB>(a, K, coop, st)
   RAC_SW(1, 8); RAC_SW(2, 8); RAC_SW(4, 8);
   RAC_SW(1, 16); RAC_SW(2, 16);
   RAC_SW(1, 32);
@@ -411,7 +456,7 @@ hipError_t sweep2_dispatch(const Sweep2Args& a, int K, int A, int B, hipStream_t
 template <typename T>
 hipError_t sweep_launch(const SweepArgs& s, hipStream_t st) {
   const T* F = (const T*)s.F;
-  const double* beta_ptr = &s.sc->beta;
+  const double* beta_ptr = s.beta_ptr;
   void* args[] = {(void*)&F, (void*)&s.ldF, (void*)&s.rows, (void*)&s.n, (void*)&s.p,
                   (void*)&s.perm, (void*)&s.Minv, (void*)&s.sp, (void*)&s.c, (void*)&s.h,
                   (void*)&s.a, (void*)&s.b, (void*)&s.Ns, (void*)&s.x, (void*)&s.z, (void*)&s.xi,
@@ -431,8 +476,8 @@ hipError_t sweep_launch(const SweepArgs& s, hipStream_t st) {
 
 hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
   if (s.tileA > 0) {
-    Sweep2Args a{s.F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.gbase, s.a, s.b, s.Ns,
-                 s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0};
+    Sweep2Args a{s.F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.c, s.h, s.xi, s.z, s.beta_ptr,
+                 s.a, s.b, s.Ns, s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0};
     int64_t rw = (s.rows + s.K - 1) / s.K;
     rw = (rw + s.tileA - 1) / s.tileA * s.tileA;
     if (rw > 64 * s.tileA) return hipErrorInvalidValue;
@@ -440,9 +485,9 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
     const int esz = s.dtype == RAC_DT_F64 ? 8 : (s.dtype == RAC_DT_F32 ? 4 : 2);
     a.vec = (s.ldF % s.tileA == 0) && ((uintptr_t)s.F % (size_t)(esz * s.tileA) == 0);
     switch (s.dtype) {
-      case RAC_DT_F64: return sweep2_dispatch<double>(a, s.K, s.tileA, s.tileB, st);
-      case RAC_DT_F32: return sweep2_dispatch<float>(a, s.K, s.tileA, s.tileB, st);
-      case RAC_DT_BF16: return sweep2_dispatch<uint16_t>(a, s.K, s.tileA, s.tileB, st);
+      case RAC_DT_F64: return sweep2_dispatch<double>(a, s.K, s.tileA, s.tileB, s.cooperative, st);
+      case RAC_DT_F32: return sweep2_dispatch<float>(a, s.K, s.tileA, s.tileB, s.cooperative, st);
+      case RAC_DT_BF16: return sweep2_dispatch<uint16_t>(a, s.K, s.tileA, s.tileB, s.cooperative, st);
       default: return hipErrorInvalidValue;
     }
   }
@@ -457,6 +502,15 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
 }  // namespace rac
 
 namespace rac {
+int sweep_max_resident(int32_t dtype, int A, int B) {
+  switch (dtype) {
+    case RAC_DT_F64: return sweep2_resident_dispatch<double>(A, B);
+    case RAC_DT_F32: return sweep2_resident_dispatch<float>(A, B);
+    case RAC_DT_BF16: return sweep2_resident_dispatch<uint16_t>(A, B);
+    default: return 0;
+  }
+}
+
 bool sweep_tile_supported(int32_t dtype, int A, int B) {
   const bool small = dtype != RAC_DT_F64;
   if (B == 8) return A == 1 || A == 2 || A == 4;

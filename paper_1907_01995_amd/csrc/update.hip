@@ -60,9 +60,10 @@ __global__ void __launch_bounds__(256) k_zdual(int64_t n, int32_t prox, double l
                                                const double* __restrict__ x, double* z, double* xi,
                                                double* zprev, DevScalars* sc, double* red,
                                                uint32_t* done, double* hist, int64_t hist_cap,
-                                               int64_t hist_base, int64_t T) {
+                                               int64_t hist_base, int64_t T, const double* beta_ptr,
+                                               int publish_beta) {
   __shared__ double sh[4];
-  const double beta = sc->beta;
+  const double beta = *beta_ptr;
   double rp2 = 0.0, rd2 = 0.0;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
     const double xj = x[j], xij = xi[j], zo = z[j];
@@ -92,6 +93,7 @@ __global__ void __launch_bounds__(256) k_zdual(int64_t n, int32_t prox, double l
   }
   const double rp = sqrt(P), rd = beta * sqrt(D);
   const int64_t k = sc->k;
+  if (publish_beta) sc->beta = beta;
   sc->rp = rp;
   sc->rd = rd;
   if (k % T == 0) { sc->rp_win = rp; sc->rd_win = rd; }
@@ -383,7 +385,7 @@ hipError_t launch_zdual(const UpdateArgs& z, hipStream_t st) {
   if (blocks > kRedBlocks) blocks = kRedBlocks;
   k_zdual<<<(unsigned)blocks, 256, 0, st>>>(z.n, z.prox, z.lam, z.alpha, z.lo, z.hi, z.b, z.has_eq,
                                             z.x, z.z, z.xi, z.zprev, z.sc, z.red, z.done, z.hist,
-                                            z.hist_cap, z.hist_base, z.T);
+                                            z.hist_cap, z.hist_base, z.T, z.beta_ptr, z.publish_beta);
   return hipGetLastError();
 }
 

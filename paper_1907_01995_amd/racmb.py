@@ -53,7 +53,8 @@ class Opts_(C.Structure):
                 ("rb_mu", C.c_double), ("rb_tau", C.c_double),
                 ("beta_schedule", C.POINTER(C.c_double)), ("mlp_weights", C.c_void_p),
                 ("mlp_ymax", C.c_double), ("check_every", C.c_int64), ("max_iter", C.c_int64),
-                ("tol", C.c_double), ("sweep_groups", C.c_int32), ("row_chunks", C.c_int32)]
+                ("tol", C.c_double), ("sweep_groups", C.c_int32), ("row_chunks", C.c_int32),
+                ("overlap", C.c_int32), ("pad0", C.c_int32)]
 
 
 class Result_(C.Structure):
@@ -234,7 +235,7 @@ class Solver:
     def __init__(self, prob: Problem, *, p=None, s=None, seed=0, instance=0, precision=PREC_FP64,
                  beta0=1.0, beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0, beta_schedule=None,
                  mlp_weights=None, mlp_ymax=float(np.log(10.0)), check_every=10, max_iter=100,
-                 tol=0.0, sweep_groups=0, row_chunks=0):
+                 tol=0.0, sweep_groups=0, row_chunks=0, overlap=True):
         self.lib = load()
         self.prob = prob
         if p is None:
@@ -249,7 +250,8 @@ class Solver:
         self.opts = Opts_(self.p, int(seed), int(instance), int(precision), int(beta_mode), float(beta0),
                           float(rb_mu), float(rb_tau), sched_ptr,
                           None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax),
-                          int(check_every), int(max_iter), float(tol), int(sweep_groups), int(row_chunks))
+                          int(check_every), int(max_iter), float(tol), int(sweep_groups), int(row_chunks),
+                          0 if overlap else -1, 0)
         self._ps = prob.struct()
         h = C.c_void_p()
         _check(self.lib.rac_solver_create(C.byref(self._ps), C.byref(self.opts), C.byref(h)),
@@ -309,9 +311,9 @@ class Solver:
         return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(self.PHASES)}
 
     def info(self):
-        v = (C.c_int64 * 7)()
+        v = (C.c_int64 * 8)()
         _check(self.lib.rac_solver_info(self.h, v), "rac_solver_info")
-        return dict(p=v[0], sp=v[1], K=v[2], R=v[3], T=v[4], tileA=v[5], tileB=v[6])
+        return dict(p=v[0], sp=v[1], K=v[2], R=v[3], T=v[4], tileA=v[5], tileB=v[6], overlap=v[7])
 
     def reset(self, beta=None):
         """Zero state (cold start) at iteration 0."""

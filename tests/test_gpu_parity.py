@@ -265,6 +265,23 @@ def test_checkpoint_resume_is_bit_exact():
         assert st[3] == xa[3] and st[4] == xa[4] and st[5] == 40
 
 
+@pytest.mark.parametrize("storage,prec", [("f32", racmb.PREC_MIXED), ("f64", racmb.PREC_FP64)])
+def test_overlapped_assembly_is_bit_identical(storage, prec):
+    # building block matrices on a second stream changes scheduling only
+    w = W.lasso(N=6000, n=512, data_seed=14, block_size=64, storage=storage)
+    gp, _ = en_pair(w)
+    outs = []
+    for ov in (True, False):
+        say("overlap", ov, storage)
+        s = racmb.Solver(gp, s=64, beta0=w.beta0, beta_mode=racmb.BETA_RESBAL, precision=prec,
+                         max_iter=45, check_every=10, overlap=ov)
+        s.run()
+        assert s.info()["overlap"] == (1 if ov else 0)
+        outs.append(s.state()[:3])
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
+
+
 def test_repeated_runs_are_deterministic():
     w = W.lasso(N=2000, n=256, data_seed=8, block_size=32, storage="f32")
     gp, _ = en_pair(w)
