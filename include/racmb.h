@@ -160,6 +160,17 @@ rac_status rac_solver_timing(rac_solver s, double* ms, int64_t* launches);
  * and 1 if the assemble phase overlaps the sweep. */
 rac_status rac_solver_info(rac_solver s, int64_t* info);
 
+/* Controller interface for external policies and for generating training data.
+ * rac_solver_features copies to host `out` (RAC_MLP_IN floats) the features that
+ * the last KKT check formed from the residual history (the network's input):
+ *   0.5 log10(r_p/r_d) now and at the window start, log10 of the window's change
+ *   of r_p and of r_d, log10 of the KKT change since the previous check, the last
+ *   log10 multiplier, (log10 KKT + 6)/3 and decisions/10, each clipped to [-4, 4].
+ * rac_solver_scale_beta multiplies beta by mult (> 0) and records it as a decision,
+ * exactly as the in-kernel controller does. */
+rac_status rac_solver_features(rac_solver s, float* out);
+rac_status rac_solver_scale_beta(rac_solver s, double mult, void* stream);
+
 /* Per-iteration history of the last run: 4 doubles per iteration, (r_p, r_d,
  * beta, KKT or NaN), copied to host memory `out` (capacity max_iter*4). */
 rac_status rac_solver_history(rac_solver s, double* out, int64_t capacity, int64_t* count);

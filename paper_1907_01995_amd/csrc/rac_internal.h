@@ -31,6 +31,7 @@ struct DevScalars {
   uint64_t fail_key; // (iteration << 32 | block) of the first non-PD block, or ~0
   int32_t status;    // 0 running, 1 converged, 2 diverged
   int32_t pad;
+  float feat[RAC_MLP_IN];   // controller features formed at the last check
 };
 
 // Element loads of the data matrix, converted exactly to FP64 / FP32.
@@ -152,6 +153,8 @@ struct ControlArgs {
   int64_t hist_base;
 };
 hipError_t launch_control(const ControlArgs& a, hipStream_t st);
+// beta *= mult, recorded as a controller decision (log10 multiplier, decision count)
+hipError_t launch_scale_beta(DevScalars* sc, double mult, hipStream_t st);
 
 // u = F x through nparts column-chunk partials (part: nparts*rows doubles), fixed-order sum.
 hipError_t launch_matvec_F_parts(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,

@@ -596,6 +596,23 @@ rac_status rac_solver_info(rac_solver s, int64_t* info) {
   return RAC_OK;
 }
 
+rac_status rac_solver_features(rac_solver s, float* out) {
+  if (!s || !out) return RAC_ERR_ARG;
+  DevScalars h;
+  HIPCHK(hipMemcpy(&h, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
+  for (int q = 0; q < RAC_MLP_IN; ++q) out[q] = h.feat[q];
+  return RAC_OK;
+}
+
+rac_status rac_solver_scale_beta(rac_solver s, double mult, void* stream) {
+  if (!s || !is_fin(mult) || !(mult > 0.0)) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_scale_beta(s->sc, mult, st));
+  HIPCHK(hipMemcpyAsync(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
+}
+
 rac_status rac_solver_history(rac_solver s, double* out, int64_t capacity, int64_t* count) {
   if (!s || !out || capacity < 0) return RAC_ERR_ARG;
   int64_t c = s->hist_count < s->hist_cap ? s->hist_count : s->hist_cap;

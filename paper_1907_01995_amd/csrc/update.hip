@@ -226,6 +226,20 @@ __global__ void __launch_bounds__(64) k_control(DevScalars* sc, const double* kk
   }
   const bool act = decide && status0 == 0 && !conv &&
                    (beta_mode == RAC_BETA_RESBAL || beta_mode == RAC_BETA_MLP);
+  // features of this check (stored for every decision point, used by the network)
+  if (tid == 0) {
+    const double rpo = sc->rp_win, rdo = sc->rd_win, kp = sc->kkt_prev;
+    f[0] = (float)clip4(0.5 * (lg10c(rp) - lg10c(rd)));
+    f[1] = (float)clip4(0.5 * (lg10c(rpo) - lg10c(rdo)));
+    f[2] = (float)clip4(lg10c(rp) - lg10c(rpo));
+    f[3] = (float)clip4(lg10c(rd) - lg10c(rdo));
+    f[4] = (float)clip4(kp > 0.0 ? lg10c(kkt) - lg10c(kp) : 0.0);
+    f[5] = (float)clip4(sc->last_l10);
+    f[6] = (float)clip4((lg10c(kkt) + 6.0) / 3.0);
+    f[7] = (float)clip4((double)sc->decisions / 10.0);
+    for (int q = 0; q < RAC_MLP_IN; ++q) sc->feat[q] = f[q];
+  }
+  __syncthreads();
   if (act) {
     double rb = 1.0;
     if (rp > rb_mu * rd) rb = rb_tau;
@@ -233,18 +247,6 @@ __global__ void __launch_bounds__(64) k_control(DevScalars* sc, const double* kk
     if (beta_mode == RAC_BETA_RESBAL) {
       if (tid == 0) mult_sh = rb;
     } else {
-      if (tid == 0) {
-        const double rpo = sc->rp_win, rdo = sc->rd_win, kp = sc->kkt_prev;
-        f[0] = (float)clip4(0.5 * (lg10c(rp) - lg10c(rd)));
-        f[1] = (float)clip4(0.5 * (lg10c(rpo) - lg10c(rdo)));
-        f[2] = (float)clip4(lg10c(rp) - lg10c(rpo));
-        f[3] = (float)clip4(lg10c(rd) - lg10c(rdo));
-        f[4] = (float)clip4(kp > 0.0 ? lg10c(kkt) - lg10c(kp) : 0.0);
-        f[5] = (float)clip4(sc->last_l10);
-        f[6] = (float)clip4((lg10c(kkt) + 6.0) / 3.0);
-        f[7] = (float)clip4((double)sc->decisions / 10.0);
-      }
-      __syncthreads();
       const float* W1 = w;
       const float* B1 = W1 + RAC_MLP_HIDDEN * RAC_MLP_IN;
       const float* W2 = B1 + RAC_MLP_HIDDEN;
@@ -396,6 +398,19 @@ hipError_t launch_kkt(const KKTArgs& k, hipStream_t st) {
     case RAC_DT_BF16: return kkt_launch<uint16_t>(k, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+__global__ void k_scale_beta(DevScalars* sc, double mult) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->beta *= mult;
+    sc->last_l10 = log10(mult);
+    sc->decisions += 1;
+  }
+}
+
+hipError_t launch_scale_beta(DevScalars* sc, double mult, hipStream_t st) {
+  k_scale_beta<<<1, 64, 0, st>>>(sc, mult);
+  return hipGetLastError();
 }
 
 hipError_t launch_control(const ControlArgs& c, hipStream_t st) {

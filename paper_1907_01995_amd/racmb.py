@@ -28,7 +28,8 @@ MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HI
 
 EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_solver_set_state",
             "rac_solver_get_state", "rac_solver_history", "rac_solver_set_timing", "rac_solver_timing",
-            "rac_solver_info", "rac_state_export", "rac_state_import",
+            "rac_solver_info", "rac_solver_features", "rac_solver_scale_beta", "rac_state_export",
+            "rac_state_import",
             "rac_permutation", "rac_kkt", "rac_objective", "rac_regression_c", "rac_block_matrices",
             "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_status_str"]
 
@@ -90,6 +91,8 @@ def load():
         "rac_solver_set_timing": [vp, C.c_int32],
         "rac_solver_timing": [vp, dp, C.POINTER(i64)],
         "rac_solver_info": [vp, C.POINTER(i64)],
+        "rac_solver_features": [vp, C.POINTER(C.c_float)],
+        "rac_solver_scale_beta": [vp, C.c_double, vp],
         "rac_state_export": [vp, vp, C.POINTER(C.c_size_t)],
         "rac_state_import": [vp, vp, C.c_size_t],
         "rac_permutation": [u64, u64, i64, i64, vp, vp],
@@ -314,6 +317,17 @@ class Solver:
         v = (C.c_int64 * 8)()
         _check(self.lib.rac_solver_info(self.h, v), "rac_solver_info")
         return dict(p=v[0], sp=v[1], K=v[2], R=v[3], T=v[4], tileA=v[5], tileB=v[6], overlap=v[7])
+
+    def features(self):
+        """Controller features formed at the last KKT check (float32[8])."""
+        out = np.zeros(MLP_IN, dtype=np.float32)
+        _check(self.lib.rac_solver_features(self.h, out.ctypes.data_as(C.POINTER(C.c_float))),
+               "rac_solver_features")
+        return out
+
+    def scale_beta(self, mult):
+        """beta *= mult, recorded as a controller decision."""
+        _check(self.lib.rac_solver_scale_beta(self.h, float(mult), _stream()), "rac_solver_scale_beta")
 
     def reset(self, beta=None):
         """Zero state (cold start) at iteration 0."""
