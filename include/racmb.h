@@ -224,6 +224,55 @@ rac_status rac_mlp_loss_grad(const float* w, const float* feats, const float* ta
 rac_status rac_mlp_adam(float* w, const float* grad, float* m, float* v, int64_t t, float lr,
                         float b1, float b2, float eps, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched solving: many instances of uneven size (each a rac_problem with its
+ * own data) and lanes (independent solves on one instance's data, e.g. the
+ * points of a lambda grid, each with its own penalty, iterate and controller),
+ * advanced together with one launch per phase for the whole batch.  Lanes of an
+ * instance share its partition of every iteration (drawn with the instance's
+ * index as the instance id) and its block Grams F_B'F_B; block inverses, steps,
+ * residuals and duals are per lane.  Each chunk of T iterations can be captured
+ * once in a hipGraph and replayed.  Lanes retire individually at KKT <= tol.
+ * Requirements: every instance has the same F_dtype, n_i <= 8192, block size
+ * s <= 64, beta_mode FIXED, RESBAL or MLP. */
+typedef struct rac_batch_s* rac_batch;
+typedef struct {
+  int32_t problem;      /* index of the instance this lane solves */
+  int32_t prox;         /* rac_prox of this lane */
+  double lambda, alpha; /* elastic-net parameters of this lane */
+  double beta0;         /* initial penalty of this lane (> 0) */
+} rac_lane;
+typedef struct {
+  int64_t block_size;   /* s (1..64): instance i has ceil(n_i/s) blocks */
+  uint64_t seed;        /* partition seed */
+  int32_t precision;    /* rac_precision */
+  int32_t beta_mode;    /* RAC_BETA_FIXED, RAC_BETA_RESBAL or RAC_BETA_MLP */
+  double rb_mu, rb_tau; /* residual balancing thresholds (defaults 10, 2 when <= 0) */
+  const float* mlp_weights;     /* device, RAC_MLP_NPARAM floats, for RAC_BETA_MLP */
+  double mlp_ymax;      /* default ln 10 when <= 0 */
+  int64_t check_every;  /* T */
+  int64_t max_iter;     /* iteration budget of one rac_batch_run call */
+  double tol;           /* a lane retires at its first check with KKT <= tol */
+  int32_t use_graph;    /* 1: capture a chunk of T iterations in a hipGraph and replay it */
+  int32_t tune;         /* 1: time the sweep variants on this batch and keep the fastest
+                           (cached per batch shape); 0: default variant */
+} rac_batch_opts;
+
+/* ninst problems (device data borrowed until rac_batch_destroy), nlanes lanes (host). */
+rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlanes, const rac_lane* lanes,
+                            const rac_batch_opts* opts, rac_batch* out);
+rac_status rac_batch_destroy(rac_batch b);
+/* Run up to max_iter iterations or until every lane has retired; *iters receives
+ * the iterations run, *active the lanes still running (host pointers). */
+rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* active);
+/* Result and state of one lane: res (host) and x, z, xi (device, n_i doubles each,
+ * any may be NULL).  res->status is the lane's rac_run_status (RAC_ERR_NOT_PD is
+ * returned when one of its blocks violated Assumption 2.1). */
+rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x, double* z, double* xi);
+/* info (host, 6 int64): lanes, instances, block Gram tasks, inverse tasks, chosen
+ * sweep row unroll, 1 if chunks are replayed from a hipGraph. */
+rac_status rac_batch_info(rac_batch b, int64_t* info);
+
 const char* rac_status_str(rac_status s);
 
 #ifdef __cplusplus

@@ -46,16 +46,15 @@ template <> __device__ __forceinline__ double to_lds<uint16_t, G_F64>(uint16_t v
 template <> __device__ __forceinline__ float to_lds<float, G_F32>(float v) { return v; }
 template <> __device__ __forceinline__ uint16_t to_lds<uint16_t, G_BF16>(uint16_t v) { return v; }
 
-constexpr int kMaxPairsPerWave = 9;   // 36 lower tiles of a 128x128 block over 4 waves
 constexpr int KT = 64;                // rows per LDS tile
 
 // One workgroup: block `blk`, rows [rb, re).  Data move as 16-byte vectors of
 // VE = 16/sizeof(T) consecutive rows of one column; the next 64-row tile is
 // loaded into registers while the matrix cores work on the current one.
 template <typename T, int MODE, int SP>
-__global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t ldF, int64_t rows,
-                                              int64_t n, int64_t p, const int32_t* __restrict__ perm,
-                                              int R, int vec, double* __restrict__ partial) {
+__device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, int64_t rows, int64_t n,
+                                          int64_t p, const int32_t* __restrict__ perm, int blk, int chunk,
+                                          int R, int vec, double* __restrict__ out) {
   typedef GramTraits<MODE> Tr;
   typedef typename Tr::E E;
   typedef typename Tr::Acc Acc;
@@ -69,7 +68,6 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
   __shared__ __attribute__((aligned(16))) E tile[SP * LD];   // tile[m * LD + k] = F[r0 + k, col_m]
   __shared__ int64_t colbase[SP];
 
-  const int blk = blockIdx.x, chunk = blockIdx.y;
   const int64_t s0 = block_start(blk, n, p);
   const int sb = (int)(block_start(blk + 1, n, p) - s0);
   // row chunks are whole tiles except the last
@@ -162,7 +160,6 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
     __syncthreads();
   }
   // write the partial lower tiles in FP64
-  double* out = partial + ((int64_t)blk * R + chunk) * (int64_t)SP * SP;
 #pragma unroll
   for (int q = 0; q < MAXP; ++q) {
     if (wave + 4 * q < NPAIR) {
@@ -175,6 +172,30 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
       }
     }
   }
+}
+
+template <typename T, int MODE, int SP>
+__global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t ldF, int64_t rows,
+                                              int64_t n, int64_t p, const int32_t* __restrict__ perm,
+                                              int R, int vec, double* __restrict__ partial) {
+  const int blk = blockIdx.x, chunk = blockIdx.y;
+  gram_body<T, MODE, SP>(F, ldF, rows, n, p, perm, blk, chunk, R, vec,
+                         partial + ((int64_t)blk * R + chunk) * (int64_t)SP * SP);
+}
+
+// Batched form: one workgroup per (instance, block) task of a batch; the Gram of
+// each block is shared by all lanes of its instance.  Iteration t of the chunk
+// selects the instance's partition for that iteration.
+template <typename T, int MODE, int SP>
+__global__ void __launch_bounds__(256) k_bgram(const BInst* __restrict__ inst, const int2* __restrict__ tasks,
+                                               const int32_t* __restrict__ perm, int t,
+                                               const int32_t* __restrict__ inst_active,
+                                               double* __restrict__ G) {
+  const int2 tk = tasks[blockIdx.x];
+  if (!inst_active[tk.x]) return;
+  const BInst I = inst[tk.x];
+  gram_body<T, MODE, SP>((const T*)I.F, I.ldF, I.rows, I.n, I.p, perm + I.poff + (int64_t)t * I.n, tk.y,
+                         0, 1, I.vec, G + (I.goff + tk.y) * (int64_t)SP * SP);
 }
 
 // Sum the partial Grams, add the diagonal and penalty terms, then invert the
@@ -336,6 +357,33 @@ hipError_t gram_launch(const GramArgs& g, hipStream_t st) {
 }
 
 }  // namespace
+
+template <typename T, int MODE>
+hipError_t bgram_launch(const BatchGramArgs& g, hipStream_t st) {
+  const T* dummy = nullptr;
+  (void)dummy;
+#define RAC_BGRAM(SPV)                                                                            \
+  if (g.sp == SPV) {                                                                              \
+    k_bgram<T, MODE, SPV><<<(unsigned)g.ntasks, 256, 0, st>>>(g.inst, g.tasks, g.perm, g.t,       \
+                                                              g.inst_active, g.G);                \
+    return hipGetLastError();                                                                    \
+  }
+  RAC_BGRAM(16) RAC_BGRAM(32) RAC_BGRAM(64)
+#undef RAC_BGRAM
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_bgram(const BatchGramArgs& g, hipStream_t st) {
+  if (g.ntasks <= 0) return hipSuccess;
+  const bool mixed = g.precision == RAC_PREC_MIXED;
+  switch (g.dtype) {
+    case RAC_DT_F64: return bgram_launch<double, G_F64>(g, st);
+    case RAC_DT_F32: return mixed ? bgram_launch<float, G_F32>(g, st) : bgram_launch<float, G_F64>(g, st);
+    case RAC_DT_BF16:
+      return mixed ? bgram_launch<uint16_t, G_BF16>(g, st) : bgram_launch<uint16_t, G_F64>(g, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_gram(const GramArgs& g, hipStream_t st) {
   const bool mixed = g.precision == RAC_PREC_MIXED;

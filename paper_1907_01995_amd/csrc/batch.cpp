@@ -1,0 +1,414 @@
+// batch.cpp -- host side of the batched engine: validation, descriptor tables,
+// workspace, the per-chunk launch sequence (optionally captured once in a
+// hipGraph and replayed), and the autotuner for the sweep's row unroll.
+//
+// A chunk of T iterations is: partitions of every active instance for the T
+// iterations; then per iteration the shared block Grams, the per-lane block
+// inverses, the per-lane sweeps and z/dual steps; then the KKT check, the
+// penalty rule and the activity count.  The host reads one integer (active
+// lanes) per chunk.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rac_internal.h"
+#include "racmb.h"
+
+using namespace rac;
+
+namespace {
+
+#define BCHK(expr)                                   \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return RAC_ERR_DEVICE;     \
+  } while (0)
+
+struct DevBufs {
+  std::vector<void*> owned;
+  template <typename T> bool alloc(T** p, size_t count) {
+    void* q = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&q, sizeof(T) * count) != hipSuccess) return false;
+    owned.push_back(q);
+    *p = (T*)q;
+    return true;
+  }
+  void release() {
+    for (void* q : owned) (void)hipFree(q);
+    owned.clear();
+  }
+};
+
+DevScalars fresh(double beta) {
+  DevScalars s{};
+  s.beta = beta;
+  s.kkt = NAN;
+  s.kkt_prev = -1.0;
+  s.rp_first = -1.0;
+  s.objective = NAN;
+  s.fail_key = ~0ULL;
+  return s;
+}
+
+std::string tune_cache_path() {
+  const char* p = std::getenv("RACMB_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/racmb_tune.txt";
+}
+
+}  // namespace
+
+struct rac_batch_s {
+  rac_batch_opts O{};
+  int ninst = 0, nunits = 0, SP = 16, T = 1;
+  std::vector<BInst> hinst;
+  std::vector<BUnit> hunit;
+  std::vector<int64_t> unit_n;
+  DevBufs buf;
+  BatchArgs A{};
+  BInst* dinst = nullptr;
+  BUnit* dunit = nullptr;
+  int2* gtasks = nullptr;
+  int ngt = 0;
+  int32_t host_active = 0;
+  int64_t k = 0;
+  hipStream_t cs = nullptr;           // the batch's own stream (capturable)
+  hipEvent_t ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_used = false;
+  std::string tune_key;
+};
+
+namespace {
+
+rac_status enqueue_chunk(rac_batch b, int Tc, hipStream_t st) {
+  BatchArgs a = b->A;
+  a.T = Tc;
+  BCHK(launch_bperm(a, st));
+  for (int t = 0; t < Tc; ++t) {
+    BatchGramArgs g{a.dtype, b->O.precision, a.sp, b->ngt, t, a.inst, b->gtasks, a.perm, a.inst_active,
+                    const_cast<double*>(a.G)};
+    BCHK(launch_bgram(g, st));
+    BCHK(launch_binv(a, t, st));
+    BCHK(launch_bsweep(a, t, st));
+    BCHK(launch_bzdual(a, st));
+  }
+  BCHK(launch_bcheck(a, Tc, Tc == b->T ? 1 : 0, st));
+  return RAC_OK;
+}
+
+// Snapshot / restore of the lane state around tuning trials.
+struct Snapshot {
+  std::vector<char> bytes;
+};
+
+rac_status state_copy(rac_batch b, bool save, Snapshot& s) {
+  int64_t xs = 0, us = 0;
+  for (const BUnit& u : b->hunit) { xs += u.n; us += u.rows; }
+  const size_t sz = sizeof(double) * (4 * xs + us) + sizeof(DevScalars) * b->nunits + sizeof(int64_t) +
+                    sizeof(int32_t) * (b->ninst + 1);
+  if (save) s.bytes.resize(sz);
+  char* p = s.bytes.data();
+  auto mv = [&](void* dev, size_t n) -> hipError_t {
+    hipError_t e = save ? hipMemcpy(p, dev, n, hipMemcpyDeviceToHost) : hipMemcpy(dev, p, n, hipMemcpyHostToDevice);
+    p += n;
+    return e;
+  };
+  BCHK(mv(b->A.X, sizeof(double) * xs));
+  BCHK(mv(b->A.Z, sizeof(double) * xs));
+  BCHK(mv(b->A.XI, sizeof(double) * xs));
+  BCHK(mv(b->A.ZP, sizeof(double) * xs));
+  BCHK(mv(b->A.U, sizeof(double) * us));
+  BCHK(mv(b->A.sc, sizeof(DevScalars) * b->nunits));
+  BCHK(mv(b->A.kdev, sizeof(int64_t)));
+  BCHK(mv(b->A.inst_active, sizeof(int32_t) * b->ninst));
+  BCHK(mv(b->A.nactive, sizeof(int32_t)));
+  return RAC_OK;
+}
+
+// Time one chunk with each sweep row unroll on this batch (from the same
+// state), keep the fastest, and remember it per batch shape.
+rac_status autotune(rac_batch b) {
+  const std::string path = tune_cache_path();
+  if (FILE* f = std::fopen(path.c_str(), "r")) {
+    char key[512];
+    int un = 0;
+    while (std::fscanf(f, "%511s %d", key, &un) == 2)
+      if (b->tune_key == key && (un == 1 || un == 2 || un == 4)) {
+        b->A.unroll = un;
+        std::fclose(f);
+        return RAC_OK;
+      }
+    std::fclose(f);
+  }
+  Snapshot snap;
+  rac_status r = state_copy(b, true, snap);
+  if (r != RAC_OK) return r;
+  hipEvent_t e0, e1;
+  BCHK(hipEventCreate(&e0));
+  BCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_un = 2;
+  for (int un : {1, 2, 4}) {
+    b->A.unroll = un;
+    BCHK(hipEventRecord(e0, b->cs));
+    r = enqueue_chunk(b, b->T, b->cs);
+    if (r != RAC_OK) return r;
+    BCHK(hipEventRecord(e1, b->cs));
+    BCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    BCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; best_un = un; }
+    r = state_copy(b, false, snap);
+    if (r != RAC_OK) return r;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->A.unroll = best_un;
+  if (FILE* f = std::fopen(path.c_str(), "a")) {
+    std::fprintf(f, "%s %d\n", b->tune_key.c_str(), best_un);
+    std::fclose(f);
+  }
+  return RAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlanes, const rac_lane* lanes,
+                            const rac_batch_opts* opts, rac_batch* out) {
+  if (!out || !opts || !inst || !lanes || ninst < 1 || nlanes < 1) return RAC_ERR_ARG;
+  *out = nullptr;
+  rac_batch_opts O = *opts;
+  if (O.block_size < 1 || O.block_size > 64) return RAC_ERR_ARG;
+  if (O.check_every < 1 || O.max_iter < 0 || !std::isfinite(O.tol) || O.tol < 0.0) return RAC_ERR_ARG;
+  if (O.precision != RAC_PREC_FP64 && O.precision != RAC_PREC_MIXED) return RAC_ERR_ARG;
+  if (O.beta_mode != RAC_BETA_FIXED && O.beta_mode != RAC_BETA_RESBAL && O.beta_mode != RAC_BETA_MLP)
+    return RAC_ERR_ARG;
+  if (O.beta_mode == RAC_BETA_MLP && !O.mlp_weights) return RAC_ERR_ARG;
+  if (O.rb_mu <= 0.0) O.rb_mu = 10.0;
+  if (O.rb_tau <= 0.0) O.rb_tau = 2.0;
+  if (!(O.mlp_ymax > 0.0)) O.mlp_ymax = std::log(10.0);
+  const int32_t dtype = inst[0].F_dtype;
+  int64_t maxn = 0;
+  for (int i = 0; i < ninst; ++i) {
+    const rac_problem& P = inst[i];
+    if (P.n < 1 || P.rows < 1 || !P.F || P.ldF < P.rows || !P.c || P.F_dtype != dtype) return RAC_ERR_ARG;
+    if (P.n > 8192 || !std::isfinite(P.Ns) || !(P.Ns > 0.0) || !std::isfinite(P.b)) return RAC_ERR_ARG;
+    if (dtype != RAC_DT_F64 && dtype != RAC_DT_F32 && dtype != RAC_DT_BF16) return RAC_ERR_ARG;
+    if (P.n > maxn) maxn = P.n;
+  }
+  for (int u = 0; u < nlanes; ++u) {
+    const rac_lane& L = lanes[u];
+    if (L.problem < 0 || L.problem >= ninst || !std::isfinite(L.beta0) || !(L.beta0 > 0.0)) return RAC_ERR_ARG;
+    if (L.prox < RAC_PROX_NONE || L.prox > RAC_PROX_BOX) return RAC_ERR_ARG;
+    if (L.prox == RAC_PROX_ELASTIC_NET &&
+        (!std::isfinite(L.lambda) || L.lambda < 0.0 || !(L.alpha >= 0.0 && L.alpha <= 1.0)))
+      return RAC_ERR_ARG;
+    const rac_problem& P = inst[L.problem];
+    if (L.prox == RAC_PROX_BOX && !(P.lo <= P.hi)) return RAC_ERR_ARG;
+  }
+  rac_batch b = new (std::nothrow) rac_batch_s();
+  if (!b) return RAC_ERR_NOMEM;
+  auto fail = [&](rac_status r) {
+    b->buf.release();
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    if (b->cs) (void)hipStreamDestroy(b->cs);
+    delete b;
+    return r;
+  };
+  b->O = O;
+  b->ninst = ninst;
+  b->nunits = nlanes;
+  b->T = (int)O.check_every;
+  const int64_t s = O.block_size;
+  b->SP = s <= 16 ? 16 : (s <= 32 ? 32 : 64);
+  // instances: partitions (T per instance) and block Grams
+  int64_t poff = 0, goff = 0, rows_sum = 0;
+  std::vector<int2> gt;
+  for (int i = 0; i < ninst; ++i) {
+    const rac_problem& P = inst[i];
+    BInst I{};
+    I.F = P.F; I.ldF = P.ldF; I.rows = P.rows; I.n = P.n; I.p = (P.n + s - 1) / s;
+    I.poff = poff; I.goff = goff; I.key_instance = (uint64_t)i;
+    const int vw = 16 / (dtype == RAC_DT_F64 ? 8 : (dtype == RAC_DT_F32 ? 4 : 2));
+    I.vec = (P.ldF % vw == 0) && ((uintptr_t)P.F % 16 == 0);
+    for (int64_t q = 0; q < I.p; ++q) gt.push_back(make_int2(i, (int)q));
+    poff += (int64_t)b->T * P.n;
+    goff += I.p;
+    b->hinst.push_back(I);
+  }
+  // lanes
+  int64_t xoff = 0, uoff = 0, moff = 0;
+  std::vector<int2> it;
+  int64_t maxp = 0;
+  for (int u = 0; u < nlanes; ++u) {
+    const rac_lane& L = lanes[u];
+    const rac_problem& P = inst[L.problem];
+    const BInst& I = b->hinst[L.problem];
+    BUnit U{};
+    U.F = P.F; U.ldF = P.ldF; U.rows = P.rows; U.n = P.n; U.p = I.p; U.Ns = P.Ns;
+    U.h = P.h; U.c = P.c; U.a = P.a; U.b = P.b; U.prox = L.prox; U.inst = L.problem;
+    U.lam = L.lambda; U.alpha = L.alpha; U.lo = P.lo; U.hi = P.hi;
+    U.xoff = xoff; U.uoff = uoff; U.goff = I.goff; U.moff = moff; U.poff = I.poff;
+    for (int64_t q = 0; q < I.p; ++q) it.push_back(make_int2(u, (int)q));
+    xoff += P.n;
+    uoff += P.rows;
+    moff += I.p;
+    rows_sum += P.rows;
+    if (I.p > maxp) maxp = I.p;
+    b->hunit.push_back(U);
+  }
+  b->ngt = (int)gt.size();
+  BatchArgs& A = b->A;
+  A.dtype = dtype; A.sp = b->SP; A.T = b->T; A.nunits = nlanes; A.ninst = ninst;
+  int np2 = 1;
+  while (np2 < maxn) np2 <<= 1;
+  A.np2 = np2;
+  A.seed = O.seed;
+  A.ninv = (int)it.size();
+  A.KC = (int)((maxn + 63) / 64);
+  A.beta_mode = O.beta_mode; A.rb_mu = O.rb_mu; A.rb_tau = O.rb_tau; A.tol = O.tol;
+  A.mlp_w = O.mlp_weights; A.mlp_ymax = O.mlp_ymax;
+  A.unroll = 2;
+  const size_t ss = (size_t)b->SP * b->SP;
+  bool ok = b->buf.alloc(&b->dinst, ninst) && b->buf.alloc(&b->dunit, nlanes) &&
+            b->buf.alloc(&b->gtasks, gt.size()) && b->buf.alloc(const_cast<int2**>(&A.inv_tasks), it.size()) &&
+            b->buf.alloc(&A.perm, poff) && b->buf.alloc(const_cast<double**>(&A.G), goff * ss) &&
+            b->buf.alloc(&A.Minv, moff * ss) && b->buf.alloc(&A.X, xoff) && b->buf.alloc(&A.Z, xoff) &&
+            b->buf.alloc(&A.XI, xoff) && b->buf.alloc(&A.ZP, xoff) && b->buf.alloc(&A.U, uoff) &&
+            b->buf.alloc(&A.sc, nlanes) && b->buf.alloc(&A.kpart, (size_t)nlanes * A.KC * 10) &&
+            b->buf.alloc(&A.inst_active, ninst) && b->buf.alloc(&A.nactive, 1) && b->buf.alloc(&A.kdev, 1);
+  if (!ok) return fail(RAC_ERR_NOMEM);
+  A.inst = b->dinst;
+  A.units = b->dunit;
+  std::vector<DevScalars> hs;
+  for (int u = 0; u < nlanes; ++u) hs.push_back(fresh(lanes[u].beta0));
+  std::vector<int32_t> act(ninst, 1);
+  const int32_t nact = nlanes;
+  const int64_t k0 = 0;
+  if (hipMemcpy(b->dinst, b->hinst.data(), sizeof(BInst) * ninst, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->dunit, b->hunit.data(), sizeof(BUnit) * nlanes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->gtasks, gt.data(), sizeof(int2) * gt.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(const_cast<int2*>(A.inv_tasks), it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(A.sc, hs.data(), sizeof(DevScalars) * nlanes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(A.inst_active, act.data(), sizeof(int32_t) * ninst, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(A.nactive, &nact, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(A.kdev, &k0, sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(A.X, 0, sizeof(double) * xoff) != hipSuccess || hipMemset(A.Z, 0, sizeof(double) * xoff) != hipSuccess ||
+      hipMemset(A.XI, 0, sizeof(double) * xoff) != hipSuccess || hipMemset(A.ZP, 0, sizeof(double) * xoff) != hipSuccess ||
+      hipMemset(A.U, 0, sizeof(double) * uoff) != hipSuccess)
+    return fail(RAC_ERR_DEVICE);
+  b->host_active = nlanes;
+  if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) return fail(RAC_ERR_DEVICE);
+  if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return fail(RAC_ERR_DEVICE);
+  char key[256];
+  std::snprintf(key, sizeof(key), "bsweep:dt%d:sp%d:lanes%d:rows%lld:T%d:gfx950", dtype, b->SP, nlanes,
+                (long long)(rows_sum / 1024), b->T);
+  b->tune_key = key;
+  if (O.tune) {
+    rac_status r = autotune(b);
+    if (r != RAC_OK) return fail(r);
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(RAC_ERR_DEVICE);
+  *out = b;
+  return RAC_OK;
+}
+
+rac_status rac_batch_destroy(rac_batch b) {
+  if (!b) return RAC_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ev) (void)hipEventDestroy(b->ev);
+  if (b->cs) (void)hipStreamDestroy(b->cs);
+  b->buf.release();
+  delete b;
+  return RAC_OK;
+}
+
+rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* active) {
+  if (!b) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  // the batch's stream starts after the caller's prior work and the caller waits for it at the end
+  BCHK(hipEventRecord(b->ev, st));
+  BCHK(hipStreamWaitEvent(b->cs, b->ev, 0));
+  int64_t done = 0;
+  while (done < b->O.max_iter && b->host_active > 0) {
+    const int Tc = (int)std::min<int64_t>(b->T, b->O.max_iter - done);
+    if (b->O.use_graph && Tc == b->T) {
+      if (!b->gexec) {
+        BCHK(hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
+        rac_status r = enqueue_chunk(b, Tc, b->cs);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cs, &g);
+        if (r != RAC_OK) return r;
+        BCHK(e);
+        b->graph = g;
+        BCHK(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+      }
+      BCHK(hipGraphLaunch(b->gexec, b->cs));
+      b->graph_used = true;
+    } else {
+      rac_status r = enqueue_chunk(b, Tc, b->cs);
+      if (r != RAC_OK) return r;
+    }
+    BCHK(hipMemcpyAsync(&b->host_active, b->A.nactive, sizeof(int32_t), hipMemcpyDeviceToHost, b->cs));
+    BCHK(hipStreamSynchronize(b->cs));
+    done += Tc;
+  }
+  b->k += done;
+  BCHK(hipEventRecord(b->ev, b->cs));
+  BCHK(hipStreamWaitEvent(st, b->ev, 0));
+  if (iters) *iters = done;
+  if (active) *active = b->host_active;
+  return RAC_OK;
+}
+
+rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x, double* z, double* xi) {
+  if (!b || lane < 0 || lane >= b->nunits) return RAC_ERR_ARG;
+  const BUnit& U = b->hunit[lane];
+  BCHK(hipStreamSynchronize(b->cs));
+  DevScalars h;
+  BCHK(hipMemcpy(&h, b->A.sc + lane, sizeof(DevScalars), hipMemcpyDeviceToHost));
+  const size_t nb = sizeof(double) * U.n;
+  if (x) BCHK(hipMemcpy(x, b->A.X + U.xoff, nb, hipMemcpyDeviceToDevice));
+  if (z) BCHK(hipMemcpy(z, b->A.Z + U.xoff, nb, hipMemcpyDeviceToDevice));
+  if (xi) BCHK(hipMemcpy(xi, b->A.XI + U.xoff, nb, hipMemcpyDeviceToDevice));
+  if (res) {
+    std::memset(res, 0, sizeof(*res));
+    res->iters = h.k;
+    res->status = h.status == 1 ? RAC_RUN_CONVERGED : (h.status == 2 ? RAC_RUN_DIVERGED : RAC_RUN_MAX_ITER);
+    res->kkt = h.kkt;
+    res->beta = h.beta;
+    res->objective = NAN;
+    res->fail_iter = h.fail_key == ~0ULL ? -1 : (int64_t)(h.fail_key >> 32);
+    res->fail_block = h.fail_key == ~0ULL ? -1 : (int64_t)(h.fail_key & 0xffffffffULL);
+  }
+  return h.fail_key == ~0ULL ? RAC_OK : RAC_ERR_NOT_PD;
+}
+
+rac_status rac_batch_info(rac_batch b, int64_t* info) {
+  if (!b || !info) return RAC_ERR_ARG;
+  info[0] = b->nunits;
+  info[1] = b->ninst;
+  info[2] = b->ngt;
+  info[3] = b->A.ninv;
+  info[4] = b->A.unroll;
+  info[5] = b->graph_used ? 1 : 0;
+  return RAC_OK;
+}
+
+}  // extern "C"

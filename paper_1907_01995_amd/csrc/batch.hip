@@ -1,0 +1,522 @@
+// batch.hip -- the batched engine: many instances of uneven size, each with
+// several lanes (independent solves on the instance's data, e.g. the points of
+// a lambda grid), advanced together one iteration at a time with one launch per
+// phase for the whole batch.  Lanes of an instance share its partitions (the
+// partition of Eq.(3) is drawn per instance) and its block Grams; each lane has
+// its own penalty, block inverses, iterate, residual, duals and controller.
+//
+// Kernels (one launch each per iteration, all lanes at once):
+//   k_bperm   one workgroup per (instance, iteration of the chunk): the
+//             instance's keys sorted by a bitonic network in LDS (n <= 8192);
+//   k_bgram   (assemble.hip) one workgroup per (instance, block);
+//   k_binv    one wavefront per (lane, block): the block matrix in registers,
+//             one column per lane, inverted by Gauss-Jordan with the pivot
+//             column broadcast through readlane -- no LDS, no barriers;
+//   k_bsweep  one workgroup per lane: the Gauss-Seidel pass over the blocks,
+//             gradient pass (rows over lanes, columns over wavefronts,
+//             transposed butterfly) and residual update pass per block;
+//   k_bzdual  one workgroup per lane: z block, dual step, norms;
+//   k_bkkt / k_bcontrol / k_bactive: KKT residual per lane, the stopping test
+//             and penalty rule (shared with the single-instance engine), and the
+//             per-instance activity used to skip retired work.
+// Retired lanes (converged or diverged) return immediately from every kernel.
+#include "control.h"
+#include "rac_internal.h"
+
+namespace rac {
+namespace {
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  int2 x = __builtin_bit_cast(int2, v);
+  x.x = __builtin_amdgcn_readlane(x.x, l);
+  x.y = __builtin_amdgcn_readlane(x.y, l);
+  return __builtin_bit_cast(double, x);
+}
+
+__device__ __forceinline__ double bsum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ double bmax(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, sh[w]);
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Partitions: bitonic sort of (key, index) pairs in LDS, padded to a power of
+// two with keys (~0, INT_MAX) that sort last.  The order is the exact
+// lexicographic order, so it equals the single-instance permutation.
+__global__ void __launch_bounds__(1024) k_bperm(const BInst* __restrict__ inst, uint64_t seed,
+                                                const int64_t* __restrict__ kdev, int32_t* __restrict__ perm,
+                                                const int32_t* __restrict__ inst_active, int np2max) {
+  const int i = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
+  if (!inst_active[i]) return;
+  const BInst I = inst[i];
+  const int n = (int)I.n;
+  int np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  extern __shared__ unsigned char smem[];
+  uint64_t* key = reinterpret_cast<uint64_t*>(smem);
+  int32_t* idx = reinterpret_cast<int32_t*>(key + np2max);
+  const uint64_t iter = (uint64_t)(*kdev + t);
+  for (int j = tid; j < np2; j += 1024) {
+    key[j] = j < n ? perm_key(seed, I.key_instance, iter, (uint64_t)j) : ~0ULL;
+    idx[j] = j < n ? j : 0x7fffffff;
+  }
+  __syncthreads();
+  for (int size = 2; size <= np2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int e = tid; e < (np2 >> 1); e += 1024) {
+        const int lo = 2 * stride * (e / stride) + (e % stride), hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t kl = key[lo], kh = key[hi];
+        const int32_t il = idx[lo], ih = idx[hi];
+        const bool greater = kl > kh || (kl == kh && il > ih);
+        if (greater == asc) {
+          key[lo] = kh; key[hi] = kl;
+          idx[lo] = ih; idx[hi] = il;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  int32_t* out = perm + I.poff + (int64_t)t * n;
+  for (int j = tid; j < n; j += 1024) out[j] = idx[j];
+}
+
+// ---------------------------------------------------------------------------
+// Block inverses: one wavefront per (lane, block).  Lane j holds column j of
+// M = G/Ns + diag(h) + beta (I + a a') in registers; at pivot k the pivot
+// column (lane k's registers) is read with readlane, one entry at a time.
+// Pivots are the LDL' (squared Cholesky) pivots; a non-positive one is
+// reported as a failure of Assumption 2.1 for the lane.
+template <int SP>
+__global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
+                                              int ntasks, const int32_t* __restrict__ perm, int t,
+                                              const double* __restrict__ G, DevScalars* sc,
+                                              double* __restrict__ Minv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int task = blockIdx.x * 4 + wave;
+  if (task >= ntasks) return;
+  const int2 tk = tasks[task];
+  if (sc[tk.x].status != 0) return;
+  const BUnit U = units[tk.x];
+  const double beta = sc[tk.x].beta;
+  const int blk = tk.y;
+  const int64_t s0 = block_start(blk, U.n, U.p);
+  const int sb = (int)(block_start(blk + 1, U.n, U.p) - s0);
+  const int32_t* pm = perm + U.poff + (int64_t)t * U.n + s0;
+  const int j = lane;
+  const int colj = j < sb ? pm[j] : 0;
+  const double hj = (U.h && j < sb) ? U.h[colj] : 0.0;
+  const double aj = (U.a && j < sb) ? U.a[colj] : 0.0;
+  const double* Gb = G + (U.goff + blk) * (int64_t)SP * SP;
+  double col[SP];
+#pragma unroll
+  for (int i = 0; i < SP; ++i) {
+    const double ai = U.a ? readlane_d(aj, i) : 0.0;   // uniform position: every lane reads lane i
+    double v;
+    if (i < sb && j < sb) {
+      const double g = i >= j ? Gb[i * SP + j] : Gb[j * SP + i];
+      v = g / U.Ns;
+      if (i == j) v += beta + hj;
+      if (U.a) v += beta * ai * aj;
+    } else {
+      v = (i == j) ? 1.0 : 0.0;
+    }
+    col[i] = v;
+  }
+  bool failed = false;
+  for (int k = 0; k < sb; ++k) {            // runtime pivot loop; entries stay in static registers
+    double rraw = 0.0;                      // this lane's entry of the pivot row, M[k][j]
+#pragma unroll
+    for (int i = 0; i < SP; ++i)
+      if (i == k) rraw = col[i];
+    const double piv = readlane_d(rraw, k);
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      failed = true;
+      if (lane == 0) {
+        unsigned long long key = ((unsigned long long)sc[tk.x].k << 32) | (unsigned)blk;
+        atomicMin((unsigned long long*)&sc[tk.x].fail_key, key);
+      }
+      break;
+    }
+    const double ip = 1.0 / piv;
+    const double rk = rraw * ip;
+#pragma unroll
+    for (int i = 0; i < SP; ++i) {
+      const double pcol = readlane_d(col[i], k);
+      double nv;
+      if (i == k) nv = (lane == k) ? ip : rk;
+      else nv = (lane == k) ? -pcol * ip : col[i] - pcol * rk;
+      col[i] = nv;
+    }
+  }
+  double* out = Minv + (U.moff + blk) * (int64_t)SP * SP;
+  if (j < SP) {   // lanes past the padded size hold no column
+#pragma unroll
+    for (int i = 0; i < SP; ++i) out[i * SP + j] = (!failed && i < sb && j < sb) ? col[i] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup per lane: the whole Gauss-Seidel pass.  Per block:
+//   gradient pass: lane l takes rows l, l+64, ...; wavefront w takes block
+//   columns w, w+4, ... (16 of them); per-lane sums are reduced across lanes
+//   by a transposed butterfly (15 + 2 exchanges for 16 columns);
+//   step d = -M^{-1} g from the lane's stored block inverse;
+//   update pass: thread r takes rows r, r+256, ... and adds F_B d to u.
+// The row loops keep UNR rows per lane in flight (autotuned).
+template <int B>
+__device__ __forceinline__ double tsum(double (&v)[B], int lane, int& c) {
+  int half = B / 2, o = 32;
+#pragma unroll
+  for (; half >= 1; half >>= 1, o >>= 1) {
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int q = 0; q < half; ++q) {
+      const double send = upper ? v[q] : v[q + half];
+      const double keep = upper ? v[q + half] : v[q];
+      v[q] = keep + __shfl_xor(send, o, 64);
+    }
+  }
+  double r = v[0];
+#pragma unroll
+  for (; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  int cc = 0, bit = 32;
+#pragma unroll
+  for (int t = B; t > 1; t >>= 1, bit >>= 1) cc = (cc << 1) | ((lane & bit) ? 1 : 0);
+  c = cc;
+  return r;
+}
+
+template <typename T, int SP, int UNR>
+__global__ void __launch_bounds__(256) k_bsweep(const BUnit* __restrict__ units, const int32_t* __restrict__ perm,
+                                                int t, const double* __restrict__ Minv, DevScalars* sc,
+                                                double* __restrict__ X, const double* __restrict__ Z,
+                                                const double* __restrict__ XI, double* __restrict__ Uall) {
+  constexpr int CB = SP / 4;   // columns per wavefront
+  const int u = blockIdx.x;
+  if (sc[u].status != 0) return;
+  const BUnit D = units[u];
+  const T* F = (const T*)D.F;
+  double* x = X + D.xoff;
+  const double* z = Z + D.xoff;
+  const double* xi = XI + D.xoff;
+  double* uu = Uall + D.uoff;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int32_t cols[SP];
+  __shared__ double gl[SP], dl[SP], pg[SP], gb[SP];
+  __shared__ double psum[256];
+  const double beta = sc[u].beta, mu = sc[u].mu;
+  double tq = sc[u].t;
+  const int32_t* pm = perm + D.poff + (int64_t)t * D.n;
+  for (int64_t blk = 0; blk < D.p; ++blk) {
+    const int64_t s0 = block_start(blk, D.n, D.p);
+    const int sb = (int)(block_start(blk + 1, D.n, D.p) - s0);
+    if (tid < sb) {
+      const int col = pm[s0 + tid];
+      cols[tid] = col;
+      const double xc = x[col];
+      double v = D.c[col] - xi[col] + beta * (xc - z[col]);
+      if (D.h) v += D.h[col] * xc;
+      if (D.a) v -= mu * D.a[col];
+      gb[tid] = v;
+    }
+    __syncthreads();
+    // gradient pass
+    double acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    int64_t cbase[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      const int j = wave + 4 * q;
+      cbase[q] = j < sb ? (int64_t)cols[j] * D.ldF : -1;
+    }
+    for (int64_t r0 = lane; r0 < D.rows; r0 += 64 * UNR) {
+#pragma unroll
+      for (int e = 0; e < UNR; ++e) {
+        const int64_t r = r0 + 64 * e;
+        if (r < D.rows) {
+          const double ur = uu[r];
+#pragma unroll
+          for (int q = 0; q < CB; ++q)
+            if (cbase[q] >= 0) acc[q] += ld_f64(F, cbase[q] + r) * ur;
+        }
+      }
+    }
+    int cidx;
+    const double tot = tsum<CB>(acc, lane, cidx);
+    if ((lane & (64 / CB - 1)) == 0) {
+      const int j = wave + 4 * cidx;
+      if (j < sb) pg[j] = tot;
+    }
+    __syncthreads();
+    if (tid < sb) {
+      double v = pg[tid] / D.Ns + gb[tid];
+      if (D.a) v += beta * D.a[cols[tid]] * (tq - D.b);
+      gl[tid] = v;
+    }
+    __syncthreads();
+    // step: four threads per column, combined in order
+    {
+      const double* Mi = Minv + (D.moff + blk) * (int64_t)SP * SP;
+      const int j = tid % SP, part = tid / SP;
+      constexpr int P = 256 / SP;
+      double a2 = 0.0;
+      if (j < sb)
+        for (int k = part; k < sb; k += P) a2 += Mi[(int64_t)k * SP + j] * gl[k];
+      psum[part * SP + j] = a2;
+    }
+    __syncthreads();
+    if (tid < SP) {
+      double s = 0.0;
+      for (int e = 0; e < 256 / SP; ++e) s += psum[e * SP + tid];
+      dl[tid] = tid < sb ? -s : 0.0;
+    }
+    __syncthreads();
+    if (D.a) {
+      double dt = 0.0;
+      for (int j = 0; j < sb; ++j) dt += D.a[cols[j]] * dl[j];
+      tq += dt;
+    }
+    // update pass
+    for (int64_t r = tid; r < D.rows; r += 256) {
+      double a2 = 0.0;
+      for (int j = 0; j < sb; ++j) a2 += ld_f64(F, (int64_t)cols[j] * D.ldF + r) * dl[j];
+      uu[r] += a2;
+    }
+    if (tid < sb) x[cols[tid]] += dl[tid];
+    __syncthreads();
+  }
+  if (tid == 0) sc[u].t = tq;
+}
+
+// ---------------------------------------------------------------------------
+// z block, dual step and norms of one lane per workgroup.
+__global__ void __launch_bounds__(256) k_bzdual(const BUnit* __restrict__ units, DevScalars* sc,
+                                                const double* __restrict__ X, double* Z, double* XI, double* ZP,
+                                                int64_t T) {
+  __shared__ double sh[4];
+  const int u = blockIdx.x;
+  if (sc[u].status != 0) return;
+  const BUnit D = units[u];
+  const double* x = X + D.xoff;
+  double* z = Z + D.xoff;
+  double* xi = XI + D.xoff;
+  double* zp = ZP + D.xoff;
+  const double beta = sc[u].beta;
+  double rp2 = 0.0, rd2 = 0.0;
+  for (int64_t j = threadIdx.x; j < D.n; j += 256) {
+    const double xj = x[j], xij = xi[j], zo = z[j];
+    double zn;
+    if (D.prox == RAC_PROX_ELASTIC_NET) {
+      const double v = beta * xj - xij, th = D.lam * D.alpha;
+      zn = (v > th ? v - th : (v < -th ? v + th : 0.0)) / (beta + D.lam * (1.0 - D.alpha));
+    } else if (D.prox == RAC_PROX_BOX) {
+      zn = fmin(fmax(xj - xij / beta, D.lo), D.hi);
+    } else {
+      zn = xj - xij / beta;
+    }
+    const double r = xj - zn, dz = zn - zo;
+    xi[j] = xij - beta * r;
+    z[j] = zn;
+    zp[j] = zo;
+    rp2 += r * r;
+    rd2 += dz * dz;
+  }
+  rp2 = bsum(rp2, sh);
+  rd2 = bsum(rd2, sh);
+  if (threadIdx.x != 0) return;
+  DevScalars& S = sc[u];
+  if (D.a) {
+    const double e = S.t - D.b;
+    S.mu -= beta * e;
+    rp2 += e * e;
+  }
+  const double rp = sqrt(rp2), rd = beta * sqrt(rd2);
+  const int64_t k = S.k;
+  S.rp = rp;
+  S.rd = rd;
+  if (k % T == 0) { S.rp_win = rp; S.rd_win = rd; }
+  if (S.rp_first < 0.0) S.rp_first = rp;
+  if (!isfinite(rp) || !isfinite(rd) || (S.rp_first > 0.0 && rp > 1e12 * S.rp_first)) S.status = 2;
+  S.k = k + 1;
+}
+
+// ---------------------------------------------------------------------------
+// KKT terms per (lane, chunk of 64 columns); chunks past a lane's n write zeros.
+template <typename T>
+__global__ void __launch_bounds__(256) k_bkkt(const BUnit* __restrict__ units, const DevScalars* sc,
+                                              const double* __restrict__ X, const double* __restrict__ Z,
+                                              const double* __restrict__ XI, const double* __restrict__ Uall,
+                                              double* __restrict__ kpart, int KC) {
+  __shared__ double sh[4];
+  const int u = blockIdx.x, ch = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* outp = kpart + ((int64_t)u * KC + ch) * 10;
+  if (sc[u].status != 0) return;
+  const BUnit D = units[u];
+  const T* F = (const T*)D.F;
+  const double mu = sc[u].mu;
+  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t j0 = (int64_t)ch * 64;
+  for (int64_t j = j0 + wave; j < j0 + 64 && j < D.n; j += 4) {
+    const T* col = F + j * D.ldF;
+    const double* uu = Uall + D.uoff;
+    double acc = 0.0;
+    for (int64_t r = lane; r < D.rows; r += 64) acc += ld_f64(col, r) * uu[r];
+    acc = wave_sum(acc);
+    if (lane == 0)
+      kkt_column_terms(acc, D.Ns, D.h ? D.h[j] : 0.0, D.c[j], D.a ? D.a[j] : 0.0, X[D.xoff + j],
+                       Z[D.xoff + j], XI[D.xoff + j], mu, D.prox, D.lam, D.alpha, D.lo, D.hi, m);
+  }
+  for (int q = 0; q < 9; ++q) {
+    const double v = bmax(m[q], sh);
+    if (threadIdx.x == 0) outp[q] = v;
+  }
+  const double v = bsum(m[9], sh);
+  if (threadIdx.x == 0) outp[9] = v;
+}
+
+__global__ void __launch_bounds__(64) k_bcontrol(const BUnit* __restrict__ units, DevScalars* sc,
+                                                 const double* __restrict__ kpart, int KC, int32_t beta_mode,
+                                                 double rb_mu, double rb_tau, double tol,
+                                                 const float* __restrict__ w, double ymax, int decide) {
+  const int u = blockIdx.x;
+  if (sc[u].status != 0) return;
+  if (sc[u].fail_key != ~0ULL) {          // a block violated Assumption 2.1: retire the lane
+    if (threadIdx.x == 0) sc[u].status = 3;
+    return;
+  }
+  const BUnit D = units[u];
+  const int nch = (int)((D.n + 63) / 64);
+  double M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < nch; ++c) {
+    const double* q = kpart + ((int64_t)u * KC + c) * 10;
+    for (int e = 0; e < 9; ++e) M[e] = fmax(M[e], q[e]);
+    M[9] += q[9];
+  }
+  double out[4];
+  kkt_from_maxima(M, D.a != nullptr, D.b, sc[u].mu, out);
+  control_block(&sc[u], out[0], beta_mode, rb_mu, rb_tau, tol, w, ymax, decide, nullptr, 0, 0);
+}
+
+// Active lanes, and for every instance whether any of its lanes is active; the
+// batch's iteration counter advances by the chunk length.
+__global__ void __launch_bounds__(256) k_bactive(const BUnit* __restrict__ units, int nunits, const DevScalars* sc,
+                                                 int32_t* inst_active, int ninst, int32_t* nactive, int64_t* kdev,
+                                                 int Tc) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  for (int i = threadIdx.x; i < ninst; i += 256) inst_active[i] = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int u = threadIdx.x; u < nunits; u += 256)
+    if (sc[u].status == 0 && sc[u].fail_key == ~0ULL) {
+      ++mine;
+      atomicOr(&inst_active[units[u].inst], 1);
+    }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *nactive = cnt;
+    *kdev += Tc;
+  }
+}
+
+template <typename T>
+hipError_t bsweep_launch(const BatchArgs& b, int t, hipStream_t st) {
+#define RAC_BS(SPV, UN)                                                                              \
+  if (b.sp == SPV && b.unroll == UN) {                                                               \
+    k_bsweep<T, SPV, UN><<<(unsigned)b.nunits, 256, 0, st>>>(b.units, b.perm, t, b.Minv, b.sc, b.X, b.Z, \
+                                                            b.XI, b.U);                              \
+    return hipGetLastError();                                                                        \
+  }
+  RAC_BS(16, 1) RAC_BS(16, 2) RAC_BS(16, 4)
+  RAC_BS(32, 1) RAC_BS(32, 2) RAC_BS(32, 4)
+  RAC_BS(64, 1) RAC_BS(64, 2) RAC_BS(64, 4)
+#undef RAC_BS
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t bkkt_launch(const BatchArgs& b, hipStream_t st) {
+  dim3 grid((unsigned)b.nunits, (unsigned)b.KC);
+  k_bkkt<T><<<grid, 256, 0, st>>>(b.units, b.sc, b.X, b.Z, b.XI, b.U, b.kpart, b.KC);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bperm(const BatchArgs& b, hipStream_t st) {
+  const size_t lds = (size_t)b.np2 * (sizeof(uint64_t) + sizeof(int32_t));
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_bperm, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(8192 * (sizeof(uint64_t) + sizeof(int32_t))));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  dim3 grid((unsigned)b.ninst, (unsigned)b.T);
+  k_bperm<<<grid, 1024, lds, st>>>(b.inst, b.seed, b.kdev, b.perm, b.inst_active, b.np2);
+  return hipGetLastError();
+}
+
+hipError_t launch_binv(const BatchArgs& b, int t, hipStream_t st) {
+  const unsigned grid = (unsigned)((b.ninv + 3) / 4);
+  if (grid == 0) return hipSuccess;
+  switch (b.sp) {
+    case 16: k_binv<16><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
+    case 32: k_binv<32><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
+    case 64: k_binv<64><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bsweep(const BatchArgs& b, int t, hipStream_t st) {
+  switch (b.dtype) {
+    case RAC_DT_F64: return bsweep_launch<double>(b, t, st);
+    case RAC_DT_F32: return bsweep_launch<float>(b, t, st);
+    case RAC_DT_BF16: return bsweep_launch<uint16_t>(b, t, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bzdual(const BatchArgs& b, hipStream_t st) {
+  k_bzdual<<<(unsigned)b.nunits, 256, 0, st>>>(b.units, b.sc, b.X, b.Z, b.XI, b.ZP, b.T);
+  return hipGetLastError();
+}
+
+hipError_t launch_bcheck(const BatchArgs& b, int Tc, int decide, hipStream_t st) {
+  hipError_t e;
+  switch (b.dtype) {
+    case RAC_DT_F64: e = bkkt_launch<double>(b, st); break;
+    case RAC_DT_F32: e = bkkt_launch<float>(b, st); break;
+    case RAC_DT_BF16: e = bkkt_launch<uint16_t>(b, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  k_bcontrol<<<(unsigned)b.nunits, 64, 0, st>>>(b.units, b.sc, b.kpart, b.KC, b.beta_mode, b.rb_mu, b.rb_tau,
+                                                 b.tol, b.mlp_w, b.mlp_ymax, decide);
+  k_bactive<<<1, 256, 0, st>>>(b.units, b.nunits, b.sc, b.inst_active, b.ninst, b.nactive, b.kdev, Tc);
+  return hipGetLastError();
+}
+
+}  // namespace rac

@@ -16,13 +16,6 @@
 namespace rac {
 namespace {
 
-__device__ __forceinline__ uint64_t perm_key(uint64_t seed, uint64_t inst, uint64_t iter,
-                                             uint64_t j) {
-  uint64_t s1 = sm64_mix(seed + kGamma * (inst + 1));
-  uint64_t s2 = sm64_mix(s1 + kGamma * (iter + 1));
-  return sm64_mix(s2 + kGamma * (j + 1));
-}
-
 __device__ __forceinline__ uint32_t bucket_of(uint64_t key, int log2nb) {
   return log2nb == 0 ? 0u : (uint32_t)(key >> (64 - log2nb));
 }

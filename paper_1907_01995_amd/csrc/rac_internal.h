@@ -29,7 +29,7 @@ struct DevScalars {
   int64_t k;         // iterations completed (global count)
   int64_t decisions; // controller decisions taken
   uint64_t fail_key; // (iteration << 32 | block) of the first non-PD block, or ~0
-  int32_t status;    // 0 running, 1 converged, 2 diverged
+  int32_t status;    // 0 running, 1 converged, 2 diverged, 3 retired after a non-PD block
   int32_t pad;
   float feat[RAC_MLP_IN];   // controller features formed at the last check
 };
@@ -62,6 +62,14 @@ __host__ __device__ __forceinline__ int64_t block_start(int64_t i, int64_t n, in
   return (i * n) / p;
 }
 
+// Partition key of variable j at iteration `iter` (a SplitMix64 chain).
+__host__ __device__ __forceinline__ uint64_t perm_key(uint64_t seed, uint64_t inst, uint64_t iter,
+                                                      uint64_t j) {
+  uint64_t s1 = sm64_mix(seed + kGamma * (inst + 1));
+  uint64_t s2 = sm64_mix(s1 + kGamma * (iter + 1));
+  return sm64_mix(s2 + kGamma * (j + 1));
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers (one per kernel family).  All return hipError_t of the launch.
 
@@ -86,6 +94,53 @@ struct GramArgs {
   double* partial;         // [p][R][sp*sp]
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Batched engine: many instances (each with its own data) and lanes (each an
+// independent solve on one instance's data, sharing its partitions and block
+// Grams).  All arrays below are device resident.
+struct BInst {             // one instance (data, sizes, partition)
+  const void* F; int64_t ldF, rows, n, p;
+  int64_t poff;            // offset of the instance's partitions in the chunk buffer (T * n entries)
+  int64_t goff;            // first block Gram of the instance in the Gram buffer
+  uint64_t key_instance;   // instance id mixed into the partition keys
+  int32_t vec;             // 16-byte vector loads allowed
+  int32_t pad;
+};
+struct BUnit {             // one lane: an independent solve on instance `inst`
+  const void* F; int64_t ldF, rows, n, p; double Ns;
+  const double* h; const double* c; const double* a; double b;
+  int32_t prox; int32_t inst; double lam, alpha, lo, hi;
+  int64_t xoff;            // offset of x, z, xi, zprev (n entries each)
+  int64_t uoff;            // offset of u (rows entries)
+  int64_t goff;            // first block Gram of its instance
+  int64_t moff;            // first block inverse of this lane
+  int64_t poff;            // partitions of its instance
+};
+struct BatchGramArgs {
+  int32_t dtype; int32_t precision; int sp; int ntasks; int t;
+  const BInst* inst; const int2* tasks; const int32_t* perm; const int32_t* inst_active; double* G;
+};
+hipError_t launch_bgram(const BatchGramArgs& a, hipStream_t st);
+
+struct BatchArgs {         // everything the per-lane kernels of one chunk need
+  int32_t dtype; int sp; int T; int nunits; int ninst; int np2;
+  uint64_t seed;
+  const BInst* inst; const BUnit* units;
+  int32_t* perm; const double* G; double* Minv;
+  const int2* inv_tasks; int ninv;
+  double* X; double* Z; double* XI; double* ZP; double* U;
+  DevScalars* sc;
+  double* kpart; int KC;   // KKT partials: [unit][KC][10]
+  int32_t* inst_active; int32_t* nactive; int64_t* kdev;
+  int32_t beta_mode; double rb_mu, rb_tau, tol; const float* mlp_w; double mlp_ymax;
+  int unroll;              // sweep row unroll (autotuned: 1, 2 or 4)
+};
+hipError_t launch_bperm(const BatchArgs& b, hipStream_t st);
+hipError_t launch_binv(const BatchArgs& b, int t, hipStream_t st);
+hipError_t launch_bsweep(const BatchArgs& b, int t, hipStream_t st);
+hipError_t launch_bzdual(const BatchArgs& b, hipStream_t st);
+hipError_t launch_bcheck(const BatchArgs& b, int Tc, int decide, hipStream_t st);   // KKT, control, activity
 
 struct FactorArgs {
   const double* partial; int R; int sp; int64_t n; int64_t p; const int32_t* perm;

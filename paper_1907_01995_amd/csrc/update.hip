@@ -10,6 +10,7 @@
 // fixed-order two-level reduction (per-workgroup partials, summed in workgroup
 // order by the last workgroup to finish), so results do not depend on timing.
 #include "rac_internal.h"
+#include "control.h"
 
 namespace rac {
 namespace {
@@ -134,38 +135,9 @@ __global__ void __launch_bounds__(256) k_kkt(const T* __restrict__ F, int64_t ld
     double acc = 0.0;
     for (int64_t r = lane; r < rows; r += 64) acc += ld_f64(col, r) * u[r];
     acc = wave_sum(acc);
-    if (lane == 0) {
-      const double xj = x[j], zj = z[j], xij = xi[j], cj = c[j];
-      const double aj = a ? a[j] : 0.0;
-      const double hx = acc / Ns + (h ? h[j] * xj : 0.0);
-      const double g = hx + cj - xij - mu * aj;
-      double d;
-      if (prox == RAC_PROX_NONE) {
-        d = fabs(xij);
-      } else if (prox == RAC_PROX_ELASTIC_NET) {
-        const double la = lam * alpha, l2 = lam * (1.0 - alpha);
-        if (zj > 0) d = fabs(-xij - (la + l2 * zj));
-        else if (zj < 0) d = fabs(-xij - (-la + l2 * zj));
-        else d = fabs(xij) > la ? fabs(xij) - la : 0.0;
-      } else {
-        const double w = -xij;
-        const bool at_lo = zj <= lo, at_hi = zj >= hi;
-        if (at_lo && at_hi) d = 0.0;
-        else if (at_lo) d = w > 0 ? w : 0.0;
-        else if (at_hi) d = w < 0 ? -w : 0.0;
-        else d = fabs(w);
-      }
-      m[0] = fmax(m[0], fabs(hx));
-      m[1] = fmax(m[1], fabs(cj));
-      m[2] = fmax(m[2], fabs(xij));
-      m[3] = fmax(m[3], fabs(xj));
-      m[4] = fmax(m[4], fabs(zj));
-      m[5] = fmax(m[5], fabs(xj - zj));
-      m[6] = fmax(m[6], fabs(g));
-      m[7] = fmax(m[7], d);
-      m[8] = fmax(m[8], fabs(aj));
-      m[9] += aj * xj;
-    }
+    if (lane == 0)
+      kkt_column_terms(acc, Ns, h ? h[j] : 0.0, c[j], a ? a[j] : 0.0, x[j], z[j], xi[j], mu, prox, lam, alpha,
+                       lo, hi, m);
   }
   for (int q = 0; q < 9; ++q) {
     double v = block_max(m[q], sh);
@@ -183,99 +155,18 @@ __global__ void __launch_bounds__(256) k_kkt(const T* __restrict__ F, int64_t ld
     M[9] += red[10 * q + 9];
   }
   *done = 0u;
-  double feas = M[5] / (1.0 + fmax(M[3], M[4]));
-  if (a) feas = fmax(feas, fabs(M[9] - b) / (1.0 + fabs(b) + M[8] * M[3]));
-  double scale = fmax(fmax(M[0], M[1]), M[2]);
-  if (a) scale = fmax(scale, fabs(mu) * M[8]);
-  if (scale < 1e-300) scale = 1e-300;
-  const double stat = M[6] / scale, dual = M[7] / scale;
-  out[1] = feas;
-  out[2] = stat;
-  out[3] = dual;
-  out[0] = fmax(feas, fmax(stat, dual));
+  kkt_from_maxima(M, a != nullptr, b, mu, out);
 }
 
 // ---------------------------------------------------------------------------
-// Penalty controller (runs once per check, one workgroup of 64 threads).
-//   residual balancing: beta *= tau if r_p > mu_rb r_d; beta /= tau if r_d > mu_rb r_p
-//   network: features -> 8-64-64-1 tanh perceptron -> beta *= exp(ymax tanh(o));
-//   a non-finite network output falls back to residual balancing.
-__device__ __forceinline__ double lg10c(double v) { return log10(v > 1e-300 ? v : 1e-300); }
-__device__ __forceinline__ double clip4(double v) { return v < -4.0 ? -4.0 : (v > 4.0 ? 4.0 : v); }
-
+// Penalty controller (runs once per check, one workgroup of 64 threads); the
+// logic is shared with the batched engine (control.h).
 __global__ void __launch_bounds__(64) k_control(DevScalars* sc, const double* kkt_out,
                                                 int32_t beta_mode, double rb_mu, double rb_tau,
                                                 double tol, const float* __restrict__ w,
                                                 double ymax, int decide, double* hist,
                                                 int64_t hist_cap, int64_t hist_base) {
-  __shared__ float f[RAC_MLP_IN];
-  __shared__ float h1[RAC_MLP_HIDDEN];
-  __shared__ float h2[RAC_MLP_HIDDEN];
-  __shared__ double mult_sh;
-  const int tid = threadIdx.x;
-  const double kkt = kkt_out[0];
-  const double rp = sc->rp, rd = sc->rd;
-  const int status0 = sc->status;
-  const bool conv = status0 == 0 && kkt <= tol;
-  __syncthreads();   // every thread has read the scalars before thread 0 updates them
-  if (tid == 0) {
-    sc->kkt = kkt;
-    const int64_t hi_ = sc->k - 1 - hist_base;
-    if (hist && hi_ >= 0 && hi_ < hist_cap) hist[4 * hi_ + 3] = kkt;
-    if (conv) sc->status = 1;
-  }
-  const bool act = decide && status0 == 0 && !conv &&
-                   (beta_mode == RAC_BETA_RESBAL || beta_mode == RAC_BETA_MLP);
-  // features of this check (stored for every decision point, used by the network)
-  if (tid == 0) {
-    const double rpo = sc->rp_win, rdo = sc->rd_win, kp = sc->kkt_prev;
-    f[0] = (float)clip4(0.5 * (lg10c(rp) - lg10c(rd)));
-    f[1] = (float)clip4(0.5 * (lg10c(rpo) - lg10c(rdo)));
-    f[2] = (float)clip4(lg10c(rp) - lg10c(rpo));
-    f[3] = (float)clip4(lg10c(rd) - lg10c(rdo));
-    f[4] = (float)clip4(kp > 0.0 ? lg10c(kkt) - lg10c(kp) : 0.0);
-    f[5] = (float)clip4(sc->last_l10);
-    f[6] = (float)clip4((lg10c(kkt) + 6.0) / 3.0);
-    f[7] = (float)clip4((double)sc->decisions / 10.0);
-    for (int q = 0; q < RAC_MLP_IN; ++q) sc->feat[q] = f[q];
-  }
-  __syncthreads();
-  if (act) {
-    double rb = 1.0;
-    if (rp > rb_mu * rd) rb = rb_tau;
-    else if (rd > rb_mu * rp) rb = 1.0 / rb_tau;
-    if (beta_mode == RAC_BETA_RESBAL) {
-      if (tid == 0) mult_sh = rb;
-    } else {
-      const float* W1 = w;
-      const float* B1 = W1 + RAC_MLP_HIDDEN * RAC_MLP_IN;
-      const float* W2 = B1 + RAC_MLP_HIDDEN;
-      const float* B2 = W2 + RAC_MLP_HIDDEN * RAC_MLP_HIDDEN;
-      const float* W3 = B2 + RAC_MLP_HIDDEN;
-      const float* B3 = W3 + RAC_MLP_HIDDEN;
-      float s = B1[tid];
-      for (int k = 0; k < RAC_MLP_IN; ++k) s += W1[tid * RAC_MLP_IN + k] * f[k];
-      h1[tid] = tanhf(s);
-      __syncthreads();
-      s = B2[tid];
-      for (int k = 0; k < RAC_MLP_HIDDEN; ++k) s += W2[tid * RAC_MLP_HIDDEN + k] * h1[k];
-      h2[tid] = tanhf(s);
-      __syncthreads();
-      float o = W3[tid] * h2[tid];
-      for (int off = 32; off >= 1; off >>= 1) o += __shfl_xor(o, off, 64);
-      if (tid == 0) {
-        const double y = ymax * tanh((double)(o + B3[0]));
-        mult_sh = isfinite(y) ? exp(y) : rb;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      sc->beta *= mult_sh;
-      sc->last_l10 = log10(mult_sh);
-      sc->decisions += 1;
-    }
-  }
-  if (tid == 0) sc->kkt_prev = kkt;
+  control_block(sc, kkt_out[0], beta_mode, rb_mu, rb_tau, tol, w, ymax, decide, hist, hist_cap, hist_base);
 }
 
 // ---------------------------------------------------------------------------

@@ -31,7 +31,8 @@ EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_so
             "rac_solver_info", "rac_solver_features", "rac_solver_scale_beta", "rac_state_export",
             "rac_state_import",
             "rac_permutation", "rac_kkt", "rac_objective", "rac_regression_c", "rac_block_matrices",
-            "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_status_str"]
+            "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_batch_create",
+            "rac_batch_destroy", "rac_batch_run", "rac_batch_lane", "rac_batch_info", "rac_status_str"]
 
 
 class RacError(RuntimeError):
@@ -56,6 +57,18 @@ class Opts_(C.Structure):
                 ("mlp_ymax", C.c_double), ("check_every", C.c_int64), ("max_iter", C.c_int64),
                 ("tol", C.c_double), ("sweep_groups", C.c_int32), ("row_chunks", C.c_int32),
                 ("overlap", C.c_int32), ("pad0", C.c_int32)]
+
+
+class Lane_(C.Structure):
+    _fields_ = [("problem", C.c_int32), ("prox", C.c_int32), ("lam", C.c_double), ("alpha", C.c_double),
+                ("beta0", C.c_double)]
+
+
+class BatchOpts_(C.Structure):
+    _fields_ = [("block_size", C.c_int64), ("seed", C.c_uint64), ("precision", C.c_int32),
+                ("beta_mode", C.c_int32), ("rb_mu", C.c_double), ("rb_tau", C.c_double),
+                ("mlp_weights", C.c_void_p), ("mlp_ymax", C.c_double), ("check_every", C.c_int64),
+                ("max_iter", C.c_int64), ("tol", C.c_double), ("use_graph", C.c_int32), ("tune", C.c_int32)]
 
 
 class Result_(C.Structure):
@@ -104,6 +117,12 @@ def load():
         "rac_mlp_forward": [vp, vp, i64, C.c_float, vp, vp],
         "rac_mlp_loss_grad": [vp, vp, vp, i64, C.c_float, vp, dp, vp],
         "rac_mlp_adam": [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float, C.c_float, vp],
+        "rac_batch_create": [C.c_int32, C.POINTER(Problem_), C.c_int32, C.POINTER(Lane_),
+                             C.POINTER(BatchOpts_), C.POINTER(vp)],
+        "rac_batch_destroy": [vp],
+        "rac_batch_run": [vp, vp, C.POINTER(i64), C.POINTER(C.c_int32)],
+        "rac_batch_lane": [vp, C.c_int32, C.POINTER(Result_), vp, vp, vp],
+        "rac_batch_info": [vp, C.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -419,3 +438,65 @@ def mlp_loss_grad(w, feats, target, ymax=float(np.log(10.0))):
 def mlp_adam(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     _check(load().rac_mlp_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), int(t), float(lr), float(b1),
                                float(b2), float(eps), _stream()), "rac_mlp_adam")
+
+
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Handle around rac_batch: many instances x lanes advanced together.
+
+    lanes: list of (problem index, prox, lambda, alpha, beta0)."""
+
+    def __init__(self, probs, lanes, *, s=64, seed=0, precision=PREC_FP64, beta_mode=BETA_FIXED,
+                 rb_mu=10.0, rb_tau=2.0, mlp_weights=None, mlp_ymax=float(np.log(10.0)), check_every=10,
+                 max_iter=100, tol=0.0, use_graph=True, tune=False):
+        self.lib = load()
+        self.probs = list(probs)
+        self._ps = (Problem_ * len(self.probs))(*[p.struct() for p in self.probs])
+        self._ls = (Lane_ * len(lanes))(*[Lane_(int(a), int(b), float(c), float(d), float(e))
+                                          for a, b, c, d, e in lanes])
+        self.lanes = list(lanes)
+        self._w = mlp_weights
+        o = BatchOpts_(int(s), int(seed), int(precision), int(beta_mode), float(rb_mu), float(rb_tau),
+                       None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax),
+                       int(check_every), int(max_iter), float(tol), 1 if use_graph else 0, 1 if tune else 0)
+        self.opts = o
+        h = C.c_void_p()
+        _check(self.lib.rac_batch_create(len(self.probs), self._ps, len(lanes), self._ls, C.byref(o),
+                                         C.byref(h)), "rac_batch_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.rac_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self):
+        """(iterations run, lanes still active)."""
+        it, act = C.c_int64(), C.c_int32()
+        _check(self.lib.rac_batch_run(self.h, _stream(), C.byref(it), C.byref(act)), "rac_batch_run")
+        return it.value, act.value
+
+    def lane(self, u, allow_not_pd=False):
+        """(Result, x, z, xi) of lane u, vectors as numpy float64."""
+        torch = _torch()
+        n = self.probs[self.lanes[u][0]].n
+        dev = self.probs[0].c.device
+        x, z, xi = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+        r = Result_()
+        code = self.lib.rac_batch_lane(self.h, int(u), C.byref(r), _ptr(x), _ptr(z), _ptr(xi))
+        if code != RAC_OK and not (allow_not_pd and code == RAC_ERR_NOT_PD):
+            raise RacError(code, "rac_batch_lane")
+        res = Result(r.iters, r.status, r.kkt, r.beta, r.objective, r.fail_iter, r.fail_block)
+        return res, x.cpu().numpy(), z.cpu().numpy(), xi.cpu().numpy()
+
+    def info(self):
+        v = (C.c_int64 * 6)()
+        _check(self.lib.rac_batch_info(self.h, v), "rac_batch_info")
+        return dict(lanes=v[0], instances=v[1], gram_tasks=v[2], inverse_tasks=v[3], unroll=v[4], graph=v[5])
