@@ -226,6 +226,22 @@ def regression_problem(D, y, lam=0.0, alpha=1.0, storage="f64", h=None, device="
                    obj_const=yy / (2.0 * N))
 
 
+def regression_problem_tensor(F, y, lam=0.0, alpha=1.0, storage="bf16", h=None) -> Problem:
+    """Elastic net from a device tensor F of shape (n, N) (column-major N x n data)."""
+    torch = _torch()
+    n, N = F.shape
+    dev = F.device
+    yt = torch.as_tensor(np.asarray(y, dtype=np.float64), device=dev)
+    c = torch.empty(n, dtype=torch.float64, device=dev)
+    _check(load().rac_regression_c(C.c_void_p(F.data_ptr()), _DT[storage], N, n, N, float(N),
+                                   _ptr(yt), _ptr(c), _stream()), "rac_regression_c")
+    ht = None if h is None else torch.as_tensor(np.asarray(h, dtype=np.float64), device=dev)
+    yy = float(np.dot(np.asarray(y, dtype=np.float64), np.asarray(y, dtype=np.float64)))
+    return Problem(F=F, storage=storage, rows=int(N), n=int(n), Ns=float(N), c=c, h=ht,
+                   prox=PROX_EN if lam > 0 else PROX_NONE, lam=float(lam), alpha=float(alpha),
+                   obj_const=yy / (2.0 * N))
+
+
 def svm_problem(X, labels, Cbox, storage="f32", device="cuda") -> Problem:
     """C-SVC dual (Sec.3.2), linear kernel: F = G' with G = diag(y) X, c = -e, a = y, box [0, C]."""
     torch = _torch()

@@ -194,3 +194,46 @@ def lasso_10000x100000(storage="bf16"):
     """High-dimensional LASSO, D 10000x100000 (BF16), 1% non-zeros, lambda = 0.05 lambda_max, s = 128."""
     return gaussian_en(10000, 100000, 0.01, 0.05, 0.05, 1.0, 5, 128, storage,
                        name="lasso_10000x100000")
+
+
+# Device-side generation for the large batched workload -------------------------
+
+@dataclass
+class DeviceRegression:
+    """One instance generated on the GPU: F (n x N tensor, i.e. column-major N x n), y on the host."""
+    F: object
+    y: np.ndarray
+    lam_max: float
+    storage: str
+
+    @property
+    def N(self):
+        return int(self.F.shape[1])
+
+    @property
+    def n(self):
+        return int(self.F.shape[0])
+
+    def host_D(self):
+        """The instance's data as a float64 N x n array (exact copy of the stored values)."""
+        return np.asfortranarray(self.F.float().cpu().numpy().T.astype(np.float64))
+
+
+def en_instance_device(N, n, seed, nnz_frac=0.1, noise=0.05, alpha=0.5, storage="bf16", device="cuda"):
+    """Gaussian design N x n drawn with torch's seeded generator on the device, rounded once to
+    `storage` (round to nearest even); x_true has nnz_frac non-zeros drawn N(0,1); y = D x_true +
+    noise N(0,1); lam_max = |D'y|_inf / (N alpha).  Same values on every run for a given seed."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    dt = {"bf16": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}[storage]
+    F = torch.randn((n, N), generator=g, device=device, dtype=torch.float32).to(dt)
+    rng = np.random.default_rng(seed)
+    nnz = max(1, int(round(nnz_frac * n)))
+    xt = np.zeros(n)
+    xt[rng.choice(n, size=nnz, replace=False)] = rng.standard_normal(nnz)
+    xd = torch.as_tensor(xt, device=device)
+    y = (F.double().T @ xd).cpu().numpy() + noise * rng.standard_normal(N)
+    yd = torch.as_tensor(y, device=device)
+    lam_max = float(torch.max(torch.abs(F.double() @ yd)).item()) / (N * alpha)
+    return DeviceRegression(F.contiguous(), y, lam_max, storage)
