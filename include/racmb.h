@@ -254,9 +254,21 @@ typedef struct {
   int64_t max_iter;     /* iteration budget of one rac_batch_run call */
   double tol;           /* a lane retires at its first check with KKT <= tol */
   int32_t use_graph;    /* 1: capture a chunk of T iterations in a hipGraph and replay it */
-  int32_t tune;         /* 1: time the sweep variants on this batch and keep the fastest
-                           (cached per batch shape); 0: default variant */
+  int32_t tune;         /* 1: time the sweep's launch layouts on this batch and keep the
+                           fastest (cached per batch shape); 0: default layout.  Tuning
+                           never changes results. */
+  int32_t sweep;        /* sweep kernel: RAC_BSWEEP_AUTO, RAC_BSWEEP_LANE or RAC_BSWEEP_TEAM */
+  int32_t pad0;
 } rac_batch_opts;
+/* Batched sweep kernels.  LANE: one workgroup per lane, which reads its instance's
+ * data on its own.  TEAM: the lanes of an instance in groups of up to 16, advanced
+ * together by a team of 16 or 32 workgroups that split the instance's rows, so one
+ * read of the data serves the whole group (FP64 matrix-core products); it needs
+ * rows_i <= 32 * 64 * NT for every instance (NT = 16 for BF16 data, 8 otherwise).
+ * AUTO takes TEAM when the batch fits it, else LANE.  Requesting TEAM for a batch
+ * that does not fit gives RAC_ERR_UNSUPPORTED.  The two kernels sum in different
+ * orders, so their results agree to rounding, not bitwise. */
+enum { RAC_BSWEEP_AUTO = 0, RAC_BSWEEP_LANE = 1, RAC_BSWEEP_TEAM = 2 };
 
 /* ninst problems (device data borrowed until rac_batch_destroy), nlanes lanes (host). */
 rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlanes, const rac_lane* lanes,
@@ -269,8 +281,9 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
  * any may be NULL).  res->status is the lane's rac_run_status (RAC_ERR_NOT_PD is
  * returned when one of its blocks violated Assumption 2.1). */
 rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x, double* z, double* xi);
-/* info (host, 6 int64): lanes, instances, block Gram tasks, inverse tasks, chosen
- * sweep row unroll, 1 if chunks are replayed from a hipGraph. */
+/* info (host, 8 int64): lanes, instances, block Gram tasks, inverse tasks, row
+ * unroll of the LANE sweep, 1 if chunks are replayed from a hipGraph, workgroups per
+ * team of the TEAM sweep (0 when the LANE sweep runs), number of teams. */
 rac_status rac_batch_info(rac_batch b, int64_t* info);
 
 const char* rac_status_str(rac_status s);

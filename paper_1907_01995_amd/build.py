@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libracmb.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["perm.hip", "assemble.hip", "sweep.hip", "update.hip", "mlp.hip", "batch.hip", "solver.cpp",
+SOURCES = ["perm.hip", "assemble.hip", "sweep.hip", "update.hip", "mlp.hip", "batch.hip", "tsweep.hip", "solver.cpp",
            "batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

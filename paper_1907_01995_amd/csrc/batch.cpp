@@ -1,6 +1,7 @@
 // batch.cpp -- host side of the batched engine: validation, descriptor tables,
-// workspace, the per-chunk launch sequence (optionally captured once in a
-// hipGraph and replayed), and the autotuner for the sweep's row unroll.
+// lane groups and team layout of the team sweep, workspace, the per-chunk launch
+// sequence (optionally captured once in a hipGraph and replayed), and the
+// autotuner (team layout of the team sweep, row unroll of the per-lane sweep).
 //
 // A chunk of T iterations is: partitions of every active instance for the T
 // iterations; then per iteration the shared block Grams, the per-lane block
@@ -9,12 +10,14 @@
 // lanes) per chunk.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "rac_internal.h"
@@ -86,6 +89,15 @@ struct rac_batch_s {
   hipGraphExec_t gexec = nullptr;
   bool graph_used = false;
   std::string tune_key;
+  // team sweep: lane groups, their LPT costs, and the current team layout
+  bool team = false;
+  TeamArgs TA{};
+  std::vector<TGroup> hgroups;
+  std::vector<double> gcost;
+  int max_teams = 0;
+  TGroup* dgroups = nullptr;
+  int32_t* dteam_off = nullptr;
+  int32_t* dteam_list = nullptr;
 };
 
 namespace {
@@ -99,7 +111,8 @@ rac_status enqueue_chunk(rac_batch b, int Tc, hipStream_t st) {
                     const_cast<double*>(a.G)};
     BCHK(launch_bgram(g, st));
     BCHK(launch_binv(a, t, st));
-    BCHK(launch_bsweep(a, t, st));
+    if (b->team) BCHK(launch_tsweep(a, b->TA, t, st));
+    else BCHK(launch_bsweep(a, t, st));
     BCHK(launch_bzdual(a, st));
   }
   BCHK(launch_bcheck(a, Tc, Tc == b->T ? 1 : 0, st));
@@ -135,15 +148,120 @@ rac_status state_copy(rac_batch b, bool save, Snapshot& s) {
   return RAC_OK;
 }
 
+// Team layout: the lane groups dealt to nteams teams by longest-processing-time
+// first on their cost (a deterministic function of the batch), uploaded for the
+// sweep.  The layout decides only which workgroups run a group, never its
+// arithmetic, so every layout gives bit-identical results.
+rac_status set_team_layout(rac_batch b, int nteams, int xcd_map) {
+  const int ng = (int)b->hgroups.size();
+  std::vector<int> order(ng);
+  for (int g = 0; g < ng; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->gcost[x] > b->gcost[y]; });
+  std::vector<double> load(nteams, 0.0);
+  std::vector<std::vector<int32_t>> lists(nteams);
+  for (int g : order) {
+    int best = 0;
+    for (int k = 1; k < nteams; ++k)
+      if (load[k] < load[best]) best = k;
+    load[best] += b->gcost[g];
+    lists[best].push_back(g);
+  }
+  std::vector<int32_t> off(nteams + 1, 0), flat;
+  for (int k = 0; k < nteams; ++k) {
+    off[k] = (int32_t)flat.size();
+    flat.insert(flat.end(), lists[k].begin(), lists[k].end());
+  }
+  off[nteams] = (int32_t)flat.size();
+  BCHK(hipMemcpy(b->dteam_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(b->dteam_list, flat.data(), sizeof(int32_t) * flat.size(), hipMemcpyHostToDevice));
+  b->TA.nteams = nteams;
+  b->TA.xcd_map = xcd_map;
+  if (b->gexec) {   // a captured graph holds the old launch configuration
+    (void)hipGraphExecDestroy(b->gexec);
+    (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+  }
+  return RAC_OK;
+}
+
+// Default team layout: as many teams as fit (a multiple of 8 so that each team
+// stays on one XCD), but no more than the groups need.
+void default_layout(rac_batch b, int& nteams, int& xcd) {
+  const int ng = (int)b->hgroups.size();
+  nteams = b->max_teams;
+  xcd = b->max_teams % 8 == 0 ? 1 : 0;
+  if (xcd) {
+    const int need = (ng + 7) / 8 * 8;
+    if (need < nteams) nteams = need;
+  } else if (ng < nteams) {
+    nteams = ng;
+  }
+}
+
+// Time one chunk with each team layout (from the same state) and keep the fastest.
+rac_status autotune_team(rac_batch b) {
+  const std::string path = tune_cache_path();
+  int nt0 = 0, x0 = 0;
+  default_layout(b, nt0, x0);
+  std::vector<std::pair<int, int>> cand = {{nt0, x0}};
+  if (x0) cand.push_back({nt0, 0});
+  if (x0 && nt0 / 2 >= 8 && (nt0 / 2) % 8 == 0) cand.push_back({nt0 / 2, 1});
+  if (FILE* f = std::fopen(path.c_str(), "r")) {
+    char line[640], key[512];
+    int a = 0, c = 0;
+    while (std::fgets(line, sizeof(line), f))
+      if (std::sscanf(line, "%511s %d %d", key, &a, &c) == 3)
+        for (auto& cd : cand)
+          if (b->tune_key == key && cd.first == a && cd.second == c) {
+            std::fclose(f);
+            return set_team_layout(b, a, c);
+          }
+    std::fclose(f);
+  }
+  Snapshot snap;
+  rac_status r = state_copy(b, true, snap);
+  if (r != RAC_OK) return r;
+  hipEvent_t e0, e1;
+  BCHK(hipEventCreate(&e0));
+  BCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  std::pair<int, int> pick = cand[0];
+  for (auto& cd : cand) {
+    r = set_team_layout(b, cd.first, cd.second);
+    if (r != RAC_OK) return r;
+    BCHK(hipEventRecord(e0, b->cs));
+    r = enqueue_chunk(b, b->T, b->cs);
+    if (r != RAC_OK) return r;
+    BCHK(hipEventRecord(e1, b->cs));
+    BCHK(hipEventSynchronize(e1));
+    uint32_t aborted = 0;
+    BCHK(hipMemcpy(&aborted, b->TA.abort_flag, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (aborted) return RAC_ERR_DEVICE;
+    float ms = 0.f;
+    BCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; pick = cd; }
+    r = state_copy(b, false, snap);
+    if (r != RAC_OK) return r;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (FILE* f = std::fopen(path.c_str(), "a")) {
+    std::fprintf(f, "%s %d %d\n", b->tune_key.c_str(), pick.first, pick.second);
+    std::fclose(f);
+  }
+  return set_team_layout(b, pick.first, pick.second);
+}
+
 // Time one chunk with each sweep row unroll on this batch (from the same
 // state), keep the fastest, and remember it per batch shape.
 rac_status autotune(rac_batch b) {
   const std::string path = tune_cache_path();
   if (FILE* f = std::fopen(path.c_str(), "r")) {
-    char key[512];
+    char line[640], key[512];
     int un = 0;
-    while (std::fscanf(f, "%511s %d", key, &un) == 2)
-      if (b->tune_key == key && (un == 1 || un == 2 || un == 4)) {
+    while (std::fgets(line, sizeof(line), f))
+      if (std::sscanf(line, "%511s %d", key, &un) == 2 && b->tune_key == key && (un == 1 || un == 2 || un == 4)) {
         b->A.unroll = un;
         std::fclose(f);
         return RAC_OK;
@@ -196,6 +314,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
   if (O.beta_mode != RAC_BETA_FIXED && O.beta_mode != RAC_BETA_RESBAL && O.beta_mode != RAC_BETA_MLP)
     return RAC_ERR_ARG;
   if (O.beta_mode == RAC_BETA_MLP && !O.mlp_weights) return RAC_ERR_ARG;
+  if (O.sweep != RAC_BSWEEP_AUTO && O.sweep != RAC_BSWEEP_LANE && O.sweep != RAC_BSWEEP_TEAM) return RAC_ERR_ARG;
   if (O.rb_mu <= 0.0) O.rb_mu = 10.0;
   if (O.rb_tau <= 0.0) O.rb_tau = 2.0;
   if (!(O.mlp_ymax > 0.0)) O.mlp_ymax = std::log(10.0);
@@ -218,6 +337,9 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
     const rac_problem& P = inst[L.problem];
     if (L.prox == RAC_PROX_BOX && !(P.lo <= P.hi)) return RAC_ERR_ARG;
   }
+  // the caller's pending work (e.g. the kernels that produced F) completes before
+  // any of the batch's own streams touches the data
+  if (hipDeviceSynchronize() != hipSuccess) return RAC_ERR_DEVICE;
   rac_batch b = new (std::nothrow) rac_batch_s();
   if (!b) return RAC_ERR_NOMEM;
   auto fail = [&](rac_status r) {
@@ -312,14 +434,80 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
       hipMemset(A.U, 0, sizeof(double) * uoff) != hipSuccess)
     return fail(RAC_ERR_DEVICE);
   b->host_active = nlanes;
+  // ---- team sweep: lane groups (up to 16 lanes of one instance), team size, tiles
+  if (O.sweep != RAC_BSWEEP_LANE) {
+    std::vector<std::vector<int>> by_inst(ninst);
+    for (int u = 0; u < nlanes; ++u) by_inst[lanes[u].problem].push_back(u);
+    int64_t maxrows = 0;
+    for (int i = 0; i < ninst; ++i)
+      if (!by_inst[i].empty() && inst[i].rows > maxrows) maxrows = inst[i].rows;
+    const int ntmax = dtype == RAC_DT_BF16 ? 16 : 8;
+    int W = 0, NT = 0;
+    for (int cw : {16, 32}) {
+      const int64_t need = (maxrows + cw - 1) / cw + 15;
+      if (need <= 64 * ntmax) {
+        W = cw;
+        NT = need <= 64 * 8 ? 8 : 16;
+        break;
+      }
+    }
+    const int resident = W ? tsweep_max_resident(dtype, NT) : 0;
+    int maxt = W ? resident / W : 0;
+    if (maxt >= 8) maxt -= maxt % 8;
+    if (maxt >= 1) {
+      const int esz = dtype == RAC_DT_F64 ? 8 : (dtype == RAC_DT_F32 ? 4 : 2);
+      for (int i = 0; i < ninst; ++i) {
+        const rac_problem& P = inst[i];
+        const int vec4 = (P.ldF % 4 == 0) && ((uintptr_t)P.F % (uintptr_t)(4 * esz) == 0);
+        const int64_t rw = (P.rows + W - 1) / W;
+        const double cost = (double)b->hinst[i].p * (double)((rw + 63) / 64 + 3);
+        for (size_t g0 = 0; g0 < by_inst[i].size(); g0 += 16) {
+          TGroup G{};
+          G.inst = i;
+          G.nl = (int32_t)std::min<size_t>(16, by_inst[i].size() - g0);
+          G.vec4 = vec4;
+          for (int q = 0; q < 16; ++q) G.lane[q] = q < G.nl ? by_inst[i][g0 + q] : -1;
+          b->hgroups.push_back(G);
+          b->gcost.push_back(cost);
+        }
+      }
+      const int ng = (int)b->hgroups.size();
+      b->max_teams = maxt;
+      b->TA.W = W;
+      b->TA.NT = NT;
+      ok = b->buf.alloc(&b->dgroups, ng) && b->buf.alloc(&b->dteam_off, maxt + 1) &&
+           b->buf.alloc(&b->dteam_list, ng) && b->buf.alloc(&b->TA.part, (size_t)maxt * 2 * W * 1024) &&
+           b->buf.alloc(&b->TA.delta, (size_t)maxt * 2 * 1024) && b->buf.alloc(&b->TA.flags, (size_t)maxt * 128) &&
+           b->buf.alloc(&b->TA.abort_flag, 1);
+      if (!ok) return fail(RAC_ERR_NOMEM);
+      if (hipMemcpy(b->dgroups, b->hgroups.data(), sizeof(TGroup) * ng, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemset(b->TA.flags, 0, sizeof(uint32_t) * (size_t)maxt * 128) != hipSuccess ||
+          hipMemset(b->TA.abort_flag, 0, sizeof(uint32_t)) != hipSuccess)
+        return fail(RAC_ERR_DEVICE);
+      b->TA.groups = b->dgroups;
+      b->TA.team_off = b->dteam_off;
+      b->TA.team_list = b->dteam_list;
+      b->team = true;
+      int nt = 0, xcd = 0;
+      default_layout(b, nt, xcd);
+      const rac_status r = set_team_layout(b, nt, xcd);
+      if (r != RAC_OK) return fail(r);
+    } else if (O.sweep == RAC_BSWEEP_TEAM) {
+      return fail(RAC_ERR_UNSUPPORTED);
+    }
+  }
   if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) return fail(RAC_ERR_DEVICE);
   if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return fail(RAC_ERR_DEVICE);
   char key[256];
-  std::snprintf(key, sizeof(key), "bsweep:dt%d:sp%d:lanes%d:rows%lld:T%d:gfx950", dtype, b->SP, nlanes,
-                (long long)(rows_sum / 1024), b->T);
+  if (b->team)
+    std::snprintf(key, sizeof(key), "tsweep:dt%d:sp%d:lanes%d:groups%d:rows%lld:W%d:NT%d:T%d:gfx950", dtype, b->SP,
+                  nlanes, (int)b->hgroups.size(), (long long)(rows_sum / 1024), b->TA.W, b->TA.NT, b->T);
+  else
+    std::snprintf(key, sizeof(key), "bsweep:dt%d:sp%d:lanes%d:rows%lld:T%d:gfx950", dtype, b->SP, nlanes,
+                  (long long)(rows_sum / 1024), b->T);
   b->tune_key = key;
   if (O.tune) {
-    rac_status r = autotune(b);
+    rac_status r = b->team ? autotune_team(b) : autotune(b);
     if (r != RAC_OK) return fail(r);
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(RAC_ERR_DEVICE);
@@ -366,7 +554,10 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
       if (r != RAC_OK) return r;
     }
     BCHK(hipMemcpyAsync(&b->host_active, b->A.nactive, sizeof(int32_t), hipMemcpyDeviceToHost, b->cs));
+    uint32_t aborted = 0;
+    if (b->team) BCHK(hipMemcpyAsync(&aborted, b->TA.abort_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, b->cs));
     BCHK(hipStreamSynchronize(b->cs));
+    if (aborted) return RAC_ERR_DEVICE;   // a team exchange timed out
     done += Tc;
   }
   b->k += done;
@@ -408,6 +599,8 @@ rac_status rac_batch_info(rac_batch b, int64_t* info) {
   info[3] = b->A.ninv;
   info[4] = b->A.unroll;
   info[5] = b->graph_used ? 1 : 0;
+  info[6] = b->team ? b->TA.W : 0;
+  info[7] = b->team ? b->TA.nteams : 0;
   return RAC_OK;
 }
 

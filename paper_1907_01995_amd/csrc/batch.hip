@@ -100,18 +100,26 @@ __global__ void __launch_bounds__(1024) k_bperm(const BInst* __restrict__ inst, 
 
 // ---------------------------------------------------------------------------
 // Block inverses: one wavefront per (lane, block).  Lane j holds column j of
-// M = G/Ns + diag(h) + beta (I + a a') in registers; at pivot k the pivot
-// column (lane k's registers) is read with readlane, one entry at a time.
-// Pivots are the LDL' (squared Cholesky) pivots; a non-positive one is
-// reported as a failure of Assumption 2.1 for the lane.
+// M = G/Ns + diag(h) + beta (I + a a') in registers and the wavefront applies
+// the symmetric sweep operator to pivots 0..sb-1:
+//   a_ij -= a_ik a_kj / d,  a_kj /= d,  a_ik /= d,  a_kk = -1/d   (d = a_kk),
+// after which the block holds -M^{-1}.  d is the k-th Schur-complement pivot,
+// i.e. the squared Cholesky pivot; a non-positive one is reported as a failure
+// of Assumption 2.1 for the lane.  Because the running matrix stays symmetric,
+// the pivot column a_ik equals the pivot row a_ki, which every lane holds in
+// its own registers: one LDS store per lane gathers it for the whole wavefront.
+// The registers are renumbered after every pivot (register r holds row
+// (r + k) mod SP), so the pivot row is always register 0 and every register
+// index is a compile-time constant.
 template <int SP>
 __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
                                               int ntasks, const int32_t* __restrict__ perm, int t,
                                               const double* __restrict__ G, DevScalars* sc,
                                               double* __restrict__ Minv) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double rowbuf[4][2 * SP];
   const int task = blockIdx.x * 4 + wave;
-  if (task >= ntasks) return;
+  if (task >= ntasks) return;   // wavefront-uniform; the kernel has no workgroup barrier
   const int2 tk = tasks[task];
   if (sc[tk.x].status != 0) return;
   const BUnit U = units[tk.x];
@@ -125,29 +133,31 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
   const double hj = (U.h && j < sb) ? U.h[colj] : 0.0;
   const double aj = (U.a && j < sb) ? U.a[colj] : 0.0;
   const double* Gb = G + (U.goff + blk) * (int64_t)SP * SP;
+  double* buf = rowbuf[wave];
+  if (U.a && j < SP) buf[j] = aj;
+  __builtin_amdgcn_wave_barrier();
   double col[SP];
 #pragma unroll
   for (int i = 0; i < SP; ++i) {
-    const double ai = U.a ? readlane_d(aj, i) : 0.0;   // uniform position: every lane reads lane i
     double v;
     if (i < sb && j < sb) {
       const double g = i >= j ? Gb[i * SP + j] : Gb[j * SP + i];
       v = g / U.Ns;
       if (i == j) v += beta + hj;
-      if (U.a) v += beta * ai * aj;
+      if (U.a) v += beta * buf[i] * aj;
     } else {
       v = (i == j) ? 1.0 : 0.0;
     }
     col[i] = v;
   }
+  __builtin_amdgcn_wave_barrier();
   bool failed = false;
-  for (int k = 0; k < sb; ++k) {            // runtime pivot loop; entries stay in static registers
-    double rraw = 0.0;                      // this lane's entry of the pivot row, M[k][j]
-#pragma unroll
-    for (int i = 0; i < SP; ++i)
-      if (i == k) rraw = col[i];
-    const double piv = readlane_d(rraw, k);
-    if (!(piv > 0.0) || !isfinite(piv)) {
+  for (int k = 0; k < sb; ++k) {
+    const double r = col[0];                    // a_kj
+    if (j < SP) { buf[j] = r; buf[j + SP] = r; }
+    __builtin_amdgcn_wave_barrier();
+    const double d = buf[k];                    // same value in every lane
+    if (!(d > 0.0) || !isfinite(d)) {
       failed = true;
       if (lane == 0) {
         unsigned long long key = ((unsigned long long)sc[tk.x].k << 32) | (unsigned)blk;
@@ -155,21 +165,23 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
       }
       break;
     }
-    const double ip = 1.0 / piv;
-    const double rk = rraw * ip;
+    const double invd = 1.0 / d;
+    const bool piv = j == k;
+    const double keep = piv ? 0.0 : 1.0;
+    const double m = piv ? -invd : r * invd;
 #pragma unroll
-    for (int i = 0; i < SP; ++i) {
-      const double pcol = readlane_d(col[i], k);
-      double nv;
-      if (i == k) nv = (lane == k) ? ip : rk;
-      else nv = (lane == k) ? -pcol * ip : col[i] - pcol * rk;
-      col[i] = nv;
-    }
+    for (int q = 1; q < SP; ++q) col[q - 1] = fma(-buf[k + q], m, keep * col[q]);   // buf[k+q] = a_(k+q mod SP),k
+    col[SP - 1] = m;
+    __builtin_amdgcn_wave_barrier();
   }
   double* out = Minv + (U.moff + blk) * (int64_t)SP * SP;
   if (j < SP) {   // lanes past the padded size hold no column
 #pragma unroll
-    for (int i = 0; i < SP; ++i) out[i * SP + j] = (!failed && i < sb && j < sb) ? col[i] : 0.0;
+    for (int q = 0; q < SP; ++q) {
+      int i = q + sb;                           // register q holds row (q + sb) mod SP
+      if (i >= SP) i -= SP;
+      out[i * SP + j] = (!failed && i < sb && j < sb) ? -col[q] : 0.0;
+    }
   }
 }
 

@@ -136,6 +136,29 @@ struct BatchArgs {         // everything the per-lane kernels of one chunk need
   int32_t beta_mode; double rb_mu, rb_tau, tol; const float* mlp_w; double mlp_ymax;
   int unroll;              // sweep row unroll (autotuned: 1, 2 or 4)
 };
+// Team sweep (tsweep.hip): lane groups of one instance advanced together.
+struct TGroup {            // up to 16 lanes of one instance
+  int32_t inst; int32_t nl;
+  int32_t vec4;            // F columns allow aligned 4-element vector loads
+  int32_t pad;
+  int32_t lane[16];        // lane ids of slots 0 .. nl-1
+};
+struct TeamArgs {
+  const TGroup* groups;
+  const int32_t* team_off; // groups of team k: team_list[team_off[k] .. team_off[k+1])
+  const int32_t* team_list;
+  int nteams; int W;       // teams, workgroups per team (16 or 32)
+  int NT;                  // register tiles of 16 rows per wavefront (8, or 16 for BF16 data)
+  int xcd_map;             // map each team onto one XCD (nteams a multiple of 8)
+  double* part;            // [nteams][2][W][64*16] gradient partials
+  double* delta;           // [nteams][2][16][64] steps
+  uint32_t* flags;         // [nteams][128]: [0, 64) partial epochs, [64, 128) step epochs
+  uint32_t* abort_flag;    // raised when a wait gives up (the batch is then unusable)
+};
+// Workgroups of the team sweep that can be resident at once (0 if NT unsupported).
+int tsweep_max_resident(int32_t dtype, int NT);
+hipError_t launch_tsweep(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st);
+
 hipError_t launch_bperm(const BatchArgs& b, hipStream_t st);
 hipError_t launch_binv(const BatchArgs& b, int t, hipStream_t st);
 hipError_t launch_bsweep(const BatchArgs& b, int t, hipStream_t st);

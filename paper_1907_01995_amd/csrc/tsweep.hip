@@ -1,0 +1,423 @@
+// tsweep.hip -- the batched Gauss-Seidel sweep of Eq.(3) with the lanes of an
+// instance advanced together, so that one read of the instance's data serves
+// every lane.
+//
+// Lanes of one instance share its partition, so for block B the products of a
+// sweep are, for the group's (up to 16) lanes at once,
+//     P = F_B' [u_1 .. u_16]          (gradient partial, block columns x lanes)
+//     [u_1 .. u_16] += F_B [d_1 .. d_16]   (residual update)
+// -- dense contractions over the rows of F, run on the matrix cores in FP64
+// (v_mfma_f64_16x16x4f64: the u vectors and the steps are FP64, so the products
+// are as exact as the single-lane FP64 path).
+//
+// Work split.  A team of W workgroups (W in {16, 32}) processes a list of
+// lane groups one after another; for each group, member w owns a contiguous
+// slice of the instance's rows and holds u of those rows for all 16 lanes in
+// registers for the whole sweep (four wavefronts, 16-row tiles dealt round-robin).  Per block:
+//   1. every member computes its partial P over its rows (FP64 MFMA), reduces
+//      it over its wavefronts in LDS and publishes it (agent-scope relaxed
+//      stores, s_waitcnt, then an epoch flag);
+//   2. lane slot L of the group is owned by member L (wavefront 0):
+//      the owner waits for all partials, sums them in a fixed order, forms the
+//      lane's gradient g_B, applies the lane's block inverse (staged in LDS by
+//      all wavefronts during the previous block's update), updates x_B and t,
+//      and publishes the step d (then a second epoch flag);
+//   3. every member waits for all steps and updates its rows of u (FP64 MFMA,
+//      u as the accumulator).
+// Partials and steps are double-buffered by epoch parity.  The flags are
+// monotone epochs that persist between launches: every member of a team
+// advances its epochs by the same count per launch, so a member's own flag at
+// launch start is the team's base.  Teams are mapped onto one XCD each
+// (workgroup b runs on XCD b mod 8), so that their exchanges stay in one L2.
+// All members of all teams are resident at once (the grid never exceeds the
+// occupancy limit of the device), which every wait relies on.
+#include "rac_internal.h"
+
+namespace rac {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void st_c(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_c(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_flag(const uint32_t* p) {
+  return __hip_atomic_load(const_cast<uint32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The calling wavefront waits until flags[0..W) have all reached epoch e.  The
+// wait is bounded: after kMaxPolls polls (seconds, against microseconds for a
+// real exchange), or as soon as another workgroup has given up, it raises the
+// abort flag and returns false; the kernel then leaves at its next barrier.
+constexpr uint32_t kMaxPolls = 1u << 21;
+__device__ __forceinline__ bool wait_team(const uint32_t* f, int W, uint32_t e, int lane, uint32_t* abort_flag) {
+  for (uint32_t poll = 0;; ++poll) {
+    const bool ok = lane >= W || (int32_t)(ld_flag(f + lane) - e) >= 0;
+    if (__all(ok)) return true;
+    if (poll >= kMaxPolls || ld_flag(abort_flag) != 0u) {
+      if (lane == 0) st_flag(abort_flag, 1u);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+constexpr int NW = 4;          // wavefronts per workgroup (one per SIMD: 512 registers each)
+constexpr int DS = 3;          // pipeline stages of the tile loads
+
+// Raw storage of four consecutive elements of a column of F.
+template <typename T> struct RawQ;
+template <> struct RawQ<uint16_t> { uint2 v; };
+template <> struct RawQ<float> { float4 v; };
+template <> struct RawQ<double> { double2 a, b; };
+
+__device__ __forceinline__ double to_f64(uint16_t v) { return (double)__uint_as_float(((uint32_t)v) << 16); }
+__device__ __forceinline__ double to_f64(float v) { return (double)v; }
+__device__ __forceinline__ double to_f64(double v) { return v; }
+
+// Rows o .. o+3 of a column (nvalid of them in range, the rest zero).  vec: the
+// four elements are one aligned vector (o a multiple of 4, column base aligned).
+template <typename T>
+__device__ __forceinline__ RawQ<T> ld_quad(const T* F, int64_t o, int nvalid, bool vec) {
+  RawQ<T> r;
+  if (vec && nvalid == 4) {
+    r = *reinterpret_cast<const RawQ<T>*>(F + o);
+  } else {
+    T e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = i < nvalid ? F[o + i] : (T)0;
+    if constexpr (sizeof(T) == 2) {
+      r.v.x = (uint32_t)e[0] | ((uint32_t)e[1] << 16);
+      r.v.y = (uint32_t)e[2] | ((uint32_t)e[3] << 16);
+    } else if constexpr (sizeof(T) == 4) {
+      r.v = make_float4(e[0], e[1], e[2], e[3]);
+    } else {
+      r.a = make_double2(e[0], e[1]);
+      r.b = make_double2(e[2], e[3]);
+    }
+  }
+  return r;
+}
+// Element i of a quad, converted exactly to FP64.
+template <typename T>
+__device__ __forceinline__ double quad_at(const RawQ<T>& r, int i) {
+  if constexpr (sizeof(T) == 2) {
+    const uint32_t wv = i < 2 ? r.v.x : r.v.y;
+    return (double)__uint_as_float((i & 1) ? (wv & 0xffff0000u) : (wv << 16));
+  } else if constexpr (sizeof(T) == 4) {
+    return (double)(i == 0 ? r.v.x : i == 1 ? r.v.y : i == 2 ? r.v.z : r.v.w);
+  } else {
+    return i == 0 ? r.a.x : i == 1 ? r.a.y : i == 2 ? r.b.x : r.b.y;
+  }
+}
+
+// Register layout (wavefront v, lane = 16 q + j): tile = v + NW s covers rows
+// rb + 16 tile .. +15; ur[s][i] holds u[rb + 16 tile + 4 q + i] of lane slot j.
+// That is the B operand of the gradient product (k = q, n = j) and, with the
+// update product's row order pi(m) = 4 (m mod 4) + m div 4, exactly its
+// accumulator layout (row 4 r + q of the output is physical row 4 q + r).
+// Both products stream the member's tiles with the next tile's loads issued
+// DS-1 tiles ahead of the current tile's matrix-core work (fenced so that the
+// compiler does not hoist further loads and run out of registers).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, int t) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane >> 4, j = lane & 15;
+  const int W = TA.W;
+  int team, w;
+  if (TA.xcd_map) {
+    const int b = (int)blockIdx.x, slot = b >> 3;
+    team = (slot / W) * 8 + (b & 7);
+    w = slot % W;
+  } else {
+    team = (int)blockIdx.x / W;
+    w = (int)blockIdx.x % W;
+  }
+  uint32_t* fl_part = TA.flags + (int64_t)team * 128;
+  uint32_t* fl_step = fl_part + 64;
+  double* part = TA.part + (int64_t)team * 2 * W * 1024;
+  double* delta = TA.delta + (int64_t)team * 2 * 1024;
+  uint32_t e = ld_flag(fl_part + w);
+  __shared__ double minv_lds[64 * 64];      // block inverse of the owned lane
+  __shared__ double red[NW][16][64];
+  __shared__ double shg[NW][64];
+  __shared__ int32_t cols[64];
+  __shared__ int32_t give_up;
+  if (tid == 0) give_up = 0;
+  const int g0 = TA.team_off[team], g1 = TA.team_off[team + 1];
+  for (int gi = g0; gi < g1; ++gi) {
+    const TGroup* G = TA.groups + TA.team_list[gi];
+    const int nl = G->nl;
+    bool any = false;
+    for (int L = 0; L < nl; ++L) any |= B.sc[G->lane[L]].status == 0;
+    if (!any) continue;                      // same decision in every member
+    const BInst I = B.inst[G->inst];
+    const T* F = (const T*)I.F;
+    const int64_t n = I.n, p = I.p, rows = I.rows, ldF = I.ldF;
+    const bool vec = G->vec4 != 0;
+    const int64_t rb = w == 0 ? 0 : ((rows * w / W) & ~(int64_t)15);
+    const int64_t re = w + 1 == W ? rows : ((rows * (w + 1) / W) & ~(int64_t)15);
+    const int ntile = re > rb ? (int)((re - rb + 15) >> 4) : 0;
+    const int uj = j < nl ? G->lane[j] : -1;
+    const bool actj = uj >= 0 && B.sc[uj].status == 0;
+    double* Uj = actj ? B.U + B.units[uj].uoff : nullptr;
+    double ur[NT][4];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+      const int tile = wave + NW * s;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = rb + 16 * tile + 4 * q + i;
+        ur[s][i] = (actj && tile < ntile && r < re) ? Uj[r] : 0.0;
+      }
+    }
+    // member w owns lane slot L = w (W >= 16, so every slot has one owner); the
+    // owner's wavefront 0 forms the slot's step, and `own` is the same in all of
+    // the member's wavefronts (they stage the slot's block inverses)
+    const int L = w;
+    const int ou = L < nl ? G->lane[L] : -1;
+    const bool own = ou >= 0 && B.sc[ou].status == 0;
+    const BUnit* OU = own ? B.units + ou : nullptr;
+    double obeta = 0.0, omu = 0.0, ot = 0.0, oNs = 1.0, ob = 0.0;
+    if (own) {
+      obeta = B.sc[ou].beta; omu = B.sc[ou].mu; ot = B.sc[ou].t; oNs = OU->Ns; ob = OU->b;
+    }
+    const int32_t* pm = B.perm + I.poff + (int64_t)t * n;
+    const int64_t rpi = 4 * (j & 3) + (j >> 2);       // row pi(j) of a tile in the update product
+    // Block inverse of the owned lane (slot w), staged in LDS one block ahead:
+    // thread tid loads entries tid + 256 i.
+    double pf[16];
+    auto minv_load = [&](int64_t bk) {
+      const int sbk = (int)(block_start(bk + 1, n, p) - block_start(bk, n, p));
+      const double* Mo = own ? B.Minv + (OU->moff + bk) * (int64_t)B.sp * B.sp : nullptr;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int el = tid + 256 * i, k = el >> 6, c = el & 63;
+        pf[i] = (Mo && k < sbk && c < sbk) ? Mo[(int64_t)k * B.sp + c] : 0.0;
+      }
+    };
+    auto minv_store = [&]() {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) minv_lds[tid + 256 * i] = pf[i];
+    };
+    minv_load(0);
+    minv_store();
+    for (int64_t blk = 0; blk < p; ++blk) {
+      const int64_t s0 = block_start(blk, n, p);
+      const int sb = (int)(block_start(blk + 1, n, p) - s0);
+      __syncthreads();                       // the previous block's cols / red are no longer read
+      if (give_up) return;                   // every wavefront leaves together
+      if (tid < sb) cols[tid] = pm[s0 + tid];
+      __syncthreads();
+      ++e;
+      const int par = (int)(e & 1u);
+      // owner: iterate-fixed gradient terms of the lane
+      double gb = 0.0, acol = 0.0;
+      if (own && lane < sb) {
+        const int col = cols[lane];
+        const double xc = B.X[OU->xoff + col];
+        gb = OU->c[col] - B.XI[OU->xoff + col] + obeta * (xc - B.Z[OU->xoff + col]);
+        if (OU->h) gb += OU->h[col] * xc;
+        if (OU->a) { acol = OU->a[col]; gb -= omu * acol; }
+      }
+      // 1. partial F_B' u over this member's rows, all lanes of the group
+      {
+        f64x4 acc[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        RawQ<T> gq[DS][4];
+        auto gload = [&](int s, RawQ<T> (&dst)[4]) {
+          const int tile = wave + NW * s;
+          const int64_t r0 = rb + 16 * tile + 4 * q;
+          const int nv = tile >= ntile ? 0 : (re - r0 >= 4 ? 4 : (re > r0 ? (int)(re - r0) : 0));
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            const int c = 16 * ct + j;
+            const bool cv = c < sb && nv > 0;
+            dst[ct] = ld_quad<T>(F, cv ? (int64_t)cols[c] * ldF + r0 : 0, cv ? nv : 0, vec);
+          }
+        };
+#pragma unroll
+        for (int s = 0; s < DS - 1 && s < NT; ++s) gload(s, gq[s]);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+          if (s + DS - 1 < NT) gload(s + DS - 1, gq[(s + DS - 1) % DS]);
+          if (wave + NW * s < ntile) {
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(quad_at<T>(gq[s % DS][ct], i), ur[s][i],
+                                                               acc[ct], 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        // acc[ct][r] of lane (q, j) = P[column 16 ct + 4 r + q][slot j]
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wave][4 * ct + r][lane] = acc[ct][r];
+      }
+      __syncthreads();
+      {
+        const int ln = tid & 63, qq = ln >> 4, jj = ln & 15;
+        double* dst = part + ((int64_t)par * W + w) * 1024;
+#pragma unroll
+        for (int rr = 0; rr < 16 / NW; ++rr) {
+          const int el = (16 / NW) * (tid >> 6) + rr;          // = 4 ct + r
+          double v = 0.0;
+#pragma unroll
+          for (int vv = 0; vv < NW; ++vv) v += red[vv][el][ln];
+          const int col = 16 * (el >> 2) + 4 * (el & 3) + qq;
+          st_c(dst + col * 16 + jj, v);
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);         // partial stores complete at device scope
+      __syncthreads();
+      if (tid == 0) st_flag(fl_part + w, e);
+      // 2. owners: full gradient (fixed member order), step, x_B, t
+      if (own && wave == 0) {
+        if (!wait_team(fl_part, W, e, lane, TA.abort_flag) && lane == 0) give_up = 1;
+        double s = 0.0;
+        if (lane < sb) {
+          const double* pp = part + (int64_t)par * W * 1024 + lane * 16 + L;
+          for (int m0 = 0; m0 < W; m0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) v[m] = m0 + m < W ? ld_c(pp + (int64_t)(m0 + m) * 1024) : 0.0;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) s += v[m];
+          }
+        }
+        double g = s / oNs + gb;
+        if (OU->a) g += obeta * acol * (ot - ob);
+        shg[wave][lane] = lane < sb ? g : 0.0;
+        __builtin_amdgcn_wave_barrier();
+        const double* Ml = minv_lds;
+        double d = 0.0;
+#pragma unroll 16
+        for (int k = 0; k < 64; ++k) d += Ml[k * 64 + lane] * shg[wave][k];
+        d = lane < sb ? -d : 0.0;
+        if (lane < sb) B.X[OU->xoff + cols[lane]] += d;
+        if (OU->a) ot += wave_sum(acol * d);
+        st_c(delta + ((int64_t)par * 16 + L) * 64 + lane, d);
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+      __syncthreads();
+      if (give_up) return;
+      if (tid == 0) st_flag(fl_step + w, e);
+      // 3. every member: steps of all lanes, then its rows of u
+      if (!wait_team(fl_step, W, e, lane, TA.abort_flag) && lane == 0) give_up = 1;
+      {
+        double dreg[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+          dreg[m] = actj ? ld_c(delta + ((int64_t)par * 16 + j) * 64 + 4 * m + q) : 0.0;
+        if (blk + 1 < p) minv_load(blk + 1);     // owners are done with this block's inverse
+        T uq[DS][16];
+        auto uload = [&](int s, T (&dst)[16]) {
+          const int tile = wave + NW * s;
+          const int64_t rr = rb + 16 * tile + rpi;
+          const bool rv = tile < ntile && rr < re;
+#pragma unroll
+          for (int m = 0; m < 16; ++m) {
+            const int c = 4 * m + q;
+            dst[m] = (rv && c < sb) ? F[(int64_t)cols[c] * ldF + rr] : (T)0;
+          }
+        };
+#pragma unroll
+        for (int s = 0; s < DS - 1 && s < NT; ++s) uload(s, uq[s]);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+          if (s + DS - 1 < NT) uload(s + DS - 1, uq[(s + DS - 1) % DS]);
+          if (wave + NW * s < ntile) {
+            f64x4 a4 = {ur[s][0], ur[s][1], ur[s][2], ur[s][3]};
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+              a4 = __builtin_amdgcn_mfma_f64_16x16x4f64(to_f64(uq[s % DS][m]), dreg[m], a4, 0, 0, 0);
+            ur[s][0] = a4[0]; ur[s][1] = a4[1]; ur[s][2] = a4[2]; ur[s][3] = a4[3];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (blk + 1 < p) minv_store();           // read after the next block's first barrier
+      }
+    }
+    // the group's u back to memory, and t of the owned lane
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+      const int tile = wave + NW * s;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = rb + 16 * tile + 4 * q + i;
+        if (actj && tile < ntile && r < re) Uj[r] = ur[s][i];
+      }
+    }
+    if (own && wave == 0 && lane == 0 && OU->a) B.sc[ou].t = ot;   // wavefront 0 carried t
+  }
+}
+
+template <typename T, int NT>
+int tsweep_resident_t() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_tsweep<T, NT>, NW * 64, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
+
+template <typename T>
+int tsweep_resident_nt(int NT) {
+  switch (NT) {
+    case 8: return tsweep_resident_t<T, 8>();
+    case 16:   // sixteen tiles fit the register file only with two-byte data
+      if constexpr (sizeof(T) == 2) return tsweep_resident_t<T, 16>();
+      return 0;
+    default: return 0;
+  }
+}
+
+template <typename T, int NT>
+hipError_t tsweep_go(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st) {
+  k_tsweep<T, NT><<<(unsigned)(ta.nteams * ta.W), NW * 64, 0, st>>>(b, ta, t);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t tsweep_launch(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st) {
+  switch (ta.NT) {
+    case 8: return tsweep_go<T, 8>(b, ta, t, st);
+    case 16:
+      if constexpr (sizeof(T) == 2) return tsweep_go<T, 16>(b, ta, t, st);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int tsweep_max_resident(int32_t dtype, int NT) {
+  switch (dtype) {
+    case RAC_DT_F64: return tsweep_resident_nt<double>(NT);
+    case RAC_DT_F32: return tsweep_resident_nt<float>(NT);
+    case RAC_DT_BF16: return tsweep_resident_nt<uint16_t>(NT);
+    default: return 0;
+  }
+}
+
+hipError_t launch_tsweep(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st) {
+  switch (b.dtype) {
+    case RAC_DT_F64: return tsweep_launch<double>(b, ta, t, st);
+    case RAC_DT_F32: return tsweep_launch<float>(b, ta, t, st);
+    case RAC_DT_BF16: return tsweep_launch<uint16_t>(b, ta, t, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rac

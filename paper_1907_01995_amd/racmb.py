@@ -22,6 +22,7 @@ PROX_NONE, PROX_EN, PROX_BOX = 0, 1, 2
 DT_F64, DT_F32, DT_BF16 = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 BETA_FIXED, BETA_RESBAL, BETA_MLP, BETA_SCHEDULE = 0, 1, 2, 3
+BSWEEP_AUTO, BSWEEP_LANE, BSWEEP_TEAM = 0, 1, 2
 MAX_BLOCK = 128
 MLP_IN, MLP_HIDDEN = 8, 64
 MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -68,7 +69,8 @@ class BatchOpts_(C.Structure):
     _fields_ = [("block_size", C.c_int64), ("seed", C.c_uint64), ("precision", C.c_int32),
                 ("beta_mode", C.c_int32), ("rb_mu", C.c_double), ("rb_tau", C.c_double),
                 ("mlp_weights", C.c_void_p), ("mlp_ymax", C.c_double), ("check_every", C.c_int64),
-                ("max_iter", C.c_int64), ("tol", C.c_double), ("use_graph", C.c_int32), ("tune", C.c_int32)]
+                ("max_iter", C.c_int64), ("tol", C.c_double), ("use_graph", C.c_int32), ("tune", C.c_int32),
+                ("sweep", C.c_int32), ("pad0", C.c_int32)]
 
 
 class Result_(C.Structure):
@@ -465,7 +467,7 @@ class Batch:
 
     def __init__(self, probs, lanes, *, s=64, seed=0, precision=PREC_FP64, beta_mode=BETA_FIXED,
                  rb_mu=10.0, rb_tau=2.0, mlp_weights=None, mlp_ymax=float(np.log(10.0)), check_every=10,
-                 max_iter=100, tol=0.0, use_graph=True, tune=False):
+                 max_iter=100, tol=0.0, use_graph=True, tune=False, sweep=BSWEEP_AUTO):
         self.lib = load()
         self.probs = list(probs)
         self._ps = (Problem_ * len(self.probs))(*[p.struct() for p in self.probs])
@@ -475,7 +477,8 @@ class Batch:
         self._w = mlp_weights
         o = BatchOpts_(int(s), int(seed), int(precision), int(beta_mode), float(rb_mu), float(rb_tau),
                        None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax),
-                       int(check_every), int(max_iter), float(tol), 1 if use_graph else 0, 1 if tune else 0)
+                       int(check_every), int(max_iter), float(tol), 1 if use_graph else 0, 1 if tune else 0,
+                       int(sweep), 0)
         self.opts = o
         h = C.c_void_p()
         _check(self.lib.rac_batch_create(len(self.probs), self._ps, len(lanes), self._ls, C.byref(o),
@@ -513,6 +516,7 @@ class Batch:
         return res, x.cpu().numpy(), z.cpu().numpy(), xi.cpu().numpy()
 
     def info(self):
-        v = (C.c_int64 * 6)()
+        v = (C.c_int64 * 8)()
         _check(self.lib.rac_batch_info(self.h, v), "rac_batch_info")
-        return dict(lanes=v[0], instances=v[1], gram_tasks=v[2], inverse_tasks=v[3], unroll=v[4], graph=v[5])
+        return dict(lanes=v[0], instances=v[1], gram_tasks=v[2], inverse_tasks=v[3], unroll=v[4], graph=v[5],
+                    team_size=v[6], teams=v[7])

@@ -47,13 +47,17 @@ def oracle_lane(op, lane, **kw):
     return O.solve(P, inst=i, beta0=beta0, **kw)
 
 
-def test_batch_lanes_match_oracle_fp64():
+@pytest.mark.parametrize("sweep", [racmb.BSWEEP_TEAM, racmb.BSWEEP_LANE])
+def test_batch_lanes_match_oracle_fp64(sweep):
     ws, gps, ops, lanes = en_batch()
-    say("batch fp64", len(lanes), "lanes")
-    b = racmb.Batch(gps, lanes, s=32, seed=7, max_iter=30, check_every=10, use_graph=True)
+    say("batch fp64", len(lanes), "lanes, sweep", sweep)
+    b = racmb.Batch(gps, lanes, s=32, seed=7, max_iter=30, check_every=10, use_graph=True, sweep=sweep)
     it, act = b.run()
     assert it == 30 and act == len(lanes)
-    assert b.info()["graph"] == 1
+    info = b.info()
+    say(info)
+    assert info["graph"] == 1
+    assert (info["team_size"] > 0) == (sweep == racmb.BSWEEP_TEAM)
     for u, lane in enumerate(lanes):
         res, x, z, xi = b.lane(u)
         ref = oracle_lane(ops[lane[0]], lane, s=32, seed=7, max_iter=30, check_every=10)
@@ -139,3 +143,47 @@ def test_batch_reports_assumption_failure_per_lane():
         else:
             ref = oracle_lane(ops[0], lane, s=32, seed=3, max_iter=20, check_every=10)
             assert res.fail_iter == -1 and rel(z, ref.z) < 1e-8
+
+
+def test_team_and_lane_sweeps_agree_on_uneven_groups():
+    """More than 16 lanes of one instance (two groups), uneven instance sizes, an
+    instance with rows just past a team's tile boundaries, BF16 data: the team
+    sweep (FP64 matrix-core products) and the per-lane sweep agree to rounding,
+    and the team sweep is deterministic."""
+    rng = np.random.default_rng(21)
+    shapes = [(1000, 150), (517, 64), (2051, 97), (33, 40)]
+    gps, lanes = [], []
+    for i, (N, n) in enumerate(shapes):
+        w = W.gaussian_en(N, n, 0.1, 0.05, 0.1, 0.5, 200 + i, 32, "bf16")
+        gps.append(racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=0.5, storage="bf16"))
+        nl = 19 if i == 0 else 3
+        for k in range(nl):
+            lam = w.lam * 2.0 ** (2 - k * 0.5)
+            lanes.append((i, racmb.PROX_EN, lam, 0.5, float(10 ** rng.uniform(-1.0, 0.5))))
+    outs = []
+    for sweep in (racmb.BSWEEP_TEAM, racmb.BSWEEP_TEAM, racmb.BSWEEP_LANE):
+        b = racmb.Batch(gps, lanes, s=32, seed=3, precision=racmb.PREC_MIXED, beta_mode=racmb.BETA_RESBAL,
+                        max_iter=60, check_every=10, use_graph=True, sweep=sweep)
+        b.run()
+        say("sweep", sweep, b.info())
+        outs.append([b.lane(u)[1:] for u in range(len(lanes))])
+        b.close()
+    for u in range(len(lanes)):
+        for a, c in zip(outs[0][u], outs[1][u]):
+            assert np.array_equal(a, c)                        # deterministic
+        for a, c in zip(outs[0][u], outs[2][u]):
+            assert rel(a, c) < 1e-9, (u, rel(a, c))            # same iteration, other summation order
+
+
+def test_team_sweep_svm_lanes_with_equality_row():
+    wv = [W.svm(n=int(n), r=12, block_size=32, data_seed=60 + k) for k, n in enumerate((300, 517))]
+    gps = [racmb.svm_problem(w.X, w.labels, w.C) for w in wv]
+    ops = [O.svm_problem(w.X.astype(np.float64), w.labels, w.C) for w in wv]
+    lanes = [(k % 2, racmb.PROX_BOX, 0.0, 1.0, 0.3 + 0.4 * k) for k in range(5)]
+    b = racmb.Batch(gps, lanes, s=32, seed=6, max_iter=40, check_every=10, use_graph=True,
+                    sweep=racmb.BSWEEP_TEAM)
+    b.run()
+    for u, lane in enumerate(lanes):
+        res, x, z, xi = b.lane(u)
+        ref = oracle_lane(ops[lane[0]], lane, s=32, seed=6, max_iter=40, check_every=10)
+        assert rel(x, ref.x) < 1e-8 and rel(z, ref.z) < 1e-8 and rel(xi, ref.xi) < 1e-8, u
