@@ -264,7 +264,7 @@ typedef struct {
  * data on its own.  TEAM: the lanes of an instance in groups of up to 16, advanced
  * together by a team of 16 or 32 workgroups that split the instance's rows, so one
  * read of the data serves the whole group (FP64 matrix-core products); it needs
- * rows_i <= 32 * 64 * NT for every instance (NT = 16 for BF16 data, 8 otherwise).
+ * rows_i <= 32 * (64 * NT - 15) for every instance (NT = 10 for BF16 data, 8 otherwise).
  * AUTO takes TEAM when the batch fits it, else LANE.  Requesting TEAM for a batch
  * that does not fit gives RAC_ERR_UNSUPPORTED.  The two kernels sum in different
  * orders, so their results agree to rounding, not bitwise. */

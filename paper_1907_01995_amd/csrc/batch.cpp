@@ -441,13 +441,13 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
     int64_t maxrows = 0;
     for (int i = 0; i < ninst; ++i)
       if (!by_inst[i].empty() && inst[i].rows > maxrows) maxrows = inst[i].rows;
-    const int ntmax = dtype == RAC_DT_BF16 ? 16 : 8;
+    const int ntmax = dtype == RAC_DT_BF16 ? 10 : 8;
     int W = 0, NT = 0;
     for (int cw : {16, 32}) {
       const int64_t need = (maxrows + cw - 1) / cw + 15;
       if (need <= 64 * ntmax) {
         W = cw;
-        NT = need <= 64 * 8 ? 8 : 16;
+        NT = need <= 64 * 8 ? 8 : ntmax;
         break;
       }
     }
@@ -459,6 +459,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
       for (int i = 0; i < ninst; ++i) {
         const rac_problem& P = inst[i];
         const int vec4 = (P.ldF % 4 == 0) && ((uintptr_t)P.F % (uintptr_t)(4 * esz) == 0);
+        const int vec8 = (P.ldF % 8 == 0) && ((uintptr_t)P.F % 16 == 0);
         const int64_t rw = (P.rows + W - 1) / W;
         const double cost = (double)b->hinst[i].p * (double)((rw + 63) / 64 + 3);
         for (size_t g0 = 0; g0 < by_inst[i].size(); g0 += 16) {
@@ -466,6 +467,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
           G.inst = i;
           G.nl = (int32_t)std::min<size_t>(16, by_inst[i].size() - g0);
           G.vec4 = vec4;
+          G.vec8 = vec8;
           for (int q = 0; q < 16; ++q) G.lane[q] = q < G.nl ? by_inst[i][g0 + q] : -1;
           b->hgroups.push_back(G);
           b->gcost.push_back(cost);
@@ -482,7 +484,8 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
       if (!ok) return fail(RAC_ERR_NOMEM);
       if (hipMemcpy(b->dgroups, b->hgroups.data(), sizeof(TGroup) * ng, hipMemcpyHostToDevice) != hipSuccess ||
           hipMemset(b->TA.flags, 0, sizeof(uint32_t) * (size_t)maxt * 128) != hipSuccess ||
-          hipMemset(b->TA.abort_flag, 0, sizeof(uint32_t)) != hipSuccess)
+          hipMemset(b->TA.abort_flag, 0, sizeof(uint32_t)) != hipSuccess ||
+          hipMemset(b->TA.delta, 0, sizeof(double) * (size_t)maxt * 2 * 1024) != hipSuccess)
         return fail(RAC_ERR_DEVICE);
       b->TA.groups = b->dgroups;
       b->TA.team_off = b->dteam_off;

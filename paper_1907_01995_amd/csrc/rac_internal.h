@@ -140,7 +140,7 @@ struct BatchArgs {         // everything the per-lane kernels of one chunk need
 struct TGroup {            // up to 16 lanes of one instance
   int32_t inst; int32_t nl;
   int32_t vec4;            // F columns allow aligned 4-element vector loads
-  int32_t pad;
+  int32_t vec8;            // ... and aligned 16-byte loads of two-byte data
   int32_t lane[16];        // lane ids of slots 0 .. nl-1
 };
 struct TeamArgs {
@@ -148,7 +148,7 @@ struct TeamArgs {
   const int32_t* team_off; // groups of team k: team_list[team_off[k] .. team_off[k+1])
   const int32_t* team_list;
   int nteams; int W;       // teams, workgroups per team (16 or 32)
-  int NT;                  // register tiles of 16 rows per wavefront (8, or 16 for BF16 data)
+  int NT;                  // register tiles of 16 rows per wavefront (8, or 10 for BF16 data)
   int xcd_map;             // map each team onto one XCD (nteams a multiple of 8)
   double* part;            // [nteams][2][W][64*16] gradient partials
   double* delta;           // [nteams][2][16][64] steps

@@ -20,7 +20,7 @@
 //   2. lane slot L of the group is owned by member L (wavefront 0):
 //      the owner waits for all partials, sums them in a fixed order, forms the
 //      lane's gradient g_B, applies the lane's block inverse (staged in LDS by
-//      all wavefronts during the previous block's update), updates x_B and t,
+//      all wavefronts at the block's start), updates x_B and t,
 //      and publishes the step d (then a second epoch flag);
 //   3. every member waits for all steps and updates its rows of u (FP64 MFMA,
 //      u as the accumulator).
@@ -144,10 +144,17 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
   double* part = TA.part + (int64_t)team * 2 * W * 1024;
   double* delta = TA.delta + (int64_t)team * 2 * 1024;
   uint32_t e = ld_flag(fl_part + w);
+  // Two-byte data: the member's rows of the block's columns are staged in LDS
+  // (column-major, stride SL elements: 32 bytes past a multiple of 128, so the
+  // update product's four-column reads fall in distinct banks) with coalesced
+  // 16-byte loads, all in flight at once; both products then read LDS.
+  constexpr bool kSlice = sizeof(T) == 2;
+  constexpr int SL = 64 * NT + 16;
+  __shared__ __attribute__((aligned(16))) uint16_t slice[kSlice ? 64 * SL : 8];
   __shared__ double minv_lds[64 * 64];      // block inverse of the owned lane
   __shared__ double red[NW][16][64];
   __shared__ double shg[NW][64];
-  __shared__ int32_t cols[64];
+  __shared__ int32_t colsb[2][64];           // column indices of this block and the next
   __shared__ int32_t give_up;
   if (tid == 0) give_up = 0;
   const int g0 = TA.team_off[team], g1 = TA.team_off[team + 1];
@@ -190,8 +197,8 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
     }
     const int32_t* pm = B.perm + I.poff + (int64_t)t * n;
     const int64_t rpi = 4 * (j & 3) + (j >> 2);       // row pi(j) of a tile in the update product
-    // Block inverse of the owned lane (slot w), staged in LDS one block ahead:
-    // thread tid loads entries tid + 256 i.
+    // Block inverse of the owned lane (slot w), staged in LDS at the start of
+    // each block together with the slice: thread tid loads entries tid + 256 i.
     double pf[16];
     auto minv_load = [&](int64_t bk) {
       const int sbk = (int)(block_start(bk + 1, n, p) - block_start(bk, n, p));
@@ -206,22 +213,82 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
 #pragma unroll
       for (int i = 0; i < 16; ++i) minv_lds[tid + 256 * i] = pf[i];
     };
-    minv_load(0);
-    minv_store();
+    // Two-byte data: the slice of a block is fetched into registers (chunk k of
+    // column c = slice rows [8k, 8k + 8); rows past the member's range up to the
+    // last tile are zero), all loads in flight at once, then stored to LDS.
+    constexpr int PER = kSlice ? 2 * NT : 1;   // chunks per thread: a column has up to 8 NT chunks, 4 threads
+    const int nr = (int)(re - rb), cpc = 2 * ntile;
+    // Thread tid stages column c = tid / 4 of the slice: chunks sub + 4 i
+    // (sub = tid % 4, i < PER; chunk k = slice rows [8k, 8k + 8)), so a thread
+    // needs one base address and the loads of four neighbouring threads cover
+    // 64 contiguous bytes.  Every load is in range: a column past the block's
+    // width re-reads the block's first column and a chunk past the member's
+    // rows re-reads its last chunk; neither is stored, and chunks past the rows
+    // up to the last tile store zeros instead.
+    auto slice_load = [&](const int32_t* ccols, int sbk) {
+      const int c = tid >> 2, sub = tid & 3;
+      const bool cv = c < sbk;
+      const int lastk = (nr - 1) >> 3;       // last chunk holding member rows (nr >= 1 when ntile >= 1)
+      if (G->vec8) {
+        // 16-byte aligned columns (ldF a multiple of 8): a chunk crossing the
+        // member's last row reads at most 7 further elements of the same padded
+        // column, zeroed in LDS below
+        const uint16_t* base = (const uint16_t*)F + (int64_t)ccols[cv ? c : 0] * ldF + rb;
+        uint4 sv[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const int k = sub + 4 * i;
+          sv[i] = *reinterpret_cast<const uint4*>(base + 8 * (k <= lastk ? k : lastk));
+        }
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          const int k = sub + 4 * i;
+          if (cv && k < cpc) *reinterpret_cast<uint4*>(&slice[c * SL + 8 * k]) = k <= lastk ? sv[i] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        if (nr & 7) {
+          __syncthreads();
+          if (tid < sbk)
+            for (int r = nr; r < ((nr + 7) & ~7); ++r) slice[tid * SL + r] = 0;
+        }
+      } else {                                // element loads (unaligned columns)
+        const uint16_t* base = (const uint16_t*)F + (int64_t)ccols[cv ? c : 0] * ldF + rb;
+        for (int i = 0; i < PER; ++i) {
+          const int k = sub + 4 * i;
+          if (cv && k < cpc) {
+            uint32_t h[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[e] = 8 * k + e < nr ? (uint32_t)base[8 * k + e] : 0u;
+            *reinterpret_cast<uint4*>(&slice[c * SL + 8 * k]) =
+                make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+          }
+        }
+      }
+    };
+    {
+      const int sb0 = (int)block_start(1, n, p);
+      __syncthreads();                       // the previous group's last block is done with colsb
+      if (tid < sb0) colsb[0][tid] = pm[tid];
+    }
     for (int64_t blk = 0; blk < p; ++blk) {
       const int64_t s0 = block_start(blk, n, p);
       const int sb = (int)(block_start(blk + 1, n, p) - s0);
-      __syncthreads();                       // the previous block's cols / red are no longer read
-      if (give_up) return;                   // every wavefront leaves together
-      if (tid < sb) cols[tid] = pm[s0 + tid];
+      const int32_t* cols = colsb[blk & 1];
+      const int sbn = blk + 1 < p ? (int)(block_start(blk + 2, n, p) - block_start(blk + 1, n, p)) : 0;
+      __syncthreads();                       // this block's cols and inverse are in LDS; the
+      if (give_up) return;                   // previous block no longer reads the slice
+      if (tid < sbn) colsb[(blk + 1) & 1][tid] = pm[s0 + sb + tid];   // next block's indices
+      minv_load(blk);                        // in flight together with the slice
+      if constexpr (kSlice) if (ntile > 0) slice_load(cols, sb);   // all of the slice's loads in flight at once
+      minv_store();
       __syncthreads();
       ++e;
       const int par = (int)(e & 1u);
       // owner: iterate-fixed gradient terms of the lane
-      double gb = 0.0, acol = 0.0;
+      double gb = 0.0, acol = 0.0, oxc = 0.0, odel = 0.0;
       if (own && lane < sb) {
         const int col = cols[lane];
         const double xc = B.X[OU->xoff + col];
+        oxc = xc;
         gb = OU->c[col] - B.XI[OU->xoff + col] + obeta * (xc - B.Z[OU->xoff + col]);
         if (OU->h) gb += OU->h[col] * xc;
         if (OU->a) { acol = OU->a[col]; gb -= omu * acol; }
@@ -231,6 +298,26 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
         f64x4 acc[4];
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        if constexpr (kSlice) {
+#pragma unroll
+          for (int s = 0; s < NT; ++s) {
+            const int tile = wave + NW * s;
+            if (tile < ntile) {
+#pragma unroll
+              for (int ct = 0; ct < 4; ++ct) {
+                const int c = 16 * ct + j;
+                const uint2 r = c < sb ? *reinterpret_cast<const uint2*>(&slice[c * SL + 16 * tile + 4 * q])
+                                       : make_uint2(0u, 0u);
+                const double f[4] = {(double)__uint_as_float(r.x << 16), (double)__uint_as_float(r.x & 0xffff0000u),
+                                     (double)__uint_as_float(r.y << 16), (double)__uint_as_float(r.y & 0xffff0000u)};
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[i], ur[s][i], acc[ct], 0, 0, 0);
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else {
         RawQ<T> gq[DS][4];
         auto gload = [&](int s, RawQ<T> (&dst)[4]) {
           const int tile = wave + NW * s;
@@ -257,6 +344,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
                                                                acc[ct], 0, 0, 0);
           }
           __builtin_amdgcn_sched_barrier(0);
+        }
         }
         // acc[ct][r] of lane (q, j) = P[column 16 ct + 4 r + q][slot j]
 #pragma unroll
@@ -287,39 +375,60 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
         double s = 0.0;
         if (lane < sb) {
           const double* pp = part + (int64_t)par * W * 1024 + lane * 16 + L;
-          for (int m0 = 0; m0 < W; m0 += 16) {
-            double v[16];
+          double v[32];
 #pragma unroll
-            for (int m = 0; m < 16; ++m) v[m] = m0 + m < W ? ld_c(pp + (int64_t)(m0 + m) * 1024) : 0.0;
+          for (int m = 0; m < 32; ++m) v[m] = ld_c(pp + (int64_t)(m < W ? m : 0) * 1024);
 #pragma unroll
-            for (int m = 0; m < 16; ++m) s += v[m];
-          }
+          for (int m = 0; m < 32; ++m) v[m] = m < W ? v[m] : 0.0;
+#pragma unroll
+          for (int m = 0; m < 32; ++m) s += v[m];
         }
         double g = s / oNs + gb;
         if (OU->a) g += obeta * acol * (ot - ob);
         shg[wave][lane] = lane < sb ? g : 0.0;
         __builtin_amdgcn_wave_barrier();
         const double* Ml = minv_lds;
-        double d = 0.0;
+        double dq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 16
-        for (int k = 0; k < 64; ++k) d += Ml[k * 64 + lane] * shg[wave][k];
-        d = lane < sb ? -d : 0.0;
-        if (lane < sb) B.X[OU->xoff + cols[lane]] += d;
-        if (OU->a) ot += wave_sum(acol * d);
-        st_c(delta + ((int64_t)par * 16 + L) * 64 + lane, d);
+        for (int k = 0; k < 64; ++k) dq[k & 3] += Ml[k * 64 + lane] * shg[wave][k];
+        odel = lane < sb ? -((dq[0] + dq[1]) + (dq[2] + dq[3])) : 0.0;
+        if (OU->a) ot += wave_sum(acol * odel);
+        st_c(delta + ((int64_t)par * 16 + L) * 64 + lane, odel);
         __builtin_amdgcn_s_waitcnt(0);
       }
       __syncthreads();
       if (give_up) return;
       if (tid == 0) st_flag(fl_step + w, e);
+      if (own && wave == 0 && lane < sb) B.X[OU->xoff + cols[lane]] = oxc + odel;   // only the owner writes x_B
       // 3. every member: steps of all lanes, then its rows of u
       if (!wait_team(fl_step, W, e, lane, TA.abort_flag) && lane == 0) give_up = 1;
       {
         double dreg[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m)
-          dreg[m] = actj ? ld_c(delta + ((int64_t)par * 16 + j) * 64 + 4 * m + q) : 0.0;
-        if (blk + 1 < p) minv_load(blk + 1);     // owners are done with this block's inverse
+        for (int m = 0; m < 16; ++m) dreg[m] = ld_c(delta + ((int64_t)par * 16 + j) * 64 + 4 * m + q);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) dreg[m] = actj ? dreg[m] : 0.0;   // slots without an active lane
+        if constexpr (kSlice) {
+          // two accumulator chains per tile (even and odd column groups), added at the end
+#pragma unroll
+          for (int s = 0; s < NT; ++s) {
+            const int tile = wave + NW * s;
+            if (tile < ntile) {
+              f64x4 a0 = {ur[s][0], ur[s][1], ur[s][2], ur[s][3]};
+              f64x4 a1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+              for (int m = 0; m < 16; m += 2) {
+                const int c0 = 4 * m + q, c1 = c0 + 4;
+                const uint32_t h0 = c0 < sb ? (uint32_t)slice[c0 * SL + 16 * tile + rpi] : 0u;
+                const uint32_t h1 = c1 < sb ? (uint32_t)slice[c1 * SL + 16 * tile + rpi] : 0u;
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)__uint_as_float(h0 << 16), dreg[m], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)__uint_as_float(h1 << 16), dreg[m + 1], a1, 0, 0, 0);
+              }
+              ur[s][0] = a0[0] + a1[0]; ur[s][1] = a0[1] + a1[1]; ur[s][2] = a0[2] + a1[2]; ur[s][3] = a0[3] + a1[3];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else {
         T uq[DS][16];
         auto uload = [&](int s, T (&dst)[16]) {
           const int tile = wave + NW * s;
@@ -345,7 +454,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
           }
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (blk + 1 < p) minv_store();           // read after the next block's first barrier
+        }
       }
     }
     // the group's u back to memory, and t of the owned lane
@@ -376,8 +485,8 @@ template <typename T>
 int tsweep_resident_nt(int NT) {
   switch (NT) {
     case 8: return tsweep_resident_t<T, 8>();
-    case 16:   // sixteen tiles fit the register file only with two-byte data
-      if constexpr (sizeof(T) == 2) return tsweep_resident_t<T, 16>();
+    case 10:   // ten tiles (640 rows) fit LDS and the register file only with two-byte data
+      if constexpr (sizeof(T) == 2) return tsweep_resident_t<T, 10>();
       return 0;
     default: return 0;
   }
@@ -393,8 +502,8 @@ template <typename T>
 hipError_t tsweep_launch(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st) {
   switch (ta.NT) {
     case 8: return tsweep_go<T, 8>(b, ta, t, st);
-    case 16:
-      if constexpr (sizeof(T) == 2) return tsweep_go<T, 16>(b, ta, t, st);
+    case 10:
+      if constexpr (sizeof(T) == 2) return tsweep_go<T, 10>(b, ta, t, st);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }

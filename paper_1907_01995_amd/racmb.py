@@ -191,8 +191,14 @@ class Problem:
     hi: float = 0.0
     obj_const: float = 0.0
 
+    @property
+    def ldF(self) -> int:
+        """Leading dimension of the column-major data: F is an (n, ldF)-strided tensor view."""
+        assert self.F.stride(1) == 1 and self.F.stride(0) >= self.rows
+        return int(self.F.stride(0))
+
     def struct(self) -> Problem_:
-        return Problem_(self.n, self.rows, self.F.data_ptr(), self.rows, _DT[self.storage], self.prox,
+        return Problem_(self.n, self.rows, self.F.data_ptr(), self.ldF, _DT[self.storage], self.prox,
                         self.Ns, None if self.h is None else self.h.data_ptr(), self.c.data_ptr(),
                         None if self.a is None else self.a.data_ptr(), self.b, self.lam, self.alpha,
                         self.lo, self.hi, self.obj_const)
@@ -229,13 +235,15 @@ def regression_problem(D, y, lam=0.0, alpha=1.0, storage="f64", h=None, device="
 
 
 def regression_problem_tensor(F, y, lam=0.0, alpha=1.0, storage="bf16", h=None) -> Problem:
-    """Elastic net from a device tensor F of shape (n, N) (column-major N x n data)."""
+    """Elastic net from a device tensor F of shape (n, N) (column-major N x n data; a
+    row-strided view (n, ldF) with ldF >= N is allowed)."""
     torch = _torch()
     n, N = F.shape
     dev = F.device
     yt = torch.as_tensor(np.asarray(y, dtype=np.float64), device=dev)
     c = torch.empty(n, dtype=torch.float64, device=dev)
-    _check(load().rac_regression_c(C.c_void_p(F.data_ptr()), _DT[storage], N, n, N, float(N),
+    assert F.stride(1) == 1 and F.stride(0) >= N
+    _check(load().rac_regression_c(C.c_void_p(F.data_ptr()), _DT[storage], N, n, int(F.stride(0)), float(N),
                                    _ptr(yt), _ptr(c), _stream()), "rac_regression_c")
     ht = None if h is None else torch.as_tensor(np.asarray(h, dtype=np.float64), device=dev)
     yy = float(np.dot(np.asarray(y, dtype=np.float64), np.asarray(y, dtype=np.float64)))

@@ -219,15 +219,19 @@ class DeviceRegression:
         return np.asfortranarray(self.F.float().cpu().numpy().T.astype(np.float64))
 
 
-def en_instance_device(N, n, seed, nnz_frac=0.1, noise=0.05, alpha=0.5, storage="bf16", device="cuda"):
+def en_instance_device(N, n, seed, nnz_frac=0.1, noise=0.05, alpha=0.5, storage="bf16", device="cuda", align=64):
     """Gaussian design N x n drawn with torch's seeded generator on the device, rounded once to
     `storage` (round to nearest even); x_true has nnz_frac non-zeros drawn N(0,1); y = D x_true +
-    noise N(0,1); lam_max = |D'y|_inf / (N alpha).  Same values on every run for a given seed."""
+    noise N(0,1); lam_max = |D'y|_inf / (N alpha).  Same values on every run for a given seed.
+    Each column starts at a multiple of `align` elements (F is an (n, ldF)-strided view)."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     dt = {"bf16": torch.bfloat16, "f32": torch.float32, "f64": torch.float64}[storage]
-    F = torch.randn((n, N), generator=g, device=device, dtype=torch.float32).to(dt)
+    ld = -(-N // align) * align
+    buf = torch.zeros((n, ld), device=device, dtype=dt)
+    buf[:, :N] = torch.randn((n, N), generator=g, device=device, dtype=torch.float32).to(dt)
+    F = buf[:, :N]
     rng = np.random.default_rng(seed)
     nnz = max(1, int(round(nnz_frac * n)))
     xt = np.zeros(n)
@@ -236,4 +240,4 @@ def en_instance_device(N, n, seed, nnz_frac=0.1, noise=0.05, alpha=0.5, storage=
     y = (F.double().T @ xd).cpu().numpy() + noise * rng.standard_normal(N)
     yd = torch.as_tensor(y, device=device)
     lam_max = float(torch.max(torch.abs(F.double() @ yd)).item()) / (N * alpha)
-    return DeviceRegression(F.contiguous(), y, lam_max, storage)
+    return DeviceRegression(F, y, lam_max, storage)
