@@ -16,7 +16,14 @@ HBM.  The line also reports, on the same data:
                   Grams, beta = 0.1 lambda as in Sec.3.1),
   roofline     -- the dominant kernel's achieved rate from HIP events recorded
                   around each launch inside the timed region,
-  cpu_baseline -- the FP64 oracle on a bounded sample of the same workload.
+  cpu_baseline -- the FP64 oracle on a bounded sample of the same workload,
+  batched      -- the batched elastic-net paths (256 instances of uneven size,
+                  N in [1000, 20000] and n in [100, 4000] log-uniform, BF16
+                  data, 16 lambda lanes each): lane-iterations per second with
+                  every lane active, per-launch phase times with the roofline of
+                  the batched sweep, and the time until every lane reaches KKT
+                  <= 1e-6 for the candidate (mixed precision, learned penalty)
+                  and for the plain FP64 fixed-penalty batch on the same values.
 """
 from __future__ import annotations
 
@@ -56,6 +63,92 @@ def algorithmic(phase, N, n, p, bA):
     return 0.0, 0.0
 
 
+def batched_leg(args, racmb, W, torch, weights, log):
+    """Batched elastic-net paths: 256 uneven instances x 16 lambda lanes, BF16 data."""
+    t0 = time.time()
+    Ns, ns = W.en_batch_sizes(256)
+    insts = [W.en_instance_device(int(N), int(n), 1000 + i, storage="bf16") for i, (N, n) in enumerate(zip(Ns, ns))]
+    probs = [racmb.regression_problem_tensor(d.F, d.y, lam=0.1 * d.lam_max, alpha=0.5, storage="bf16")
+             for d in insts]
+    lanes = [(i, racmb.PROX_EN, float(l), 0.5, 0.1 * float(l))
+             for i, d in enumerate(insts) for l in W.lambda_grid(d.lam_max, 16, 0.01)]
+    torch.cuda.synchronize()
+    elems = float(np.sum(Ns.astype(np.float64) * ns))
+    log("batched workload generated in %.1fs (%d lanes, %.3e stored values)" % (time.time() - t0, len(lanes), elems))
+    mode = racmb.BETA_MLP if weights is not None else racmb.BETA_RESBAL
+    cand = dict(s=64, seed=11, precision=racmb.PREC_MIXED, beta_mode=mode, mlp_weights=weights, check_every=10)
+    out = {"workload": "en_paths_256x16", "instances": 256, "lanes": len(lanes), "stored_values": elems,
+           "data_storage": "bf16", "block_size": 64, "alpha": 0.5, "lambda_grid": "lam_max * 0.01^(j/15), j<16",
+           "beta_mode": "mlp" if weights is not None else "residual_balancing"}
+
+    # ---- throughput: every lane active (tol 0), chunks replayed from the hipGraph
+    b = racmb.Batch(probs, lanes, max_iter=10, tol=0.0, use_graph=True, tune=True, **cand)
+    for _ in range(max(args.batched_warmup // 10, 1)):
+        b.run()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    k = 0
+    for _ in range(max(args.batched_steps // 10, 1)):
+        k += b.run()[0]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    info = b.info()
+    out.update({"iterations": k, "seconds": dt, "ms_per_iteration": 1e3 * dt / k,
+                "lane_iterations_per_s": len(lanes) * k / dt, "team_size": info["team_size"],
+                "teams": info["teams"], "graph": info["graph"]})
+    log("batched throughput: %d iterations in %.3fs -> %.2f ms/iteration, %.3e lane-iterations/s %s"
+        % (k, dt, 1e3 * dt / k, len(lanes) * k / dt, info))
+    # ---- per-launch device time (events around every launch) for the roofline
+    b.set_timing(True)
+    for _ in range(max(args.batched_steps // 20, 1)):
+        b.run()
+    ph = b.timing()
+    b.close()
+    del b
+    rows = {}
+    for name, (ms, cnt) in ph.items():
+        if cnt:
+            rows[name] = {"avg_us": 1e3 * ms / cnt, "launches": cnt}
+    sw = ph["sweep"]
+    avg = sw[0] / sw[1] / 1e3
+    flops = 4.0 * 16 * elems                       # F_B'u and F_B d, every lane, every block
+    nbytes = 2.0 * elems + 16 * 8.0 * (2 * float(np.sum(Ns)) + 6 * float(np.sum(ns)))
+    roof = {"bound": "mfma", "achieved": flops / avg / 1e12, "peak": MFMA_PEAK["f64"] / 1e12,
+            "unit": "TFLOP/s", "kernel": "k_tsweep" if info["team_size"] else "k_bsweep",
+            "avg_launch_us": avg * 1e6, "flops_per_launch": flops, "hbm_bytes_per_launch": nbytes,
+            "hbm_GBps": nbytes / avg / 1e9, "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    rows["sweep"]["TFLOPs"] = roof["achieved"]
+    out["roofline"] = roof
+    out["phases"] = rows
+    log("batched phases %s" % rows)
+
+    # ---- time until every lane's KKT <= 1e-6: candidate vs plain FP64 fixed beta
+    if not args.no_time_to_tol:
+        tt = {}
+        plain = dict(s=64, seed=11, precision=racmb.PREC_FP64, beta_mode=racmb.BETA_FIXED, check_every=10)
+        for name, kw, cap in (("candidate", cand, args.batched_cap), ("plain_fp64_fixed_beta", plain, 3 * args.batched_cap)):
+            bb = racmb.Batch(probs, lanes, max_iter=cap, tol=1e-6, use_graph=True, tune=True, **kw)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            it, act = bb.run()
+            torch.cuda.synchronize()
+            tt[name] = {"seconds": time.perf_counter() - a, "iterations": it, "lanes_converged": len(lanes) - act,
+                        "all_converged": act == 0, "iteration_cap": cap}
+            if name == "candidate":
+                zc = [bb.lane(u)[2] for u in range(0, len(lanes), 97)]
+            else:
+                zp = [bb.lane(u)[2] for u in range(0, len(lanes), 97)]
+            bb.close()
+            del bb
+            log("batched time-to-tol %s: %s" % (name, tt[name]))
+        tt["speedup"] = tt["plain_fp64_fixed_beta"]["seconds"] / tt["candidate"]["seconds"]
+        tt["candidate_vs_plain_rel_z_sampled"] = float(max(
+            np.max(np.abs(a_ - b_)) / max(np.max(np.abs(b_)), 1e-300) for a_, b_ in zip(zc, zp)))
+        out["time_to_tol"] = tt
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +157,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=40)
+    ap.add_argument("--batched-warmup", type=int, default=10)
+    ap.add_argument("--batched-cap", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -188,6 +285,8 @@ def main():
             out["time_to_tol"]["oracle_objective_rel_err"] = abs(
                 O.objective(op, xc[1]) - out["time_to_tol"]["candidate"]["objective"]) / abs(
                 O.objective(op, xc[1]))
+    if not args.no_batched:
+        out["batched"] = batched_leg(args, racmb, W, torch, weights, log)
     print(json.dumps(out), flush=True)
 
 

@@ -285,6 +285,12 @@ rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x,
  * unroll of the LANE sweep, 1 if chunks are replayed from a hipGraph, workgroups per
  * team of the TEAM sweep (0 when the LANE sweep runs), number of teams. */
 rac_status rac_batch_info(rac_batch b, int64_t* info);
+/* Per-phase device time of the batch's launches, as for rac_solver_set_timing /
+ * rac_solver_timing (same phases; "factor" is the block inverses).  While timing is
+ * enabled, chunks are launched directly rather than replayed from the hipGraph, with
+ * events around every launch. */
+rac_status rac_batch_set_timing(rac_batch b, int32_t enable);   /* also clears the totals */
+rac_status rac_batch_timing(rac_batch b, double* ms, int64_t* launches);
 
 const char* rac_status_str(rac_status s);
 

@@ -98,24 +98,78 @@ struct rac_batch_s {
   TGroup* dgroups = nullptr;
   int32_t* dteam_off = nullptr;
   int32_t* dteam_list = nullptr;
+  // per-phase timing (events around every launch; chunks are then launched directly)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_t;
+  std::vector<int> ev_phase;
+  double phase_ms[RAC_NUM_PHASES] = {};
+  int64_t phase_count[RAC_NUM_PHASES] = {};
 };
 
 namespace {
 
+// Events around one launch when timing is on (never inside a graph capture).
+struct BTimer {
+  rac_batch b;
+  hipStream_t st;
+  hipError_t begin() {
+    if (!b->timing) return hipSuccess;
+    const size_t i = 2 * b->ev_phase.size();
+    while (b->ev_t.size() < i + 2) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      b->ev_t.push_back(e);
+    }
+    return hipEventRecord(b->ev_t[i], st);
+  }
+  hipError_t end(int phase) {
+    if (!b->timing) return hipSuccess;
+    const size_t i = 2 * b->ev_phase.size();
+    b->ev_phase.push_back(phase);
+    return hipEventRecord(b->ev_t[i + 1], st);
+  }
+};
+
 rac_status enqueue_chunk(rac_batch b, int Tc, hipStream_t st) {
   BatchArgs a = b->A;
   a.T = Tc;
+  BTimer tm{b, st};
+  BCHK(tm.begin());
   BCHK(launch_bperm(a, st));
+  BCHK(tm.end(RAC_PHASE_PARTITION));
   for (int t = 0; t < Tc; ++t) {
     BatchGramArgs g{a.dtype, b->O.precision, a.sp, b->ngt, t, a.inst, b->gtasks, a.perm, a.inst_active,
                     const_cast<double*>(a.G)};
+    BCHK(tm.begin());
     BCHK(launch_bgram(g, st));
+    BCHK(tm.end(RAC_PHASE_GRAM));
+    BCHK(tm.begin());
     BCHK(launch_binv(a, t, st));
+    BCHK(tm.end(RAC_PHASE_FACTOR));
+    BCHK(tm.begin());
     if (b->team) BCHK(launch_tsweep(a, b->TA, t, st));
     else BCHK(launch_bsweep(a, t, st));
+    BCHK(tm.end(RAC_PHASE_SWEEP));
+    BCHK(tm.begin());
     BCHK(launch_bzdual(a, st));
+    BCHK(tm.end(RAC_PHASE_ZDUAL));
   }
+  BCHK(tm.begin());
   BCHK(launch_bcheck(a, Tc, Tc == b->T ? 1 : 0, st));
+  BCHK(tm.end(RAC_PHASE_CHECK));
+  return RAC_OK;
+}
+
+rac_status collect_timing(rac_batch b) {
+  if (!b->timing) return RAC_OK;
+  for (size_t q = 0; q < b->ev_phase.size(); ++q) {
+    float ms = 0.f;
+    BCHK(hipEventElapsedTime(&ms, b->ev_t[2 * q], b->ev_t[2 * q + 1]));
+    b->phase_ms[b->ev_phase[q]] += ms;
+    b->phase_count[b->ev_phase[q]] += 1;
+  }
+  b->ev_phase.clear();
   return RAC_OK;
 }
 
@@ -524,9 +578,28 @@ rac_status rac_batch_destroy(rac_batch b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->ev) (void)hipEventDestroy(b->ev);
+  for (hipEvent_t e : b->ev_t) (void)hipEventDestroy(e);
   if (b->cs) (void)hipStreamDestroy(b->cs);
   b->buf.release();
   delete b;
+  return RAC_OK;
+}
+
+rac_status rac_batch_set_timing(rac_batch b, int32_t enable) {
+  if (!b) return RAC_ERR_ARG;
+  BCHK(hipStreamSynchronize(b->cs));
+  b->timing = enable != 0;
+  b->ev_phase.clear();
+  for (int q = 0; q < RAC_NUM_PHASES; ++q) { b->phase_ms[q] = 0.0; b->phase_count[q] = 0; }
+  return RAC_OK;
+}
+
+rac_status rac_batch_timing(rac_batch b, double* ms, int64_t* launches) {
+  if (!b || !ms) return RAC_ERR_ARG;
+  for (int q = 0; q < RAC_NUM_PHASES; ++q) {
+    ms[q] = b->phase_ms[q];
+    if (launches) launches[q] = b->phase_count[q];
+  }
   return RAC_OK;
 }
 
@@ -539,7 +612,7 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
   int64_t done = 0;
   while (done < b->O.max_iter && b->host_active > 0) {
     const int Tc = (int)std::min<int64_t>(b->T, b->O.max_iter - done);
-    if (b->O.use_graph && Tc == b->T) {
+    if (b->O.use_graph && Tc == b->T && !b->timing) {
       if (!b->gexec) {
         BCHK(hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal));
         rac_status r = enqueue_chunk(b, Tc, b->cs);
@@ -561,6 +634,10 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
     if (b->team) BCHK(hipMemcpyAsync(&aborted, b->TA.abort_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, b->cs));
     BCHK(hipStreamSynchronize(b->cs));
     if (aborted) return RAC_ERR_DEVICE;   // a team exchange timed out
+    {
+      const rac_status r = collect_timing(b);
+      if (r != RAC_OK) return r;
+    }
     done += Tc;
   }
   b->k += done;

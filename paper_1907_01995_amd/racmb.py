@@ -33,7 +33,8 @@ EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_so
             "rac_state_import",
             "rac_permutation", "rac_kkt", "rac_objective", "rac_regression_c", "rac_block_matrices",
             "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_batch_create",
-            "rac_batch_destroy", "rac_batch_run", "rac_batch_lane", "rac_batch_info", "rac_status_str"]
+            "rac_batch_destroy", "rac_batch_run", "rac_batch_lane", "rac_batch_info", "rac_batch_set_timing",
+            "rac_batch_timing", "rac_status_str"]
 
 
 class RacError(RuntimeError):
@@ -125,6 +126,8 @@ def load():
         "rac_batch_run": [vp, vp, C.POINTER(i64), C.POINTER(C.c_int32)],
         "rac_batch_lane": [vp, C.c_int32, C.POINTER(Result_), vp, vp, vp],
         "rac_batch_info": [vp, C.POINTER(i64)],
+        "rac_batch_set_timing": [vp, C.c_int32],
+        "rac_batch_timing": [vp, dp, C.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -358,6 +361,7 @@ class Solver:
                "rac_solver_timing")
         return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(self.PHASES)}
 
+
     def info(self):
         v = (C.c_int64 * 8)()
         _check(self.lib.rac_solver_info(self.h, v), "rac_solver_info")
@@ -522,6 +526,15 @@ class Batch:
             raise RacError(code, "rac_batch_lane")
         res = Result(r.iters, r.status, r.kkt, r.beta, r.objective, r.fail_iter, r.fail_block)
         return res, x.cpu().numpy(), z.cpu().numpy(), xi.cpu().numpy()
+
+    def set_timing(self, enable=True):
+        _check(self.lib.rac_batch_set_timing(self.h, 1 if enable else 0), "rac_batch_set_timing")
+
+    def timing(self):
+        """{phase: (milliseconds, launches)} since set_timing."""
+        ms, cnt = (C.c_double * 6)(), (C.c_int64 * 6)()
+        _check(self.lib.rac_batch_timing(self.h, ms, cnt), "rac_batch_timing")
+        return {name: (ms[q], cnt[q]) for q, name in enumerate(Solver.PHASES)}
 
     def info(self):
         v = (C.c_int64 * 8)()

@@ -187,3 +187,16 @@ def test_team_sweep_svm_lanes_with_equality_row():
         res, x, z, xi = b.lane(u)
         ref = oracle_lane(ops[lane[0]], lane, s=32, seed=6, max_iter=40, check_every=10)
         assert rel(x, ref.x) < 1e-8 and rel(z, ref.z) < 1e-8 and rel(xi, ref.xi) < 1e-8, u
+
+
+def test_batch_phase_timing_counts_every_launch():
+    ws, gps, ops, lanes = en_batch(ninst=2, lanes_per=2, seed=13)
+    b = racmb.Batch(gps, lanes, s=32, seed=1, max_iter=20, check_every=10, use_graph=True)
+    b.set_timing(True)
+    b.run()
+    ph = b.timing()
+    assert ph["sweep"][1] == 20 and ph["gram"][1] == 20 and ph["factor"][1] == 20 and ph["check"][1] == 2
+    assert all(ms > 0 for ms, cnt in ph.values() if cnt)
+    res, x, z, xi = b.lane(0)
+    ref = oracle_lane(ops[lanes[0][0]], lanes[0], s=32, seed=1, max_iter=20, check_every=10)
+    assert rel(z, ref.z) < 1e-8                       # timing does not change the iteration
