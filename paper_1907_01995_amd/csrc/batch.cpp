@@ -96,6 +96,8 @@ struct rac_batch_s {
   std::vector<double> gcost;
   int max_teams = 0;
   TGroup* dgroups = nullptr;
+  int2* dkkt_tasks = nullptr;   // (group, 64-column chunk) of the grouped KKT check
+  int nkkt_tasks = 0;
   int32_t* dteam_off = nullptr;
   int32_t* dteam_list = nullptr;
   // per-phase timing (events around every launch; chunks are then launched directly)
@@ -156,7 +158,8 @@ rac_status enqueue_chunk(rac_batch b, int Tc, hipStream_t st) {
     BCHK(tm.end(RAC_PHASE_ZDUAL));
   }
   BCHK(tm.begin());
-  BCHK(launch_bcheck(a, Tc, Tc == b->T ? 1 : 0, st));
+  if (b->team) BCHK(launch_gkkt(a, b->dgroups, b->dkkt_tasks, b->nkkt_tasks, st));
+  BCHK(launch_bcheck(a, Tc, Tc == b->T ? 1 : 0, b->team ? 1 : 0, st));
   BCHK(tm.end(RAC_PHASE_CHECK));
   return RAC_OK;
 }
@@ -536,7 +539,13 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
            b->buf.alloc(&b->TA.delta, (size_t)maxt * 2 * 1024) && b->buf.alloc(&b->TA.flags, (size_t)maxt * 128) &&
            b->buf.alloc(&b->TA.abort_flag, 1);
       if (!ok) return fail(RAC_ERR_NOMEM);
-      if (hipMemcpy(b->dgroups, b->hgroups.data(), sizeof(TGroup) * ng, hipMemcpyHostToDevice) != hipSuccess ||
+      std::vector<int2> kt;
+      for (int g = 0; g < ng; ++g)
+        for (int64_t ch = 0; ch < (inst[b->hgroups[g].inst].n + 63) / 64; ++ch) kt.push_back(make_int2(g, (int)ch));
+      b->nkkt_tasks = (int)kt.size();
+      if (!b->buf.alloc(&b->dkkt_tasks, kt.size())) return fail(RAC_ERR_NOMEM);
+      if (hipMemcpy(b->dkkt_tasks, kt.data(), sizeof(int2) * kt.size(), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(b->dgroups, b->hgroups.data(), sizeof(TGroup) * ng, hipMemcpyHostToDevice) != hipSuccess ||
           hipMemset(b->TA.flags, 0, sizeof(uint32_t) * (size_t)maxt * 128) != hipSuccess ||
           hipMemset(b->TA.abort_flag, 0, sizeof(uint32_t)) != hipSuccess ||
           hipMemset(b->TA.delta, 0, sizeof(double) * (size_t)maxt * 2 * 1024) != hipSuccess)

@@ -516,13 +516,15 @@ hipError_t launch_bzdual(const BatchArgs& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_bcheck(const BatchArgs& b, int Tc, int decide, hipStream_t st) {
-  hipError_t e;
-  switch (b.dtype) {
-    case RAC_DT_F64: e = bkkt_launch<double>(b, st); break;
-    case RAC_DT_F32: e = bkkt_launch<float>(b, st); break;
-    case RAC_DT_BF16: e = bkkt_launch<uint16_t>(b, st); break;
-    default: return hipErrorInvalidValue;
+hipError_t launch_bcheck(const BatchArgs& b, int Tc, int decide, int grouped_kkt, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (!grouped_kkt) {
+    switch (b.dtype) {
+      case RAC_DT_F64: e = bkkt_launch<double>(b, st); break;
+      case RAC_DT_F32: e = bkkt_launch<float>(b, st); break;
+      case RAC_DT_BF16: e = bkkt_launch<uint16_t>(b, st); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   k_bcontrol<<<(unsigned)b.nunits, 64, 0, st>>>(b.units, b.sc, b.kpart, b.KC, b.beta_mode, b.rb_mu, b.rb_tau,

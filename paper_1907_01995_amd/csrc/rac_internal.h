@@ -158,12 +158,15 @@ struct TeamArgs {
 // Workgroups of the team sweep that can be resident at once (0 if NT unsupported).
 int tsweep_max_resident(int32_t dtype, int NT);
 hipError_t launch_tsweep(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st);
+// KKT terms of lane groups, one workgroup per (group, 64-column chunk) task.
+hipError_t launch_gkkt(const BatchArgs& b, const TGroup* groups, const int2* tasks, int ntasks, hipStream_t st);
 
 hipError_t launch_bperm(const BatchArgs& b, hipStream_t st);
 hipError_t launch_binv(const BatchArgs& b, int t, hipStream_t st);
 hipError_t launch_bsweep(const BatchArgs& b, int t, hipStream_t st);
 hipError_t launch_bzdual(const BatchArgs& b, hipStream_t st);
-hipError_t launch_bcheck(const BatchArgs& b, int Tc, int decide, hipStream_t st);   // KKT, control, activity
+// KKT (unless grouped_kkt: already formed by launch_gkkt), control, activity
+hipError_t launch_bcheck(const BatchArgs& b, int Tc, int decide, int grouped_kkt, hipStream_t st);
 
 struct FactorArgs {
   const double* partial; int R; int sp; int64_t n; int64_t p; const int32_t* perm;

@@ -31,6 +31,7 @@
 // (workgroup b runs on XCD b mod 8), so that their exchanges stay in one L2.
 // All members of all teams are resident at once (the grid never exceeds the
 // occupancy limit of the device), which every wait relies on.
+#include "control.h"
 #include "rac_internal.h"
 
 namespace rac {
@@ -471,6 +472,98 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// KKT terms of a lane group: one workgroup per (group, chunk of 64 columns).
+// P = F_chunk' [u_1 .. u_16] over all rows on the matrix cores (one read of the
+// data for the whole group; wavefront v takes tiles v, v+4, ...), then the
+// per-column terms of every active lane and their maxima / sums over the chunk,
+// written where the per-lane control kernel reads them (kpart[lane][chunk][10]).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gkkt(BatchArgs B, const TGroup* __restrict__ groups,
+                                              const int2* __restrict__ tasks) {
+  const int2 tk = tasks[blockIdx.x];
+  const TGroup* G = groups + tk.x;
+  const int chunk = tk.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, j = lane & 15;
+  const int nl = G->nl;
+  bool any = false;
+  for (int L = 0; L < nl; ++L) any |= B.sc[G->lane[L]].status == 0;
+  if (!any) return;                          // uniform: the workgroup leaves together
+  const BInst I = B.inst[G->inst];
+  const T* F = (const T*)I.F;
+  const int64_t rows = I.rows, ldF = I.ldF, c0 = 64 * (int64_t)chunk;
+  const int nc = I.n - c0 < 64 ? (int)(I.n - c0) : 64;
+  const bool vec = G->vec4 != 0;
+  const int uj = j < nl ? G->lane[j] : -1;
+  const bool actj = uj >= 0 && B.sc[uj].status == 0;
+  const double* Uj = B.U + (actj ? B.units[uj].uoff : 0);
+  f64x4 acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int64_t ntile = (rows + 15) >> 4;
+  for (int64_t tile = wave; tile < ntile; tile += 4) {
+    const int64_t r0 = 16 * tile + 4 * q;
+    const int nv = rows - r0 >= 4 ? 4 : (rows > r0 ? (int)(rows - r0) : 0);
+    double uv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) uv[i] = Uj[actj && i < nv ? r0 + i : 0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) uv[i] = (actj && i < nv) ? uv[i] : 0.0;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int c = 16 * ct + j;
+      const bool cv = c < nc && nv > 0;
+      const RawQ<T> f = ld_quad<T>(F, cv ? (c0 + c) * ldF + r0 : 0, cv ? nv : 0, vec);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(quad_at<T>(f, i), uv[i], acc[ct], 0, 0, 0);
+    }
+  }
+  __shared__ double red[4][16][64];
+  __shared__ double mred[16][16][10];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[wave][4 * ct + r][lane] = acc[ct][r];
+  __syncthreads();
+  // thread tid: slot tid & 15, columns 16 (tid >> 6) + 4 rr + ((tid & 63) >> 4), rr < 4
+  const int slot = tid & 15, ln = tid & 63;
+  const int us = slot < nl ? G->lane[slot] : -1;
+  const bool acts = us >= 0 && B.sc[us].status == 0;
+  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (acts) {
+    const BUnit* D = B.units + us;
+    const double mu = B.sc[us].mu;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int el = 4 * (tid >> 6) + rr;
+      const int cl = 16 * (el >> 2) + 4 * (el & 3) + (ln >> 4);
+      if (cl < nc) {
+        const double v = red[0][el][ln] + red[1][el][ln] + red[2][el][ln] + red[3][el][ln];
+        const int64_t col = c0 + cl;
+        kkt_column_terms(v, D->Ns, D->h ? D->h[col] : 0.0, D->c[col], D->a ? D->a[col] : 0.0,
+                         B.X[D->xoff + col], B.Z[D->xoff + col], B.XI[D->xoff + col], mu, D->prox, D->lam,
+                         D->alpha, D->lo, D->hi, m);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 10; ++e) mred[slot][tid >> 4][e] = m[e];
+  __syncthreads();
+  if (tid < 16 && tid < nl) {
+    const int u = G->lane[tid];
+    if (B.sc[u].status == 0) {
+      double* outp = B.kpart + ((int64_t)u * B.KC + chunk) * 10;
+#pragma unroll
+      for (int e = 0; e < 10; ++e) {
+        double v = mred[tid][0][e];
+        for (int k = 1; k < 16; ++k) v = e < 9 ? fmax(v, mred[tid][k][e]) : v + mred[tid][k][e];
+        outp[e] = v;
+      }
+    }
+  }
+}
+
 template <typename T, int NT>
 int tsweep_resident_t() {
   int dev = 0, cus = 0, per = 0;
@@ -510,6 +603,17 @@ hipError_t tsweep_launch(const BatchArgs& b, const TeamArgs& ta, int t, hipStrea
 }
 
 }  // namespace
+
+hipError_t launch_gkkt(const BatchArgs& b, const TGroup* groups, const int2* tasks, int ntasks, hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  switch (b.dtype) {
+    case RAC_DT_F64: k_gkkt<double><<<(unsigned)ntasks, 256, 0, st>>>(b, groups, tasks); break;
+    case RAC_DT_F32: k_gkkt<float><<<(unsigned)ntasks, 256, 0, st>>>(b, groups, tasks); break;
+    case RAC_DT_BF16: k_gkkt<uint16_t><<<(unsigned)ntasks, 256, 0, st>>>(b, groups, tasks); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 int tsweep_max_resident(int32_t dtype, int NT) {
   switch (dtype) {
