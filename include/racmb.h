@@ -262,9 +262,10 @@ typedef struct {
 } rac_batch_opts;
 /* Batched sweep kernels.  LANE: one workgroup per lane, which reads its instance's
  * data on its own.  TEAM: the lanes of an instance in groups of up to 16, advanced
- * together by a team of 16 or 32 workgroups that split the instance's rows, so one
- * read of the data serves the whole group (FP64 matrix-core products); it needs
- * rows_i <= 32 * (64 * NT - 15) for every instance (NT = 10 for BF16 data, 8 otherwise).
+ * together by a team of workgroups that split the instance's rows, so one read of
+ * the data serves the whole group (FP64 matrix-core products).  A group runs on a
+ * team of 16 workgroups when ceil(rows_i/16) + 15 <= 64 NT, else of 32; TEAM needs
+ * ceil(rows_i/32) + 15 <= 64 NT for every instance (NT = 10 for BF16 data, 8 otherwise).
  * AUTO takes TEAM when the batch fits it, else LANE.  Requesting TEAM for a batch
  * that does not fit gives RAC_ERR_UNSUPPORTED.  The two kernels sum in different
  * orders, so their results agree to rounding, not bitwise. */
@@ -282,8 +283,8 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
  * returned when one of its blocks violated Assumption 2.1). */
 rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x, double* z, double* xi);
 /* info (host, 8 int64): lanes, instances, block Gram tasks, inverse tasks, row
- * unroll of the LANE sweep, 1 if chunks are replayed from a hipGraph, workgroups per
- * team of the TEAM sweep (0 when the LANE sweep runs), number of teams. */
+ * unroll of the LANE sweep, 1 if chunks are replayed from a hipGraph, workgroups of
+ * the widest team of the TEAM sweep (0 when the LANE sweep runs), number of teams. */
 rac_status rac_batch_info(rac_batch b, int64_t* info);
 /* Per-phase device time of the batch's launches, as for rac_solver_set_timing /
  * rac_solver_timing (same phases; "factor" is the block inverses).  While timing is

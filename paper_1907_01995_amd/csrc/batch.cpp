@@ -93,8 +93,15 @@ struct rac_batch_s {
   bool team = false;
   TeamArgs TA{};
   std::vector<TGroup> hgroups;
-  std::vector<double> gcost;
-  int max_teams = 0;
+  std::vector<double> gcost;   // predicted cost of a group (LPT key)
+  std::vector<int> gwidth;     // team width a group runs on (16 or 32)
+  int max_teams = 0;           // resident / 16
+  int resident = 0;            // team-sweep workgroups resident at once (the launch size)
+  int k32 = 0, k16 = 0;        // current layout
+  int32_t* dteam_w = nullptr;
+  int64_t* dteam_part = nullptr;
+  int32_t* dblk_team = nullptr;
+  int32_t* dblk_member = nullptr;
   TGroup* dgroups = nullptr;
   int2* dkkt_tasks = nullptr;   // (group, 64-column chunk) of the grouped KKT check
   int nkkt_tasks = 0;
@@ -205,34 +212,84 @@ rac_status state_copy(rac_batch b, bool save, Snapshot& s) {
   return RAC_OK;
 }
 
-// Team layout: the lane groups dealt to nteams teams by longest-processing-time
-// first on their cost (a deterministic function of the batch), uploaded for the
-// sweep.  The layout decides only which workgroups run a group, never its
-// arithmetic, so every layout gives bit-identical results.
-rac_status set_team_layout(rac_batch b, int nteams, int xcd_map) {
-  const int ng = (int)b->hgroups.size();
-  std::vector<int> order(ng);
-  for (int g = 0; g < ng; ++g) order[g] = g;
+// Longest-processing-time assignment of the groups of one team width to k teams;
+// returns the largest team load and fills lists.
+double lpt(const rac_batch b, int width, int k, std::vector<std::vector<int32_t>>* lists) {
+  if (lists) lists->assign(k, {});
+  if (k <= 0) return 0.0;
+  std::vector<int> order;
+  for (int g = 0; g < (int)b->hgroups.size(); ++g)
+    if (b->gwidth[g] == width) order.push_back(g);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->gcost[x] > b->gcost[y]; });
-  std::vector<double> load(nteams, 0.0);
-  std::vector<std::vector<int32_t>> lists(nteams);
+  std::vector<double> load(k, 0.0);
   for (int g : order) {
     int best = 0;
-    for (int k = 1; k < nteams; ++k)
-      if (load[k] < load[best]) best = k;
+    for (int t = 1; t < k; ++t)
+      if (load[t] < load[best]) best = t;
     load[best] += b->gcost[g];
-    lists[best].push_back(g);
+    if (lists) (*lists)[best].push_back(g);
   }
-  std::vector<int32_t> off(nteams + 1, 0), flat;
-  for (int k = 0; k < nteams; ++k) {
-    off[k] = (int32_t)flat.size();
-    flat.insert(flat.end(), lists[k].begin(), lists[k].end());
+  return *std::max_element(load.begin(), load.end());
+}
+
+// Team layout with k32 teams of 32 workgroups and k16 teams of 16 (a group runs
+// on a team of its own width, so its arithmetic never depends on the layout and
+// every layout gives bit-identical results).  Teams are placed inside one XCD
+// each when the resident workgroups split evenly over the eight XCDs; the table
+// gives every workgroup of the launch its team (or -1) and member index.  The
+// epoch flags restart from zero, since a team may change its width.
+rac_status set_team_layout(rac_batch b, int k32, int k16) {
+  std::vector<std::vector<int32_t>> l32, l16;
+  lpt(b, 32, k32, &l32);
+  lpt(b, 16, k16, &l16);
+  const int nteams = k32 + k16;
+  std::vector<int32_t> off(nteams + 1, 0), flat, tw(nteams);
+  std::vector<int64_t> tpart(nteams);
+  int64_t poff = 0;
+  for (int t = 0; t < nteams; ++t) {
+    const std::vector<int32_t>& L = t < k32 ? l32[t] : l16[t - k32];
+    off[t] = (int32_t)flat.size();
+    flat.insert(flat.end(), L.begin(), L.end());
+    tw[t] = t < k32 ? 32 : 16;
+    tpart[t] = poff;
+    poff += 2 * 1024 * (int64_t)tw[t];
   }
   off[nteams] = (int32_t)flat.size();
+  const int R = b->resident;
+  std::vector<int32_t> bt(R, -1), bm(R, 0);
+  if (R % 8 == 0 && R / 8 >= 32) {
+    const int per = R / 8;
+    std::vector<int> used(8, 0);
+    for (int t = 0; t < nteams; ++t) {       // widest first: teams of 32, then of 16
+      int x = 0;
+      while (x < 8 && used[x] + tw[t] > per) ++x;
+      if (x == 8) return RAC_ERR_ARG;        // cannot happen: the widths sum to at most R
+      for (int m = 0; m < tw[t]; ++m) {
+        const int blk = 8 * (used[x] + m) + x;
+        bt[blk] = t;
+        bm[blk] = m;
+      }
+      used[x] += tw[t];
+    }
+  } else {
+    int next = 0;
+    for (int t = 0; t < nteams; ++t)
+      for (int m = 0; m < tw[t]; ++m, ++next) { bt[next] = t; bm[next] = m; }
+  }
+  BCHK(hipDeviceSynchronize());
   BCHK(hipMemcpy(b->dteam_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice));
-  BCHK(hipMemcpy(b->dteam_list, flat.data(), sizeof(int32_t) * flat.size(), hipMemcpyHostToDevice));
+  if (!flat.empty())
+    BCHK(hipMemcpy(b->dteam_list, flat.data(), sizeof(int32_t) * flat.size(), hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(b->dteam_w, tw.data(), sizeof(int32_t) * nteams, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(b->dteam_part, tpart.data(), sizeof(int64_t) * nteams, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(b->dblk_team, bt.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice));
+  BCHK(hipMemcpy(b->dblk_member, bm.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice));
+  BCHK(hipMemset(b->TA.flags, 0, sizeof(uint32_t) * (size_t)b->max_teams * 128));
+  BCHK(hipDeviceSynchronize());
   b->TA.nteams = nteams;
-  b->TA.xcd_map = xcd_map;
+  b->TA.nblocks = R;
+  b->k32 = k32;
+  b->k16 = k16;
   if (b->gexec) {   // a captured graph holds the old launch configuration
     (void)hipGraphExecDestroy(b->gexec);
     (void)hipGraphDestroy(b->graph);
@@ -242,28 +299,33 @@ rac_status set_team_layout(rac_batch b, int nteams, int xcd_map) {
   return RAC_OK;
 }
 
-// Default team layout: as many teams as fit (a multiple of 8 so that each team
-// stays on one XCD), but no more than the groups need.
-void default_layout(rac_batch b, int& nteams, int& xcd) {
-  const int ng = (int)b->hgroups.size();
-  nteams = b->max_teams;
-  xcd = b->max_teams % 8 == 0 ? 1 : 0;
-  if (xcd) {
-    const int need = (ng + 7) / 8 * 8;
-    if (need < nteams) nteams = need;
-  } else if (ng < nteams) {
-    nteams = ng;
+// Layouts worth trying, best predicted first: every split of the resident
+// workgroups into teams of 32 and 16 that gives each width it needs a team,
+// ranked by the largest predicted team load.
+std::vector<std::pair<int, int>> team_layouts(rac_batch b) {
+  bool need32 = false, need16 = false;
+  for (int w : b->gwidth) (w == 32 ? need32 : need16) = true;
+  const int R = b->resident;
+  std::vector<std::pair<double, std::pair<int, int>>> c;
+  for (int k32 = 0; 32 * k32 <= R; ++k32) {
+    const int k16 = (R - 32 * k32) / 16;
+    if ((need32 && k32 == 0) || (need16 && k16 == 0)) continue;
+    const int u32 = need32 ? k32 : 0, u16 = need16 ? k16 : 0;
+    c.push_back({std::max(lpt(b, 32, u32, nullptr), lpt(b, 16, u16, nullptr)), {u32, u16}});
   }
+  std::stable_sort(c.begin(), c.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+  std::vector<std::pair<int, int>> out;
+  for (auto& e : c)
+    if (std::find(out.begin(), out.end(), e.second) == out.end()) out.push_back(e.second);
+  return out;
 }
 
-// Time one chunk with each team layout (from the same state) and keep the fastest.
+// Time one chunk with each of the best predicted team layouts (from the same
+// state) and keep the fastest.
 rac_status autotune_team(rac_batch b) {
   const std::string path = tune_cache_path();
-  int nt0 = 0, x0 = 0;
-  default_layout(b, nt0, x0);
-  std::vector<std::pair<int, int>> cand = {{nt0, x0}};
-  if (x0) cand.push_back({nt0, 0});
-  if (x0 && nt0 / 2 >= 8 && (nt0 / 2) % 8 == 0) cand.push_back({nt0 / 2, 1});
+  std::vector<std::pair<int, int>> cand = team_layouts(b);
+  if (cand.size() > 3) cand.resize(3);
   if (FILE* f = std::fopen(path.c_str(), "r")) {
     char line[640], key[512];
     int a = 0, c = 0;
@@ -491,34 +553,34 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
       hipMemset(A.U, 0, sizeof(double) * uoff) != hipSuccess)
     return fail(RAC_ERR_DEVICE);
   b->host_active = nlanes;
-  // ---- team sweep: lane groups (up to 16 lanes of one instance), team size, tiles
+  // ---- team sweep: lane groups (up to 16 lanes of one instance), each run by a
+  // team of 16 workgroups when the instance's rows fit 16 members, else of 32
   if (O.sweep != RAC_BSWEEP_LANE) {
     std::vector<std::vector<int>> by_inst(ninst);
     for (int u = 0; u < nlanes; ++u) by_inst[lanes[u].problem].push_back(u);
-    int64_t maxrows = 0;
-    for (int i = 0; i < ninst; ++i)
-      if (!by_inst[i].empty() && inst[i].rows > maxrows) maxrows = inst[i].rows;
     const int ntmax = dtype == RAC_DT_BF16 ? 10 : 8;
-    int W = 0, NT = 0;
-    for (int cw : {16, 32}) {
-      const int64_t need = (maxrows + cw - 1) / cw + 15;
-      if (need <= 64 * ntmax) {
-        W = cw;
-        NT = need <= 64 * 8 ? 8 : ntmax;
-        break;
-      }
+    auto member_rows = [](int64_t rows, int w) { return (rows + w - 1) / w + 15; };   // bound on a member's rows
+    bool fits = true;
+    int64_t need = 0;
+    std::vector<int> width(ninst, 0);
+    for (int i = 0; i < ninst; ++i) {
+      if (by_inst[i].empty()) continue;
+      width[i] = member_rows(inst[i].rows, 16) <= 64 * ntmax ? 16 : 32;
+      if (member_rows(inst[i].rows, width[i]) > 64 * ntmax) fits = false;
+      need = std::max<int64_t>(need, member_rows(inst[i].rows, width[i]));
     }
-    const int resident = W ? tsweep_max_resident(dtype, NT) : 0;
-    int maxt = W ? resident / W : 0;
-    if (maxt >= 8) maxt -= maxt % 8;
-    if (maxt >= 1) {
+    const int NT = need <= 64 * 8 ? 8 : ntmax;
+    const int resident = fits ? tsweep_max_resident(dtype, NT) : 0;
+    if (resident >= 32) {
       const int esz = dtype == RAC_DT_F64 ? 8 : (dtype == RAC_DT_F32 ? 4 : 2);
       for (int i = 0; i < ninst; ++i) {
+        if (by_inst[i].empty()) continue;
         const rac_problem& P = inst[i];
         const int vec4 = (P.ldF % 4 == 0) && ((uintptr_t)P.F % (uintptr_t)(4 * esz) == 0);
         const int vec8 = (P.ldF % 8 == 0) && ((uintptr_t)P.F % 16 == 0);
-        const int64_t rw = (P.rows + W - 1) / W;
-        const double cost = (double)b->hinst[i].p * (double)((rw + 63) / 64 + 3);
+        // predicted time of one of the group's blocks (us): exchanges plus the member's products
+        const double rw = (double)((P.rows + width[i] - 1) / width[i]);
+        const double cost = (double)b->hinst[i].p * (14.0 + 12.0 * rw / 640.0);
         for (size_t g0 = 0; g0 < by_inst[i].size(); g0 += 16) {
           TGroup G{};
           G.inst = i;
@@ -528,14 +590,18 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
           for (int q = 0; q < 16; ++q) G.lane[q] = q < G.nl ? by_inst[i][g0 + q] : -1;
           b->hgroups.push_back(G);
           b->gcost.push_back(cost);
+          b->gwidth.push_back(width[i]);
         }
       }
       const int ng = (int)b->hgroups.size();
+      const int maxt = resident / 16;
+      b->resident = resident;
       b->max_teams = maxt;
-      b->TA.W = W;
       b->TA.NT = NT;
       ok = b->buf.alloc(&b->dgroups, ng) && b->buf.alloc(&b->dteam_off, maxt + 1) &&
-           b->buf.alloc(&b->dteam_list, ng) && b->buf.alloc(&b->TA.part, (size_t)maxt * 2 * W * 1024) &&
+           b->buf.alloc(&b->dteam_list, ng) && b->buf.alloc(&b->dteam_w, maxt) &&
+           b->buf.alloc(&b->dteam_part, maxt) && b->buf.alloc(&b->dblk_team, resident) &&
+           b->buf.alloc(&b->dblk_member, resident) && b->buf.alloc(&b->TA.part, (size_t)resident * 2 * 1024) &&
            b->buf.alloc(&b->TA.delta, (size_t)maxt * 2 * 1024) && b->buf.alloc(&b->TA.flags, (size_t)maxt * 128) &&
            b->buf.alloc(&b->TA.abort_flag, 1);
       if (!ok) return fail(RAC_ERR_NOMEM);
@@ -546,17 +612,20 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
       if (!b->buf.alloc(&b->dkkt_tasks, kt.size())) return fail(RAC_ERR_NOMEM);
       if (hipMemcpy(b->dkkt_tasks, kt.data(), sizeof(int2) * kt.size(), hipMemcpyHostToDevice) != hipSuccess ||
           hipMemcpy(b->dgroups, b->hgroups.data(), sizeof(TGroup) * ng, hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemset(b->TA.flags, 0, sizeof(uint32_t) * (size_t)maxt * 128) != hipSuccess ||
           hipMemset(b->TA.abort_flag, 0, sizeof(uint32_t)) != hipSuccess ||
           hipMemset(b->TA.delta, 0, sizeof(double) * (size_t)maxt * 2 * 1024) != hipSuccess)
         return fail(RAC_ERR_DEVICE);
       b->TA.groups = b->dgroups;
       b->TA.team_off = b->dteam_off;
       b->TA.team_list = b->dteam_list;
+      b->TA.team_w = b->dteam_w;
+      b->TA.team_part = b->dteam_part;
+      b->TA.blk_team = b->dblk_team;
+      b->TA.blk_member = b->dblk_member;
       b->team = true;
-      int nt = 0, xcd = 0;
-      default_layout(b, nt, xcd);
-      const rac_status r = set_team_layout(b, nt, xcd);
+      const std::vector<std::pair<int, int>> lay = team_layouts(b);
+      if (lay.empty()) return fail(RAC_ERR_UNSUPPORTED);
+      const rac_status r = set_team_layout(b, lay[0].first, lay[0].second);
       if (r != RAC_OK) return fail(r);
     } else if (O.sweep == RAC_BSWEEP_TEAM) {
       return fail(RAC_ERR_UNSUPPORTED);
@@ -565,9 +634,13 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
   if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) return fail(RAC_ERR_DEVICE);
   if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return fail(RAC_ERR_DEVICE);
   char key[256];
-  if (b->team)
-    std::snprintf(key, sizeof(key), "tsweep:dt%d:sp%d:lanes%d:groups%d:rows%lld:W%d:NT%d:T%d:gfx950", dtype, b->SP,
-                  nlanes, (int)b->hgroups.size(), (long long)(rows_sum / 1024), b->TA.W, b->TA.NT, b->T);
+  if (b->team) {
+    int n32 = 0;
+    for (int w : b->gwidth) n32 += w == 32;
+    std::snprintf(key, sizeof(key), "tsweep2:dt%d:sp%d:lanes%d:groups%d:g32_%d:rows%lld:NT%d:R%d:T%d:gfx950", dtype,
+                  b->SP, nlanes, (int)b->hgroups.size(), n32, (long long)(rows_sum / 1024), b->TA.NT, b->resident,
+                  b->T);
+  }
   else
     std::snprintf(key, sizeof(key), "bsweep:dt%d:sp%d:lanes%d:rows%lld:T%d:gfx950", dtype, b->SP, nlanes,
                   (long long)(rows_sum / 1024), b->T);
@@ -688,7 +761,7 @@ rac_status rac_batch_info(rac_batch b, int64_t* info) {
   info[3] = b->A.ninv;
   info[4] = b->A.unroll;
   info[5] = b->graph_used ? 1 : 0;
-  info[6] = b->team ? b->TA.W : 0;
+  info[6] = b->team ? (b->k32 > 0 ? 32 : 16) : 0;
   info[7] = b->team ? b->TA.nteams : 0;
   return RAC_OK;
 }

@@ -10,7 +10,7 @@
 // (v_mfma_f64_16x16x4f64: the u vectors and the steps are FP64, so the products
 // are as exact as the single-lane FP64 path).
 //
-// Work split.  A team of W workgroups (W in {16, 32}) processes a list of
+// Work split.  A team of W workgroups (W = 16 or 32, per team) processes a list of
 // lane groups one after another; for each group, member w owns a contiguous
 // slice of the instance's rows and holds u of those rows for all 16 lanes in
 // registers for the whole sweep (four wavefronts, 16-row tiles dealt round-robin).  Per block:
@@ -27,8 +27,9 @@
 // Partials and steps are double-buffered by epoch parity.  The flags are
 // monotone epochs that persist between launches: every member of a team
 // advances its epochs by the same count per launch, so a member's own flag at
-// launch start is the team's base.  Teams are mapped onto one XCD each
-// (workgroup b runs on XCD b mod 8), so that their exchanges stay in one L2.
+// launch start is the team's base.  The host's layout table gives each
+// workgroup its team and member index; teams of 16 and 32 workgroups are placed
+// within one XCD each (workgroup b runs on XCD b mod 8).
 // All members of all teams are resident at once (the grid never exceeds the
 // occupancy limit of the device), which every wait relies on.
 #include "control.h"
@@ -130,19 +131,13 @@ template <typename T, int NT>
 __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, int t) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q = lane >> 4, j = lane & 15;
-  const int W = TA.W;
-  int team, w;
-  if (TA.xcd_map) {
-    const int b = (int)blockIdx.x, slot = b >> 3;
-    team = (slot / W) * 8 + (b & 7);
-    w = slot % W;
-  } else {
-    team = (int)blockIdx.x / W;
-    w = (int)blockIdx.x % W;
-  }
+  const int team = TA.blk_team[blockIdx.x];
+  if (team < 0) return;                      // idle workgroup of the layout (no barrier reached)
+  const int w = TA.blk_member[blockIdx.x];
+  const int W = TA.team_w[team];
   uint32_t* fl_part = TA.flags + (int64_t)team * 128;
   uint32_t* fl_step = fl_part + 64;
-  double* part = TA.part + (int64_t)team * 2 * W * 1024;
+  double* part = TA.part + TA.team_part[team];
   double* delta = TA.delta + (int64_t)team * 2 * 1024;
   uint32_t e = ld_flag(fl_part + w);
   // Two-byte data: the member's rows of the block's columns are staged in LDS
@@ -587,7 +582,7 @@ int tsweep_resident_nt(int NT) {
 
 template <typename T, int NT>
 hipError_t tsweep_go(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st) {
-  k_tsweep<T, NT><<<(unsigned)(ta.nteams * ta.W), NW * 64, 0, st>>>(b, ta, t);
+  k_tsweep<T, NT><<<(unsigned)ta.nblocks, NW * 64, 0, st>>>(b, ta, t);
   return hipGetLastError();
 }
 
