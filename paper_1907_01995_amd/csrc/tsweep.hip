@@ -219,8 +219,9 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
     // needs one base address and the loads of four neighbouring threads cover
     // 64 contiguous bytes.  Every load is in range: a column past the block's
     // width re-reads the block's first column and a chunk past the member's
-    // rows re-reads its last chunk; neither is stored, and chunks past the rows
-    // up to the last tile store zeros instead.
+    // rows re-reads its last chunk; both store zeros instead, so the slice is
+    // zero outside the block's columns and the member's rows and the products
+    // read it without masks.
     auto slice_load = [&](const int32_t* ccols, int sbk) {
       const int c = tid >> 2, sub = tid & 3;
       const bool cv = c < sbk;
@@ -237,9 +238,10 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
           sv[i] = *reinterpret_cast<const uint4*>(base + 8 * (k <= lastk ? k : lastk));
         }
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
+        for (int i = 0; i < PER; ++i) {       // columns past the block's width are zeroed too
           const int k = sub + 4 * i;
-          if (cv && k < cpc) *reinterpret_cast<uint4*>(&slice[c * SL + 8 * k]) = k <= lastk ? sv[i] : make_uint4(0u, 0u, 0u, 0u);
+          if (k < cpc)
+            *reinterpret_cast<uint4*>(&slice[c * SL + 8 * k]) = (cv && k <= lastk) ? sv[i] : make_uint4(0u, 0u, 0u, 0u);
         }
         if (nr & 7) {
           __syncthreads();
@@ -250,10 +252,10 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
         const uint16_t* base = (const uint16_t*)F + (int64_t)ccols[cv ? c : 0] * ldF + rb;
         for (int i = 0; i < PER; ++i) {
           const int k = sub + 4 * i;
-          if (cv && k < cpc) {
+          if (k < cpc) {
             uint32_t h[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) h[e] = 8 * k + e < nr ? (uint32_t)base[8 * k + e] : 0u;
+            for (int e = 0; e < 8; ++e) h[e] = (cv && 8 * k + e < nr) ? (uint32_t)base[8 * k + e] : 0u;
             *reinterpret_cast<uint4*>(&slice[c * SL + 8 * k]) =
                 make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
           }
@@ -302,8 +304,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
 #pragma unroll
               for (int ct = 0; ct < 4; ++ct) {
                 const int c = 16 * ct + j;
-                const uint2 r = c < sb ? *reinterpret_cast<const uint2*>(&slice[c * SL + 16 * tile + 4 * q])
-                                       : make_uint2(0u, 0u);
+                const uint2 r = *reinterpret_cast<const uint2*>(&slice[c * SL + 16 * tile + 4 * q]);
                 const double f[4] = {(double)__uint_as_float(r.x << 16), (double)__uint_as_float(r.x & 0xffff0000u),
                                      (double)__uint_as_float(r.y << 16), (double)__uint_as_float(r.y & 0xffff0000u)};
 #pragma unroll
@@ -415,8 +416,8 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
 #pragma unroll
               for (int m = 0; m < 16; m += 2) {
                 const int c0 = 4 * m + q, c1 = c0 + 4;
-                const uint32_t h0 = c0 < sb ? (uint32_t)slice[c0 * SL + 16 * tile + rpi] : 0u;
-                const uint32_t h1 = c1 < sb ? (uint32_t)slice[c1 * SL + 16 * tile + rpi] : 0u;
+                const uint32_t h0 = slice[c0 * SL + 16 * tile + rpi];
+                const uint32_t h1 = slice[c1 * SL + 16 * tile + rpi];
                 a0 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)__uint_as_float(h0 << 16), dreg[m], a0, 0, 0, 0);
                 a1 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)__uint_as_float(h1 << 16), dreg[m + 1], a1, 0, 0, 0);
               }
