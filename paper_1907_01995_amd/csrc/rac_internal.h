@@ -148,13 +148,13 @@ struct TeamArgs {
   const int32_t* team_off; // groups of team k: team_list[team_off[k] .. team_off[k+1])
   const int32_t* team_list;
   const int32_t* team_w;   // workgroups of team k (16 or 32)
-  const int64_t* team_part;// offset (doubles) of team k's partial area [2][W_k][64*16]
+  const int64_t* team_part;// offset (doubles) of team k's partial area [2][16 slots][W_k][64 columns]
   const int32_t* blk_team; // team of workgroup b (-1: idle), and its member index
   const int32_t* blk_member;
   int nteams; int nblocks; // teams, workgroups launched
   int NT;                  // register tiles of 16 rows per wavefront (8, or 10 for BF16 data)
   double* part;            // gradient partials of all teams
-  double* delta;           // [nteams][2][16][64] steps
+  double* delta;           // [nteams][2][64 columns][16 slots] steps
   uint32_t* flags;         // [nteams][128]: [0, 64) partial epochs, [64, 128) step epochs
   uint32_t* abort_flag;    // raised when a wait gives up (the batch is then unusable)
 };

@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
       __syncthreads();
       {
         const int ln = tid & 63, qq = ln >> 4, jj = ln & 15;
-        double* dst = part + ((int64_t)par * W + w) * 1024;
+        double* dst = part + (int64_t)par * 16 * W * 64;   // [slot][member][column]
 #pragma unroll
         for (int rr = 0; rr < 16 / NW; ++rr) {
           const int el = (16 / NW) * (tid >> 6) + rr;          // = 4 ct + r
@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
 #pragma unroll
           for (int vv = 0; vv < NW; ++vv) v += red[vv][el][ln];
           const int col = 16 * (el >> 2) + 4 * (el & 3) + qq;
-          st_c(dst + col * 16 + jj, v);
+          st_c(dst + ((int64_t)jj * W + w) * 64 + col, v);
         }
       }
       __builtin_amdgcn_s_waitcnt(0);         // partial stores complete at device scope
@@ -371,10 +371,10 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
         if (!wait_team(fl_part, W, e, lane, TA.abort_flag) && lane == 0) give_up = 1;
         double s = 0.0;
         if (lane < sb) {
-          const double* pp = part + (int64_t)par * W * 1024 + lane * 16 + L;
+          const double* pp = part + ((int64_t)par * 16 + L) * W * 64 + lane;   // member m at + 64 m
           double v[32];
 #pragma unroll
-          for (int m = 0; m < 32; ++m) v[m] = ld_c(pp + (int64_t)(m < W ? m : 0) * 1024);
+          for (int m = 0; m < 32; ++m) v[m] = ld_c(pp + (int64_t)(m < W ? m : 0) * 64);
 #pragma unroll
           for (int m = 0; m < 32; ++m) v[m] = m < W ? v[m] : 0.0;
 #pragma unroll
@@ -390,7 +390,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
         for (int k = 0; k < 64; ++k) dq[k & 3] += Ml[k * 64 + lane] * shg[wave][k];
         odel = lane < sb ? -((dq[0] + dq[1]) + (dq[2] + dq[3])) : 0.0;
         if (OU->a) ot += wave_sum(acol * odel);
-        st_c(delta + ((int64_t)par * 16 + L) * 64 + lane, odel);
+        st_c(delta + ((int64_t)par * 64 + lane) * 16 + L, odel);   // [column][slot]
         __builtin_amdgcn_s_waitcnt(0);
       }
       __syncthreads();
@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
       {
         double dreg[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) dreg[m] = ld_c(delta + ((int64_t)par * 16 + j) * 64 + 4 * m + q);
+        for (int m = 0; m < 16; ++m) dreg[m] = ld_c(delta + ((int64_t)par * 64 + 4 * m + q) * 16 + j);
 #pragma unroll
         for (int m = 0; m < 16; ++m) dreg[m] = actj ? dreg[m] : 0.0;   // slots without an active lane
         if constexpr (kSlice) {
