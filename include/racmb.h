@@ -109,7 +109,10 @@ typedef struct {
                            stream during the sweep when all sweep groups fit on the device;
                            negative: one stream.  Overlapped solvers assume no other solver's
                            sweep runs on the device at the same time. */
-  int32_t pad0;
+  int32_t packed;       /* 0 (default): with the register-tile sweep, the Gram kernel also copies
+                           each iteration's blocks into the sweep's register order (two copies of
+                           about F's size, by iteration parity); negative: the sweep gathers the
+                           block columns from F. */
 } rac_opts;
 
 typedef struct {
@@ -146,8 +149,9 @@ rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, 
                                 double* beta, int64_t* iter, void* stream);
 
 /* Phase timing (HIP events on the run's stream, accumulated over runs until the
- * next rac_solver_set_timing call).  Phases, in order: partition draw, block Gram,
- * block factor, sweep, z/dual step, KKT check + penalty rule. */
+ * next rac_solver_set_timing call).  Phases, in order: partition draw, block Gram
+ * (with the packed copy, when the solver keeps one), block factor, sweep, z/dual
+ * step, KKT check + penalty rule. */
 #define RAC_NUM_PHASES 6
 enum { RAC_PHASE_PARTITION = 0, RAC_PHASE_GRAM = 1, RAC_PHASE_FACTOR = 2, RAC_PHASE_SWEEP = 3,
        RAC_PHASE_ZDUAL = 4, RAC_PHASE_CHECK = 5 };

@@ -51,43 +51,63 @@ constexpr int KT = 64;                // rows per LDS tile
 // One workgroup: block `blk`, rows [rb, re).  Data move as 16-byte vectors of
 // VE = 16/sizeof(T) consecutive rows of one column; the next 64-row tile is
 // loaded into registers while the matrix cores work on the current one.
-template <typename T, int MODE, int SP>
+// X (cross): the columns of blocks blk and blk+1 are staged together and every
+// 16 x 16 tile of F_{blk+1}' F_blk is formed (out[row of blk+1][column of blk]).
+// With a packed destination (pk.Fp non-null) the loaded values of the block's
+// real entries are also written, unchanged, to the sweep's register-order copy:
+// entry (row r, column m of block blk) goes to
+//   ((((blk K + g) 4 + m % 4) B + m / 4) 64 A) + (r - g RW),   g = r / RW.
+// Positions no real entry maps to (short blocks, rows past the end, group
+// padding) are never written; the buffer is zeroed once when it is created.
+template <typename T, int MODE, int SP, bool X = false>
 __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, int64_t rows, int64_t n,
                                           int64_t p, const int32_t* __restrict__ perm, int blk, int chunk,
-                                          int R, int vec, double* __restrict__ out) {
+                                          int R, int vec, double* __restrict__ out,
+                                          PackDst pk = PackDst{}) {
   typedef GramTraits<MODE> Tr;
   typedef typename Tr::E E;
   typedef typename Tr::Acc Acc;
   constexpr int VE = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int VPC = KT / VE;                  // vectors per column per tile
-  constexpr int NVEC = SP * VPC;
+  constexpr int NCOL = X ? 2 * SP : SP;         // staged columns
+  constexpr int NVEC = NCOL * VPC;
   constexpr int NV = (NVEC + 255) / 256;        // vectors per thread per tile
   constexpr int LD = KT + Tr::PAD;              // LDS row stride of the column-major tile
-  constexpr int NT = SP / 16, NPAIR = NT * (NT + 1) / 2;
+  constexpr int NT = SP / 16, NPAIR = X ? NT * NT : NT * (NT + 1) / 2;
   constexpr int MAXP = (NPAIR + 3) / 4;
-  __shared__ __attribute__((aligned(16))) E tile[SP * LD];   // tile[m * LD + k] = F[r0 + k, col_m]
-  __shared__ int64_t colbase[SP];
+  __shared__ __attribute__((aligned(16))) E tile[NCOL * LD];   // tile[m * LD + k] = F[r0 + k, col_m]
+  __shared__ int64_t colbase[NCOL];
 
   const int64_t s0 = block_start(blk, n, p);
   const int sb = (int)(block_start(blk + 1, n, p) - s0);
+  const int64_t s1 = block_start(blk + 1, n, p);
+  const int sb1 = X ? (int)(block_start(blk + 2, n, p) - s1) : 0;
   // row chunks are whole tiles except the last
   const int64_t ntiles = (rows + KT - 1) / KT;
   const int64_t rb = block_start(chunk, ntiles, R) * KT;
   const int64_t re_t = block_start(chunk + 1, ntiles, R) * KT;
   const int64_t re = re_t < rows ? re_t : rows;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int m = tid; m < SP; m += 256) colbase[m] = m < sb ? (int64_t)perm[s0 + m] * ldF : -1;
+  for (int m = tid; m < NCOL; m += 256) {
+    if (m < SP) colbase[m] = m < sb ? (int64_t)perm[s0 + m] * ldF : -1;
+    else colbase[m] = m - SP < sb1 ? (int64_t)perm[s1 + m - SP] * ldF : -1;
+  }
 
   Acc acc[MAXP];
   int pti[MAXP], ptj[MAXP];
 #pragma unroll
   for (int q = 0; q < MAXP; ++q) {
     acc[q] = Acc{0, 0, 0, 0};
-    int pr = wave + 4 * q;               // pair index -> (ti >= tj), row-major over the lower triangle
-    int ti = 0;
-    while ((ti + 1) * (ti + 2) / 2 <= pr) ++ti;
-    pti[q] = ti;
-    ptj[q] = pr - ti * (ti + 1) / 2;
+    int pr = wave + 4 * q;
+    if constexpr (X) {                   // pair index -> (ti of block blk+1, tj of block blk)
+      pti[q] = pr / NT;
+      ptj[q] = pr % NT;
+    } else {                             // pair index -> (ti >= tj), row-major over the lower triangle
+      int ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= pr) ++ti;
+      pti[q] = ti;
+      ptj[q] = pr - ti * (ti + 1) / 2;
+    }
   }
   __syncthreads();
 
@@ -121,16 +141,45 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
       }
     }
   };
+  // the staged vectors of this tile (rows r0 ..) into the packed copy
+  auto pack = [&](int64_t r0) {
+    T* Fp = (T*)pk.Fp;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int v = tid + 256 * q;
+      const int m = v / VPC, seg = v % VPC;
+      if (v >= NVEC || m >= sb || X) continue;
+      const int64_t r = r0 + seg * VE;
+      if (r >= re) continue;
+      const int g = (int)(r / pk.RW);
+      const int64_t rr = r - (int64_t)g * pk.RW;
+      T* dst = Fp + (((((int64_t)blk * pk.K + g) * 4 + (m & 3)) * pk.B + (m >> 2)) * 64) * pk.A;
+      if (r + VE <= re && rr + VE <= pk.RW && (rr % VE) == 0) {
+        uint4 raw;
+        T* e = reinterpret_cast<T*>(&raw);
+#pragma unroll
+        for (int u = 0; u < VE; ++u) e[u] = stage[q][u];
+        *reinterpret_cast<uint4*>(dst + rr) = raw;
+      } else {
+        for (int u = 0; u < VE && r + u < re; ++u) {
+          const int gu = (int)((r + u) / pk.RW);
+          Fp[(((((int64_t)blk * pk.K + gu) * 4 + (m & 3)) * pk.B + (m >> 2)) * 64) * pk.A +
+             (r + u - (int64_t)gu * pk.RW)] = stage[q][u];
+        }
+      }
+    }
+  };
 
   if (rb < re) load(rb);
   for (int64_t r0 = rb; r0 < re; r0 += KT) {
+    if (pk.Fp) pack(r0);
     store();
     __syncthreads();
     if (r0 + KT < re) load(r0 + KT);     // next tile in flight during the MFMAs
 #pragma unroll
     for (int q = 0; q < MAXP; ++q) {
       if (wave + 4 * q < NPAIR) {
-        const int am = pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
+        const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
         if constexpr (MODE == G_F64) {
 #pragma unroll
           for (int kk = 0; kk < KT; kk += 4) {
@@ -174,13 +223,35 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
   }
 }
 
+// Cross-Grams of the block pairs (2w, 2w+1): one workgroup per (pair, row chunk).
+template <typename T, int MODE, int SP>
+__global__ void __launch_bounds__(256) k_xgram(const T* __restrict__ F, int64_t ldF, int64_t rows,
+                                               int64_t n, int64_t p, const int32_t* __restrict__ perm,
+                                               int R, int vec, double* __restrict__ partial) {
+  const int w = blockIdx.x, chunk = blockIdx.y;
+  gram_body<T, MODE, SP, true>(F, ldF, rows, n, p, perm, 2 * w, chunk, R, vec,
+                               partial + ((int64_t)w * R + chunk) * (int64_t)SP * SP);
+}
+
+// C_w = (sum of the R chunk partials, in order) / Ns.
+__global__ void __launch_bounds__(256) k_xsum(const double* __restrict__ partial, int R, int spsq, double Ns,
+                                              double* __restrict__ C) {
+  const int w = blockIdx.x;
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (e >= spsq) return;
+  const double* q = partial + (int64_t)w * R * spsq + e;
+  double s = 0.0;
+  for (int r = 0; r < R; ++r) s += q[(int64_t)r * spsq];
+  C[(int64_t)w * spsq + e] = s / Ns;
+}
+
 template <typename T, int MODE, int SP>
 __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t ldF, int64_t rows,
                                               int64_t n, int64_t p, const int32_t* __restrict__ perm,
-                                              int R, int vec, double* __restrict__ partial) {
+                                              int R, int vec, double* __restrict__ partial, PackDst pk) {
   const int blk = blockIdx.x, chunk = blockIdx.y;
   gram_body<T, MODE, SP>(F, ldF, rows, n, p, perm, blk, chunk, R, vec,
-                         partial + ((int64_t)blk * R + chunk) * (int64_t)SP * SP);
+                         partial + ((int64_t)blk * R + chunk) * (int64_t)SP * SP, pk);
 }
 
 // Batched form: one workgroup per (instance, block) task of a batch; the Gram of
@@ -348,7 +419,7 @@ hipError_t gram_launch(const GramArgs& g, hipStream_t st) {
 #define RAC_GRAM(SPV)                                                                          \
   if (g.sp == SPV) {                                                                           \
     k_gram<T, MODE, SPV><<<grid, 256, 0, st>>>(F, g.ldF, g.rows, g.n, g.p, g.perm, g.R, vec,   \
-                                               g.partial);                                    \
+                                               g.partial, g.pack);                            \
     return hipGetLastError();                                                                 \
   }
   RAC_GRAM(16) RAC_GRAM(32) RAC_GRAM(64) RAC_GRAM(128)
@@ -356,7 +427,44 @@ hipError_t gram_launch(const GramArgs& g, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+template <typename T, int MODE>
+hipError_t xgram_launch(const GramArgs& g, hipStream_t st) {
+  const int nw = (int)(g.p / 2);
+  if (nw == 0) return hipSuccess;
+  dim3 grid((unsigned)nw, (unsigned)g.R);
+  const int vec = (g.ldF % (16 / (int)sizeof(T)) == 0) && ((uintptr_t)g.F % 16 == 0);
+  const T* F = (const T*)g.F;
+#define RAC_XGRAM(SPV)                                                                         \
+  if (g.sp == SPV) {                                                                           \
+    k_xgram<T, MODE, SPV><<<grid, 256, 0, st>>>(F, g.ldF, g.rows, g.n, g.p, g.perm, g.R, vec,  \
+                                                g.partial);                                   \
+    return hipGetLastError();                                                                 \
+  }
+  RAC_XGRAM(16) RAC_XGRAM(32) RAC_XGRAM(64)
+#undef RAC_XGRAM
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+hipError_t launch_xgram(const GramArgs& g, double Ns, double* C, hipStream_t st) {
+  const int nw = (int)(g.p / 2);
+  if (nw == 0) return hipSuccess;
+  const bool mixed = g.precision == RAC_PREC_MIXED;
+  hipError_t e;
+  switch (g.dtype) {
+    case RAC_DT_F64: e = xgram_launch<double, G_F64>(g, st); break;
+    case RAC_DT_F32: e = mixed ? xgram_launch<float, G_F32>(g, st) : xgram_launch<float, G_F64>(g, st); break;
+    case RAC_DT_BF16:
+      e = mixed ? xgram_launch<uint16_t, G_BF16>(g, st) : xgram_launch<uint16_t, G_F64>(g, st);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  const int spsq = g.sp * g.sp;
+  k_xsum<<<dim3((unsigned)nw, (unsigned)((spsq + 255) / 256)), 256, 0, st>>>(g.partial, g.R, spsq, Ns, C);
+  return hipGetLastError();
+}
 
 template <typename T, int MODE>
 hipError_t bgram_launch(const BatchGramArgs& g, hipStream_t st) {

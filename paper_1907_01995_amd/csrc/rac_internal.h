@@ -85,6 +85,13 @@ struct PermWork {          // scratch of the bucketed key sort (per iteration of
 hipError_t launch_permutations(uint64_t seed, uint64_t inst, int64_t iter0, int64_t T, int64_t n,
                                const PermWork& w, int32_t* perm /* [T][n] */, hipStream_t st);
 
+// Destination of the packed copy that the Gram kernel writes for the register-tile
+// sweep (Fp null: none): K groups of RW rows, tiles of 64A rows x 4B columns.
+struct PackDst {
+  void* Fp;
+  int64_t RW;
+  int K, A, B;
+};
 struct GramArgs {
   const void* F; int32_t dtype; int64_t ldF; int64_t rows; int64_t n; int64_t p;
   const int32_t* perm;     // this iteration's permutation
@@ -92,8 +99,12 @@ struct GramArgs {
   int R;                   // row chunks
   int sp;                  // padded block size (multiple of 16, <= 128)
   double* partial;         // [p][R][sp*sp]
+  PackDst pack;            // packed copy written alongside (optional)
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t st);
+// Cross-Grams C_w = F_{2w+1}' F_{2w} / Ns of the block pairs (w < p/2), via row-chunk
+// partials in a.partial ([p/2][R][sp*sp]), into C ([p/2][sp*sp], row = block 2w+1).
+hipError_t launch_xgram(const GramArgs& a, double Ns, double* C, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Batched engine: many instances (each with its own data) and lanes (each an
@@ -194,11 +205,19 @@ struct SweepArgs {
   const double* beta_ptr;  // penalty of this iteration
   int tileA, tileB;        // register tile: rows per lane, columns per wavefront (0: streaming path)
   int cooperative;         // launch with the cooperative API (else a plain launch, K <= resident limit)
+  const double* Cx;        // cross-Grams of the block pairs ([p/2][sp*sp]): windows of two blocks; null: one block
+  const void* Fp;          // packed tiles of this iteration written by the Gram kernel, or null (gather from F)
 };
-// Largest number of sweep workgroups that can be resident at once for a tile shape.
-int sweep_max_resident(int32_t dtype, int A, int B);
+// Rows per sweep group for K groups and A rows per lane (0 if 64A rows do not cover a group).
+int64_t sweep_rows_per_group(int64_t rows, int K, int A);
+// Elements of one packed copy of F for the register-tile sweep: p * K * 256 * A * B.
+int64_t sweep_packed_elems(int64_t p, int K, int A, int B);
+
+// Largest number of sweep workgroups that can be resident at once for a tile shape
+// (windowed: the kernel with windows of two blocks).
+int sweep_max_resident(int32_t dtype, int A, int B, bool windowed = false);
 // Register-tile shapes with a compiled sweep kernel (A rows per lane, B columns per wavefront).
-bool sweep_tile_supported(int32_t dtype, int A, int B);
+bool sweep_tile_supported(int32_t dtype, int A, int B, bool windowed = false);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
 
 struct UpdateArgs {

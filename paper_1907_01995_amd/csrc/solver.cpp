@@ -184,6 +184,9 @@ struct rac_solver_s {
   int mv_nparts = 1;
   double* uz = nullptr;     // F z for the objective
   int tileA = 0, tileB = 0; // register tile of the sweep (0: streaming sweep)
+  uint8_t* Fp = nullptr;    // two packed copies of F in the sweep's register order (by iteration parity)
+  size_t Fp_bytes = 0;      // bytes of one copy
+  int64_t packRW = 0;       // rows per sweep group
   bool overlap = false;     // assemble on a second stream during the previous sweep
   hipStream_t sB = nullptr;
   hipEvent_t ev_start = nullptr, ev_fac[2] = {nullptr, nullptr}, ev_sweep[2] = {nullptr, nullptr};
@@ -280,8 +283,10 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     const double* beta_ptr = sched ? s->d_sched + (run_offset + t) : &s->sc->beta;
     // assemble: the inverse buffer of this parity was last read by the sweep two iterations ago
     if (s->overlap && t >= 2) HIPCHK(hipStreamWaitEvent(sa, s->ev_sweep[par], 0));
+    // the Gram kernel also writes this iteration's packed copy (read by the sweep below)
+    void* Fp = s->Fp ? (void*)(s->Fp + par * s->Fp_bytes) : nullptr;
     GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
-               s->partial};
+               s->partial, PackDst{Fp, s->packRW, s->K, s->tileA, s->tileB}};
     HIPCHK(tm.begin(sa));
     HIPCHK(launch_gram(g, sa));
     HIPCHK(tm.end(RAC_PHASE_GRAM));
@@ -298,7 +303,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     }
     SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, Minv, s->sp, P.c, P.h, P.a,
                 P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
-                beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1};
+                beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, nullptr, Fp};
     HIPCHK(tm.begin(st));
     HIPCHK(launch_sweep(w, st));
     HIPCHK(tm.end(RAC_PHASE_SWEEP));
@@ -392,7 +397,20 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
     }
   }
   if (s->K > s->rows) s->K = (int)s->rows;
+  // overlap the assemble phase with the sweep when all sweep groups fit on the device at once
+  const bool can_overlap = s->tileA > 0 && s->K > 1 &&
+                           s->K <= sweep_max_resident(prob->F_dtype, s->tileA, s->tileB) && O.overlap >= 0;
   s->R = O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows);
+  if (can_overlap && O.row_chunks == 0) {
+    // leave the sweep's K compute units free of Gram workgroups: a sweep group needs
+    // a whole compute unit, so the next iteration's Gram would otherwise delay it
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+      const int64_t cap = (cus - s->K) / s->p;
+      if (cap < s->R) s->R = (int)(cap < 1 ? 1 : cap);
+    }
+  }
   if (s->R > s->rows) s->R = (int)s->rows;
   s->mv_nparts = matvec_parts(n);
 
@@ -427,9 +445,17 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->hist, (size_t)s->hist_cap * 4)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->mv_part, (size_t)s->mv_nparts * s->rows)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->uz, (size_t)s->rows)) != RAC_OK) return fail(r);
-  // overlap the assemble phase with the sweep when all sweep groups fit on the device at once
-  if (s->tileA > 0 && s->K > 1 && s->K <= sweep_max_resident(prob->F_dtype, s->tileA, s->tileB) &&
-      O.overlap >= 0) {
+  // packed copies of the blocks for the register-tile sweep (one per iteration parity)
+  if (s->tileA > 0 && O.packed >= 0) {
+    const size_t esz = prob->F_dtype == RAC_DT_F64 ? 8 : (prob->F_dtype == RAC_DT_F32 ? 4 : 2);
+    s->Fp_bytes = (size_t)sweep_packed_elems(s->p, s->K, s->tileA, s->tileB) * esz;
+    s->packRW = sweep_rows_per_group(s->rows, s->K, s->tileA);
+    if (s->packRW <= 0) return fail(RAC_ERR_ARG);
+    if ((r = s->buf.alloc(&s->Fp, 2 * s->Fp_bytes)) != RAC_OK) return fail(r);
+    // positions that no entry of F maps to stay zero for the solver's lifetime
+    if (hipMemset(s->Fp, 0, 2 * s->Fp_bytes) != hipSuccess) return fail(RAC_ERR_DEVICE);
+  }
+  if (can_overlap) {
     if (hipStreamCreateWithFlags(&s->sB, hipStreamNonBlocking) != hipSuccess) return fail(RAC_ERR_DEVICE);
     bool ok = hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming) == hipSuccess;
     for (int q = 0; q < 2 && ok; ++q)

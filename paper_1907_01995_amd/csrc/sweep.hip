@@ -151,6 +151,7 @@ struct Sweep2Args {
   double* x; double* u; DevScalars* sc; double* partials; uint64_t* flags; uint64_t epoch_base;
   int64_t RW;              // rows per group (a multiple of A, at most 64A)
   int vec;                 // column starts allow A-element vector loads
+  const void* Fp;          // packed tiles of this iteration's blocks, or null (gather from F)
 };
 
 // Lane l holds rows r0 + A l + a (a < A) of the group's range: A consecutive
@@ -212,18 +213,42 @@ __device__ __forceinline__ double transpose_sum(double (&v)[B], int lane, int& c
   return r;
 }
 
+// Packed tiles: the Gram kernel also copies each block's columns into the exact
+// register order of the sweep, tile (block i, group g) = [4 wavefronts][B][64
+// lanes][A] values of the storage type, zero outside the block and the rows.
+// One group then reads one contiguous run per block instead of 4B scattered
+// column segments (whose address translations dominate the fetch otherwise).
+template <typename T, int A, int B>
+__device__ __forceinline__ void load_packed(const T* __restrict__ Fp, int64_t i, int K, int g, int lane, int wave,
+                                            typename RegT<T>::type (&tile)[A][B]) {
+  const T* base = Fp + ((((i * K + g) * 4 + wave) * B) * 64 + lane) * (int64_t)A;
+#pragma unroll
+  for (int bb = 0; bb < B; ++bb) {
+    if constexpr (A > 1) {
+      typedef T VT __attribute__((ext_vector_type(A)));
+      const VT v = *reinterpret_cast<const VT*>(base + (int64_t)bb * 64 * A);
+#pragma unroll
+      for (int aa = 0; aa < A; ++aa) tile[aa][bb] = ld_reg(reinterpret_cast<const T*>(&v), aa);
+    } else {
+      tile[0][bb] = ld_reg(base, (int64_t)bb * 64);
+    }
+  }
+}
+
 template <typename T, int A, int B>
 __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   typedef typename RegT<T>::type R;
   constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
   constexpr int KM = (NC + P - 1) / P;            // Minv entries per thread
   constexpr bool MREG = KM <= 16;                 // keep the next block's inverse in registers
+  constexpr int NL = 128 / P;                     // partial loads per batch (K <= 128 in one batch)
   const int K = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jc = tid % NC, part = tid / NC;
   const int64_t r0 = (int64_t)g * s.RW;
   const int64_t r1 = r0 + s.RW < s.rows ? r0 + s.RW : s.rows;
   const T* F = (const T*)s.F;
+  const T* Fp = (const T*)s.Fp;
   __shared__ double sh_g[kMaxBlock];
   __shared__ double sh_d[kMaxBlock];
   __shared__ double sh_pg[256];
@@ -239,6 +264,12 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     if (s.h) v += s.h[col] * xc;
     if (s.a) v -= mu * s.a[col];
     return v;
+  };
+  auto bsize = [&](int64_t i) { return (int)(block_start(i + 1, s.n, s.p) - block_start(i, s.n, s.p)); };
+  // tile of block i: packed copy, else gathered through the block's column indices
+  auto fetch = [&](int64_t i, R (&tile)[A][B]) {
+    if (Fp) load_packed<T, A, B>(Fp, i, K, g, lane, wave, tile);
+    else load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[i & 1], bsize(i), lane, wave, s.vec, tile);
   };
   double ureg[A];
 #pragma unroll
@@ -258,22 +289,22 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       }
     }
   };
+  double ga = 0.0, gbn = 0.0;
   {
-    const int sb0 = (int)block_start(1, s.n, s.p);
+    const int sb0 = bsize(0);
     if (tid < sb0) sh_cols[0][tid] = s.perm[tid];
     __syncthreads();
-    load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[0], sb0, lane, wave, s.vec, ta);
+    fetch(0, ta);
     load_minv(0, sb0);
+    if (tid < sb0) ga = gbase(sh_cols[0][tid]);
   }
-  double gb = tid < (int)block_start(1, s.n, s.p) ? gbase(sh_cols[0][tid]) : 0.0;
 
-  auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B]) {
-    const int64_t s0 = block_start(i, s.n, s.p);
-    const int sb = (int)(block_start(i + 1, s.n, s.p) - s0);
+  auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B], double& gcur, double& gnxt) {
+    const int sb = bsize(i);
     const int32_t* cols = sh_cols[i & 1];
     const bool more = i + 1 < s.p;
     const int64_t s1 = block_start(i + 1, s.n, s.p);
-    const int sb1 = more ? (int)(block_start(i + 2, s.n, s.p) - s1) : 0;
+    const int sb1 = more ? bsize(i + 1) : 0;
     if (tid < sb1) sh_cols[(i + 1) & 1][tid] = s.perm[s1 + tid];   // indices of the next block
     // partial F_B'u over this group's rows, transposed across lanes
     double* buf = s.partials + (int64_t)(i & 1) * K * kMaxBlock;
@@ -296,41 +327,37 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     __syncthreads();
     if (K > 1 && tid == 0)
       __hip_atomic_store(&s.flags[g], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // prefetch the next block's tile and gbase while the other groups finish.
-    // Wavefront 0 polls the flags first: a poll waits on all of its wavefront's
-    // outstanding loads, so its share of the prefetch is issued after the flags.
-    double gb_next = 0.0;
-    if (more && wave != 0) {
-      load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(i + 1) & 1], sb1, lane, wave, s.vec, nxt);
-    }
-    if (wave == 0) {
-      if (K > 1) {
-        // every lane checks its flags each round; the wavefront leaves when all are raised
-        while (true) {
-          bool ok = true;
-          for (int q = lane; q < K; q += 64)
-            ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
-          if (__all(ok)) break;
-          __builtin_amdgcn_s_sleep(1);
-        }
+    if (K > 1 && wave == 0) {
+      // every lane checks its flags each round; the wavefront leaves when all are raised
+      while (true) {
+        bool ok = true;
+        for (int q = lane; q < K; q += 64)
+          ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+        if (__all(ok)) break;
+        __builtin_amdgcn_s_sleep(1);
       }
-      if (more) load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(i + 1) & 1], sb1, lane, wave, s.vec, nxt);
     }
-    if (more && tid < sb1) gb_next = gbase(sh_cols[(i + 1) & 1][tid]);
     __syncthreads();
-    // full gradient: P threads per column, every P-th group, all loads in flight at once
+    // This block's partials first; then the next block's tile and gradient
+    // inputs, which stream in during the solve and the update (loads return in
+    // order, so nothing below waits for them before the end of the block).
+    double rx = 0.0, rc = 0.0, rxi = 0.0, rz = 0.0, rh = 0.0, ra = 0.0;
     {
-      constexpr int NL = 128 / P;        // enough for K <= 128 in one batch
       double acc = 0.0;
-      if (jc < sb) {
-        for (int q = part; q < K; q += NL * P) {
-          double v[NL];
+      for (int q = part; q < K; q += NL * P) {
+        double v[NL];
 #pragma unroll
-          for (int e = 0; e < NL; ++e)
-            v[e] = (q + e * P < K) ? ld_coherent(&buf[(int64_t)(q + e * P) * kMaxBlock + jc]) : 0.0;
+        for (int e = 0; e < NL; ++e)
+          v[e] = (q + e * P < K && jc < sb) ? ld_coherent(&buf[(int64_t)(q + e * P) * kMaxBlock + jc]) : 0.0;
 #pragma unroll
-          for (int e = 0; e < NL; ++e) acc += v[e];
-        }
+        for (int e = 0; e < NL; ++e) acc += v[e];
+      }
+      fetch(more ? i + 1 : i, nxt);
+      if (tid < sb1) {
+        const int col = sh_cols[(i + 1) & 1][tid];
+        rx = s.x[col]; rc = s.c[col]; rxi = s.xi[col]; rz = s.z[col];
+        if (s.h) rh = s.h[col];
+        if (s.a) ra = s.a[col];
       }
       sh_pg[part * NC + jc] = acc;
     }
@@ -339,7 +366,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       double tot = 0.0;
 #pragma unroll
       for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
-      double v = tot / s.Ns + gb;
+      double v = tot / s.Ns + gcur;
       if (s.a) v += beta * s.a[cols[tid]] * (t - s.b);
       sh_g[tid] = v;
     }
@@ -391,13 +418,19 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       ureg[aa] += ((sh_red[q] + sh_red[64 * A + q]) + sh_red[2 * 64 * A + q]) + sh_red[3 * 64 * A + q];
     }
     if (g == 0 && tid < sb) s.x[cols[tid]] += sh_d[tid];
-    gb = gb_next;
+    // the next block's iterate-independent gradient terms (its columns are untouched by this block)
+    if (tid < sb1) {
+      double v = rc - rxi + beta * (rx - rz);
+      if (s.h) v += rh * rx;
+      if (s.a) v -= mu * ra;
+      gnxt = v;
+    }
     __syncthreads();
   };
 
   for (int64_t i = 0; i < s.p; i += 2) {
-    block(i, ta, tb);
-    if (i + 1 < s.p) block(i + 1, tb, ta);
+    block(i, ta, tb, ga, gbn);
+    if (i + 1 < s.p) block(i + 1, tb, ta, gbn, ga);
   }
 #pragma unroll
   for (int aa = 0; aa < A; ++aa) {
@@ -405,6 +438,297 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     if (r < r1) s.u[r] = ureg[aa];
   }
   if (g == 0 && tid == 0) s.sc->t = t;
+}
+
+// ---------------------------------------------------------------------------
+// Lookahead windows: blocks 2w and 2w+1 share one exchange.  Block 2w+1's
+// gradient needs u after block 2w's update, and
+//   F_{2w+1}'(u + F_{2w} d_{2w}) / Ns = F_{2w+1}'u / Ns + C_w d_{2w},
+//   C_w = F_{2w+1}' F_{2w} / Ns   (the pair's cross-Gram, formed with the Grams),
+// so both partials are published together and every group adds C_w d_{2w}
+// before solving block 2w+1: the same iteration with half the exchanges.  A
+// trailing single block (p odd) is a window of one.  Tiles of the next window
+// are loaded while the exchange is awaited; the inverses and cross-Gram of the
+// next window are loaded while this window's solves finish.
+template <typename T, int A, int B>
+__global__ void __launch_bounds__(256) k_sweepw(Sweep2Args s, const double* __restrict__ Cx) {
+  typedef typename RegT<T>::type R;
+  constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
+  constexpr int KM = (NC + P - 1) / P;            // inverse / cross-Gram entries per thread
+  static_assert(KM <= 16, "the window's inverses are kept in registers");
+  constexpr int NL = 128 / P;                     // partial loads per batch
+  const int K = gridDim.x, g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int jc = tid % NC, part = tid / NC;
+  const int64_t r0 = (int64_t)g * s.RW;
+  const int64_t r1 = r0 + s.RW < s.rows ? r0 + s.RW : s.rows;
+  const T* F = (const T*)s.F;
+  const int64_t p = s.p, nw = (p + 1) / 2;
+  __shared__ double sh_g[kMaxBlock];
+  __shared__ double sh_d[2][kMaxBlock];
+  __shared__ double sh_pg[256];
+  __shared__ double sh_pc[256];
+  __shared__ double sh_red[4 * 64 * A];
+  __shared__ int32_t sh_cols[2][2][kMaxBlock];    // [window parity][block of the window][column]
+  const double beta = *s.beta_ptr;
+  const double mu = s.sc->mu;
+  double t = s.sc->t;
+  auto bstart = [&](int64_t i) { return block_start(i, s.n, p); };
+  auto bsize = [&](int64_t i) { return i < p ? (int)(bstart(i + 1) - bstart(i)) : 0; };
+  auto gbase = [&](int col) {
+    const double xc = s.x[col];
+    double v = s.c[col] - s.xi[col] + beta * (xc - s.z[col]);
+    if (s.h) v += s.h[col] * xc;
+    if (s.a) v -= mu * s.a[col];
+    return v;
+  };
+  double ureg[A];
+#pragma unroll
+  for (int aa = 0; aa < A; ++aa) {
+    const int64_t r = r0 + (int64_t)A * lane + aa;
+    ureg[aa] = r < r1 ? s.u[r] : 0.0;
+  }
+  R t1[A][B], t2[A][B], n1[A][B], n2[A][B];
+  double m1[KM], m2[KM], cx[KM];
+  auto load_minv = [&](int64_t i, double (&mr)[KM]) {
+    const int sbi = bsize(i);
+    const double* Mi = s.Minv + (i < p ? i : 0) * (int64_t)s.sp * s.sp;
+#pragma unroll
+    for (int e = 0; e < KM; ++e) {
+      const int k = part + P * e;
+      mr[e] = (jc < sbi && k < sbi) ? Mi[(int64_t)k * s.sp + jc] : 0.0;
+    }
+  };
+  auto load_cx = [&](int64_t w) {                 // cx[e] = C_w[jc][part + P e]
+    const int sa = bsize(2 * w), sbb = bsize(2 * w + 1);
+    const double* C = Cx + (sbb > 0 ? w : 0) * (int64_t)s.sp * s.sp;
+#pragma unroll
+    for (int e = 0; e < KM; ++e) {
+      const int k = part + P * e;
+      cx[e] = (jc < sbb && k < sa) ? C[(int64_t)jc * s.sp + k] : 0.0;
+    }
+  };
+  {
+    const int sa = bsize(0), sbb = bsize(1);
+    if (tid < sa) sh_cols[0][0][tid] = s.perm[tid];
+    if (tid < sbb) sh_cols[0][1][tid] = s.perm[bstart(1) + tid];
+    __syncthreads();
+    load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[0][0], sa, lane, wave, s.vec, t1);
+    load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[0][1], sbb, lane, wave, s.vec, t2);
+    load_minv(0, m1);
+    load_minv(1, m2);
+    load_cx(0);
+  }
+  double gb1 = tid < bsize(0) ? gbase(sh_cols[0][0][tid]) : 0.0;
+  double gb2 = tid < bsize(1) ? gbase(sh_cols[0][1][tid]) : 0.0;
+
+  // the block solve d = -M^{-1} g (g in sh_g) into sh_d[slot]: P threads per column, combined in order
+  auto solve = [&](const double (&mr)[KM], int sbi, int slot) {
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < KM; ++e) {
+      const int k = part + P * e;
+      acc += mr[e] * sh_g[k < sbi ? k : 0] * (k < sbi ? 1.0 : 0.0);
+    }
+    sh_pg[part * NC + jc] = acc;
+    __syncthreads();
+    if (tid < NC) {
+      double tot = 0.0;
+#pragma unroll
+      for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
+      sh_d[slot][tid] = tid < sbi ? -tot : 0.0;
+    }
+  };
+
+  auto window = [&](int64_t w, R (&c1)[A][B], R (&c2)[A][B], R (&x1)[A][B], R (&x2)[A][B]) {
+    const int sa = bsize(2 * w), sbb = bsize(2 * w + 1);
+    const int32_t* cols1 = sh_cols[w & 1][0];
+    const int32_t* cols2 = sh_cols[w & 1][1];
+    const bool more = w + 1 < nw;
+    const int na = bsize(2 * w + 2), nb = bsize(2 * w + 3);
+    if (tid < na) sh_cols[(w + 1) & 1][0][tid] = s.perm[bstart(2 * w + 2) + tid];
+    if (tid < nb) sh_cols[(w + 1) & 1][1][tid] = s.perm[bstart(2 * w + 3) + tid];
+    // partials of both blocks over this group's rows
+    double* buf = s.partials + (int64_t)(w & 1) * K * 2 * kMaxBlock;
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      R (&cur)[A][B] = blk == 0 ? c1 : c2;
+      const int sbx = blk == 0 ? sa : sbb;
+      double v[B];
+#pragma unroll
+      for (int bb = 0; bb < B; ++bb) {
+        double acc = 0.0;
+#pragma unroll
+        for (int aa = 0; aa < A; ++aa) acc += (double)cur[aa][bb] * ureg[aa];
+        v[bb] = acc;
+      }
+      int c;
+      const double tot = transpose_sum<B>(v, lane, c);
+      const int j = wave + 4 * c;
+      if ((lane & (64 / B - 1)) == 0 && j < sbx)
+        st_coherent(&buf[((int64_t)g * 2 + blk) * kMaxBlock + j], tot);
+    }
+    const uint64_t epoch = s.epoch_base + (uint64_t)(2 * w) + 1;
+    __builtin_amdgcn_s_waitcnt(0);   // partial stores complete at device scope; next indices landed
+    __syncthreads();
+    if (K > 1 && tid == 0)
+      __hip_atomic_store(&s.flags[g], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // next window's tiles and gradient constants while the other groups finish;
+    // wavefront 0 polls first (a poll waits on all of its wavefront's loads)
+    double gn1 = 0.0, gn2 = 0.0;
+    if (more && wave != 0) {
+      load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][0], na, lane, wave, s.vec, x1);
+      load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][1], nb, lane, wave, s.vec, x2);
+    }
+    if (wave == 0) {
+      if (K > 1) {
+        while (true) {
+          bool ok = true;
+          for (int q = lane; q < K; q += 64)
+            ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+          if (__all(ok)) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      if (more) {
+        load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][0], na, lane, wave, s.vec, x1);
+        load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][1], nb, lane, wave, s.vec, x2);
+      }
+    }
+    if (more && tid < na) gn1 = gbase(sh_cols[(w + 1) & 1][0][tid]);
+    if (more && tid < nb) gn2 = gbase(sh_cols[(w + 1) & 1][1][tid]);
+    __syncthreads();
+    // both blocks' partials over the K groups, in a fixed order per (column, part)
+    double p1 = 0.0, p2 = 0.0;
+    for (int q = part; q < K; q += NL * P) {
+      double v1[NL], v2[NL];
+#pragma unroll
+      for (int e = 0; e < NL; ++e) {
+        const int64_t qq = q + e * P;
+        v1[e] = (qq < K && jc < sa) ? ld_coherent(&buf[(qq * 2 + 0) * kMaxBlock + jc]) : 0.0;
+        v2[e] = (qq < K && jc < sbb) ? ld_coherent(&buf[(qq * 2 + 1) * kMaxBlock + jc]) : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < NL; ++e) { p1 += v1[e]; p2 += v2[e]; }
+    }
+    sh_pg[part * NC + jc] = p1;
+    __syncthreads();
+    // block 2w
+    if (tid < sa) {
+      double tot = 0.0;
+#pragma unroll
+      for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
+      double v = tot / s.Ns + gb1;
+      if (s.a) v += beta * s.a[cols1[tid]] * (t - s.b);
+      sh_g[tid] = v;
+    }
+    __syncthreads();
+    solve(m1, sa, 0);
+    if (more) load_minv(2 * w + 2, m1);
+    __syncthreads();
+    if (s.a) {
+      double dt = 0.0;
+      for (int j = 0; j < sa; ++j) dt += s.a[cols1[j]] * sh_d[0][j];
+      t += dt;
+    }
+    // block 2w+1: its partials plus C_w d_{2w}
+    if (sbb > 0) {
+      double cc = 0.0;
+#pragma unroll
+      for (int e = 0; e < KM; ++e) {
+        const int k = part + P * e;
+        cc += cx[e] * sh_d[0][k < sa ? k : 0] * (k < sa ? 1.0 : 0.0);
+      }
+      sh_pg[part * NC + jc] = p2;
+      sh_pc[part * NC + jc] = cc;
+      __syncthreads();
+      if (tid < sbb) {
+        double tot = 0.0, cor = 0.0;
+#pragma unroll
+        for (int e = 0; e < P; ++e) { tot += sh_pg[e * NC + tid]; cor += sh_pc[e * NC + tid]; }
+        double v = tot / s.Ns + cor + gb2;
+        if (s.a) v += beta * s.a[cols2[tid]] * (t - s.b);
+        sh_g[tid] = v;
+      }
+      __syncthreads();
+      solve(m2, sbb, 1);
+    } else if (tid < NC) {
+      sh_d[1][tid] = 0.0;
+    }
+    if (more) {
+      load_minv(2 * w + 3, m2);
+      load_cx(w + 1);
+    }
+    __syncthreads();
+    if (s.a && sbb > 0) {
+      double dt = 0.0;
+      for (int j = 0; j < sbb; ++j) dt += s.a[cols2[j]] * sh_d[1][j];
+      t += dt;
+    }
+    // rows of u from both register tiles, summed over the four wavefronts in order
+#pragma unroll
+    for (int aa = 0; aa < A; ++aa) {
+      double v = 0.0;
+#pragma unroll
+      for (int bb = 0; bb < B; ++bb)
+        v += (double)c1[aa][bb] * sh_d[0][wave + 4 * bb] + (double)c2[aa][bb] * sh_d[1][wave + 4 * bb];
+      sh_red[wave * 64 * A + 64 * aa + lane] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int aa = 0; aa < A; ++aa) {
+      const int q = 64 * aa + lane;
+      ureg[aa] += ((sh_red[q] + sh_red[64 * A + q]) + sh_red[2 * 64 * A + q]) + sh_red[3 * 64 * A + q];
+    }
+    if (g == 0 && tid < sa) s.x[cols1[tid]] += sh_d[0][tid];
+    if (g == 0 && tid < sbb) s.x[cols2[tid]] += sh_d[1][tid];
+    gb1 = gn1;
+    gb2 = gn2;
+    __syncthreads();
+  };
+
+  for (int64_t w = 0; w < nw; w += 2) {
+    window(w, t1, t2, n1, n2);
+    if (w + 1 < nw) window(w + 1, n1, n2, t1, t2);
+  }
+#pragma unroll
+  for (int aa = 0; aa < A; ++aa) {
+    const int64_t r = r0 + (int64_t)A * lane + aa;
+    if (r < r1) s.u[r] = ureg[aa];
+  }
+  if (g == 0 && tid == 0) s.sc->t = t;
+}
+
+template <typename T, int A, int B>
+hipError_t sweepw_launch(const Sweep2Args& a, const double* Cx, int K, int coop, hipStream_t st) {
+  if (K == 1 || !coop) {
+    k_sweepw<T, A, B><<<(unsigned)K, 256, 0, st>>>(a, Cx);
+    return hipGetLastError();
+  }
+  Sweep2Args c = a;
+  const double* cx = Cx;
+  void* args[] = {(void*)&c, (void*)&cx};
+  return hipLaunchCooperativeKernel((const void*)k_sweepw<T, A, B>, dim3((unsigned)K), dim3(256), args, 0, st);
+}
+
+template <typename T>
+hipError_t sweepw_dispatch(const Sweep2Args& a, const double* Cx, int K, int A, int B, int coop, hipStream_t st) {
+#define RAC_SWW(AA, BB) if (A == AA && B == BB) return sweepw_launch<T, AA, BB>(a, Cx, K, coop, st)
+  RAC_SWW(1, 8); RAC_SWW(2, 8);
+  RAC_SWW(1, 16); RAC_SWW(2, 16);
+  if constexpr (sizeof(T) < 8) { RAC_SWW(4, 8); RAC_SWW(4, 16); }
+#undef RAC_SWW
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int A, int B>
+int sweepw_resident() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_sweepw<T, A, B>, 256, 0) != hipSuccess)
+    return 0;
+  return cus * per;
 }
 
 // A plain launch is used only when the caller has checked that all K groups can
@@ -429,6 +753,16 @@ int sweep2_resident() {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_sweep2<T, A, B>, 256, 0) != hipSuccess)
     return 0;
   return cus * per;
+}
+
+template <typename T>
+int sweepw_resident_dispatch(int A, int B) {
+#define RAC_SRW(AA, BB) if (A == AA && B == BB) return sweepw_resident<T, AA, BB>()
+  RAC_SRW(1, 8); RAC_SRW(2, 8);
+  RAC_SRW(1, 16); RAC_SRW(2, 16);
+  if constexpr (sizeof(T) < 8) { RAC_SRW(4, 8); RAC_SRW(4, 16); }
+#undef RAC_SRW
+  return 0;
 }
 
 template <typename T>
@@ -474,16 +808,33 @@ hipError_t sweep_launch(const SweepArgs& s, hipStream_t st) {
 
 }  // namespace
 
+int64_t sweep_rows_per_group(int64_t rows, int K, int A) {
+  if (K < 1 || A < 1) return 0;
+  int64_t rw = (rows + K - 1) / K;
+  rw = (rw + A - 1) / A * A;
+  return rw > 64 * A ? 0 : rw;
+}
+
+int64_t sweep_packed_elems(int64_t p, int K, int A, int B) { return p * K * 256 * (int64_t)A * B; }
+
 hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
   if (s.tileA > 0) {
     Sweep2Args a{s.F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.c, s.h, s.xi, s.z, s.beta_ptr,
-                 s.a, s.b, s.Ns, s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0};
-    int64_t rw = (s.rows + s.K - 1) / s.K;
-    rw = (rw + s.tileA - 1) / s.tileA * s.tileA;
-    if (rw > 64 * s.tileA) return hipErrorInvalidValue;
+                 s.a, s.b, s.Ns, s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0, s.Fp};
+    const int64_t rw = sweep_rows_per_group(s.rows, s.K, s.tileA);
+    if (rw == 0) return hipErrorInvalidValue;
     a.RW = rw;
     const int esz = s.dtype == RAC_DT_F64 ? 8 : (s.dtype == RAC_DT_F32 ? 4 : 2);
     a.vec = (s.ldF % s.tileA == 0) && ((uintptr_t)s.F % (size_t)(esz * s.tileA) == 0);
+    if (s.Cx) {
+      if (s.sp > 64) return hipErrorInvalidValue;
+      switch (s.dtype) {
+        case RAC_DT_F64: return sweepw_dispatch<double>(a, s.Cx, s.K, s.tileA, s.tileB, s.cooperative, st);
+        case RAC_DT_F32: return sweepw_dispatch<float>(a, s.Cx, s.K, s.tileA, s.tileB, s.cooperative, st);
+        case RAC_DT_BF16: return sweepw_dispatch<uint16_t>(a, s.Cx, s.K, s.tileA, s.tileB, s.cooperative, st);
+        default: return hipErrorInvalidValue;
+      }
+    }
     switch (s.dtype) {
       case RAC_DT_F64: return sweep2_dispatch<double>(a, s.K, s.tileA, s.tileB, s.cooperative, st);
       case RAC_DT_F32: return sweep2_dispatch<float>(a, s.K, s.tileA, s.tileB, s.cooperative, st);
@@ -502,7 +853,15 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
 }  // namespace rac
 
 namespace rac {
-int sweep_max_resident(int32_t dtype, int A, int B) {
+int sweep_max_resident(int32_t dtype, int A, int B, bool windowed) {
+  if (windowed) {
+    switch (dtype) {
+      case RAC_DT_F64: return sweepw_resident_dispatch<double>(A, B);
+      case RAC_DT_F32: return sweepw_resident_dispatch<float>(A, B);
+      case RAC_DT_BF16: return sweepw_resident_dispatch<uint16_t>(A, B);
+      default: return 0;
+    }
+  }
   switch (dtype) {
     case RAC_DT_F64: return sweep2_resident_dispatch<double>(A, B);
     case RAC_DT_F32: return sweep2_resident_dispatch<float>(A, B);
@@ -511,8 +870,9 @@ int sweep_max_resident(int32_t dtype, int A, int B) {
   }
 }
 
-bool sweep_tile_supported(int32_t dtype, int A, int B) {
+bool sweep_tile_supported(int32_t dtype, int A, int B, bool windowed) {
   const bool small = dtype != RAC_DT_F64;
+  if (windowed) return (B == 8 || B == 16) && (A == 1 || A == 2 || (A == 4 && small));
   if (B == 8) return A == 1 || A == 2 || A == 4;
   if (B == 16) return A == 1 || A == 2 || (A == 4 && small);
   if (B == 32) return A == 1 || (A == 2 && small);

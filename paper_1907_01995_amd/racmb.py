@@ -58,7 +58,7 @@ class Opts_(C.Structure):
                 ("beta_schedule", C.POINTER(C.c_double)), ("mlp_weights", C.c_void_p),
                 ("mlp_ymax", C.c_double), ("check_every", C.c_int64), ("max_iter", C.c_int64),
                 ("tol", C.c_double), ("sweep_groups", C.c_int32), ("row_chunks", C.c_int32),
-                ("overlap", C.c_int32), ("pad0", C.c_int32)]
+                ("overlap", C.c_int32), ("packed", C.c_int32)]
 
 
 class Lane_(C.Structure):
@@ -286,7 +286,7 @@ class Solver:
     def __init__(self, prob: Problem, *, p=None, s=None, seed=0, instance=0, precision=PREC_FP64,
                  beta0=1.0, beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0, beta_schedule=None,
                  mlp_weights=None, mlp_ymax=float(np.log(10.0)), check_every=10, max_iter=100,
-                 tol=0.0, sweep_groups=0, row_chunks=0, overlap=True):
+                 tol=0.0, sweep_groups=0, row_chunks=0, overlap=True, packed=True):
         self.lib = load()
         self.prob = prob
         if p is None:
@@ -302,7 +302,7 @@ class Solver:
                           float(rb_mu), float(rb_tau), sched_ptr,
                           None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax),
                           int(check_every), int(max_iter), float(tol), int(sweep_groups), int(row_chunks),
-                          0 if overlap else -1, 0)
+                          0 if overlap else -1, 0 if packed else -1)
         self._ps = prob.struct()
         h = C.c_void_p()
         _check(self.lib.rac_solver_create(C.byref(self._ps), C.byref(self.opts), C.byref(h)),
@@ -355,8 +355,8 @@ class Solver:
 
     def timing(self):
         """{phase: (total ms, launches)} accumulated since set_timing."""
-        ms = np.zeros(6)
-        cnt = (C.c_int64 * 6)()
+        ms = np.zeros(len(self.PHASES))
+        cnt = (C.c_int64 * len(self.PHASES))()
         _check(self.lib.rac_solver_timing(self.h, ms.ctypes.data_as(C.POINTER(C.c_double)), cnt),
                "rac_solver_timing")
         return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(self.PHASES)}
@@ -532,7 +532,7 @@ class Batch:
 
     def timing(self):
         """{phase: (milliseconds, launches)} since set_timing."""
-        ms, cnt = (C.c_double * 6)(), (C.c_int64 * 6)()
+        ms, cnt = (C.c_double * len(Solver.PHASES))(), (C.c_int64 * len(Solver.PHASES))()
         _check(self.lib.rac_batch_timing(self.h, ms, cnt), "rac_batch_timing")
         return {name: (ms[q], cnt[q]) for q, name in enumerate(Solver.PHASES)}
 

@@ -271,15 +271,45 @@ def test_overlapped_assembly_is_bit_identical(storage, prec):
     w = W.lasso(N=6000, n=512, data_seed=14, block_size=64, storage=storage)
     gp, _ = en_pair(w)
     outs = []
+    R = 0
     for ov in (True, False):
         say("overlap", ov, storage)
+        # the same row chunks both ways (an overlapped solver picks fewer by default)
         s = racmb.Solver(gp, s=64, beta0=w.beta0, beta_mode=racmb.BETA_RESBAL, precision=prec,
-                         max_iter=45, check_every=10, overlap=ov)
+                         max_iter=45, check_every=10, overlap=ov, row_chunks=R)
         s.run()
         assert s.info()["overlap"] == (1 if ov else 0)
+        R = s.info()["R"]
         outs.append(s.state()[:3])
     for u, v in zip(*outs):
         assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("storage,prec,N,n,s,K", [("f32", racmb.PREC_MIXED, 6003, 500, 64, 0),
+                                                  ("bf16", racmb.PREC_MIXED, 3001, 333, 32, 0),
+                                                  ("f64", racmb.PREC_FP64, 1000, 201, 20, 7),
+                                                  ("f32", racmb.PREC_FP64, 2500, 130, 64, 0)])
+def test_packed_and_gathered_sweeps_are_bit_identical(storage, prec, N, n, s, K):
+    """The packed copy holds the same values in the sweep's register order, so the
+    sweep computes the same sums in the same order: identical iterates.  Ragged
+    row counts (last group short) and short blocks (zero columns in the tile)."""
+    w = W.lasso(N=N, n=n, data_seed=N % 97, block_size=s, storage=storage)
+    gp, op = en_pair(w)
+    outs = []
+    for packed in (True, False):
+        say("packed", packed, storage, N, n, s, K)
+        sv = racmb.Solver(gp, s=s, beta0=w.beta0, beta_mode=racmb.BETA_RESBAL, precision=prec,
+                          max_iter=40, check_every=10, sweep_groups=K, packed=packed)
+        sv.run()
+        info = sv.info()
+        assert info["tileA"] > 0
+        outs.append(sv.state()[:3])
+        sv.close()
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
+    if prec == racmb.PREC_FP64:
+        ref = O.solve(op, s=s, beta0=w.beta0, beta_mode=O.BETA_RESBAL, max_iter=40, check_every=10)
+        assert rel(outs[0][1], ref.z) < 1e-8 and rel(outs[0][2], ref.xi) < 1e-8
 
 
 def test_repeated_runs_are_deterministic():
