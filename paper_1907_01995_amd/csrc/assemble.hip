@@ -46,7 +46,15 @@ template <> __device__ __forceinline__ double to_lds<uint16_t, G_F64>(uint16_t v
 template <> __device__ __forceinline__ float to_lds<float, G_F32>(float v) { return v; }
 template <> __device__ __forceinline__ uint16_t to_lds<uint16_t, G_BF16>(uint16_t v) { return v; }
 
-constexpr int KT = 64;                // rows per LDS tile
+// Rows per LDS tile: about 64 KB of staged columns (at most 256 rows), so that
+// each column segment fetched per tile is long (the block's columns are
+// scattered over F, and short segments make the gather translation-bound).
+template <int MODE, int NCOL>
+constexpr int gram_kt() {
+  constexpr int bytes = (int)sizeof(typename GramTraits<MODE>::E) * NCOL;
+  constexpr int kt = 65536 / bytes;
+  return kt >= 256 ? 256 : (kt >= 128 ? 128 : 64);
+}
 
 // One workgroup: block `blk`, rows [rb, re).  Data move as 16-byte vectors of
 // VE = 16/sizeof(T) consecutive rows of one column; the next 64-row tile is
@@ -67,9 +75,10 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
   typedef GramTraits<MODE> Tr;
   typedef typename Tr::E E;
   typedef typename Tr::Acc Acc;
+  constexpr int NCOL = X ? 2 * SP : SP;         // staged columns
+  constexpr int KT = gram_kt<MODE, NCOL>();     // rows per tile
   constexpr int VE = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int VPC = KT / VE;                  // vectors per column per tile
-  constexpr int NCOL = X ? 2 * SP : SP;         // staged columns
   constexpr int NVEC = NCOL * VPC;
   constexpr int NV = (NVEC + 255) / 256;        // vectors per thread per tile
   constexpr int LD = KT + Tr::PAD;              // LDS row stride of the column-major tile
@@ -141,20 +150,27 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
       }
     }
   };
-  // the staged vectors of this tile (rows r0 ..) into the packed copy
+  // The staged vectors of this tile (rows r0 ..) into the packed copy.  All of a
+  // thread's vectors cover the same rows (VPC divides 256), so the group of those
+  // rows is found once per tile; rows are below 2^31 (checked by the host).
+  static_assert(256 % VPC == 0, "a thread's vectors share their rows");
+  const bool pk_vec = pk.Fp && (pk.RW % VE) == 0;   // every vector lies inside one group, aligned
   auto pack = [&](int64_t r0) {
     T* Fp = (T*)pk.Fp;
+    const int seg = tid % VPC;
+    const int64_t r = r0 + seg * VE;
+    if (r >= re) return;
+    const uint32_t rw = (uint32_t)pk.RW;
+    const uint32_t g = (uint32_t)r / rw;
+    const int64_t rr = r - (int64_t)g * rw;
+    const bool whole = pk_vec && r + VE <= re;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int v = tid + 256 * q;
-      const int m = v / VPC, seg = v % VPC;
+      const int m = v / VPC;
       if (v >= NVEC || m >= sb || X) continue;
-      const int64_t r = r0 + seg * VE;
-      if (r >= re) continue;
-      const int g = (int)(r / pk.RW);
-      const int64_t rr = r - (int64_t)g * pk.RW;
       T* dst = Fp + (((((int64_t)blk * pk.K + g) * 4 + (m & 3)) * pk.B + (m >> 2)) * 64) * pk.A;
-      if (r + VE <= re && rr + VE <= pk.RW && (rr % VE) == 0) {
+      if (whole) {
         uint4 raw;
         T* e = reinterpret_cast<T*>(&raw);
 #pragma unroll
@@ -162,9 +178,9 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
         *reinterpret_cast<uint4*>(dst + rr) = raw;
       } else {
         for (int u = 0; u < VE && r + u < re; ++u) {
-          const int gu = (int)((r + u) / pk.RW);
+          const uint32_t gu = (uint32_t)(r + u) / rw;
           Fp[(((((int64_t)blk * pk.K + gu) * 4 + (m & 3)) * pk.B + (m >> 2)) * 64) * pk.A +
-             (r + u - (int64_t)gu * pk.RW)] = stage[q][u];
+             (r + u - (int64_t)gu * rw)] = stage[q][u];
         }
       }
     }
@@ -176,27 +192,47 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
     store();
     __syncthreads();
     if (r0 + KT < re) load(r0 + KT);     // next tile in flight during the MFMAs
+    // Each lane feeds the rows of one 16-byte LDS read to consecutive MFMAs (the
+    // Gram sums over rows, so any assignment of rows to MFMA steps is valid as
+    // long as both operands use the same one); the wave's tile pairs form
+    // independent accumulation chains, interleaved.
+    if constexpr (MODE == G_F64) {
+#pragma unroll 2
+      for (int kk = 0; kk < KT; kk += 8) {
 #pragma unroll
-    for (int q = 0; q < MAXP; ++q) {
-      if (wave + 4 * q < NPAIR) {
-        const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
-        if constexpr (MODE == G_F64) {
-#pragma unroll
-          for (int kk = 0; kk < KT; kk += 4) {
-            double av = tile[am * LD + kk + (lane >> 4)];
-            double bv = tile[bn * LD + kk + (lane >> 4)];
-            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+        for (int q = 0; q < MAXP; ++q) {
+          if (wave + 4 * q < NPAIR) {
+            const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
+            const double2 a2 = *reinterpret_cast<const double2*>(&tile[am * LD + kk + 2 * (lane >> 4)]);
+            const double2 b2 = *reinterpret_cast<const double2*>(&tile[bn * LD + kk + 2 * (lane >> 4)]);
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.x, b2.x, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.y, b2.y, acc[q], 0, 0, 0);
           }
-        } else if constexpr (MODE == G_F32) {
+        }
+      }
+    } else if constexpr (MODE == G_F32) {
+#pragma unroll 2
+      for (int kk = 0; kk < KT; kk += 16) {
 #pragma unroll
-          for (int kk = 0; kk < KT; kk += 4) {
-            float av = tile[am * LD + kk + (lane >> 4)];
-            float bv = tile[bn * LD + kk + (lane >> 4)];
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
+        for (int q = 0; q < MAXP; ++q) {
+          if (wave + 4 * q < NPAIR) {
+            const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
+            const float4 a4 = *reinterpret_cast<const float4*>(&tile[am * LD + kk + 4 * (lane >> 4)]);
+            const float4 b4 = *reinterpret_cast<const float4*>(&tile[bn * LD + kk + 4 * (lane >> 4)]);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc[q], 0, 0, 0);
           }
-        } else {
+        }
+      }
+    } else {
+#pragma unroll 2
+      for (int kk = 0; kk < KT; kk += 32) {
 #pragma unroll
-          for (int kk = 0; kk < KT; kk += 32) {
+        for (int q = 0; q < MAXP; ++q) {
+          if (wave + 4 * q < NPAIR) {
+            const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
             const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[am * LD + kk + 8 * (lane >> 4)]);
             const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&tile[bn * LD + kk + 8 * (lane >> 4)]);
             acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, av),

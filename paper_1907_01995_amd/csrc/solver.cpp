@@ -446,7 +446,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->mv_part, (size_t)s->mv_nparts * s->rows)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->uz, (size_t)s->rows)) != RAC_OK) return fail(r);
   // packed copies of the blocks for the register-tile sweep (one per iteration parity)
-  if (s->tileA > 0 && O.packed >= 0) {
+  if (s->tileA > 0 && O.packed >= 0 && s->rows <= INT32_MAX) {
     const size_t esz = prob->F_dtype == RAC_DT_F64 ? 8 : (prob->F_dtype == RAC_DT_F32 ? 4 : 2);
     s->Fp_bytes = (size_t)sweep_packed_elems(s->p, s->K, s->tileA, s->tileB) * esz;
     s->packRW = sweep_rows_per_group(s->rows, s->K, s->tileA);
