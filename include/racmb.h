@@ -156,6 +156,10 @@ rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, 
 enum { RAC_PHASE_PARTITION = 0, RAC_PHASE_GRAM = 1, RAC_PHASE_FACTOR = 2, RAC_PHASE_SWEEP = 3,
        RAC_PHASE_ZDUAL = 4, RAC_PHASE_CHECK = 5 };
 rac_status rac_solver_set_timing(rac_solver s, int32_t enable);   /* also clears the totals */
+/* Times only the phases whose bit (1 << RAC_PHASE_*) is set in mask (0: none); also
+ * clears the totals.  Fewer events around the launches disturb the run less.
+ * RAC_ERR_ARG for bits past RAC_NUM_PHASES. */
+rac_status rac_solver_set_timing_mask(rac_solver s, uint32_t mask);
 /* ms (host, RAC_NUM_PHASES) receives the summed milliseconds per phase, launches
  * (host, RAC_NUM_PHASES or NULL) the number of timed launches per phase. */
 rac_status rac_solver_timing(rac_solver s, double* ms, int64_t* launches);

@@ -481,6 +481,101 @@ hipError_t xgram_launch(const GramArgs& g, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+// One wavefront per block (SP <= 64), the lower-latency form of k_factor for
+// the single-instance solver: lane j holds column j of M_B in registers and
+// applies the symmetric sweep operator to pivots 0..sb-1,
+//   a_ij -= a_ik a_kj / d,  a_kj /= d,  a_ik /= d,  a_kk = -1/d   (d = a_kk),
+// after which the block holds -M_B^{-1}; d is the k-th Schur-complement pivot (the
+// squared Cholesky pivot), so a non-positive one is the failure of Assumption 2.1
+// reported with its iteration and block.  The running matrix stays symmetric, so
+// the pivot column equals the pivot row, which every lane holds in register 0
+// (registers are renumbered after every pivot; all indices are compile-time).
+// No workgroup barrier: one LDS write and read per pivot within the wavefront.
+template <int SP>
+__global__ void __launch_bounds__(64) k_factor_wave(const double* __restrict__ partial, int R, int64_t n,
+                                                    int64_t p, const int32_t* __restrict__ perm, double Ns,
+                                                    const double* __restrict__ h, const double* __restrict__ a,
+                                                    const double* beta_ptr, double beta_val,
+                                                    double* __restrict__ out, DevScalars* sc,
+                                                    int64_t iter_global) {
+  static_assert(SP <= 64, "one lane per column");
+  constexpr int HALF = SP > 32 ? SP / 2 : SP;
+  __shared__ double buf[2 * SP];
+  const int blk = blockIdx.x, j = threadIdx.x;
+  const int64_t s0 = block_start(blk, n, p);
+  const int sb = (int)(block_start(blk + 1, n, p) - s0);
+  const double beta = beta_ptr ? *beta_ptr : beta_val;
+  const int colj = j < sb ? perm[s0 + j] : 0;
+  const double hj = (h && j < sb) ? h[colj] : 0.0;
+  const double aj = (a && j < sb) ? a[colj] : 0.0;
+  if (a && j < SP) buf[j] = aj;
+  // column j of the summed Gram: the R row-chunk partials in order (lower triangle stored)
+  double col[SP];
+#pragma unroll
+  for (int i = 0; i < SP; ++i) col[i] = 0.0;
+  const double* part = partial + (int64_t)blk * R * SP * SP;
+  for (int r = 0; r < R; ++r) {
+    const double* pr = part + (int64_t)r * SP * SP;
+#pragma unroll
+    for (int h0 = 0; h0 < SP; h0 += HALF) {
+      double v[HALF];
+#pragma unroll
+      for (int q = 0; q < HALF; ++q) {
+        const int i = h0 + q;
+        v[q] = (i < sb && j < sb) ? pr[i >= j ? i * SP + j : j * SP + i] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < HALF; ++q) col[h0 + q] += v[q];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int i = 0; i < SP; ++i) {
+    double v;
+    if (i < sb && j < sb) {
+      v = col[i] / Ns;
+      if (i == j) v += beta + hj;
+      if (a) v += beta * buf[i] * aj;
+    } else {
+      v = (i == j) ? 1.0 : 0.0;   // padding: an identity block, decoupled from the real one
+    }
+    col[i] = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+  bool failed = false;
+  for (int k = 0; k < sb; ++k) {
+    const double rk = col[0];                   // a_kj
+    if (j < SP) { buf[j] = rk; buf[j + SP] = rk; }
+    __builtin_amdgcn_wave_barrier();
+    const double d = buf[k];                    // the same value in every lane
+    if (!(d > 0.0) || !isfinite(d)) {
+      failed = true;
+      if (j == 0 && sc) {
+        const unsigned long long key = ((unsigned long long)iter_global << 32) | (unsigned)blk;
+        atomicMin((unsigned long long*)&sc->fail_key, key);
+      }
+      break;
+    }
+    const double invd = 1.0 / d;
+    const bool pv = j == k;
+    const double keep = pv ? 0.0 : 1.0;
+    const double m = pv ? -invd : rk * invd;
+#pragma unroll
+    for (int q = 1; q < SP; ++q) col[q - 1] = fma(-buf[k + q], m, keep * col[q]);   // buf[k+q] = a_(k+q mod SP),k
+    col[SP - 1] = m;
+    __builtin_amdgcn_wave_barrier();
+  }
+  double* dst = out + (int64_t)blk * SP * SP;
+  if (j < SP) {
+#pragma unroll
+    for (int q = 0; q < SP; ++q) {
+      int i = q + sb;                           // register q holds row (q + sb) mod SP
+      if (i >= SP) i -= SP;
+      dst[i * SP + j] = (!failed && i < sb && j < sb) ? -col[q] : 0.0;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_xgram(const GramArgs& g, double Ns, double* C, hipStream_t st) {
@@ -541,6 +636,17 @@ hipError_t launch_gram(const GramArgs& g, hipStream_t st) {
 }
 
 hipError_t launch_factor(const FactorArgs& f, hipStream_t st) {
+  if (!f.write_matrix && f.sp <= 64) {
+#define RAC_FACTORW(SPV)                                                                                  \
+    if (f.sp == SPV) {                                                                                   \
+      k_factor_wave<SPV><<<(unsigned)f.p, 64, 0, st>>>(f.partial, f.R, f.n, f.p, f.perm, f.Ns, f.h, f.a,  \
+                                                       f.beta_ptr, f.beta_val, f.Minv, f.sc,           \
+                                                       f.iter_global);                                 \
+      return hipGetLastError();                                                                        \
+    }
+    RAC_FACTORW(16) RAC_FACTORW(32) RAC_FACTORW(64)
+#undef RAC_FACTORW
+  }
 #define RAC_FACTOR(SPV)                                                                              \
   if (f.sp == SPV) {                                                                                 \
     k_factor<SPV><<<(unsigned)f.p, 256, 0, st>>>(f.partial, f.R, f.n, f.p, f.perm, f.Ns, f.h, f.a,     \

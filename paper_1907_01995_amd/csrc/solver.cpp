@@ -192,7 +192,7 @@ struct rac_solver_s {
   hipEvent_t ev_start = nullptr, ev_fac[2] = {nullptr, nullptr}, ev_sweep[2] = {nullptr, nullptr};
   DevScalars hsc{};
   // optional per-phase timing with HIP events on the run's stream
-  bool timing = false;
+  uint32_t tmask = 0;                    // phases timed (bit q: phase q)
   std::vector<hipEvent_t> ev;            // pool, two per timed launch
   std::vector<int> ev_phase;             // phase of each recorded pair in the current chunk
   double phase_ms[RAC_NUM_PHASES] = {0};
@@ -225,14 +225,16 @@ rac_status fx_into_u(rac_solver s, const double* x, double* u, hipStream_t st) {
   return RAC_OK;
 }
 
-// Event pairs around timed launches: begin() records the start event of the
-// next pair, end() its stop event and remembers the phase.
+// Event pairs around timed launches of the phases selected in the timing mask:
+// begin() records the start event of the next pair, end() its stop event and
+// remembers the phase.
 struct PhaseTimer {
   rac_solver s;
   hipStream_t st;
-  hipError_t begin(hipStream_t on) { st = on; return begin(); }
-  hipError_t begin() {
-    if (!s->timing) return hipSuccess;
+  bool on(int phase) const { return ((s->tmask >> phase) & 1u) != 0; }
+  hipError_t begin(hipStream_t stream, int phase) { st = stream; return begin(phase); }
+  hipError_t begin(int phase) {
+    if (!on(phase)) return hipSuccess;
     const size_t i = 2 * s->ev_phase.size();
     while (s->ev.size() < i + 2) {
       hipEvent_t e;
@@ -243,7 +245,7 @@ struct PhaseTimer {
     return hipEventRecord(s->ev[i], st);
   }
   hipError_t end(int phase) {
-    if (!s->timing) return hipSuccess;
+    if (!on(phase)) return hipSuccess;
     const size_t i = 2 * s->ev_phase.size();
     s->ev_phase.push_back(phase);
     return hipEventRecord(s->ev[i + 1], st);
@@ -251,7 +253,7 @@ struct PhaseTimer {
 };
 
 rac_status collect_timing(rac_solver s) {
-  if (!s->timing) return RAC_OK;
+  if (s->ev_phase.empty()) return RAC_OK;
   for (size_t q = 0; q < s->ev_phase.size(); ++q) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, s->ev[2 * q], s->ev[2 * q + 1]));
@@ -266,7 +268,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   const rac_problem& P = s->P;
   PhaseTimer tm{s, st};
   const int64_t k0 = s->hsc.k;
-  HIPCHK(tm.begin());
+  HIPCHK(tm.begin(RAC_PHASE_PARTITION));
   HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
   HIPCHK(tm.end(RAC_PHASE_PARTITION));
   const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
@@ -287,14 +289,14 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     void* Fp = s->Fp ? (void*)(s->Fp + par * s->Fp_bytes) : nullptr;
     GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
                s->partial, PackDst{Fp, s->packRW, s->K, s->tileA, s->tileB}};
-    HIPCHK(tm.begin(sa));
+    HIPCHK(tm.begin(sa, RAC_PHASE_GRAM));
     HIPCHK(launch_gram(g, sa));
     HIPCHK(tm.end(RAC_PHASE_GRAM));
     FactorArgs f{};
     f.partial = s->partial; f.R = s->R; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
     f.Ns = P.Ns; f.h = P.h; f.a = P.a; f.beta_ptr = beta_ptr; f.beta_val = 0.0; f.Minv = Minv;
     f.write_matrix = 0; f.sc = s->sc; f.iter_global = k0 + t;
-    HIPCHK(tm.begin(sa));
+    HIPCHK(tm.begin(sa, RAC_PHASE_FACTOR));
     HIPCHK(launch_factor(f, sa));
     HIPCHK(tm.end(RAC_PHASE_FACTOR));
     if (s->overlap) {
@@ -304,7 +306,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, Minv, s->sp, P.c, P.h, P.a,
                 P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
                 beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, nullptr, Fp};
-    HIPCHK(tm.begin(st));
+    HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
     HIPCHK(launch_sweep(w, st));
     HIPCHK(tm.end(RAC_PHASE_SWEEP));
     if (s->overlap) HIPCHK(hipEventRecord(s->ev_sweep[par], st));
@@ -314,7 +316,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     za.b = P.b; za.has_eq = P.a ? 1 : 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
     za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
     za.hist_base = k0 - run_offset; za.T = s->T; za.beta_ptr = beta_ptr; za.publish_beta = sched ? 1 : 0;
-    HIPCHK(tm.begin(st));
+    HIPCHK(tm.begin(st, RAC_PHASE_ZDUAL));
     HIPCHK(launch_zdual(za, st));
     HIPCHK(tm.end(RAC_PHASE_ZDUAL));
   }
@@ -324,7 +326,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   ka.alpha = P.alpha; ka.lo = P.lo; ka.hi = P.hi; ka.x = s->x; ka.z = s->z; ka.xi = s->xi;
   ka.u = s->u; ka.mu_ptr = &s->sc->mu; ka.mu_val = 0.0; ka.red = s->red; ka.done = s->done;
   ka.out = s->kkt_out;
-  HIPCHK(tm.begin(st));
+  HIPCHK(tm.begin(st, RAC_PHASE_CHECK));
   HIPCHK(launch_kkt(ka, st));
   ControlArgs ca{};
   ca.sc = s->sc; ca.kkt_out = s->kkt_out; ca.beta_mode = s->O.beta_mode; ca.rb_mu = s->O.rb_mu;
@@ -593,8 +595,12 @@ rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, 
 }
 
 rac_status rac_solver_set_timing(rac_solver s, int32_t enable) {
-  if (!s) return RAC_ERR_ARG;
-  s->timing = enable != 0;
+  return rac_solver_set_timing_mask(s, enable ? (1u << RAC_NUM_PHASES) - 1u : 0u);
+}
+
+rac_status rac_solver_set_timing_mask(rac_solver s, uint32_t mask) {
+  if (!s || (mask >> RAC_NUM_PHASES) != 0) return RAC_ERR_ARG;
+  s->tmask = mask;
   for (int q = 0; q < RAC_NUM_PHASES; ++q) { s->phase_ms[q] = 0.0; s->phase_count[q] = 0; }
   s->ev_phase.clear();
   return RAC_OK;
