@@ -98,7 +98,7 @@ rac_status alloc_perm_work(Buffers& B, int64_t T, int64_t n, PermWork* w, int32_
   ALLOC(B, w->offset, (size_t)(T * (nb + 1)));
   ALLOC(B, w->fill, (size_t)(T * nb));
   ALLOC(B, w->members, (size_t)(T * n));
-  ALLOC(B, *perm, (size_t)(T * n));
+  ALLOC(B, *perm, (size_t)(2 * T * n));
   HIPCHK(hipMemset(w->count, 0, sizeof(uint32_t) * T * nb));
   HIPCHK(hipMemset(w->fill, 0, sizeof(uint32_t) * T * nb));
   return RAC_OK;
@@ -164,7 +164,8 @@ struct rac_solver_s {
   int64_t n = 0, rows = 0, p = 0, T = 1;
   int sp = 16, R = 1, K = 1;
   Buffers buf;
-  int32_t* perm = nullptr;
+  int32_t* perm = nullptr;  // partitions of a chunk's iterations, two buffers of [T][n] (by chunk)
+  int pbuf = 0;             // buffer of the current chunk
   PermWork pw{};
   double* partial = nullptr;
   double* Minv = nullptr;
@@ -190,6 +191,10 @@ struct rac_solver_s {
   bool overlap = false;     // assemble on a second stream during the previous sweep
   hipStream_t sB = nullptr;
   hipEvent_t ev_start = nullptr, ev_fac[2] = {nullptr, nullptr}, ev_sweep[2] = {nullptr, nullptr};
+  hipEvent_t ev_check = nullptr;   // scalars of a chunk copied out: the next chunk's factor may run
+  int64_t swept[2] = {-1, -1};     // iteration of the last sweep recorded in ev_sweep[parity] this run
+  int64_t pre_k = -1;              // iteration whose partition, Gram and factor are already enqueued
+  DevScalars* hsc_pin = nullptr;   // pinned copy of the scalars read after each chunk
   DevScalars hsc{};
   // optional per-phase timing with HIP events on the run's stream
   uint32_t tmask = 0;                    // phases timed (bit q: phase q)
@@ -256,6 +261,7 @@ rac_status collect_timing(rac_solver s) {
   if (s->ev_phase.empty()) return RAC_OK;
   for (size_t q = 0; q < s->ev_phase.size(); ++q) {
     float ms = 0.f;
+    HIPCHK(hipEventSynchronize(s->ev[2 * q + 1]));   // launches enqueued ahead may still run
     HIPCHK(hipEventElapsedTime(&ms, s->ev[2 * q], s->ev[2 * q + 1]));
     s->phase_ms[s->ev_phase[q]] += ms;
     s->phase_count[s->ev_phase[q]] += 1;
@@ -264,52 +270,112 @@ rac_status collect_timing(rac_solver s) {
   return RAC_OK;
 }
 
+// Gram (with the packed copy) of iteration k on the assemble stream.  Its
+// inverse and packed buffers (by parity of k) were last read by the sweep of
+// iteration k - 2, which it waits for when that sweep belongs to this run.
+rac_status enqueue_gram(rac_solver s, int64_t k, const int32_t* perm, hipStream_t sa, PhaseTimer& tm) {
+  const rac_problem& P = s->P;
+  const int par = (int)(k & 1);
+  if (s->overlap && s->swept[par] >= 0) HIPCHK(hipStreamWaitEvent(sa, s->ev_sweep[par], 0));
+  void* Fp = s->Fp ? (void*)(s->Fp + par * s->Fp_bytes) : nullptr;
+  GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
+             s->partial, PackDst{Fp, s->packRW, s->K, s->tileA, s->tileB}};
+  HIPCHK(tm.begin(sa, RAC_PHASE_GRAM));
+  HIPCHK(launch_gram(g, sa));
+  HIPCHK(tm.end(RAC_PHASE_GRAM));
+  return RAC_OK;
+}
+
+// Factor of iteration k after its Gram; with overlap the sweep's stream waits on ev_fac.
+rac_status enqueue_factor(rac_solver s, int64_t k, const int32_t* perm, const double* beta_ptr, hipStream_t sa,
+                          PhaseTimer& tm) {
+  const rac_problem& P = s->P;
+  const int par = (int)(k & 1);
+  FactorArgs f{};
+  f.partial = s->partial; f.R = s->R; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
+  f.Ns = P.Ns; f.h = P.h; f.a = P.a; f.beta_ptr = beta_ptr; f.beta_val = 0.0;
+  f.Minv = s->Minv + par * (size_t)s->p * s->sp * s->sp;
+  f.write_matrix = 0; f.sc = s->sc; f.iter_global = k;
+  HIPCHK(tm.begin(sa, RAC_PHASE_FACTOR));
+  HIPCHK(launch_factor(f, sa));
+  HIPCHK(tm.end(RAC_PHASE_FACTOR));
+  if (s->overlap) HIPCHK(hipEventRecord(s->ev_fac[par], sa));
+  return RAC_OK;
+}
+
+const double* beta_of(rac_solver s, int64_t run_offset) {
+  return s->O.beta_mode == RAC_BETA_SCHEDULE ? s->d_sched + run_offset : &s->sc->beta;
+}
+
+// With overlap, the partitions of the next chunk (starting at iteration k1, Tn
+// iterations) and the Gram of its first iteration go on the assemble stream
+// right away, so they run during this chunk's last sweep; the factor, which
+// needs the penalty decided at this chunk's check, waits for the check and the
+// copy of the scalars.  None of this touches the iterate.
+rac_status preissue_next_chunk(rac_solver s, int64_t k1, int64_t Tn, int64_t run_offset, hipStream_t st) {
+  PhaseTimer tm{s, st};
+  hipStream_t sa = s->sB;
+  const int b = 1 - s->pbuf;
+  int32_t* pb = s->perm + (size_t)b * s->T * s->n;
+  // the buffer was last read by the previous chunk's sweeps, all before the sweep of k1 - 2
+  if (s->swept[k1 & 1] >= 0) HIPCHK(hipStreamWaitEvent(sa, s->ev_sweep[k1 & 1], 0));
+  HIPCHK(tm.begin(sa, RAC_PHASE_PARTITION));
+  HIPCHK(launch_permutations(s->O.seed, s->O.instance, k1, Tn, s->n, s->pw, pb, sa));
+  HIPCHK(tm.end(RAC_PHASE_PARTITION));
+  rac_status e = enqueue_gram(s, k1, pb, sa, tm);
+  if (e != RAC_OK) return e;
+  HIPCHK(hipEventRecord(s->ev_check, st));
+  HIPCHK(hipStreamWaitEvent(sa, s->ev_check, 0));
+  e = enqueue_factor(s, k1, pb, beta_of(s, run_offset), sa, tm);
+  if (e != RAC_OK) return e;
+  s->pre_k = k1;
+  return RAC_OK;
+}
+
 rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
   const rac_problem& P = s->P;
   PhaseTimer tm{s, st};
   const int64_t k0 = s->hsc.k;
-  HIPCHK(tm.begin(RAC_PHASE_PARTITION));
-  HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
-  HIPCHK(tm.end(RAC_PHASE_PARTITION));
   const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
   hipStream_t sa = s->overlap ? s->sB : st;   // stream of the assemble phase
-  if (s->overlap) {
-    HIPCHK(hipEventRecord(s->ev_start, st));   // partitions drawn, previous chunk's penalty final
-    HIPCHK(hipStreamWaitEvent(sa, s->ev_start, 0));
-  }
-  const size_t mstride = (size_t)s->p * s->sp * s->sp;
-  for (int64_t t = 0; t < Tc; ++t) {
-    const int32_t* perm = s->perm + t * s->n;
-    const int par = (int)((k0 + t) & 1);
-    double* Minv = s->Minv + par * mstride;
-    const double* beta_ptr = sched ? s->d_sched + (run_offset + t) : &s->sc->beta;
-    // assemble: the inverse buffer of this parity was last read by the sweep two iterations ago
-    if (s->overlap && t >= 2) HIPCHK(hipStreamWaitEvent(sa, s->ev_sweep[par], 0));
-    // the Gram kernel also writes this iteration's packed copy (read by the sweep below)
-    void* Fp = s->Fp ? (void*)(s->Fp + par * s->Fp_bytes) : nullptr;
-    GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
-               s->partial, PackDst{Fp, s->packRW, s->K, s->tileA, s->tileB}};
-    HIPCHK(tm.begin(sa, RAC_PHASE_GRAM));
-    HIPCHK(launch_gram(g, sa));
-    HIPCHK(tm.end(RAC_PHASE_GRAM));
-    FactorArgs f{};
-    f.partial = s->partial; f.R = s->R; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
-    f.Ns = P.Ns; f.h = P.h; f.a = P.a; f.beta_ptr = beta_ptr; f.beta_val = 0.0; f.Minv = Minv;
-    f.write_matrix = 0; f.sc = s->sc; f.iter_global = k0 + t;
-    HIPCHK(tm.begin(sa, RAC_PHASE_FACTOR));
-    HIPCHK(launch_factor(f, sa));
-    HIPCHK(tm.end(RAC_PHASE_FACTOR));
+  const bool pre = s->overlap && s->pre_k == k0;   // partitions and first assemble already enqueued
+  s->pre_k = -1;
+  if (pre) {
+    s->pbuf = 1 - s->pbuf;
+  } else {
+    s->pbuf = 0;
+    HIPCHK(tm.begin(RAC_PHASE_PARTITION));
+    HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
+    HIPCHK(tm.end(RAC_PHASE_PARTITION));
     if (s->overlap) {
-      HIPCHK(hipEventRecord(s->ev_fac[par], sa));
-      HIPCHK(hipStreamWaitEvent(st, s->ev_fac[par], 0));
+      HIPCHK(hipEventRecord(s->ev_start, st));   // partitions drawn, previous chunk's penalty final
+      HIPCHK(hipStreamWaitEvent(sa, s->ev_start, 0));
     }
+  }
+  const int32_t* pbase = s->perm + (size_t)s->pbuf * s->T * s->n;
+  for (int64_t t = 0; t < Tc; ++t) {
+    const int64_t k = k0 + t;
+    const int32_t* perm = pbase + t * s->n;
+    const int par = (int)(k & 1);
+    double* Minv = s->Minv + par * (size_t)s->p * s->sp * s->sp;
+    const double* beta_ptr = beta_of(s, run_offset + t);
+    if (!(pre && t == 0)) {
+      rac_status e = enqueue_gram(s, k, perm, sa, tm);
+      if (e == RAC_OK) e = enqueue_factor(s, k, perm, beta_ptr, sa, tm);
+      if (e != RAC_OK) return e;
+    }
+    if (s->overlap) HIPCHK(hipStreamWaitEvent(st, s->ev_fac[par], 0));
+    const void* Fp = s->Fp ? (const void*)(s->Fp + par * s->Fp_bytes) : nullptr;
     SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, Minv, s->sp, P.c, P.h, P.a,
                 P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
                 beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, nullptr, Fp};
     HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
     HIPCHK(launch_sweep(w, st));
     HIPCHK(tm.end(RAC_PHASE_SWEEP));
-    if (s->overlap) HIPCHK(hipEventRecord(s->ev_sweep[par], st));
+    if (s->overlap) {
+      HIPCHK(hipEventRecord(s->ev_sweep[par], st));
+      s->swept[par] = k;
+    }
     s->epoch += (uint64_t)s->p;
     UpdateArgs za{};
     za.n = s->n; za.prox = P.prox; za.lam = P.lambda; za.alpha = P.alpha; za.lo = P.lo; za.hi = P.hi;
@@ -418,6 +484,8 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
 
   auto fail = [&](rac_status r) {
     s->buf.release();
+    if (s->hsc_pin) (void)hipHostFree(s->hsc_pin);
+    if (s->ev_check) (void)hipEventDestroy(s->ev_check);
     if (s->ev_start) (void)hipEventDestroy(s->ev_start);
     for (int q = 0; q < 2; ++q) {
       if (s->ev_fac[q]) (void)hipEventDestroy(s->ev_fac[q]);
@@ -428,6 +496,10 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
     return r;
   };
   rac_status r;
+  if (hipHostMalloc((void**)&s->hsc_pin, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+    s->hsc_pin = nullptr;
+    return fail(RAC_ERR_NOMEM);
+  }
   if ((r = alloc_perm_work(s->buf, s->T, n, &s->pw, &s->perm)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->partial, (size_t)(s->p * s->R) * s->sp * s->sp)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->Minv, (size_t)2 * s->p * s->sp * s->sp)) != RAC_OK) return fail(r);
@@ -459,7 +531,8 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if (can_overlap) {
     if (hipStreamCreateWithFlags(&s->sB, hipStreamNonBlocking) != hipSuccess) return fail(RAC_ERR_DEVICE);
-    bool ok = hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&s->ev_start, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&s->ev_check, hipEventDisableTiming) == hipSuccess;
     for (int q = 0; q < 2 && ok; ++q)
       ok = hipEventCreateWithFlags(&s->ev_fac[q], hipEventDisableTiming) == hipSuccess &&
            hipEventCreateWithFlags(&s->ev_sweep[q], hipEventDisableTiming) == hipSuccess;
@@ -494,11 +567,13 @@ rac_status rac_solver_destroy(rac_solver s) {
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   if (s->ev_start) (void)hipEventDestroy(s->ev_start);
+  if (s->ev_check) (void)hipEventDestroy(s->ev_check);
   for (int q = 0; q < 2; ++q) {
     if (s->ev_fac[q]) (void)hipEventDestroy(s->ev_fac[q]);
     if (s->ev_sweep[q]) (void)hipEventDestroy(s->ev_sweep[q]);
   }
   if (s->sB) (void)hipStreamDestroy(s->sB);
+  if (s->hsc_pin) (void)hipHostFree(s->hsc_pin);
   s->buf.release();
   delete s;
   return RAC_OK;
@@ -520,14 +595,28 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
   rac_status rc = RAC_OK;
   int32_t run_status = RAC_RUN_MAX_ITER;
   rac_status e = RAC_OK;
+  s->pre_k = -1;
+  s->swept[0] = s->swept[1] = -1;
+  // the assemble stream starts after everything the caller enqueued before this run
+  if (s->overlap) {
+    HIPCHK(hipEventRecord(s->ev_start, st));
+    HIPCHK(hipStreamWaitEvent(s->sB, s->ev_start, 0));
+  }
   while (done_iters < budget) {
     const int64_t k = s->hsc.k;
     int64_t Tc = s->T - (k % s->T);
     if (Tc > budget - done_iters) Tc = budget - done_iters;
     e = enqueue_iteration_chunk(s, Tc, done_iters, st);
     if (e != RAC_OK) return e;
-    HIPCHK(hipMemcpyAsync(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(s->hsc_pin, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+    if (s->overlap && done_iters + Tc < budget) {
+      const int64_t k1 = k + Tc;
+      int64_t Tn = s->T - (k1 % s->T);
+      if (Tn > budget - done_iters - Tc) Tn = budget - done_iters - Tc;
+      if ((e = preissue_next_chunk(s, k1, Tn, done_iters + Tc, st)) != RAC_OK) return e;
+    }
     HIPCHK(hipStreamSynchronize(st));
+    s->hsc = *s->hsc_pin;
     if ((e = collect_timing(s)) != RAC_OK) return e;
     done_iters += Tc;
     if (s->hsc.fail_key != ~0ULL) {
@@ -540,6 +629,11 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
     if (s->hsc.status == 2) { run_status = RAC_RUN_DIVERGED; break; }
   }
   s->hist_count = s->hsc.k - k_start;
+  s->pre_k = -1;
+  if (s->overlap) {   // work enqueued ahead on the assemble stream ends before anything after this run
+    HIPCHK(hipEventRecord(s->ev_start, s->sB));
+    HIPCHK(hipStreamWaitEvent(st, s->ev_start, 0));
+  }
   // objective at z
   e = fx_into_u(s, s->z, s->uz, st);
   if (e != RAC_OK) return e;

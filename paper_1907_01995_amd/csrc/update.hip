@@ -117,6 +117,25 @@ __global__ void __launch_bounds__(256) k_zdual(int64_t n, int32_t prox, double l
 // re-summed from x.  red holds 10 values per workgroup:
 //   0 |Hx|, 1 |c|, 2 |xi|, 3 |x|, 4 |z|, 5 |x-z|, 6 |grad f - xi - mu a|,
 //   7 dist(-xi, dP(z)), 8 |a|, 9 sum a.x
+// Four consecutive entries of a column as doubles (16-byte loads for FP32 and
+// FP64 storage, 8-byte for BF16); the caller guarantees the alignment.
+__device__ __forceinline__ void ld4(const float* p, double (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const uint16_t* p, double (&o)[4]) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xffff0000u);
+  o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xffff0000u);
+}
+__device__ __forceinline__ void ld4(const double* p, double (&o)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p), b = *reinterpret_cast<const double2*>(p + 2);
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+
+// KKT check: each wavefront forms F_j'u for KC columns at once (u is read once
+// per KC columns); lane l takes rows 4l.. of every 256-row step with vector
+// loads when the columns are aligned (vec), the remaining rows one by one.
 template <typename T>
 __global__ void __launch_bounds__(256) k_kkt(const T* __restrict__ F, int64_t ldF, int64_t rows,
                                              int64_t n, double Ns, const double* __restrict__ h,
@@ -125,19 +144,51 @@ __global__ void __launch_bounds__(256) k_kkt(const T* __restrict__ F, int64_t ld
                                              double hi, const double* __restrict__ x,
                                              const double* __restrict__ z, const double* __restrict__ xi,
                                              const double* __restrict__ u, const double* mu_ptr,
-                                             double mu_val, double* red, uint32_t* done, double* out) {
+                                             double mu_val, double* red, uint32_t* done, double* out, int vec) {
+  constexpr int KC = 2;
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double mu = mu_ptr ? *mu_ptr : mu_val;
   double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t j = (int64_t)blockIdx.x * 4 + wave; j < n; j += (int64_t)gridDim.x * 4) {
-    const T* col = F + j * ldF;
-    double acc = 0.0;
-    for (int64_t r = lane; r < rows; r += 64) acc += ld_f64(col, r) * u[r];
-    acc = wave_sum(acc);
-    if (lane == 0)
-      kkt_column_terms(acc, Ns, h ? h[j] : 0.0, c[j], a ? a[j] : 0.0, x[j], z[j], xi[j], mu, prox, lam, alpha,
-                       lo, hi, m);
+  const int64_t rows4 = vec ? rows / 256 * 256 : 0;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * KC; j0 < n; j0 += nwaves * KC) {
+    const T* col[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) col[k] = F + (j0 + k < n ? j0 + k : n - 1) * ldF;   // a valid column
+    double acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+#pragma unroll 4
+    for (int64_t r = 4 * lane; r < rows4; r += 256) {
+      double uu[4];
+      ld4(u + r, uu);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        double f[4];
+        ld4(col[k] + r, f);
+        acc[k] += f[0] * uu[0];
+        acc[k] += f[1] * uu[1];
+        acc[k] += f[2] * uu[2];
+        acc[k] += f[3] * uu[3];
+      }
+    }
+    for (int64_t r = rows4 + lane; r < rows; r += 64) {
+      const double ur = u[r];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc[k] += ld_f64(col[k], r) * ur;
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const int64_t j = j0 + k;
+        if (j < n)
+          kkt_column_terms(acc[k], Ns, h ? h[j] : 0.0, c[j], a ? a[j] : 0.0, x[j], z[j], xi[j], mu, prox, lam,
+                           alpha, lo, hi, m);
+      }
+    }
   }
   for (int q = 0; q < 9; ++q) {
     double v = block_max(m[q], sh);
@@ -254,11 +305,13 @@ __global__ void __launch_bounds__(256) k_objective(int64_t rows, int64_t n, doub
 
 template <typename T>
 hipError_t kkt_launch(const KKTArgs& k, hipStream_t st) {
-  int64_t blocks = (k.n + 3) / 4;
+  int64_t blocks = (k.n + 7) / 8;   // two columns per wavefront
   if (blocks > kRedBlocks) blocks = kRedBlocks;
+  const size_t al = sizeof(T) == 8 ? 16 : 4 * sizeof(T);
+  const int vec = (k.ldF % 4 == 0) && ((uintptr_t)k.F % al == 0) && ((uintptr_t)k.u % 16 == 0);
   k_kkt<T><<<(unsigned)blocks, 256, 0, st>>>((const T*)k.F, k.ldF, k.rows, k.n, k.Ns, k.h, k.c, k.a,
                                               k.b, k.prox, k.lam, k.alpha, k.lo, k.hi, k.x, k.z,
-                                              k.xi, k.u, k.mu_ptr, k.mu_val, k.red, k.done, k.out);
+                                              k.xi, k.u, k.mu_ptr, k.mu_val, k.red, k.done, k.out, vec);
   return hipGetLastError();
 }
 
