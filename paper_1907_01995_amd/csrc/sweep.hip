@@ -28,6 +28,7 @@
 // s_waitcnt before the flag store -- no cache write-back or invalidation.
 // Partials are double-buffered by block parity, so one exchange per block suffices.
 #include "rac_internal.h"
+#include <type_traits>
 
 namespace rac {
 namespace {
@@ -235,6 +236,63 @@ __device__ __forceinline__ void load_packed(const T* __restrict__ Fp, int64_t i,
   }
 }
 
+// Lane exchange x -> x of lane (l xor O).  Within the 16-lane rows (O <= 8) by
+// DPP moves, which stay in the vector ALU: O = 8 is a row rotation by 8, O = 4 a
+// half-row mirror (l xor 7) followed by the quad permutation l xor 3, O = 2 and
+// O = 1 quad permutations.  Across rows (O = 16, 32) by the LDS permute unit.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int O>
+__device__ __forceinline__ double lane_xor(double x) {
+  if constexpr (O == 8) return dpp_move<0x128>(x);                      // row_ror:8
+  else if constexpr (O == 4) return dpp_move<0x1B>(dpp_move<0x141>(x));  // row_half_mirror, quad_perm [3,2,1,0]
+  else if constexpr (O == 2) return dpp_move<0x4E>(x);                  // quad_perm [2,3,0,1]
+  else if constexpr (O == 1) return dpp_move<0xB1>(x);                  // quad_perm [1,0,3,2]
+  else return __shfl_xor(x, O, 64);
+}
+
+// Per-column sums of B per-lane values (B = 8 or 16) over the 64 lanes: halving
+// exchanges at lane distances 8, 4, 2 (, 1) inside each 16-lane row leave lane l
+// with a row partial of column c = (l & 15) >> (4 - log2 B); full sums finish
+// the row (B = 8: distance 1) and add the four rows (distances 16, 32).  Every
+// lane ends with its column's total; the summation pattern is fixed.
+template <int B>
+__device__ __forceinline__ double row_transpose_sum(double (&v)[B], int lane, int& c) {
+  static_assert(B == 8 || B == 16, "row-local transposition covers 8 or 16 columns");
+  auto stage = [&](auto o_tag, int half) {
+    constexpr int O = decltype(o_tag)::value;
+    const bool upper = (lane & O) != 0;
+#pragma unroll
+    for (int q = 0; q < B / 2; ++q) {
+      if (q < half) {
+        const double send = upper ? v[q] : v[q + half];
+        const double keep = upper ? v[q + half] : v[q];
+        v[q] = keep + lane_xor<O>(send);
+      }
+    }
+  };
+  stage(std::integral_constant<int, 8>{}, B / 2);
+  stage(std::integral_constant<int, 4>{}, B / 4);
+  stage(std::integral_constant<int, 2>{}, B / 8);
+  double r = v[0];
+  if constexpr (B == 16) {
+    stage(std::integral_constant<int, 1>{}, 1);
+    r = v[0];
+    c = lane & 15;
+  } else {
+    r += lane_xor<1>(r);
+    c = (lane & 15) >> 1;
+  }
+  r += lane_xor<16>(r);
+  r += lane_xor<32>(r);
+  return r;
+}
+
 template <typename T, int A, int B>
 __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   typedef typename RegT<T>::type R;
@@ -318,9 +376,15 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
         v[bb] = acc;
       }
       int c;
-      const double tot = transpose_sum<B>(v, lane, c);
-      const int j = wave + 4 * c;
-      if ((lane & (64 / B - 1)) == 0 && j < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + j], tot);
+      if constexpr (B <= 16) {
+        const double tot = row_transpose_sum<B>(v, lane, c);
+        const int j = wave + 4 * c;
+        if (lane < 16 && (B == 16 || (lane & 1) == 0) && j < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + j], tot);
+      } else {
+        const double tot = transpose_sum<B>(v, lane, c);
+        const int j = wave + 4 * c;
+        if ((lane & (64 / B - 1)) == 0 && j < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + j], tot);
+      }
     }
     const uint64_t epoch = s.epoch_base + (uint64_t)i + 1;
     __builtin_amdgcn_s_waitcnt(0);   // partial stores complete at device scope; next indices landed
