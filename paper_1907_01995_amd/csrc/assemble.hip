@@ -97,17 +97,21 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
   const int64_t re_t = block_start(chunk + 1, ntiles, R) * KT;
   const int64_t re = re_t < rows ? re_t : rows;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // Padding columns (past a block's size) load the block's first column: every
+  // consumer ignores the Gram entries of padding, and the packed copy skips them.
   for (int m = tid; m < NCOL; m += 256) {
-    if (m < SP) colbase[m] = m < sb ? (int64_t)perm[s0 + m] * ldF : -1;
-    else colbase[m] = m - SP < sb1 ? (int64_t)perm[s1 + m - SP] * ldF : -1;
+    if (m < SP) colbase[m] = (int64_t)perm[s0 + (m < sb ? m : 0)] * ldF;
+    else colbase[m] = (int64_t)perm[(m - SP < sb1 ? s1 + m - SP : s0)] * ldF;
   }
 
+  // Every wavefront runs MAXP tile pairs; a wavefront with fewer real pairs runs
+  // spare ones on pair 0 and never writes them, so the MFMA loop has no branches.
   Acc acc[MAXP];
   int pti[MAXP], ptj[MAXP];
 #pragma unroll
   for (int q = 0; q < MAXP; ++q) {
     acc[q] = Acc{0, 0, 0, 0};
-    int pr = wave + 4 * q;
+    int pr = wave + 4 * q < NPAIR ? wave + 4 * q : 0;
     if constexpr (X) {                   // pair index -> (ti of block blk+1, tj of block blk)
       pti[q] = pr / NT;
       ptj[q] = pr % NT;
@@ -122,6 +126,20 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
 
   T stage[NV][VE];
   auto load = [&](int64_t r0) {
+    if (vec && r0 + KT <= re) {   // a whole tile in range: plain vector loads
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int v = tid + 256 * q;
+        if (v < NVEC) {
+          const int m = v / VPC, seg = v % VPC;
+          const uint4 raw = *reinterpret_cast<const uint4*>(F + colbase[m] + r0 + seg * VE);
+          const T* e = reinterpret_cast<const T*>(&raw);
+#pragma unroll
+          for (int u = 0; u < VE; ++u) stage[q][u] = e[u];
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int v = tid + 256 * q;
@@ -201,7 +219,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
       for (int kk = 0; kk < KT; kk += 8) {
 #pragma unroll
         for (int q = 0; q < MAXP; ++q) {
-          if (wave + 4 * q < NPAIR) {
+          {
             const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
             const double2 a2 = *reinterpret_cast<const double2*>(&tile[am * LD + kk + 2 * (lane >> 4)]);
             const double2 b2 = *reinterpret_cast<const double2*>(&tile[bn * LD + kk + 2 * (lane >> 4)]);
@@ -215,7 +233,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
       for (int kk = 0; kk < KT; kk += 16) {
 #pragma unroll
         for (int q = 0; q < MAXP; ++q) {
-          if (wave + 4 * q < NPAIR) {
+          {
             const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
             const float4 a4 = *reinterpret_cast<const float4*>(&tile[am * LD + kk + 4 * (lane >> 4)]);
             const float4 b4 = *reinterpret_cast<const float4*>(&tile[bn * LD + kk + 4 * (lane >> 4)]);
@@ -231,7 +249,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
       for (int kk = 0; kk < KT; kk += 32) {
 #pragma unroll
         for (int q = 0; q < MAXP; ++q) {
-          if (wave + 4 * q < NPAIR) {
+          {
             const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
             const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[am * LD + kk + 8 * (lane >> 4)]);
             const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&tile[bn * LD + kk + 8 * (lane >> 4)]);
