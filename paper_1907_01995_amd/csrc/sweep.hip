@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   const int64_t r1 = r0 + s.RW < s.rows ? r0 + s.RW : s.rows;
   const T* F = (const T*)s.F;
   const T* Fp = (const T*)s.Fp;
-  __shared__ double sh_g[kMaxBlock];
+  __shared__ __attribute__((aligned(16))) double sh_g[kMaxBlock];
   __shared__ double sh_d[kMaxBlock];
   __shared__ double sh_pg[256];
   __shared__ double sh_red[4 * 64 * A];
@@ -341,8 +341,8 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     if constexpr (MREG) {
       const double* Mi = s.Minv + i * (int64_t)s.sp * s.sp;
 #pragma unroll
-      for (int e = 0; e < KM; ++e) {
-        const int k = part + P * e;
+      for (int e = 0; e < KM; ++e) {   // rows part*KM .. of the inverse's column jc
+        const int k = part * KM + e;
         mreg[e] = (jc < sbi && k < sbi) ? Mi[(int64_t)k * s.sp + jc] : 0.0;
       }
     }
@@ -426,12 +426,15 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       sh_pg[part * NC + jc] = acc;
     }
     __syncthreads();
-    if (tid < sb) {
-      double tot = 0.0;
+    if (tid < NC) {   // zero past the block, so the solve needs no masks
+      double v = 0.0;
+      if (tid < sb) {
+        double tot = 0.0;
 #pragma unroll
-      for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
-      double v = tot / s.Ns + gcur;
-      if (s.a) v += beta * s.a[cols[tid]] * (t - s.b);
+        for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
+        v = tot / s.Ns + gcur;
+        if (s.a) v += beta * s.a[cols[tid]] * (t - s.b);
+      }
       sh_g[tid] = v;
     }
     __syncthreads();
@@ -439,10 +442,14 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     {
       double acc = 0.0;
       if constexpr (MREG) {
+        // the part's KM consecutive entries of g as 16-byte broadcast reads
+        const double* gk = sh_g + part * KM;
+        static_assert(KM % 2 == 0, "pairs of g");
 #pragma unroll
-        for (int e = 0; e < KM; ++e) {
-          const int k = part + P * e;
-          acc += mreg[e] * sh_g[k < sb ? k : 0] * (k < sb ? 1.0 : 0.0);
+        for (int e = 0; e < KM; e += 2) {
+          const double2 g2 = *reinterpret_cast<const double2*>(gk + e);
+          acc += mreg[e] * g2.x;
+          acc += mreg[e + 1] * g2.y;
         }
       } else {
         const double* Mi = s.Minv + i * (int64_t)s.sp * s.sp;
