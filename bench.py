@@ -63,6 +63,21 @@ def algorithmic(phase, N, n, p, bA):
     return 0.0, 0.0
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counters of the
+    kernel (scaled by a plain copy of known size), or None when the kernel's sources
+    have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    from paper_1907_01995_amd import profsum
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != profsum.source_hash(kernel):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def batched_leg(args, racmb, W, torch, weights, log):
     """Batched elastic-net paths: 256 uneven instances x 16 lambda lanes, BF16 data."""
     t0 = time.time()
@@ -164,6 +179,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--batched-warmup", type=int, default=10)
     ap.add_argument("--batched-cap", type=int, default=500)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="add plain 256 MiB device copies (counter calibration for rocprofv3 --pmc runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -208,6 +225,13 @@ def main():
     sweep_t = sol.timing()["sweep"]
     info = sol.info()
     ips = res.iters / elapsed
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # every phase, timed in a separate run of the same length
     tim = racmb.Solver(prob32, max_iter=args.steps, tol=0.0, **cand_kw)
     tim.set_timing(True)
@@ -235,8 +259,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = {"sweep": "k_sweep2", "gram": "k_gram", "factor": "k_factor",
+    roof["traffic"] = measured_traffic("k_sweep2", "lasso_20000x2000")
+    roof["kernel"] = {"sweep": "k_sweep2", "gram": "k_gram", "factor": "k_factor_wave",
                       "zdual": "k_zdual", "check": "k_kkt+k_control", "partition": "k_perm_*"}[dom]
     roof["avg_launch_us"] = avg * 1e6
 

@@ -59,15 +59,13 @@ constexpr int gram_kt() {
 // One workgroup: block `blk`, rows [rb, re).  Data move as 16-byte vectors of
 // VE = 16/sizeof(T) consecutive rows of one column; the next 64-row tile is
 // loaded into registers while the matrix cores work on the current one.
-// X (cross): the columns of blocks blk and blk+1 are staged together and every
-// 16 x 16 tile of F_{blk+1}' F_blk is formed (out[row of blk+1][column of blk]).
 // With a packed destination (pk.Fp non-null) the loaded values of the block's
 // real entries are also written, unchanged, to the sweep's register-order copy:
 // entry (row r, column m of block blk) goes to
 //   ((((blk K + g) 4 + m % 4) B + m / 4) 64 A) + (r - g RW),   g = r / RW.
 // Positions no real entry maps to (short blocks, rows past the end, group
 // padding) are never written; the buffer is zeroed once when it is created.
-template <typename T, int MODE, int SP, bool X = false>
+template <typename T, int MODE, int SP>
 __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, int64_t rows, int64_t n,
                                           int64_t p, const int32_t* __restrict__ perm, int blk, int chunk,
                                           int R, int vec, double* __restrict__ out,
@@ -75,22 +73,20 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
   typedef GramTraits<MODE> Tr;
   typedef typename Tr::E E;
   typedef typename Tr::Acc Acc;
-  constexpr int NCOL = X ? 2 * SP : SP;         // staged columns
+  constexpr int NCOL = SP;                      // staged columns
   constexpr int KT = gram_kt<MODE, NCOL>();     // rows per tile
   constexpr int VE = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int VPC = KT / VE;                  // vectors per column per tile
   constexpr int NVEC = NCOL * VPC;
   constexpr int NV = (NVEC + 255) / 256;        // vectors per thread per tile
   constexpr int LD = KT + Tr::PAD;              // LDS row stride of the column-major tile
-  constexpr int NT = SP / 16, NPAIR = X ? NT * NT : NT * (NT + 1) / 2;
+  constexpr int NT = SP / 16, NPAIR = NT * (NT + 1) / 2;
   constexpr int MAXP = (NPAIR + 3) / 4;
   __shared__ __attribute__((aligned(16))) E tile[NCOL * LD];   // tile[m * LD + k] = F[r0 + k, col_m]
   __shared__ int64_t colbase[NCOL];
 
   const int64_t s0 = block_start(blk, n, p);
   const int sb = (int)(block_start(blk + 1, n, p) - s0);
-  const int64_t s1 = block_start(blk + 1, n, p);
-  const int sb1 = X ? (int)(block_start(blk + 2, n, p) - s1) : 0;
   // row chunks are whole tiles except the last
   const int64_t ntiles = (rows + KT - 1) / KT;
   const int64_t rb = block_start(chunk, ntiles, R) * KT;
@@ -99,10 +95,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // Padding columns (past a block's size) load the block's first column: every
   // consumer ignores the Gram entries of padding, and the packed copy skips them.
-  for (int m = tid; m < NCOL; m += 256) {
-    if (m < SP) colbase[m] = (int64_t)perm[s0 + (m < sb ? m : 0)] * ldF;
-    else colbase[m] = (int64_t)perm[(m - SP < sb1 ? s1 + m - SP : s0)] * ldF;
-  }
+  for (int m = tid; m < NCOL; m += 256) colbase[m] = (int64_t)perm[s0 + (m < sb ? m : 0)] * ldF;
 
   // Every wavefront runs MAXP tile pairs; a wavefront with fewer real pairs runs
   // spare ones on pair 0 and never writes them, so the MFMA loop has no branches.
@@ -112,15 +105,10 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
   for (int q = 0; q < MAXP; ++q) {
     acc[q] = Acc{0, 0, 0, 0};
     int pr = wave + 4 * q < NPAIR ? wave + 4 * q : 0;
-    if constexpr (X) {                   // pair index -> (ti of block blk+1, tj of block blk)
-      pti[q] = pr / NT;
-      ptj[q] = pr % NT;
-    } else {                             // pair index -> (ti >= tj), row-major over the lower triangle
-      int ti = 0;
-      while ((ti + 1) * (ti + 2) / 2 <= pr) ++ti;
-      pti[q] = ti;
-      ptj[q] = pr - ti * (ti + 1) / 2;
-    }
+    int ti = 0;                          // pair index -> (ti >= tj), row-major over the lower triangle
+    while ((ti + 1) * (ti + 2) / 2 <= pr) ++ti;
+    pti[q] = ti;
+    ptj[q] = pr - ti * (ti + 1) / 2;
   }
   __syncthreads();
 
@@ -186,7 +174,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
     for (int q = 0; q < NV; ++q) {
       const int v = tid + 256 * q;
       const int m = v / VPC;
-      if (v >= NVEC || m >= sb || X) continue;
+      if (v >= NVEC || m >= sb) continue;
       T* dst = Fp + (((((int64_t)blk * pk.K + g) * 4 + (m & 3)) * pk.B + (m >> 2)) * 64) * pk.A;
       if (whole) {
         uint4 raw;
@@ -220,7 +208,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
 #pragma unroll
         for (int q = 0; q < MAXP; ++q) {
           {
-            const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
+            const int am = pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
             const double2 a2 = *reinterpret_cast<const double2*>(&tile[am * LD + kk + 2 * (lane >> 4)]);
             const double2 b2 = *reinterpret_cast<const double2*>(&tile[bn * LD + kk + 2 * (lane >> 4)]);
             acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.x, b2.x, acc[q], 0, 0, 0);
@@ -234,7 +222,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
 #pragma unroll
         for (int q = 0; q < MAXP; ++q) {
           {
-            const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
+            const int am = pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
             const float4 a4 = *reinterpret_cast<const float4*>(&tile[am * LD + kk + 4 * (lane >> 4)]);
             const float4 b4 = *reinterpret_cast<const float4*>(&tile[bn * LD + kk + 4 * (lane >> 4)]);
             acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc[q], 0, 0, 0);
@@ -250,7 +238,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
 #pragma unroll
         for (int q = 0; q < MAXP; ++q) {
           {
-            const int am = (X ? SP : 0) + pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
+            const int am = pti[q] * 16 + (lane & 15), bn = ptj[q] * 16 + (lane & 15);
             const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[am * LD + kk + 8 * (lane >> 4)]);
             const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&tile[bn * LD + kk + 8 * (lane >> 4)]);
             acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8v, av),
@@ -275,28 +263,6 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
       }
     }
   }
-}
-
-// Cross-Grams of the block pairs (2w, 2w+1): one workgroup per (pair, row chunk).
-template <typename T, int MODE, int SP>
-__global__ void __launch_bounds__(256) k_xgram(const T* __restrict__ F, int64_t ldF, int64_t rows,
-                                               int64_t n, int64_t p, const int32_t* __restrict__ perm,
-                                               int R, int vec, double* __restrict__ partial) {
-  const int w = blockIdx.x, chunk = blockIdx.y;
-  gram_body<T, MODE, SP, true>(F, ldF, rows, n, p, perm, 2 * w, chunk, R, vec,
-                               partial + ((int64_t)w * R + chunk) * (int64_t)SP * SP);
-}
-
-// C_w = (sum of the R chunk partials, in order) / Ns.
-__global__ void __launch_bounds__(256) k_xsum(const double* __restrict__ partial, int R, int spsq, double Ns,
-                                              double* __restrict__ C) {
-  const int w = blockIdx.x;
-  const int e = blockIdx.y * 256 + threadIdx.x;
-  if (e >= spsq) return;
-  const double* q = partial + (int64_t)w * R * spsq + e;
-  double s = 0.0;
-  for (int r = 0; r < R; ++r) s += q[(int64_t)r * spsq];
-  C[(int64_t)w * spsq + e] = s / Ns;
 }
 
 template <typename T, int MODE, int SP>
@@ -481,24 +447,6 @@ hipError_t gram_launch(const GramArgs& g, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-template <typename T, int MODE>
-hipError_t xgram_launch(const GramArgs& g, hipStream_t st) {
-  const int nw = (int)(g.p / 2);
-  if (nw == 0) return hipSuccess;
-  dim3 grid((unsigned)nw, (unsigned)g.R);
-  const int vec = (g.ldF % (16 / (int)sizeof(T)) == 0) && ((uintptr_t)g.F % 16 == 0);
-  const T* F = (const T*)g.F;
-#define RAC_XGRAM(SPV)                                                                         \
-  if (g.sp == SPV) {                                                                           \
-    k_xgram<T, MODE, SPV><<<grid, 256, 0, st>>>(F, g.ldF, g.rows, g.n, g.p, g.perm, g.R, vec,  \
-                                                g.partial);                                   \
-    return hipGetLastError();                                                                 \
-  }
-  RAC_XGRAM(16) RAC_XGRAM(32) RAC_XGRAM(64)
-#undef RAC_XGRAM
-  return hipErrorInvalidValue;
-}
-
 // One wavefront per block (SP <= 64), the lower-latency form of k_factor for
 // the single-instance solver: lane j holds column j of M_B in registers and
 // applies the symmetric sweep operator to pivots 0..sb-1,
@@ -596,24 +544,6 @@ __global__ void __launch_bounds__(64) k_factor_wave(const double* __restrict__ p
 
 }  // namespace
 
-hipError_t launch_xgram(const GramArgs& g, double Ns, double* C, hipStream_t st) {
-  const int nw = (int)(g.p / 2);
-  if (nw == 0) return hipSuccess;
-  const bool mixed = g.precision == RAC_PREC_MIXED;
-  hipError_t e;
-  switch (g.dtype) {
-    case RAC_DT_F64: e = xgram_launch<double, G_F64>(g, st); break;
-    case RAC_DT_F32: e = mixed ? xgram_launch<float, G_F32>(g, st) : xgram_launch<float, G_F64>(g, st); break;
-    case RAC_DT_BF16:
-      e = mixed ? xgram_launch<uint16_t, G_BF16>(g, st) : xgram_launch<uint16_t, G_F64>(g, st);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  if (e != hipSuccess) return e;
-  const int spsq = g.sp * g.sp;
-  k_xsum<<<dim3((unsigned)nw, (unsigned)((spsq + 255) / 256)), 256, 0, st>>>(g.partial, g.R, spsq, Ns, C);
-  return hipGetLastError();
-}
 
 template <typename T, int MODE>
 hipError_t bgram_launch(const BatchGramArgs& g, hipStream_t st) {

@@ -102,9 +102,6 @@ struct GramArgs {
   PackDst pack;            // packed copy written alongside (optional)
 };
 hipError_t launch_gram(const GramArgs& a, hipStream_t st);
-// Cross-Grams C_w = F_{2w+1}' F_{2w} / Ns of the block pairs (w < p/2), via row-chunk
-// partials in a.partial ([p/2][R][sp*sp]), into C ([p/2][sp*sp], row = block 2w+1).
-hipError_t launch_xgram(const GramArgs& a, double Ns, double* C, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Batched engine: many instances (each with its own data) and lanes (each an
@@ -205,7 +202,6 @@ struct SweepArgs {
   const double* beta_ptr;  // penalty of this iteration
   int tileA, tileB;        // register tile: rows per lane, columns per wavefront (0: streaming path)
   int cooperative;         // launch with the cooperative API (else a plain launch, K <= resident limit)
-  const double* Cx;        // cross-Grams of the block pairs ([p/2][sp*sp]): windows of two blocks; null: one block
   const void* Fp;          // packed tiles of this iteration written by the Gram kernel, or null (gather from F)
 };
 // Rows per sweep group for K groups and A rows per lane (0 if 64A rows do not cover a group).
@@ -213,11 +209,10 @@ int64_t sweep_rows_per_group(int64_t rows, int K, int A);
 // Elements of one packed copy of F for the register-tile sweep: p * K * 256 * A * B.
 int64_t sweep_packed_elems(int64_t p, int K, int A, int B);
 
-// Largest number of sweep workgroups that can be resident at once for a tile shape
-// (windowed: the kernel with windows of two blocks).
-int sweep_max_resident(int32_t dtype, int A, int B, bool windowed = false);
+// Largest number of sweep workgroups that can be resident at once for a tile shape.
+int sweep_max_resident(int32_t dtype, int A, int B);
 // Register-tile shapes with a compiled sweep kernel (A rows per lane, B columns per wavefront).
-bool sweep_tile_supported(int32_t dtype, int A, int B, bool windowed = false);
+bool sweep_tile_supported(int32_t dtype, int A, int B);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
 
 struct UpdateArgs {

@@ -368,7 +368,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     const void* Fp = s->Fp ? (const void*)(s->Fp + par * s->Fp_bytes) : nullptr;
     SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, Minv, s->sp, P.c, P.h, P.a,
                 P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
-                beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, nullptr, Fp};
+                beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, Fp};
     HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
     HIPCHK(launch_sweep(w, st));
     HIPCHK(tm.end(RAC_PHASE_SWEEP));

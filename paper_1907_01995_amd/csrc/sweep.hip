@@ -511,297 +511,6 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   if (g == 0 && tid == 0) s.sc->t = t;
 }
 
-// ---------------------------------------------------------------------------
-// Lookahead windows: blocks 2w and 2w+1 share one exchange.  Block 2w+1's
-// gradient needs u after block 2w's update, and
-//   F_{2w+1}'(u + F_{2w} d_{2w}) / Ns = F_{2w+1}'u / Ns + C_w d_{2w},
-//   C_w = F_{2w+1}' F_{2w} / Ns   (the pair's cross-Gram, formed with the Grams),
-// so both partials are published together and every group adds C_w d_{2w}
-// before solving block 2w+1: the same iteration with half the exchanges.  A
-// trailing single block (p odd) is a window of one.  Tiles of the next window
-// are loaded while the exchange is awaited; the inverses and cross-Gram of the
-// next window are loaded while this window's solves finish.
-template <typename T, int A, int B>
-__global__ void __launch_bounds__(256) k_sweepw(Sweep2Args s, const double* __restrict__ Cx) {
-  typedef typename RegT<T>::type R;
-  constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
-  constexpr int KM = (NC + P - 1) / P;            // inverse / cross-Gram entries per thread
-  static_assert(KM <= 16, "the window's inverses are kept in registers");
-  constexpr int NL = 128 / P;                     // partial loads per batch
-  const int K = gridDim.x, g = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int jc = tid % NC, part = tid / NC;
-  const int64_t r0 = (int64_t)g * s.RW;
-  const int64_t r1 = r0 + s.RW < s.rows ? r0 + s.RW : s.rows;
-  const T* F = (const T*)s.F;
-  const int64_t p = s.p, nw = (p + 1) / 2;
-  __shared__ double sh_g[kMaxBlock];
-  __shared__ double sh_d[2][kMaxBlock];
-  __shared__ double sh_pg[256];
-  __shared__ double sh_pc[256];
-  __shared__ double sh_red[4 * 64 * A];
-  __shared__ int32_t sh_cols[2][2][kMaxBlock];    // [window parity][block of the window][column]
-  const double beta = *s.beta_ptr;
-  const double mu = s.sc->mu;
-  double t = s.sc->t;
-  auto bstart = [&](int64_t i) { return block_start(i, s.n, p); };
-  auto bsize = [&](int64_t i) { return i < p ? (int)(bstart(i + 1) - bstart(i)) : 0; };
-  auto gbase = [&](int col) {
-    const double xc = s.x[col];
-    double v = s.c[col] - s.xi[col] + beta * (xc - s.z[col]);
-    if (s.h) v += s.h[col] * xc;
-    if (s.a) v -= mu * s.a[col];
-    return v;
-  };
-  double ureg[A];
-#pragma unroll
-  for (int aa = 0; aa < A; ++aa) {
-    const int64_t r = r0 + (int64_t)A * lane + aa;
-    ureg[aa] = r < r1 ? s.u[r] : 0.0;
-  }
-  R t1[A][B], t2[A][B], n1[A][B], n2[A][B];
-  double m1[KM], m2[KM], cx[KM];
-  auto load_minv = [&](int64_t i, double (&mr)[KM]) {
-    const int sbi = bsize(i);
-    const double* Mi = s.Minv + (i < p ? i : 0) * (int64_t)s.sp * s.sp;
-#pragma unroll
-    for (int e = 0; e < KM; ++e) {
-      const int k = part + P * e;
-      mr[e] = (jc < sbi && k < sbi) ? Mi[(int64_t)k * s.sp + jc] : 0.0;
-    }
-  };
-  auto load_cx = [&](int64_t w) {                 // cx[e] = C_w[jc][part + P e]
-    const int sa = bsize(2 * w), sbb = bsize(2 * w + 1);
-    const double* C = Cx + (sbb > 0 ? w : 0) * (int64_t)s.sp * s.sp;
-#pragma unroll
-    for (int e = 0; e < KM; ++e) {
-      const int k = part + P * e;
-      cx[e] = (jc < sbb && k < sa) ? C[(int64_t)jc * s.sp + k] : 0.0;
-    }
-  };
-  {
-    const int sa = bsize(0), sbb = bsize(1);
-    if (tid < sa) sh_cols[0][0][tid] = s.perm[tid];
-    if (tid < sbb) sh_cols[0][1][tid] = s.perm[bstart(1) + tid];
-    __syncthreads();
-    load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[0][0], sa, lane, wave, s.vec, t1);
-    load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[0][1], sbb, lane, wave, s.vec, t2);
-    load_minv(0, m1);
-    load_minv(1, m2);
-    load_cx(0);
-  }
-  double gb1 = tid < bsize(0) ? gbase(sh_cols[0][0][tid]) : 0.0;
-  double gb2 = tid < bsize(1) ? gbase(sh_cols[0][1][tid]) : 0.0;
-
-  // the block solve d = -M^{-1} g (g in sh_g) into sh_d[slot]: P threads per column, combined in order
-  auto solve = [&](const double (&mr)[KM], int sbi, int slot) {
-    double acc = 0.0;
-#pragma unroll
-    for (int e = 0; e < KM; ++e) {
-      const int k = part + P * e;
-      acc += mr[e] * sh_g[k < sbi ? k : 0] * (k < sbi ? 1.0 : 0.0);
-    }
-    sh_pg[part * NC + jc] = acc;
-    __syncthreads();
-    if (tid < NC) {
-      double tot = 0.0;
-#pragma unroll
-      for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
-      sh_d[slot][tid] = tid < sbi ? -tot : 0.0;
-    }
-  };
-
-  auto window = [&](int64_t w, R (&c1)[A][B], R (&c2)[A][B], R (&x1)[A][B], R (&x2)[A][B]) {
-    const int sa = bsize(2 * w), sbb = bsize(2 * w + 1);
-    const int32_t* cols1 = sh_cols[w & 1][0];
-    const int32_t* cols2 = sh_cols[w & 1][1];
-    const bool more = w + 1 < nw;
-    const int na = bsize(2 * w + 2), nb = bsize(2 * w + 3);
-    if (tid < na) sh_cols[(w + 1) & 1][0][tid] = s.perm[bstart(2 * w + 2) + tid];
-    if (tid < nb) sh_cols[(w + 1) & 1][1][tid] = s.perm[bstart(2 * w + 3) + tid];
-    // partials of both blocks over this group's rows
-    double* buf = s.partials + (int64_t)(w & 1) * K * 2 * kMaxBlock;
-#pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-      R (&cur)[A][B] = blk == 0 ? c1 : c2;
-      const int sbx = blk == 0 ? sa : sbb;
-      double v[B];
-#pragma unroll
-      for (int bb = 0; bb < B; ++bb) {
-        double acc = 0.0;
-#pragma unroll
-        for (int aa = 0; aa < A; ++aa) acc += (double)cur[aa][bb] * ureg[aa];
-        v[bb] = acc;
-      }
-      int c;
-      const double tot = transpose_sum<B>(v, lane, c);
-      const int j = wave + 4 * c;
-      if ((lane & (64 / B - 1)) == 0 && j < sbx)
-        st_coherent(&buf[((int64_t)g * 2 + blk) * kMaxBlock + j], tot);
-    }
-    const uint64_t epoch = s.epoch_base + (uint64_t)(2 * w) + 1;
-    __builtin_amdgcn_s_waitcnt(0);   // partial stores complete at device scope; next indices landed
-    __syncthreads();
-    if (K > 1 && tid == 0)
-      __hip_atomic_store(&s.flags[g], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // next window's tiles and gradient constants while the other groups finish;
-    // wavefront 0 polls first (a poll waits on all of its wavefront's loads)
-    double gn1 = 0.0, gn2 = 0.0;
-    if (more && wave != 0) {
-      load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][0], na, lane, wave, s.vec, x1);
-      load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][1], nb, lane, wave, s.vec, x2);
-    }
-    if (wave == 0) {
-      if (K > 1) {
-        while (true) {
-          bool ok = true;
-          for (int q = lane; q < K; q += 64)
-            ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
-          if (__all(ok)) break;
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-      if (more) {
-        load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][0], na, lane, wave, s.vec, x1);
-        load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[(w + 1) & 1][1], nb, lane, wave, s.vec, x2);
-      }
-    }
-    if (more && tid < na) gn1 = gbase(sh_cols[(w + 1) & 1][0][tid]);
-    if (more && tid < nb) gn2 = gbase(sh_cols[(w + 1) & 1][1][tid]);
-    __syncthreads();
-    // both blocks' partials over the K groups, in a fixed order per (column, part)
-    double p1 = 0.0, p2 = 0.0;
-    for (int q = part; q < K; q += NL * P) {
-      double v1[NL], v2[NL];
-#pragma unroll
-      for (int e = 0; e < NL; ++e) {
-        const int64_t qq = q + e * P;
-        v1[e] = (qq < K && jc < sa) ? ld_coherent(&buf[(qq * 2 + 0) * kMaxBlock + jc]) : 0.0;
-        v2[e] = (qq < K && jc < sbb) ? ld_coherent(&buf[(qq * 2 + 1) * kMaxBlock + jc]) : 0.0;
-      }
-#pragma unroll
-      for (int e = 0; e < NL; ++e) { p1 += v1[e]; p2 += v2[e]; }
-    }
-    sh_pg[part * NC + jc] = p1;
-    __syncthreads();
-    // block 2w
-    if (tid < sa) {
-      double tot = 0.0;
-#pragma unroll
-      for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
-      double v = tot / s.Ns + gb1;
-      if (s.a) v += beta * s.a[cols1[tid]] * (t - s.b);
-      sh_g[tid] = v;
-    }
-    __syncthreads();
-    solve(m1, sa, 0);
-    if (more) load_minv(2 * w + 2, m1);
-    __syncthreads();
-    if (s.a) {
-      double dt = 0.0;
-      for (int j = 0; j < sa; ++j) dt += s.a[cols1[j]] * sh_d[0][j];
-      t += dt;
-    }
-    // block 2w+1: its partials plus C_w d_{2w}
-    if (sbb > 0) {
-      double cc = 0.0;
-#pragma unroll
-      for (int e = 0; e < KM; ++e) {
-        const int k = part + P * e;
-        cc += cx[e] * sh_d[0][k < sa ? k : 0] * (k < sa ? 1.0 : 0.0);
-      }
-      sh_pg[part * NC + jc] = p2;
-      sh_pc[part * NC + jc] = cc;
-      __syncthreads();
-      if (tid < sbb) {
-        double tot = 0.0, cor = 0.0;
-#pragma unroll
-        for (int e = 0; e < P; ++e) { tot += sh_pg[e * NC + tid]; cor += sh_pc[e * NC + tid]; }
-        double v = tot / s.Ns + cor + gb2;
-        if (s.a) v += beta * s.a[cols2[tid]] * (t - s.b);
-        sh_g[tid] = v;
-      }
-      __syncthreads();
-      solve(m2, sbb, 1);
-    } else if (tid < NC) {
-      sh_d[1][tid] = 0.0;
-    }
-    if (more) {
-      load_minv(2 * w + 3, m2);
-      load_cx(w + 1);
-    }
-    __syncthreads();
-    if (s.a && sbb > 0) {
-      double dt = 0.0;
-      for (int j = 0; j < sbb; ++j) dt += s.a[cols2[j]] * sh_d[1][j];
-      t += dt;
-    }
-    // rows of u from both register tiles, summed over the four wavefronts in order
-#pragma unroll
-    for (int aa = 0; aa < A; ++aa) {
-      double v = 0.0;
-#pragma unroll
-      for (int bb = 0; bb < B; ++bb)
-        v += (double)c1[aa][bb] * sh_d[0][wave + 4 * bb] + (double)c2[aa][bb] * sh_d[1][wave + 4 * bb];
-      sh_red[wave * 64 * A + 64 * aa + lane] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int aa = 0; aa < A; ++aa) {
-      const int q = 64 * aa + lane;
-      ureg[aa] += ((sh_red[q] + sh_red[64 * A + q]) + sh_red[2 * 64 * A + q]) + sh_red[3 * 64 * A + q];
-    }
-    if (g == 0 && tid < sa) s.x[cols1[tid]] += sh_d[0][tid];
-    if (g == 0 && tid < sbb) s.x[cols2[tid]] += sh_d[1][tid];
-    gb1 = gn1;
-    gb2 = gn2;
-    __syncthreads();
-  };
-
-  for (int64_t w = 0; w < nw; w += 2) {
-    window(w, t1, t2, n1, n2);
-    if (w + 1 < nw) window(w + 1, n1, n2, t1, t2);
-  }
-#pragma unroll
-  for (int aa = 0; aa < A; ++aa) {
-    const int64_t r = r0 + (int64_t)A * lane + aa;
-    if (r < r1) s.u[r] = ureg[aa];
-  }
-  if (g == 0 && tid == 0) s.sc->t = t;
-}
-
-template <typename T, int A, int B>
-hipError_t sweepw_launch(const Sweep2Args& a, const double* Cx, int K, int coop, hipStream_t st) {
-  if (K == 1 || !coop) {
-    k_sweepw<T, A, B><<<(unsigned)K, 256, 0, st>>>(a, Cx);
-    return hipGetLastError();
-  }
-  Sweep2Args c = a;
-  const double* cx = Cx;
-  void* args[] = {(void*)&c, (void*)&cx};
-  return hipLaunchCooperativeKernel((const void*)k_sweepw<T, A, B>, dim3((unsigned)K), dim3(256), args, 0, st);
-}
-
-template <typename T>
-hipError_t sweepw_dispatch(const Sweep2Args& a, const double* Cx, int K, int A, int B, int coop, hipStream_t st) {
-#define RAC_SWW(AA, BB) if (A == AA && B == BB) return sweepw_launch<T, AA, BB>(a, Cx, K, coop, st)
-  RAC_SWW(1, 8); RAC_SWW(2, 8);
-  RAC_SWW(1, 16); RAC_SWW(2, 16);
-  if constexpr (sizeof(T) < 8) { RAC_SWW(4, 8); RAC_SWW(4, 16); }
-#undef RAC_SWW
-  return hipErrorInvalidValue;
-}
-
-template <typename T, int A, int B>
-int sweepw_resident() {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_sweepw<T, A, B>, 256, 0) != hipSuccess)
-    return 0;
-  return cus * per;
-}
-
 // A plain launch is used only when the caller has checked that all K groups can
 // be resident together (every other kernel that may run beside the sweep
 // finishes without waiting on it, so the late groups are always scheduled).
@@ -824,16 +533,6 @@ int sweep2_resident() {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_sweep2<T, A, B>, 256, 0) != hipSuccess)
     return 0;
   return cus * per;
-}
-
-template <typename T>
-int sweepw_resident_dispatch(int A, int B) {
-#define RAC_SRW(AA, BB) if (A == AA && B == BB) return sweepw_resident<T, AA, BB>()
-  RAC_SRW(1, 8); RAC_SRW(2, 8);
-  RAC_SRW(1, 16); RAC_SRW(2, 16);
-  if constexpr (sizeof(T) < 8) { RAC_SRW(4, 8); RAC_SRW(4, 16); }
-#undef RAC_SRW
-  return 0;
 }
 
 template <typename T>
@@ -897,15 +596,6 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
     a.RW = rw;
     const int esz = s.dtype == RAC_DT_F64 ? 8 : (s.dtype == RAC_DT_F32 ? 4 : 2);
     a.vec = (s.ldF % s.tileA == 0) && ((uintptr_t)s.F % (size_t)(esz * s.tileA) == 0);
-    if (s.Cx) {
-      if (s.sp > 64) return hipErrorInvalidValue;
-      switch (s.dtype) {
-        case RAC_DT_F64: return sweepw_dispatch<double>(a, s.Cx, s.K, s.tileA, s.tileB, s.cooperative, st);
-        case RAC_DT_F32: return sweepw_dispatch<float>(a, s.Cx, s.K, s.tileA, s.tileB, s.cooperative, st);
-        case RAC_DT_BF16: return sweepw_dispatch<uint16_t>(a, s.Cx, s.K, s.tileA, s.tileB, s.cooperative, st);
-        default: return hipErrorInvalidValue;
-      }
-    }
     switch (s.dtype) {
       case RAC_DT_F64: return sweep2_dispatch<double>(a, s.K, s.tileA, s.tileB, s.cooperative, st);
       case RAC_DT_F32: return sweep2_dispatch<float>(a, s.K, s.tileA, s.tileB, s.cooperative, st);
@@ -924,15 +614,7 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
 }  // namespace rac
 
 namespace rac {
-int sweep_max_resident(int32_t dtype, int A, int B, bool windowed) {
-  if (windowed) {
-    switch (dtype) {
-      case RAC_DT_F64: return sweepw_resident_dispatch<double>(A, B);
-      case RAC_DT_F32: return sweepw_resident_dispatch<float>(A, B);
-      case RAC_DT_BF16: return sweepw_resident_dispatch<uint16_t>(A, B);
-      default: return 0;
-    }
-  }
+int sweep_max_resident(int32_t dtype, int A, int B) {
   switch (dtype) {
     case RAC_DT_F64: return sweep2_resident_dispatch<double>(A, B);
     case RAC_DT_F32: return sweep2_resident_dispatch<float>(A, B);
@@ -941,9 +623,8 @@ int sweep_max_resident(int32_t dtype, int A, int B, bool windowed) {
   }
 }
 
-bool sweep_tile_supported(int32_t dtype, int A, int B, bool windowed) {
+bool sweep_tile_supported(int32_t dtype, int A, int B) {
   const bool small = dtype != RAC_DT_F64;
-  if (windowed) return (B == 8 || B == 16) && (A == 1 || A == 2 || (A == 4 && small));
   if (B == 8) return A == 1 || A == 2 || A == 4;
   if (B == 16) return A == 1 || A == 2 || (A == 4 && small);
   if (B == 32) return A == 1 || (A == 2 && small);
