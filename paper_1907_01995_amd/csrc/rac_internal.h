@@ -30,7 +30,7 @@ struct DevScalars {
   int64_t decisions; // controller decisions taken
   uint64_t fail_key; // (iteration << 32 | block) of the first non-PD block, or ~0
   int32_t status;    // 0 running, 1 converged, 2 diverged, 3 retired after a non-PD block
-  int32_t pad;
+  int32_t wait_abort;  // set when a sweep's bounded wait for other groups ran out (device error)
   float feat[RAC_MLP_IN];   // controller features formed at the last check
 };
 
@@ -195,7 +195,7 @@ struct SweepArgs {
   const double* c; const double* h; const double* a; double b; double Ns;
   double* x; const double* z; const double* xi; double* u;
   DevScalars* sc;
-  double* partials;        // [2][K][kMaxBlock]
+  double* partials;        // [3][K][kMaxBlock]
   uint64_t* flags;         // [K * kFlagStride], monotone epochs
   uint64_t epoch_base;
   int K;

@@ -509,7 +509,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->zprev, (size_t)n)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->u, (size_t)s->rows)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->sc, 1)) != RAC_OK) return fail(r);
-  if ((r = s->buf.alloc(&s->sweep_part, (size_t)2 * s->K * kMaxBlock)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->sweep_part, (size_t)3 * s->K * kMaxBlock)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->flags, (size_t)s->K * kFlagStride)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->red, (size_t)kRedSlots)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->done, 4)) != RAC_OK) return fail(r);
@@ -586,8 +586,9 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
   res->fail_iter = -1;
   res->fail_block = -1;
   s->hsc.status = 0;
+  s->hsc.wait_abort = 0;
   s->hsc.fail_key = ~0ULL;
-  HIPCHK(hipMemcpyAsync(&s->sc->status, &s->hsc.status, sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(&s->sc->status, &s->hsc.status, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(&s->sc->fail_key, &s->hsc.fail_key, sizeof(uint64_t), hipMemcpyHostToDevice, st));
   const int64_t budget = s->O.max_iter;
   const int64_t k_start = s->hsc.k;
@@ -617,6 +618,10 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
     }
     HIPCHK(hipStreamSynchronize(st));
     s->hsc = *s->hsc_pin;
+    if (s->hsc.wait_abort) {   // a sweep gave up waiting for its groups: the iterate is not usable
+      if (s->overlap) (void)hipStreamSynchronize(s->sB);
+      return RAC_ERR_DEVICE;
+    }
     if ((e = collect_timing(s)) != RAC_OK) return e;
     done_iters += Tc;
     if (s->hsc.fail_key != ~0ULL) {

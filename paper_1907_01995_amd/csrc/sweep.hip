@@ -236,6 +236,13 @@ __device__ __forceinline__ void load_packed(const T* __restrict__ Fp, int64_t i,
   }
 }
 
+// An empty partial slot: a signalling-NaN bit pattern (arithmetic only produces
+// quiet NaNs), compared bit for bit.
+constexpr uint64_t kEmptyBits = 0x7FF4A5A55A5AA5A5ull;
+constexpr double kEmpty = __builtin_bit_cast(double, kEmptyBits);
+__device__ __forceinline__ bool is_empty(double v) { return __builtin_bit_cast(uint64_t, v) == kEmptyBits; }
+constexpr int kMaxSpin = 1 << 20;   // polls of one batch of partials before a group gives up
+
 // Lane exchange x -> x of lane (l xor O).  Within the 16-lane rows (O <= 8) by
 // DPP moves, which stay in the vector ALU: O = 8 is a row rotation by 8, O = 4 a
 // half-row mirror (l xor 7) followed by the quad permutation l xor 3, O = 2 and
@@ -312,6 +319,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   __shared__ double sh_pg[256];
   __shared__ double sh_red[4 * 64 * A];
   __shared__ int32_t sh_cols[2][kMaxBlock];
+  __shared__ int sh_abort;
   const double beta = *s.beta_ptr;
   const double mu = s.sc->mu;
   double t = s.sc->t;
@@ -351,13 +359,30 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   {
     const int sb0 = bsize(0);
     if (tid < sb0) sh_cols[0][tid] = s.perm[tid];
+    if (tid == 0) sh_abort = 0;
     __syncthreads();
     fetch(0, ta);
     load_minv(0, sb0);
     if (tid < sb0) ga = gbase(sh_cols[0][tid]);
   }
 
-  auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B], double& gcur, double& gnxt) {
+  // Exchange of the per-group partials.  Blocks 0 (and every block when B > 16)
+  // use epoch flags: partials complete, then the group's flag, then loads after
+  // all flags are raised.  From block 1 on (B <= 16) the partials themselves are
+  // polled: block i uses slot buffer i % 3, slots start as kEmpty (a signalling-NaN
+  // pattern that no arithmetic produces), and a reader loads until none is empty.
+  // A group empties its slot of block i - 1 once it has seen every group's
+  // block-i partial (each group publishes block i only after reading block i - 1),
+  // and waits for that store before publishing its next partials, so a reader
+  // that has seen a group's block-i partial sees the emptied slot or the new
+  // value, never the one from three blocks ago.  The same lane stores a slot's
+  // values and empties it.  Block 0's flags order the first emptying of
+  // buffers 1 and 2 before any reader.  Waits are bounded: a group that gives up
+  // raises wait_abort and leaves, and so do the groups waiting on it.
+  constexpr bool SENT = B <= 16;
+  const bool writer = B == 16 ? lane < 16 : (B == 8 ? (lane < 16 && (lane & 1) == 0) : false);
+  const int wcol = wave + 4 * (B == 16 ? (lane & 15) : ((lane & 15) >> 1));   // a writer's column
+  auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B], double& gcur, double& gnxt) -> bool {
     const int sb = bsize(i);
     const int32_t* cols = sh_cols[i & 1];
     const bool more = i + 1 < s.p;
@@ -365,7 +390,8 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     const int sb1 = more ? bsize(i + 1) : 0;
     if (tid < sb1) sh_cols[(i + 1) & 1][tid] = s.perm[s1 + tid];   // indices of the next block
     // partial F_B'u over this group's rows, transposed across lanes
-    double* buf = s.partials + (int64_t)(i & 1) * K * kMaxBlock;
+    double* buf = s.partials + (int64_t)(SENT ? i % 3 : (i & 1)) * K * kMaxBlock;
+    const bool poll_data = SENT && i > 0;
     {
       double v[B];
 #pragma unroll
@@ -378,27 +404,33 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       int c;
       if constexpr (B <= 16) {
         const double tot = row_transpose_sum<B>(v, lane, c);
-        const int j = wave + 4 * c;
-        if (lane < 16 && (B == 16 || (lane & 1) == 0) && j < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + j], tot);
+        if (i == 0 && writer) {   // this group's slots of blocks 1 and 2 start empty
+          st_coherent(&s.partials[((int64_t)1 * K + g) * kMaxBlock + wcol], kEmpty);
+          st_coherent(&s.partials[((int64_t)2 * K + g) * kMaxBlock + wcol], kEmpty);
+        }
+        if (i > 0) __builtin_amdgcn_s_waitcnt(0);   // the emptying of this slot is visible first
+        if (writer && wcol < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + wcol], tot);
       } else {
         const double tot = transpose_sum<B>(v, lane, c);
         const int j = wave + 4 * c;
         if ((lane & (64 / B - 1)) == 0 && j < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + j], tot);
       }
     }
-    const uint64_t epoch = s.epoch_base + (uint64_t)i + 1;
-    __builtin_amdgcn_s_waitcnt(0);   // partial stores complete at device scope; next indices landed
-    __syncthreads();
-    if (K > 1 && tid == 0)
-      __hip_atomic_store(&s.flags[g], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (K > 1 && wave == 0) {
-      // every lane checks its flags each round; the wavefront leaves when all are raised
-      while (true) {
-        bool ok = true;
-        for (int q = lane; q < K; q += 64)
-          ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
-        if (__all(ok)) break;
-        __builtin_amdgcn_s_sleep(1);
+    if (!poll_data) {
+      const uint64_t epoch = s.epoch_base + (uint64_t)i + 1;
+      __builtin_amdgcn_s_waitcnt(0);   // partial stores complete at device scope; next indices landed
+      __syncthreads();
+      if (K > 1 && tid == 0)
+        __hip_atomic_store(&s.flags[g], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (K > 1 && wave == 0) {
+        // every lane checks its flags each round; the wavefront leaves when all are raised
+        while (true) {
+          bool ok = true;
+          for (int q = lane; q < K; q += 64)
+            ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+          if (__all(ok)) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
       }
     }
     __syncthreads();
@@ -410,9 +442,17 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       double acc = 0.0;
       for (int q = part; q < K; q += NL * P) {
         double v[NL];
+        for (int tries = 0;; ++tries) {
+          bool ok = true;
 #pragma unroll
-        for (int e = 0; e < NL; ++e)
-          v[e] = (q + e * P < K && jc < sb) ? ld_coherent(&buf[(int64_t)(q + e * P) * kMaxBlock + jc]) : 0.0;
+          for (int e = 0; e < NL; ++e) {
+            v[e] = (q + e * P < K && jc < sb) ? ld_coherent(&buf[(int64_t)(q + e * P) * kMaxBlock + jc]) : 0.0;
+            ok &= !(poll_data && is_empty(v[e]));
+          }
+          if (ok) break;
+          if (tries >= kMaxSpin) { sh_abort = 1; break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
 #pragma unroll
         for (int e = 0; e < NL; ++e) acc += v[e];
       }
@@ -426,6 +466,14 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       sh_pg[part * NC + jc] = acc;
     }
     __syncthreads();
+    if (poll_data) {
+      if (sh_abort) {   // a group never published: leave (every thread sees the same flag)
+        if (tid == 0) __hip_atomic_store(&s.sc->wait_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+      // every group has published block i, so none still reads block i - 1: empty our slot of it
+      if (writer) st_coherent(&s.partials[((int64_t)((i - 1) % 3) * K + g) * kMaxBlock + wcol], kEmpty);
+    }
     if (tid < NC) {   // zero past the block, so the solve needs no masks
       double v = 0.0;
       if (tid < sb) {
@@ -497,11 +545,12 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       gnxt = v;
     }
     __syncthreads();
+    return true;
   };
 
   for (int64_t i = 0; i < s.p; i += 2) {
-    block(i, ta, tb, ga, gbn);
-    if (i + 1 < s.p) block(i + 1, tb, ta, gbn, ga);
+    if (!block(i, ta, tb, ga, gbn)) return;
+    if (i + 1 < s.p && !block(i + 1, tb, ta, gbn, ga)) return;
   }
 #pragma unroll
   for (int aa = 0; aa < A; ++aa) {
