@@ -242,7 +242,9 @@ struct KKTArgs {
   double* red;             // kRedSlots doubles
   uint32_t* done;
   double* out;             // [4] KKT, feas, stat, dual
+  double* part;            // [kKKTChunks][n] partial F_j'u over row chunks, or null (one pass per column)
 };
+constexpr int kKKTChunks = 4;   // row chunks of the two-pass KKT check
 hipError_t launch_kkt(const KKTArgs& a, hipStream_t st);
 
 struct ControlArgs {

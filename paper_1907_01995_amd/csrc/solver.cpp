@@ -177,6 +177,7 @@ struct rac_solver_s {
   double* red = nullptr;
   uint32_t* done = nullptr;
   double* kkt_out = nullptr;
+  double* kkt_part = nullptr;   // [kKKTChunks][n] partial column products of the check
   double* obj_out = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0, hist_count = 0;
@@ -391,7 +392,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   ka.h = P.h; ka.c = P.c; ka.a = P.a; ka.b = P.b; ka.prox = P.prox; ka.lam = P.lambda;
   ka.alpha = P.alpha; ka.lo = P.lo; ka.hi = P.hi; ka.x = s->x; ka.z = s->z; ka.xi = s->xi;
   ka.u = s->u; ka.mu_ptr = &s->sc->mu; ka.mu_val = 0.0; ka.red = s->red; ka.done = s->done;
-  ka.out = s->kkt_out;
+  ka.out = s->kkt_out; ka.part = s->kkt_part;
   HIPCHK(tm.begin(st, RAC_PHASE_CHECK));
   HIPCHK(launch_kkt(ka, st));
   ControlArgs ca{};
@@ -514,6 +515,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->red, (size_t)kRedSlots)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->done, 4)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->kkt_out, 4)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->kkt_part, (size_t)kKKTChunks * n)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->obj_out, 1)) != RAC_OK) return fail(r);
   s->hist_cap = O.max_iter > 0 ? O.max_iter : 1;
   if ((r = s->buf.alloc(&s->hist, (size_t)s->hist_cap * 4)) != RAC_OK) return fail(r);

@@ -209,6 +209,95 @@ __global__ void __launch_bounds__(256) k_kkt(const T* __restrict__ F, int64_t ld
   kkt_from_maxima(M, a != nullptr, b, mu, out);
 }
 
+// Two-pass form of the check for the solver: k_kkt_dots forms F_j'u over one of
+// kKKTChunks row chunks (grid: column pairs x chunks, so that every compute unit
+// streams its share of F), and k_kkt_terms sums the chunks of each column in
+// order and reduces the per-column terms as k_kkt does.
+template <typename T>
+__global__ void __launch_bounds__(256) k_kkt_dots(const T* __restrict__ F, int64_t ldF, int64_t rows,
+                                                  int64_t n, const double* __restrict__ u, double* part,
+                                                  int vec) {
+  constexpr int KC = 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int chunk = blockIdx.y, nch = gridDim.y;
+  // row chunks are multiples of 256 rows except the last
+  const int64_t steps = (rows + 255) / 256;
+  const int64_t rb = block_start(chunk, steps, nch) * 256;
+  const int64_t re_ = block_start(chunk + 1, steps, nch) * 256;
+  const int64_t re = re_ < rows ? re_ : rows;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * KC; j0 < n; j0 += nwaves * KC) {
+    const T* col[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) col[k] = F + (j0 + k < n ? j0 + k : n - 1) * ldF;
+    double acc[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+    const int64_t rv = vec ? rb + (re - rb) / 256 * 256 : rb;   // vector loads up to rv
+#pragma unroll 4
+    for (int64_t r = rb + 4 * lane; r < rv; r += 256) {
+      double uu[4];
+      ld4(u + r, uu);
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        double f[4];
+        ld4(col[k] + r, f);
+        acc[k] += f[0] * uu[0];
+        acc[k] += f[1] * uu[1];
+        acc[k] += f[2] * uu[2];
+        acc[k] += f[3] * uu[3];
+      }
+    }
+    for (int64_t r = rv + lane; r < re; r += 64) {
+      const double ur = u[r];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) acc[k] += ld_f64(col[k], r) * ur;
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < KC; ++k)
+        if (j0 + k < n) part[(int64_t)chunk * n + j0 + k] = acc[k];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_kkt_terms(int64_t n, int nch, const double* __restrict__ part, double Ns,
+                                                   const double* __restrict__ h, const double* __restrict__ c,
+                                                   const double* __restrict__ a, double b, int32_t prox,
+                                                   double lam, double alpha, double lo, double hi,
+                                                   const double* __restrict__ x, const double* __restrict__ z,
+                                                   const double* __restrict__ xi, const double* mu_ptr,
+                                                   double mu_val, double* red, uint32_t* done, double* out) {
+  __shared__ double sh[4];
+  const double mu = mu_ptr ? *mu_ptr : mu_val;
+  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    double acc = 0.0;
+    for (int q = 0; q < nch; ++q) acc += part[(int64_t)q * n + j];
+    kkt_column_terms(acc, Ns, h ? h[j] : 0.0, c[j], a ? a[j] : 0.0, x[j], z[j], xi[j], mu, prox, lam, alpha,
+                     lo, hi, m);
+  }
+  for (int q = 0; q < 9; ++q) {
+    double v = block_max(m[q], sh);
+    if (threadIdx.x == 0) red[10 * blockIdx.x + q] = v;
+  }
+  {
+    double v = block_sum(m[9], sh);
+    if (threadIdx.x == 0) red[10 * blockIdx.x + 9] = v;
+  }
+  if (!last_block(done)) return;
+  if (threadIdx.x != 0) return;
+  double M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (unsigned q = 0; q < gridDim.x; ++q) {
+    for (int e = 0; e < 9; ++e) M[e] = fmax(M[e], red[10 * q + e]);
+    M[9] += red[10 * q + 9];
+  }
+  *done = 0u;
+  kkt_from_maxima(M, a != nullptr, b, mu, out);
+}
+
 // ---------------------------------------------------------------------------
 // Penalty controller (runs once per check, one workgroup of 64 threads); the
 // logic is shared with the batched engine (control.h).
@@ -309,6 +398,20 @@ hipError_t kkt_launch(const KKTArgs& k, hipStream_t st) {
   if (blocks > kRedBlocks) blocks = kRedBlocks;
   const size_t al = sizeof(T) == 8 ? 16 : 4 * sizeof(T);
   const int vec = (k.ldF % 4 == 0) && ((uintptr_t)k.F % al == 0) && ((uintptr_t)k.u % 16 == 0);
+  if (k.part) {
+    const int64_t steps = (k.rows + 255) / 256;
+    const int nch = (int)(steps < kKKTChunks ? steps : kKKTChunks);
+    int64_t cb = (k.n + 7) / 8;
+    if (cb > 65535) cb = 65535;
+    k_kkt_dots<T><<<dim3((unsigned)cb, (unsigned)nch), 256, 0, st>>>((const T*)k.F, k.ldF, k.rows, k.n, k.u,
+                                                                      k.part, vec);
+    int64_t tb = (k.n + 255) / 256;
+    if (tb > kRedBlocks) tb = kRedBlocks;
+    k_kkt_terms<<<(unsigned)tb, 256, 0, st>>>(k.n, nch, k.part, k.Ns, k.h, k.c, k.a, k.b, k.prox, k.lam,
+                                              k.alpha, k.lo, k.hi, k.x, k.z, k.xi, k.mu_ptr, k.mu_val, k.red,
+                                              k.done, k.out);
+    return hipGetLastError();
+  }
   k_kkt<T><<<(unsigned)blocks, 256, 0, st>>>((const T*)k.F, k.ldF, k.rows, k.n, k.Ns, k.h, k.c, k.a,
                                               k.b, k.prox, k.lam, k.alpha, k.lo, k.hi, k.x, k.z,
                                               k.xi, k.u, k.mu_ptr, k.mu_val, k.red, k.done, k.out, vec);
