@@ -138,7 +138,10 @@ rac_status rac_solver_destroy(rac_solver s);
 /* Run up to opts.max_iter iterations (Eq.(3)) from the current state, stopping at
  * the first KKT check <= tol, on `stream` (a hipStream_t; NULL = default stream).
  * Synchronises the stream and fills *res.  Returns RAC_ERR_NOT_PD when
- * Assumption 2.1 failed (res->fail_iter, res->fail_block name the block). */
+ * Assumption 2.1 failed (res->fail_iter, res->fail_block name the block), and
+ * RAC_ERR_DEVICE when a sweep's bounded wait for its other row groups ran out
+ * (the state is then not usable; the limit can be lowered for tests through the
+ * environment variable RACMB_SWEEP_MAX_SPIN, read at rac_solver_create). */
 rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res);
 
 /* Copy the state in or out (device pointers, n doubles each; mu on the host).

@@ -203,6 +203,7 @@ struct SweepArgs {
   int tileA, tileB;        // register tile: rows per lane, columns per wavefront (0: streaming path)
   int cooperative;         // launch with the cooperative API (else a plain launch, K <= resident limit)
   const void* Fp;          // packed tiles of this iteration written by the Gram kernel, or null (gather from F)
+  int max_spin;            // polls before a sweep group gives up waiting (negative: the default)
 };
 // Rows per sweep group for K groups and A rows per lane (0 if 64A rows do not cover a group).
 int64_t sweep_rows_per_group(int64_t rows, int K, int A);

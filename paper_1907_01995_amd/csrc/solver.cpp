@@ -21,6 +21,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -189,6 +190,7 @@ struct rac_solver_s {
   uint8_t* Fp = nullptr;    // two packed copies of F in the sweep's register order (by iteration parity)
   size_t Fp_bytes = 0;      // bytes of one copy
   int64_t packRW = 0;       // rows per sweep group
+  int max_spin = -1;        // sweep wait limit (RACMB_SWEEP_MAX_SPIN, for tests of the error path)
   bool overlap = false;     // assemble on a second stream during the previous sweep
   hipStream_t sB = nullptr;
   hipEvent_t ev_start = nullptr, ev_fac[2] = {nullptr, nullptr}, ev_sweep[2] = {nullptr, nullptr};
@@ -369,7 +371,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     const void* Fp = s->Fp ? (const void*)(s->Fp + par * s->Fp_bytes) : nullptr;
     SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, Minv, s->sp, P.c, P.h, P.a,
                 P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
-                beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, Fp};
+                beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, Fp, s->max_spin};
     HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
     HIPCHK(launch_sweep(w, st));
     HIPCHK(tm.end(RAC_PHASE_SWEEP));
@@ -482,6 +484,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if (s->R > s->rows) s->R = (int)s->rows;
   s->mv_nparts = matvec_parts(n);
+  if (const char* e = std::getenv("RACMB_SWEEP_MAX_SPIN")) s->max_spin = std::atoi(e);
 
   auto fail = [&](rac_status r) {
     s->buf.release();

@@ -153,6 +153,7 @@ struct Sweep2Args {
   int64_t RW;              // rows per group (a multiple of A, at most 64A)
   int vec;                 // column starts allow A-element vector loads
   const void* Fp;          // packed tiles of this iteration's blocks, or null (gather from F)
+  int max_spin;            // polls of one batch of partials before a group gives up
 };
 
 // Lane l holds rows r0 + A l + a (a < A) of the group's range: A consecutive
@@ -241,7 +242,7 @@ __device__ __forceinline__ void load_packed(const T* __restrict__ Fp, int64_t i,
 constexpr uint64_t kEmptyBits = 0x7FF4A5A55A5AA5A5ull;
 constexpr double kEmpty = __builtin_bit_cast(double, kEmptyBits);
 __device__ __forceinline__ bool is_empty(double v) { return __builtin_bit_cast(uint64_t, v) == kEmptyBits; }
-constexpr int kMaxSpin = 1 << 20;   // polls of one batch of partials before a group gives up
+constexpr int kMaxSpin = 1 << 20;   // default polls of one batch of partials before a group gives up
 
 // Lane exchange x -> x of lane (l xor O).  Within the 16-lane rows (O <= 8) by
 // DPP moves, which stay in the vector ALU: O = 8 is a row rotation by 8, O = 4 a
@@ -450,7 +451,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
             ok &= !(poll_data && is_empty(v[e]));
           }
           if (ok) break;
-          if (tries >= kMaxSpin) { sh_abort = 1; break; }
+          if (tries >= s.max_spin) { sh_abort = 1; break; }
           __builtin_amdgcn_s_sleep(1);
         }
 #pragma unroll
@@ -639,7 +640,8 @@ int64_t sweep_packed_elems(int64_t p, int K, int A, int B) { return p * K * 256 
 hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
   if (s.tileA > 0) {
     Sweep2Args a{s.F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.c, s.h, s.xi, s.z, s.beta_ptr,
-                 s.a, s.b, s.Ns, s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0, s.Fp};
+                 s.a, s.b, s.Ns, s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0, s.Fp,
+                 s.max_spin >= 0 ? s.max_spin : kMaxSpin};
     const int64_t rw = sweep_rows_per_group(s.rows, s.K, s.tileA);
     if (rw == 0) return hipErrorInvalidValue;
     a.RW = rw;

@@ -312,6 +312,32 @@ def test_packed_and_gathered_sweeps_are_bit_identical(storage, prec, N, n, s, K)
         assert rel(outs[0][1], ref.z) < 1e-8 and rel(outs[0][2], ref.xi) < 1e-8
 
 
+def test_sweep_wait_limit_reports_a_device_error(monkeypatch):
+    """The sweep's waits for other groups are bounded. With the limit forced to zero
+    polls from the host, groups give up at their first wait, every kernel still exits,
+    and the run returns RAC_ERR_DEVICE; solvers created afterwards run normally."""
+    w = W.lasso(N=6000, n=512, data_seed=14, block_size=64, storage="f32")
+    gp, _ = en_pair(w)
+    kw = dict(s=64, beta0=w.beta0, beta_mode=racmb.BETA_RESBAL, precision=racmb.PREC_MIXED,
+              max_iter=20, check_every=10)
+    monkeypatch.setenv("RACMB_SWEEP_MAX_SPIN", "0")
+    sv = racmb.Solver(gp, **kw)
+    assert sv.info()["K"] > 1 and sv.info()["tileA"] > 0
+    with pytest.raises(racmb.RacError) as err:
+        sv.run()
+    assert err.value.code == racmb.RAC_ERR_DEVICE
+    sv.close()
+    monkeypatch.delenv("RACMB_SWEEP_MAX_SPIN")
+    outs = []
+    for _ in range(2):
+        sv = racmb.Solver(gp, **kw)
+        sv.run()
+        outs.append(sv.state()[:3])
+        sv.close()
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
+
+
 def test_repeated_runs_are_deterministic():
     w = W.lasso(N=2000, n=256, data_seed=8, block_size=32, storage="f32")
     gp, _ = en_pair(w)
