@@ -183,8 +183,8 @@ def main():
                     help="add plain 256 MiB device copies (counter calibration for rocprofv3 --pmc runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(see DESIGN.md for how the path would shard)" % args.gpus, file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus %d is not supported (a single instance "
+              "would shard by rows of F, batches by instance, neither is implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

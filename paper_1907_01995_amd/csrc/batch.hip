@@ -10,9 +10,13 @@
 //             instance's keys sorted by a bitonic network in LDS (n <= 8192);
 //   k_bgram   (assemble.hip) one workgroup per (instance, block);
 //   k_binv    one wavefront per (lane, block): the block matrix in registers,
-//             one column per lane, inverted by Gauss-Jordan with the pivot
-//             column broadcast through readlane -- no LDS, no barriers;
-//   k_bsweep  one workgroup per lane: the Gauss-Seidel pass over the blocks,
+//             one column per lane, inverted by Gauss-Jordan with symmetric
+//             pivots; the pivot row (equal to the pivot column) is gathered
+//             with one LDS store per lane and read back as broadcasts -- no
+//             workgroup barriers;
+//   k_tsweep  (tsweep.hip) the team sweep: the lanes of an instance in groups
+//             of up to 16, one read of the data for the whole group;
+//   k_bsweep  the per-lane fallback, one workgroup per lane: the Gauss-Seidel pass over the blocks,
 //             gradient pass (rows over lanes, columns over wavefronts,
 //             transposed butterfly) and residual update pass per block;
 //   k_bzdual  one workgroup per lane: z block, dual step, norms;
@@ -25,13 +29,6 @@
 
 namespace rac {
 namespace {
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  int2 x = __builtin_bit_cast(int2, v);
-  x.x = __builtin_amdgcn_readlane(x.x, l);
-  x.y = __builtin_amdgcn_readlane(x.y, l);
-  return __builtin_bit_cast(double, x);
-}
 
 __device__ __forceinline__ double bsum(double v, double* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
