@@ -187,34 +187,6 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ F, int64_t ldF, 
   }
 }
 
-// Sum B per-lane values across the 64 lanes, transposed: B-1 halving exchanges
-// leave lane l with one column's partial over a lane subset, then full
-// reductions over the remaining lane bits.  Lane l ends with the total of
-// column index c(l) (bits 5, 4, ... of l, most significant first); it is
-// returned together with c.  The summation pattern is fixed.
-template <int B>
-__device__ __forceinline__ double transpose_sum(double (&v)[B], int lane, int& c) {
-  int half = B / 2, o = 32;
-#pragma unroll
-  for (; half >= 1; half >>= 1, o >>= 1) {
-    const bool upper = (lane & o) != 0;
-#pragma unroll
-    for (int q = 0; q < half; ++q) {
-      const double send = upper ? v[q] : v[q + half];
-      const double keep = upper ? v[q + half] : v[q];
-      v[q] = keep + __shfl_xor(send, o, 64);
-    }
-  }
-  double r = v[0];
-#pragma unroll
-  for (; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
-  int cc = 0, bit = 32;
-#pragma unroll
-  for (int t = B; t > 1; t >>= 1, bit >>= 1) cc = (cc << 1) | ((lane & bit) ? 1 : 0);
-  c = cc;
-  return r;
-}
-
 // Packed tiles: the Gram kernel also copies each block's columns into the exact
 // register order of the sweep, tile (block i, group g) = [4 wavefronts][B][64
 // lanes][A] values of the storage type, zero outside the block and the rows.
@@ -301,6 +273,34 @@ __device__ __forceinline__ double row_transpose_sum(double (&v)[B], int lane, in
   return r;
 }
 
+// Sum B per-lane values across the 64 lanes, transposed (B = 32): halving
+// exchanges at lane distances 32, 16, 8, 4, 2 leave lane l with one column's
+// partial over a lane subset, then a full reduction over the remaining lane
+// bit.  Lane l ends with the total of column index c(l) (bits 5, 4, ... of l,
+// most significant first); it is returned together with c.  The stages are
+// unrolled at compile time so that v stays in registers, and the summation
+// pattern is fixed.
+template <int HALF, int O, int B>
+__device__ __forceinline__ void transpose_stage(double (&v)[B], int lane) {
+  const bool upper = (lane & O) != 0;
+#pragma unroll
+  for (int q = 0; q < HALF; ++q) {
+    const double send = upper ? v[q] : v[q + HALF];
+    const double keep = upper ? v[q + HALF] : v[q];
+    v[q] = keep + lane_xor<O>(send);
+  }
+  if constexpr (HALF > 1) transpose_stage<HALF / 2, O / 2, B>(v, lane);
+}
+template <int B>
+__device__ __forceinline__ double transpose_sum(double (&v)[B], int lane, int& c) {
+  static_assert(B == 32, "the row-local transposition covers 8 or 16 columns");
+  transpose_stage<B / 2, 32, B>(v, lane);
+  double r = v[0];
+  r += lane_xor<1>(r);
+  c = lane >> 1;
+  return r;
+}
+
 template <typename T, int A, int B>
 __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   typedef typename RegT<T>::type R;
@@ -380,9 +380,15 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   // values and empties it.  Block 0's flags order the first emptying of
   // buffers 1 and 2 before any reader.  Waits are bounded: a group that gives up
   // raises wait_abort and leaves, and so do the groups waiting on it.
+  // (B = 32 keeps the flags: polling its 64 partials per thread at once does not
+  // fit the register file beside two 32-column tiles.)
   constexpr bool SENT = B <= 16;
-  const bool writer = B == 16 ? lane < 16 : (B == 8 ? (lane < 16 && (lane & 1) == 0) : false);
-  const int wcol = wave + 4 * (B == 16 ? (lane & 15) : ((lane & 15) >> 1));   // a writer's column
+  // the lane that stores a column's partial (and empties its slot), and that
+  // column: after the transposed sums, lane l of a 16-lane row holds column l
+  // (B = 16) or l / 2 (B = 8) of the row's totals, and lane l holds column
+  // l / 2 (B = 32)
+  const bool writer = B == 32 ? (lane & 1) == 0 : (B == 16 ? lane < 16 : (lane < 16 && (lane & 1) == 0));
+  const int wcol = wave + 4 * (B == 32 ? (lane >> 1) : (B == 16 ? (lane & 15) : ((lane & 15) >> 1)));
   auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B], double& gcur, double& gnxt) -> bool {
     const int sb = bsize(i);
     const int32_t* cols = sh_cols[i & 1];
@@ -403,18 +409,16 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
         v[bb] = acc;
       }
       int c;
-      if constexpr (B <= 16) {
-        const double tot = row_transpose_sum<B>(v, lane, c);
-        if (i == 0 && writer) {   // this group's slots of blocks 1 and 2 start empty
+      double tot;
+      if constexpr (B <= 16) tot = row_transpose_sum<B>(v, lane, c);
+      else tot = transpose_sum<B>(v, lane, c);
+      {
+        if (SENT && i == 0 && writer) {   // this group's slots of blocks 1 and 2 start empty
           st_coherent(&s.partials[((int64_t)1 * K + g) * kMaxBlock + wcol], kEmpty);
           st_coherent(&s.partials[((int64_t)2 * K + g) * kMaxBlock + wcol], kEmpty);
         }
-        if (i > 0) __builtin_amdgcn_s_waitcnt(0);   // the emptying of this slot is visible first
+        if (SENT && i > 0) __builtin_amdgcn_s_waitcnt(0);   // the emptying of this slot is visible first
         if (writer && wcol < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + wcol], tot);
-      } else {
-        const double tot = transpose_sum<B>(v, lane, c);
-        const int j = wave + 4 * c;
-        if ((lane & (64 / B - 1)) == 0 && j < sb) st_coherent(&buf[(int64_t)g * kMaxBlock + j], tot);
       }
     }
     if (!poll_data) {
@@ -501,10 +505,20 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
           acc += mreg[e + 1] * g2.y;
         }
       } else {
+        // the inverse's entries in batches of 16 loads in flight, then summed in k order
         const double* Mi = s.Minv + i * (int64_t)s.sp * s.sp;
         if (jc < sb) {
-#pragma unroll 16
-          for (int k = part; k < sb; k += P) acc += Mi[(int64_t)k * s.sp + jc] * sh_g[k];
+          for (int k0 = part; k0 < sb; k0 += 16 * P) {
+            double mv[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+              const int k = k0 + e * P;
+              mv[e] = k < sb ? Mi[(int64_t)k * s.sp + jc] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+              if (k0 + e * P < sb) acc += mv[e] * sh_g[k0 + e * P];
+          }
         }
       }
       sh_pg[part * NC + jc] = acc;

@@ -288,7 +288,9 @@ def test_overlapped_assembly_is_bit_identical(storage, prec):
 @pytest.mark.parametrize("storage,prec,N,n,s,K", [("f32", racmb.PREC_MIXED, 6003, 500, 64, 0),
                                                   ("bf16", racmb.PREC_MIXED, 3001, 333, 32, 0),
                                                   ("f64", racmb.PREC_FP64, 1000, 201, 20, 7),
-                                                  ("f32", racmb.PREC_FP64, 2500, 130, 64, 0)])
+                                                  ("f32", racmb.PREC_FP64, 2500, 130, 64, 0),
+                                                  ("bf16", racmb.PREC_FP64, 3001, 700, 128, 0),
+                                                  ("f64", racmb.PREC_FP64, 2000, 300, 128, 0)])
 def test_packed_and_gathered_sweeps_are_bit_identical(storage, prec, N, n, s, K):
     """The packed copy holds the same values in the sweep's register order, so the
     sweep computes the same sums in the same order: identical iterates.  Ragged
