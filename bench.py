@@ -23,7 +23,13 @@ HBM.  The line also reports, on the same data:
                   every lane active, per-launch phase times with the roofline of
                   the batched sweep, and the time until every lane reaches KKT
                   <= 1e-6 for the candidate (mixed precision, learned penalty)
-                  and for the plain FP64 fixed-penalty batch on the same values.
+                  and for the plain FP64 fixed-penalty batch on the same values,
+  hidim        -- the high-dimensional LASSO, D 10000 x 100000 Gaussian (BF16),
+                  1% non-zeros, lambda = 0.05 lambda_max, blocks of 128
+                  (p = 782): time to KKT <= 1e-6 for the candidate (mixed
+                  precision, learned penalty) and for the plain FP64
+                  fixed-penalty solver on the same values (FP64 copy of the
+                  data), the latter capped at --hidim-cap iterations.
 """
 from __future__ import annotations
 
@@ -167,6 +173,41 @@ def batched_leg(args, racmb, W, torch, weights, log):
     return out
 
 
+def hidim_leg(args, racmb, W, torch, weights, log):
+    """High-dimensional LASSO 10000 x 100000: time to KKT <= 1e-6, candidate vs plain FP64."""
+    t0 = time.time()
+    w = W.lasso_10000x100000("bf16")
+    log("hidim workload generated in %.1fs" % (time.time() - t0))
+    s = w.block_size
+    out = {"workload": "lasso_10000x100000", "N": w.N, "n": w.n, "block_size": s, "p": -(-w.n // s),
+           "data_storage": "bf16", "lambda": "0.05 lam_max"}
+    mode = racmb.BETA_MLP if weights is not None else racmb.BETA_RESBAL
+    runs = (("candidate", "bf16", dict(precision=racmb.PREC_MIXED, beta_mode=mode, mlp_weights=weights,
+                                        max_iter=5000)),
+            ("plain_fp64_fixed_beta", "f64", dict(precision=racmb.PREC_FP64, beta_mode=racmb.BETA_FIXED,
+                                                  max_iter=args.hidim_cap)))
+    for name, storage, kw in runs:
+        D = w.D if storage == "bf16" else w.D.astype(np.float64)
+        gp = racmb.regression_problem(D, w.y, lam=w.lam, alpha=1.0, storage=storage)
+        del D
+        so = racmb.Solver(gp, s=s, beta0=w.beta0, check_every=10, tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = so.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - a
+        out[name] = {"seconds": dt, "iters": r.iters, "kkt": r.kkt, "converged": r.status == racmb.RUN_CONVERGED,
+                     "objective": r.objective, "ms_per_iteration": 1e3 * dt / max(r.iters, 1),
+                     "iteration_cap": kw["max_iter"]}
+        so.close()
+        del so, gp
+        torch.cuda.empty_cache()
+        log("hidim time-to-tol %s: %s" % (name, out[name]))
+    ratio = out["plain_fp64_fixed_beta"]["seconds"] / out["candidate"]["seconds"]
+    out["speedup" if out["plain_fp64_fixed_beta"]["converged"] else "speedup_at_least"] = ratio
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +220,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=40)
     ap.add_argument("--batched-warmup", type=int, default=10)
     ap.add_argument("--batched-cap", type=int, default=500)
+    ap.add_argument("--no-hidim", action="store_true")
+    ap.add_argument("--hidim-cap", type=int, default=1500,
+                    help="iteration cap of the plain FP64 solver in the high-dimensional leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="add plain 256 MiB device copies (counter calibration for rocprofv3 --pmc runs)")
     args = ap.parse_args()
@@ -323,6 +367,8 @@ def main():
                 O.objective(op, xc[1]))
     if not args.no_batched:
         out["batched"] = batched_leg(args, racmb, W, torch, weights, log)
+    if not args.no_hidim and not args.no_time_to_tol:
+        out["hidim"] = hidim_leg(args, racmb, W, torch, weights, log)
     print(json.dumps(out), flush=True)
 
 
