@@ -137,6 +137,71 @@ __device__ __forceinline__ float ld_reg(const uint16_t* p, int64_t i) {
 }
 __device__ __forceinline__ double ld_reg(const double* p, int64_t i) { return p[i]; }
 
+// Register tile of A rows x B columns of F in the storage type's register form:
+// FP64 and FP32 one value per register, BF16 two per 32-bit register (rows 2r
+// and 2r + 1 of a column in the low and high halves, as they lie in memory), so
+// that two 32-column tiles leave room for the rest of the sweep.  at(aa, bb)
+// converts exactly to FP64.
+template <typename T, int A, int B>
+struct Tile {
+  typedef typename RegT<T>::type R;
+  R v[A][B];
+  __device__ __forceinline__ double at(int aa, int bb) const { return (double)v[aa][bb]; }
+  __device__ __forceinline__ void zero(int bb) {
+#pragma unroll
+    for (int aa = 0; aa < A; ++aa) v[aa][bb] = (R)0;
+  }
+  // A consecutive, vector-aligned elements of a column
+  __device__ __forceinline__ void load_vec(int bb, const T* p) {
+    if constexpr (A > 1) {
+      typedef T VT __attribute__((ext_vector_type(A)));
+      const VT x = *reinterpret_cast<const VT*>(p);
+#pragma unroll
+      for (int aa = 0; aa < A; ++aa) v[aa][bb] = ld_reg(reinterpret_cast<const T*>(&x), aa);
+    } else {
+      v[0][bb] = ld_reg(p, 0);
+    }
+  }
+  // the first nvalid of A consecutive elements, zeros after them
+  __device__ __forceinline__ void load_elems(int bb, const T* p, int64_t nvalid) {
+#pragma unroll
+    for (int aa = 0; aa < A; ++aa) v[aa][bb] = aa < nvalid ? ld_reg(p, aa) : (R)0;
+  }
+};
+template <int A, int B>
+struct Tile<uint16_t, A, B> {
+  static constexpr int W = (A + 1) / 2;
+  uint32_t w[W][B];
+  __device__ __forceinline__ double at(int aa, int bb) const {
+    const uint32_t x = w[aa >> 1][bb];
+    return (double)__uint_as_float((aa & 1) ? (x & 0xffff0000u) : (x << 16));
+  }
+  __device__ __forceinline__ void zero(int bb) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) w[q][bb] = 0u;
+  }
+  __device__ __forceinline__ void load_vec(int bb, const uint16_t* p) {
+    if constexpr (A == 1) {
+      w[0][bb] = p[0];
+    } else if constexpr (A == 2) {
+      w[0][bb] = *reinterpret_cast<const uint32_t*>(p);
+    } else {
+      static_assert(A == 4, "BF16 tiles hold 1, 2 or 4 rows per lane");
+      const uint2 x = *reinterpret_cast<const uint2*>(p);
+      w[0][bb] = x.x;
+      w[1][bb] = x.y;
+    }
+  }
+  __device__ __forceinline__ void load_elems(int bb, const uint16_t* p, int64_t nvalid) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const uint32_t lo = 2 * q < nvalid ? (uint32_t)p[2 * q] : 0u;
+      const uint32_t hi = (2 * q + 1 < A && 2 * q + 1 < nvalid) ? (uint32_t)p[2 * q + 1] : 0u;
+      w[q][bb] = lo | (hi << 16);
+    }
+  }
+};
+
 __device__ __forceinline__ void st_coherent(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -161,28 +226,17 @@ struct Sweep2Args {
 template <typename T, int A, int B>
 __device__ __forceinline__ void load_tile(const T* __restrict__ F, int64_t ldF, int64_t r0, int64_t r1,
                                           const int32_t* cols, int sb, int lane, int wave, int vec,
-                                          typename RegT<T>::type (&tile)[A][B]) {
-  typedef typename RegT<T>::type R;
+                                          Tile<T, A, B>& tile) {
   const int64_t rl = r0 + (int64_t)A * lane;
 #pragma unroll
   for (int bb = 0; bb < B; ++bb) {
     const int j = wave + 4 * bb;
     if (j < sb) {
-      const T* colp = F + (int64_t)cols[j] * ldF;
-      if constexpr (A > 1) {
-        if (vec && rl + A <= r1) {
-          typedef T VT __attribute__((ext_vector_type(A)));
-          const VT v = *reinterpret_cast<const VT*>(colp + rl);
-#pragma unroll
-          for (int aa = 0; aa < A; ++aa) tile[aa][bb] = ld_reg(reinterpret_cast<const T*>(&v), aa);
-          continue;
-        }
-      }
-#pragma unroll
-      for (int aa = 0; aa < A; ++aa) tile[aa][bb] = (rl + aa < r1) ? ld_reg(colp, rl + aa) : (R)0;
+      const T* colp = F + (int64_t)cols[j] * ldF + rl;
+      if (A > 1 && vec && rl + A <= r1) tile.load_vec(bb, colp);
+      else tile.load_elems(bb, colp, r1 - rl);
     } else {
-#pragma unroll
-      for (int aa = 0; aa < A; ++aa) tile[aa][bb] = (R)0;
+      tile.zero(bb);
     }
   }
 }
@@ -194,19 +248,10 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ F, int64_t ldF, 
 // column segments (whose address translations dominate the fetch otherwise).
 template <typename T, int A, int B>
 __device__ __forceinline__ void load_packed(const T* __restrict__ Fp, int64_t i, int K, int g, int lane, int wave,
-                                            typename RegT<T>::type (&tile)[A][B]) {
+                                            Tile<T, A, B>& tile) {
   const T* base = Fp + ((((i * K + g) * 4 + wave) * B) * 64 + lane) * (int64_t)A;
 #pragma unroll
-  for (int bb = 0; bb < B; ++bb) {
-    if constexpr (A > 1) {
-      typedef T VT __attribute__((ext_vector_type(A)));
-      const VT v = *reinterpret_cast<const VT*>(base + (int64_t)bb * 64 * A);
-#pragma unroll
-      for (int aa = 0; aa < A; ++aa) tile[aa][bb] = ld_reg(reinterpret_cast<const T*>(&v), aa);
-    } else {
-      tile[0][bb] = ld_reg(base, (int64_t)bb * 64);
-    }
-  }
+  for (int bb = 0; bb < B; ++bb) tile.load_vec(bb, base + (int64_t)bb * 64 * A);
 }
 
 // An empty partial slot: a signalling-NaN bit pattern (arithmetic only produces
@@ -303,7 +348,6 @@ __device__ __forceinline__ double transpose_sum(double (&v)[B], int lane, int& c
 
 template <typename T, int A, int B>
 __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
-  typedef typename RegT<T>::type R;
   constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
   constexpr int KM = (NC + P - 1) / P;            // Minv entries per thread
   constexpr bool MREG = KM <= 16;                 // keep the next block's inverse in registers
@@ -321,6 +365,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   __shared__ double sh_red[4 * 64 * A];
   __shared__ int32_t sh_cols[2][kMaxBlock];
   __shared__ int sh_abort;
+  __shared__ double sh_a[2][kMaxBlock];          // equality-row entries of this block's and the next block's columns
   const double beta = *s.beta_ptr;
   const double mu = s.sc->mu;
   double t = s.sc->t;
@@ -334,7 +379,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   };
   auto bsize = [&](int64_t i) { return (int)(block_start(i + 1, s.n, s.p) - block_start(i, s.n, s.p)); };
   // tile of block i: packed copy, else gathered through the block's column indices
-  auto fetch = [&](int64_t i, R (&tile)[A][B]) {
+  auto fetch = [&](int64_t i, Tile<T, A, B>& tile) {
     if (Fp) load_packed<T, A, B>(Fp, i, K, g, lane, wave, tile);
     else load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[i & 1], bsize(i), lane, wave, s.vec, tile);
   };
@@ -344,7 +389,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     const int64_t r = r0 + (int64_t)A * lane + aa;
     ureg[aa] = r < r1 ? s.u[r] : 0.0;
   }
-  R ta[A][B], tb[A][B];
+  Tile<T, A, B> ta, tb;
   double mreg[MREG ? KM : 1];
   auto load_minv = [&](int64_t i, int sbi) {
     if constexpr (MREG) {
@@ -364,7 +409,10 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     __syncthreads();
     fetch(0, ta);
     load_minv(0, sb0);
-    if (tid < sb0) ga = gbase(sh_cols[0][tid]);
+    if (tid < sb0) {
+      ga = gbase(sh_cols[0][tid]);
+      if (s.a) sh_a[0][tid] = s.a[sh_cols[0][tid]];
+    }
   }
 
   // Exchange of the per-group partials.  Blocks 0 (and every block when B > 16)
@@ -389,7 +437,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   // l / 2 (B = 32)
   const bool writer = B == 32 ? (lane & 1) == 0 : (B == 16 ? lane < 16 : (lane < 16 && (lane & 1) == 0));
   const int wcol = wave + 4 * (B == 32 ? (lane >> 1) : (B == 16 ? (lane & 15) : ((lane & 15) >> 1)));
-  auto block = [&](int64_t i, R (&cur)[A][B], R (&nxt)[A][B], double& gcur, double& gnxt) -> bool {
+  auto block = [&](int64_t i, Tile<T, A, B>& cur, Tile<T, A, B>& nxt, double& gcur, double& gnxt) -> bool {
     const int sb = bsize(i);
     const int32_t* cols = sh_cols[i & 1];
     const bool more = i + 1 < s.p;
@@ -405,7 +453,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       for (int bb = 0; bb < B; ++bb) {
         double acc = 0.0;
 #pragma unroll
-        for (int aa = 0; aa < A; ++aa) acc += (double)cur[aa][bb] * ureg[aa];
+        for (int aa = 0; aa < A; ++aa) acc += cur.at(aa, bb) * ureg[aa];
         v[bb] = acc;
       }
       int c;
@@ -486,7 +534,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
 #pragma unroll
         for (int e = 0; e < P; ++e) tot += sh_pg[e * NC + tid];
         v = tot / s.Ns + gcur;
-        if (s.a) v += beta * s.a[cols[tid]] * (t - s.b);
+        if (s.a) v += beta * sh_a[i & 1][tid] * (t - s.b);
       }
       sh_g[tid] = v;
     }
@@ -533,8 +581,10 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     if (more) load_minv(i + 1, sb1);   // the next inverse arrives during the update below
     __syncthreads();
     if (s.a) {
+      const double* ab = sh_a[i & 1];
       double dt = 0.0;
-      for (int j = 0; j < sb; ++j) dt += s.a[cols[j]] * sh_d[j];
+#pragma unroll 8
+      for (int j = 0; j < sb; ++j) dt += ab[j] * sh_d[j];
       t += dt;   // every thread forms the same sum in the same order
     }
     // rows of u from the register tile, summed over the four wavefronts in order
@@ -542,7 +592,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     for (int aa = 0; aa < A; ++aa) {
       double v = 0.0;
 #pragma unroll
-      for (int bb = 0; bb < B; ++bb) v += (double)cur[aa][bb] * sh_d[wave + 4 * bb];
+      for (int bb = 0; bb < B; ++bb) v += cur.at(aa, bb) * sh_d[wave + 4 * bb];
       sh_red[wave * 64 * A + 64 * aa + lane] = v;
     }
     __syncthreads();
@@ -556,7 +606,10 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     if (tid < sb1) {
       double v = rc - rxi + beta * (rx - rz);
       if (s.h) v += rh * rx;
-      if (s.a) v -= mu * ra;
+      if (s.a) {
+        v -= mu * ra;
+        sh_a[(i + 1) & 1][tid] = ra;
+      }
       gnxt = v;
     }
     __syncthreads();
