@@ -54,7 +54,7 @@ typedef enum {
   RAC_ERR_NOT_PD = 2,      /* Assumption 2.1 violated: a block matrix H_BB + beta(I + a_B a_B')
                               had a non-positive Cholesky pivot; the failing (iteration, block)
                               is reported in rac_result */
-  RAC_ERR_DEVICE = 3,      /* a HIP call failed */
+  RAC_ERR_DEVICE = 3,      /* a HIP call failed, or a persistent kernel's bounded wait ran out */
   RAC_ERR_NOMEM = 4,       /* workspace allocation failed */
   RAC_ERR_UNSUPPORTED = 5  /* valid but not implemented (e.g. dtype/precision pair) */
 } rac_status;
@@ -287,7 +287,11 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
                             const rac_batch_opts* opts, rac_batch* out);
 rac_status rac_batch_destroy(rac_batch b);
 /* Run up to max_iter iterations or until every lane has retired; *iters receives
- * the iterations run, *active the lanes still running (host pointers). */
+ * the iterations run, *active the lanes still running (host pointers).  Lanes whose
+ * block matrices violate Assumption 2.1 retire with the failing (iteration, block)
+ * recorded (read it with rac_batch_lane).  Returns RAC_ERR_DEVICE when a team
+ * sweep's bounded wait for another workgroup of its team ran out; the batch is then
+ * not usable. */
 rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* active);
 /* Result and state of one lane: res (host) and x, z, xi (device, n_i doubles each,
  * any may be NULL).  res->status is the lane's rac_run_status (RAC_ERR_NOT_PD is
