@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
   constexpr int KM = (NC + P - 1) / P;            // Minv entries per thread
   constexpr bool MREG = KM <= 16;                 // keep the next block's inverse in registers
-  constexpr int NL = 128 / P;                     // partial loads per batch (K <= 128 in one batch)
+  constexpr int NL = 128 / P > 32 ? 32 : 128 / P;  // partial loads per batch (register budget: at most 32)
   const int K = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jc = tid % NC, part = tid / NC;
@@ -415,10 +415,9 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     }
   }
 
-  // Exchange of the per-group partials.  Blocks 0 (and every block when B > 16)
-  // use epoch flags: partials complete, then the group's flag, then loads after
-  // all flags are raised.  From block 1 on (B <= 16) the partials themselves are
-  // polled: block i uses slot buffer i % 3, slots start as kEmpty (a signalling-NaN
+  // Exchange of the per-group partials.  Block 0 uses epoch flags: partials
+  // complete, then the group's flag, then loads after all flags are raised.
+  // From block 1 on the partials themselves are polled: block i uses slot buffer i % 3, slots start as kEmpty (a signalling-NaN
   // pattern that no arithmetic produces), and a reader loads until none is empty.
   // A group empties its slot of block i - 1 once it has seen every group's
   // block-i partial (each group publishes block i only after reading block i - 1),
@@ -428,9 +427,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   // values and empties it.  Block 0's flags order the first emptying of
   // buffers 1 and 2 before any reader.  Waits are bounded: a group that gives up
   // raises wait_abort and leaves, and so do the groups waiting on it.
-  // (B = 32 keeps the flags: polling its 64 partials per thread at once does not
-  // fit the register file beside two 32-column tiles.)
-  constexpr bool SENT = B <= 16;
+  constexpr bool SENT = true;
   // the lane that stores a column's partial (and empties its slot), and that
   // column: after the transposed sums, lane l of a 16-lane row holds column l
   // (B = 16) or l / 2 (B = 8) of the row's totals, and lane l holds column
