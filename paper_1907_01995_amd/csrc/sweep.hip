@@ -11,22 +11,23 @@
 //
 // Work split: K cooperating workgroups each own a contiguous range of at most
 // 64*A rows of F, and hence of u, which never leaves its owner (registers).
-// Lane l of every wavefront holds rows l, l+64, ...; wavefront w holds block
-// columns w, w+4, ... (B of them).  Per block:
+// Lane l of every wavefront holds rows A l .. A l + A - 1 of the range;
+// wavefront w holds block columns w, w+4, ... (B of them).  Per block:
 //   1. the block's tile of F (rows x columns) is already in registers: it was
-//      prefetched while the previous block was being exchanged, so each element
-//      of F is read from HBM once per sweep and serves both products below;
-//   2. partial F_B'u over the group's rows (FP64 accumulation, wavefront
-//      shuffles), published with agent-scope relaxed atomic stores, then one
-//      flag per group (a monotone epoch, no contended counter); the flags are
-//      packed densely so that a poll of all of them is a few cache lines;
-//   3. the next block's tile and gbase are loaded while the flags are awaited;
+//      read from the packed copy the Gram kernel wrote (or gathered from F)
+//      while the previous block was finishing, so each element of F is read
+//      from HBM once per sweep and serves both products below;
+//   2. partial F_B'u over the group's rows (FP64 accumulation, transposed
+//      lane exchanges), published with agent-scope relaxed atomic stores;
+//   3. every group polls the K partials until none is the empty pattern (block
+//      0: epoch flags first), then issues the next block's tile and gradient
+//      inputs, which arrive during the solve and the update;
 //   4. every group sums the K partials in the same fixed order, applies M_B^{-1}
-//      (precomputed by the factor kernel) and so holds the identical step d;
+//      (formed by the factor kernel) and so holds the identical step d;
 //   5. its rows of u are updated from the register tile; group 0 writes x_B.
-// Cross-group traffic uses only sc1 (device-coherent) loads and stores and an
-// s_waitcnt before the flag store -- no cache write-back or invalidation.
-// Partials are double-buffered by block parity, so one exchange per block suffices.
+// Cross-group traffic uses only device-coherent (agent-scope) loads and stores
+// and s_waitcnt -- no cache write-back or invalidation.  Partials rotate through
+// three buffers; the protocol is described at the exchange below.
 #include "rac_internal.h"
 #include <type_traits>
 
