@@ -43,7 +43,8 @@ __global__ void __launch_bounds__(256) k_sweep(const T* __restrict__ F, int64_t 
                                                double* x, const double* __restrict__ z,
                                                const double* __restrict__ xi, double* u,
                                                DevScalars* sc, const double* beta_ptr,
-                                               double* partials, uint64_t* flags, uint64_t epoch_base) {
+                                               double* partials, uint64_t* flags, uint64_t epoch_base,
+                                               int max_spin) {
   const int K = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t r0 = block_start(g, rows, K), r1 = block_start(g + 1, rows, K);
@@ -51,6 +52,8 @@ __global__ void __launch_bounds__(256) k_sweep(const T* __restrict__ F, int64_t 
   __shared__ double dl[kMaxBlock];     // step d = -M^{-1} g
   __shared__ int32_t cols[kMaxBlock];
   __shared__ double t_sh;
+  __shared__ int abort_sh;
+  if (tid == 0) abort_sh = 0;
   const double beta = *beta_ptr;
   const double mu = sc->mu;
   double t = sc->t;
@@ -78,13 +81,21 @@ __global__ void __launch_bounds__(256) k_sweep(const T* __restrict__ F, int64_t 
       if (tid == 0)
         __hip_atomic_store(&flags[(int64_t)g * kFlagStride], epoch, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
-      if (wave == 0) {
-        for (int q = lane; q < K; q += 64)
-          while (__hip_atomic_load(&flags[(int64_t)q * kFlagStride], __ATOMIC_ACQUIRE,
-                                   __HIP_MEMORY_SCOPE_AGENT) < epoch)
+      if (wave == 0) {   // bounded: gives up after max_spin polls of one flag
+        bool gave_up = false;
+        for (int q = lane; q < K && !gave_up; q += 64)
+          for (int tries = 0; __hip_atomic_load(&flags[(int64_t)q * kFlagStride], __ATOMIC_ACQUIRE,
+                                                __HIP_MEMORY_SCOPE_AGENT) < epoch; ++tries) {
+            if (tries >= max_spin) { gave_up = true; break; }
             __builtin_amdgcn_s_sleep(1);
+          }
+        if (gave_up) abort_sh = 1;
       }
       __syncthreads();
+      if (abort_sh) {   // a group never published: leave (every thread sees the same flag)
+        if (tid == 0) __hip_atomic_store(&sc->wait_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
       __atomic_thread_fence(__ATOMIC_ACQUIRE);
     }
     // 3. full gradient (fixed summation order over groups), then the step
@@ -474,12 +485,17 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       if (K > 1 && tid == 0)
         __hip_atomic_store(&s.flags[g], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (K > 1 && wave == 0) {
-        // every lane checks its flags each round; the wavefront leaves when all are raised
-        while (true) {
+        // every lane checks its flags each round; the wavefront leaves when all are
+        // raised, or gives up after max_spin rounds
+        for (int tries = 0;; ++tries) {
           bool ok = true;
           for (int q = lane; q < K; q += 64)
             ok &= __hip_atomic_load(&s.flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
           if (__all(ok)) break;
+          if (tries >= s.max_spin) {
+            if (lane == 0) sh_abort = 1;
+            break;
+          }
           __builtin_amdgcn_s_sleep(1);
         }
       }
@@ -517,11 +533,13 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       sh_pg[part * NC + jc] = acc;
     }
     __syncthreads();
+    // a group never published (its flag or its partials): leave, every thread
+    // sees the same flag (the loads above stayed in bounds; their values are unused)
+    if (sh_abort) {
+      if (tid == 0) __hip_atomic_store(&s.sc->wait_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
     if (poll_data) {
-      if (sh_abort) {   // a group never published: leave (every thread sees the same flag)
-        if (tid == 0) __hip_atomic_store(&s.sc->wait_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
       // every group has published block i, so none still reads block i - 1: empty our slot of it
       if (writer) st_coherent(&s.partials[((int64_t)((i - 1) % 3) * K + g) * kMaxBlock + wcol], kEmpty);
     }
@@ -676,15 +694,16 @@ template <typename T>
 hipError_t sweep_launch(const SweepArgs& s, hipStream_t st) {
   const T* F = (const T*)s.F;
   const double* beta_ptr = s.beta_ptr;
+  int max_spin = s.max_spin >= 0 ? s.max_spin : kMaxSpin;
   void* args[] = {(void*)&F, (void*)&s.ldF, (void*)&s.rows, (void*)&s.n, (void*)&s.p,
                   (void*)&s.perm, (void*)&s.Minv, (void*)&s.sp, (void*)&s.c, (void*)&s.h,
                   (void*)&s.a, (void*)&s.b, (void*)&s.Ns, (void*)&s.x, (void*)&s.z, (void*)&s.xi,
                   (void*)&s.u, (void*)&s.sc, (void*)&beta_ptr, (void*)&s.partials,
-                  (void*)&s.flags, (void*)&s.epoch_base};
+                  (void*)&s.flags, (void*)&s.epoch_base, (void*)&max_spin};
   if (s.K == 1) {
     k_sweep<T><<<1, 256, 0, st>>>(F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.c, s.h, s.a,
                                   s.b, s.Ns, s.x, s.z, s.xi, s.u, s.sc, beta_ptr, s.partials,
-                                  s.flags, s.epoch_base);
+                                  s.flags, s.epoch_base, max_spin);
     return hipGetLastError();
   }
   return hipLaunchCooperativeKernel((const void*)k_sweep<T>, dim3((unsigned)s.K), dim3(256), args, 0,

@@ -314,17 +314,22 @@ def test_packed_and_gathered_sweeps_are_bit_identical(storage, prec, N, n, s, K)
         assert rel(outs[0][1], ref.z) < 1e-8 and rel(outs[0][2], ref.xi) < 1e-8
 
 
-def test_sweep_wait_limit_reports_a_device_error(monkeypatch):
+@pytest.mark.parametrize("s,K", [(64, 0), (128, 0), (64, 2)])
+def test_sweep_wait_limit_reports_a_device_error(monkeypatch, s, K):
     """The sweep's waits for other groups are bounded. With the limit forced to zero
     polls from the host, groups give up at their first wait, every kernel still exits,
-    and the run returns RAC_ERR_DEVICE; solvers created afterwards run normally."""
-    w = W.lasso(N=6000, n=512, data_seed=14, block_size=64, storage="f32")
+    and the run returns RAC_ERR_DEVICE; solvers created afterwards run normally.
+    Blocks of 64 and 128 (16- and 32-column register tiles), and K = 2 row groups of
+    1500 rows, more than a register tile holds (the streaming sweep)."""
+    w = W.lasso(N=6000 if K == 0 else 3000, n=512, data_seed=14, block_size=s, storage="f32")
     gp, _ = en_pair(w)
-    kw = dict(s=64, beta0=w.beta0, beta_mode=racmb.BETA_RESBAL, precision=racmb.PREC_MIXED,
-              max_iter=20, check_every=10)
+    kw = dict(s=s, beta0=w.beta0, beta_mode=racmb.BETA_RESBAL, precision=racmb.PREC_MIXED,
+              max_iter=20, check_every=10, sweep_groups=K)
+    say("wait limit", s, K)
     monkeypatch.setenv("RACMB_SWEEP_MAX_SPIN", "0")
     sv = racmb.Solver(gp, **kw)
-    assert sv.info()["K"] > 1 and sv.info()["tileA"] > 0
+    info = sv.info()
+    assert info["K"] > 1 and (info["tileA"] > 0) == (K == 0)
     with pytest.raises(racmb.RacError) as err:
         sv.run()
     assert err.value.code == racmb.RAC_ERR_DEVICE
@@ -338,6 +343,20 @@ def test_sweep_wait_limit_reports_a_device_error(monkeypatch):
         sv.close()
     for u, v in zip(*outs):
         assert np.array_equal(u, v)
+
+
+def test_streaming_sweep_matches_oracle():
+    """Two row groups of 1500 rows, more than a register tile holds, select the
+    streaming sweep (columns read straight from F, one wavefront per column)."""
+    w = W.lasso(N=3000, n=300, data_seed=15, block_size=32, storage="f64")
+    gp, op = en_pair(w)
+    say("streaming sweep 3000x300, K = 2")
+    s, r, x, z, xi, mu = gpu_solve(gp, s=32, beta0=w.beta0, max_iter=30, check_every=10, seed=5,
+                                   sweep_groups=2)
+    assert s.info()["tileA"] == 0 and s.info()["K"] == 2
+    ref = O.solve(op, s=32, beta0=w.beta0, max_iter=30, check_every=10, seed=5)
+    for a, b in ((x, ref.x), (z, ref.z), (xi, ref.xi)):
+        assert rel(a, b) < 1e-8, rel(a, b)
 
 
 def test_repeated_runs_are_deterministic():
