@@ -15,7 +15,7 @@ HBM.  The line also reports, on the same data:
                   and for the plain FP64 fixed-beta solver (FP64 data, FP64
                   Grams, beta = 0.1 lambda as in Sec.3.1),
   roofline     -- the dominant kernel's achieved rate from HIP events recorded
-                  around each launch inside the timed region,
+                  around every 8th launch inside the timed region,
   cpu_baseline -- the FP64 oracle on a bounded sample of the same workload,
   batched      -- the batched elastic-net paths (256 instances of uneven size,
                   N in [1000, 20000] and n in [100, 4000] log-uniform, BF16
@@ -48,6 +48,7 @@ if ROOT not in sys.path:
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 MFMA_PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
 METRIC = "time-to-1e-6 KKT residual & ADMM iters/s: learned-β batched vs plain FP64"
+TIMING_STRIDE = 8            # sweeps timed with HIP events in the throughput run: iterations k % 8 == 0
 WEIGHTS = os.path.join(ROOT, "paper_1907_01995_amd", "controller_weights.npy")
 
 
@@ -257,9 +258,10 @@ def main():
     if args.warmup > 0:
         warm.run()
     warm.close()
-    # HIP events around the sweep launches only (the dominant kernel): two events
-    # per iteration disturb the timed run far less than events around every phase
-    sol.set_timing(True, phases=["sweep"])
+    # HIP events around the sweep launches (the dominant kernel) of every 8th
+    # iteration only: the average launch time comes from the timed run itself,
+    # and 25 event pairs disturb it far less than events around every launch
+    sol.set_timing(True, phases=["sweep"], stride=TIMING_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = sol.run()

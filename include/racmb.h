@@ -163,6 +163,11 @@ rac_status rac_solver_set_timing(rac_solver s, int32_t enable);   /* also clears
  * clears the totals.  Fewer events around the launches disturb the run less.
  * RAC_ERR_ARG for bits past RAC_NUM_PHASES. */
 rac_status rac_solver_set_timing_mask(rac_solver s, uint32_t mask);
+/* Times the per-iteration phases (Gram, factor, sweep, z/dual) only on iterations k
+ * with k mod stride == 0 (stride >= 1; 1, the default, times every iteration); the
+ * partition and check phases are timed at every occurrence.  Fewer event pairs
+ * disturb a timed run less.  Also clears the totals.  RAC_ERR_ARG for stride < 1. */
+rac_status rac_solver_set_timing_stride(rac_solver s, int64_t stride);
 /* ms (host, RAC_NUM_PHASES) receives the summed milliseconds per phase, launches
  * (host, RAC_NUM_PHASES or NULL) the number of timed launches per phase. */
 rac_status rac_solver_timing(rac_solver s, double* ms, int64_t* launches);

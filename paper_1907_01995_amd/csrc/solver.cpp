@@ -201,6 +201,7 @@ struct rac_solver_s {
   DevScalars hsc{};
   // optional per-phase timing with HIP events on the run's stream
   uint32_t tmask = 0;                    // phases timed (bit q: phase q)
+  int64_t tstride = 1;                   // per-iteration phases timed on iterations k % tstride == 0
   std::vector<hipEvent_t> ev;            // pool, two per timed launch
   std::vector<int> ev_phase;             // phase of each recorded pair in the current chunk
   double phase_ms[RAC_NUM_PHASES] = {0};
@@ -239,7 +240,10 @@ rac_status fx_into_u(rac_solver s, const double* x, double* u, hipStream_t st) {
 struct PhaseTimer {
   rac_solver s;
   hipStream_t st;
-  bool on(int phase) const { return ((s->tmask >> phase) & 1u) != 0; }
+  int64_t k = -1;                        // iteration of the phase being enqueued (-1: once per chunk)
+  bool on(int phase) const {
+    return ((s->tmask >> phase) & 1u) != 0 && (k < 0 || s->tstride <= 1 || k % s->tstride == 0);
+  }
   hipError_t begin(hipStream_t stream, int phase) { st = stream; return begin(phase); }
   hipError_t begin(int phase) {
     if (!on(phase)) return hipSuccess;
@@ -283,6 +287,7 @@ rac_status enqueue_gram(rac_solver s, int64_t k, const int32_t* perm, hipStream_
   void* Fp = s->Fp ? (void*)(s->Fp + par * s->Fp_bytes) : nullptr;
   GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, s->O.precision, s->R, s->sp,
              s->partial, PackDst{Fp, s->packRW, s->K, s->tileA, s->tileB}};
+  tm.k = k;
   HIPCHK(tm.begin(sa, RAC_PHASE_GRAM));
   HIPCHK(launch_gram(g, sa));
   HIPCHK(tm.end(RAC_PHASE_GRAM));
@@ -299,6 +304,7 @@ rac_status enqueue_factor(rac_solver s, int64_t k, const int32_t* perm, const do
   f.Ns = P.Ns; f.h = P.h; f.a = P.a; f.beta_ptr = beta_ptr; f.beta_val = 0.0;
   f.Minv = s->Minv + par * (size_t)s->p * s->sp * s->sp;
   f.write_matrix = 0; f.sc = s->sc; f.iter_global = k;
+  tm.k = k;
   HIPCHK(tm.begin(sa, RAC_PHASE_FACTOR));
   HIPCHK(launch_factor(f, sa));
   HIPCHK(tm.end(RAC_PHASE_FACTOR));
@@ -322,6 +328,7 @@ rac_status preissue_next_chunk(rac_solver s, int64_t k1, int64_t Tn, int64_t run
   int32_t* pb = s->perm + (size_t)b * s->T * s->n;
   // the buffer was last read by the previous chunk's sweeps, all before the sweep of k1 - 2
   if (s->swept[k1 & 1] >= 0) HIPCHK(hipStreamWaitEvent(sa, s->ev_sweep[k1 & 1], 0));
+  tm.k = -1;
   HIPCHK(tm.begin(sa, RAC_PHASE_PARTITION));
   HIPCHK(launch_permutations(s->O.seed, s->O.instance, k1, Tn, s->n, s->pw, pb, sa));
   HIPCHK(tm.end(RAC_PHASE_PARTITION));
@@ -347,6 +354,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     s->pbuf = 1 - s->pbuf;
   } else {
     s->pbuf = 0;
+    tm.k = -1;
     HIPCHK(tm.begin(RAC_PHASE_PARTITION));
     HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
     HIPCHK(tm.end(RAC_PHASE_PARTITION));
@@ -372,6 +380,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, perm, Minv, s->sp, P.c, P.h, P.a,
                 P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
                 beta_ptr, s->tileA, s->tileB, s->overlap ? 0 : 1, Fp, s->max_spin};
+    tm.k = k;
     HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
     HIPCHK(launch_sweep(w, st));
     HIPCHK(tm.end(RAC_PHASE_SWEEP));
@@ -385,6 +394,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     za.b = P.b; za.has_eq = P.a ? 1 : 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
     za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
     za.hist_base = k0 - run_offset; za.T = s->T; za.beta_ptr = beta_ptr; za.publish_beta = sched ? 1 : 0;
+    tm.k = k;
     HIPCHK(tm.begin(st, RAC_PHASE_ZDUAL));
     HIPCHK(launch_zdual(za, st));
     HIPCHK(tm.end(RAC_PHASE_ZDUAL));
@@ -395,6 +405,7 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
   ka.alpha = P.alpha; ka.lo = P.lo; ka.hi = P.hi; ka.x = s->x; ka.z = s->z; ka.xi = s->xi;
   ka.u = s->u; ka.mu_ptr = &s->sc->mu; ka.mu_val = 0.0; ka.red = s->red; ka.done = s->done;
   ka.out = s->kkt_out; ka.part = s->kkt_part;
+  tm.k = -1;
   HIPCHK(tm.begin(st, RAC_PHASE_CHECK));
   HIPCHK(launch_kkt(ka, st));
   ControlArgs ca{};
@@ -705,6 +716,14 @@ rac_status rac_solver_set_timing(rac_solver s, int32_t enable) {
 rac_status rac_solver_set_timing_mask(rac_solver s, uint32_t mask) {
   if (!s || (mask >> RAC_NUM_PHASES) != 0) return RAC_ERR_ARG;
   s->tmask = mask;
+  for (int q = 0; q < RAC_NUM_PHASES; ++q) { s->phase_ms[q] = 0.0; s->phase_count[q] = 0; }
+  s->ev_phase.clear();
+  return RAC_OK;
+}
+
+rac_status rac_solver_set_timing_stride(rac_solver s, int64_t stride) {
+  if (!s || stride < 1) return RAC_ERR_ARG;
+  s->tstride = stride;
   for (int q = 0; q < RAC_NUM_PHASES; ++q) { s->phase_ms[q] = 0.0; s->phase_count[q] = 0; }
   s->ev_phase.clear();
   return RAC_OK;

@@ -29,7 +29,7 @@ MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HI
 
 EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_solver_set_state",
             "rac_solver_get_state", "rac_solver_history", "rac_solver_set_timing", "rac_solver_timing",
-            "rac_solver_set_timing_mask",
+            "rac_solver_set_timing_mask", "rac_solver_set_timing_stride",
             "rac_solver_info", "rac_solver_features", "rac_solver_scale_beta", "rac_state_export",
             "rac_state_import",
             "rac_permutation", "rac_kkt", "rac_objective", "rac_regression_c", "rac_block_matrices",
@@ -107,6 +107,7 @@ def load():
         "rac_solver_history": [vp, dp, i64, C.POINTER(i64)],
         "rac_solver_set_timing": [vp, C.c_int32],
         "rac_solver_set_timing_mask": [vp, C.c_uint32],
+        "rac_solver_set_timing_stride": [vp, i64],
         "rac_solver_timing": [vp, dp, C.POINTER(i64)],
         "rac_solver_info": [vp, C.POINTER(i64)],
         "rac_solver_features": [vp, C.POINTER(C.c_float)],
@@ -352,8 +353,10 @@ class Solver:
 
     PHASES = ("partition", "gram", "factor", "sweep", "zdual", "check")
 
-    def set_timing(self, enable=True, phases=None):
-        """Per-phase HIP-event timing; `phases` (names) restricts it to those phases."""
+    def set_timing(self, enable=True, phases=None, stride=1):
+        """Per-phase HIP-event timing; `phases` (names) restricts it to those phases, and
+        `stride` times the per-iteration phases of every stride-th iteration only."""
+        _check(self.lib.rac_solver_set_timing_stride(self.h, int(stride)), "rac_solver_set_timing_stride")
         if phases is None:
             _check(self.lib.rac_solver_set_timing(self.h, 1 if enable else 0), "rac_solver_set_timing")
             return

@@ -375,19 +375,21 @@ def test_solver_phase_timing_does_not_change_results():
     w = W.lasso(N=2000, n=256, data_seed=8, block_size=32, storage="f32")
     gp, _ = en_pair(w)
     outs = []
-    for timing in (False, True):
+    for timing, stride in ((False, 1), (True, 1), (True, 4)):
         s = racmb.Solver(gp, s=32, precision=racmb.PREC_MIXED, beta0=w.beta0, beta_mode=racmb.BETA_RESBAL,
                          max_iter=30, check_every=10)
-        s.set_timing(timing)
+        s.set_timing(timing, stride=stride)
         s.run()
         if timing:
             ph = s.timing()
-            assert ph["sweep"][1] == 30 and ph["gram"][1] == 30 and ph["check"][1] == 3
+            per_iter = 30 if stride == 1 else 8            # iterations 0, 4, ..., 28
+            assert ph["sweep"][1] == per_iter and ph["gram"][1] == per_iter and ph["check"][1] == 3
             assert ph["sweep"][0] > 0
         outs.append(s.state()[:3])
         s.close()
-    for u, v in zip(*outs):
-        assert np.array_equal(u, v)
+    for o in outs[1:]:
+        for u, v in zip(outs[0], o):
+            assert np.array_equal(u, v)
 
 
 # ---------------------------------------------------------------------------
