@@ -13,7 +13,14 @@ and wraps it with ctypes.  The problem mappings below follow the paper:
 * elastic net (Sec.3.1, Eq.(5)-(8)): ``c = -X'y/N`` and ``H = X'X/N`` (the
   paper's ``A = X/sqrt(N)``), split ``beta - z = 0`` with z as one block;
 * C-SVC dual (Sec.3.2, Eq.(9)) with a linear kernel: ``Q = G G'`` where
-  ``G = diag(y) X``, ``c = -e``, equality ``y'z = 0`` and the box ``[0, C]``.
+  ``G = diag(y) X``, ``c = -e``, equality ``y'z = 0`` and the box ``[0, C]``;
+  with the Gaussian kernel of Sec.3.2, ``Q_ij = y_i y_j exp(-gamma |x_i - x_j|^2)``
+  is passed as the explicit dense part ``Hd`` of H;
+* the general QP of Eq.(1)/Eq.(4): ``H = F'F/Ns + Hd + diag h`` and several
+  equality rows ``A x = beq``.
+
+``solve(..., rp=True)`` runs RP-MBADMM (Sec.1): contiguous fixed blocks solved
+in an order drawn at random every iteration.
 
 Functions without a pin in tests/test_oracle_pins.py would be marked
 "parity unpinned" here; at present every function below has one.
@@ -71,11 +78,11 @@ def _load():
     lib.orc_paper_S.restype = C.c_double
     lib.orc_paper_S.argtypes = [C.c_double, C.c_double]
     lib.orc_kkt.restype = C.c_double
-    lib.orc_kkt.argtypes = [i64, i64, dp, C.c_double, dp, dp, dp, C.c_double, C.c_int,
+    lib.orc_kkt.argtypes = [i64, i64, dp, C.c_double, dp, dp, dp, i64, dp, dp, C.c_int,
                             C.c_double, C.c_double, C.c_double, C.c_double, dp, dp, dp,
-                            C.c_double, dp]
+                            dp, dp]
     lib.orc_objective.restype = C.c_double
-    lib.orc_objective.argtypes = [i64, i64, dp, C.c_double, dp, dp, C.c_int, C.c_double,
+    lib.orc_objective.argtypes = [i64, i64, dp, C.c_double, dp, dp, dp, C.c_int, C.c_double,
                                   C.c_double, C.c_double, dp]
     lib.orc_mlp_nparam.restype = i64
     lib.orc_mlp_forward.restype = None
@@ -89,9 +96,9 @@ def _load():
     lib.orc_controller_features.argtypes = [C.c_double] * 7 + [i64, dp]
     lib.orc_solve.restype = C.c_int
     lib.orc_solve.argtypes = [
-        i64, i64, dp, C.c_double, dp, dp, dp, C.c_double, C.c_int, C.c_double, C.c_double,
+        i64, i64, dp, C.c_double, dp, dp, dp, i64, dp, dp, C.c_int, C.c_double, C.c_double,
         C.c_double, C.c_double,
-        i64, u64, u64, i64,
+        i64, C.c_int, u64, u64, i64,
         C.c_int, C.c_double, dp, C.c_double, C.c_double,
         dp, C.c_double,
         i64, i64, C.c_double,
@@ -118,7 +125,10 @@ def _f64(a, order="C"):
 
 @dataclass
 class Problem:
-    """min 1/2 x'(F'F/Ns + diag h)x + c'x + P(z) + obj_const s.t. a'x = b, x = z."""
+    """min 1/2 x'(F'F/Ns + Hd + diag h)x + c'x + P(z) + obj_const s.t. A x = beq, x = z.
+
+    One equality row can be given as ``a`` (n) and ``b``; several as ``A``
+    (meq x n) and ``beq`` (meq).  ``F`` may have zero rows when ``Hd`` carries H."""
     F: np.ndarray                  # rowsF x n, float64, column-major
     Ns: float
     c: np.ndarray
@@ -131,6 +141,9 @@ class Problem:
     lo: float = 0.0
     hi: float = 0.0
     obj_const: float = 0.0
+    Hd: np.ndarray | None = None   # n x n dense symmetric addend of H
+    A: np.ndarray | None = None    # meq x n equality rows
+    beq: np.ndarray | None = None  # meq
 
     @property
     def n(self):
@@ -139,6 +152,18 @@ class Problem:
     @property
     def m(self):
         return self.F.shape[0]
+
+    def eq(self):
+        """(meq, A as a C-ordered meq x n float64 array or None, beq or None)."""
+        if self.A is not None:
+            A = _f64(np.atleast_2d(self.A))
+            return A.shape[0], A, _f64(np.atleast_1d(self.beq))
+        if self.a is not None:
+            return 1, _f64(np.asarray(self.a)[None, :]), np.array([float(self.b)])
+        return 0, None, None
+
+    def Hd_f(self):
+        return None if self.Hd is None else _f64(self.Hd, order="F")
 
 
 def en_problem(D, y, lam=0.0, alpha=1.0, h=None) -> Problem:
@@ -163,6 +188,48 @@ def svm_problem(X, labels, Cbox) -> Problem:
     n = X.shape[0]
     return Problem(F=F, Ns=1.0, c=-np.ones(n), a=yl.copy(), b=0.0, prox=PROX_BOX, lo=0.0,
                    hi=float(Cbox))
+
+
+def gaussian_kernel(X, Y, gamma):
+    """K_ij = exp(-gamma |x_i - y_j|^2), the kernel of the SVM experiments (Sec.3.2)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    d = np.empty((X.shape[0], Y.shape[0]))
+    for i in range(X.shape[0]):
+        diff = Y - X[i]
+        d[i] = np.sum(diff * diff, axis=1)
+    return np.exp(-gamma * d)
+
+
+def svm_kernel_problem(X, labels, Cbox, gamma) -> Problem:
+    """C-SVC dual of Eq.(9) with the Gaussian kernel: H = Q, Q_ij = y_i y_j K_ij, given
+    explicitly (no factor F), c = -e, equality y'z = 0, box [0, C]."""
+    yl = np.asarray(labels, dtype=np.float64)
+    n = yl.shape[0]
+    Q = yl[:, None] * gaussian_kernel(X, X, gamma) * yl[None, :]
+    return Problem(F=np.zeros((0, n), order="F"), Ns=1.0, c=-np.ones(n), a=yl.copy(), b=0.0,
+                   prox=PROX_BOX, lo=0.0, hi=float(Cbox), Hd=np.asfortranarray(Q))
+
+
+def svm_bias(res) -> float:
+    """Bias of the decision function: b = -mu, the multiplier of y'alpha = 0 (on a
+    free support vector i, y_i f(x_i) = 1 gives b = y_i - sum_j alpha_j y_j K_ij)."""
+    return -float(np.atleast_1d(res.mu)[0])
+
+
+def svm_decision(X_train, labels, alpha, bias, gamma, X_test):
+    """f(x) = sum_j alpha_j y_j K(x_j, x) + b (Gaussian kernel; gamma None: linear kernel)."""
+    coef = np.asarray(alpha, dtype=np.float64) * np.asarray(labels, dtype=np.float64)
+    if gamma is None:
+        w = np.asarray(X_train, dtype=np.float64).T @ coef
+        return np.asarray(X_test, dtype=np.float64) @ w + bias
+    return gaussian_kernel(X_test, X_train, gamma) @ coef + bias
+
+
+def svm_accuracy(f, labels) -> float:
+    """Fraction of points whose label has the sign of the decision value (f = 0 counts as +1)."""
+    pred = np.where(np.asarray(f) >= 0.0, 1.0, -1.0)
+    return float(np.mean(pred == np.asarray(labels)))
 
 
 # ---------------------------------------------------------------------------
@@ -201,17 +268,28 @@ def paper_S(a, b) -> float:
     return float(_load().orc_paper_S(a, b))
 
 
+def _mu_vec(meq, mu):
+    v = np.zeros(max(meq, 1))
+    if meq:
+        v[:meq] = np.atleast_1d(np.asarray(mu, dtype=np.float64))
+    return v
+
+
 def kkt(P: Problem, x, z, xi, mu=0.0, parts=False):
     out = np.zeros(3)
     x, z, xi = _f64(x), _f64(z), _f64(xi)
-    v = _load().orc_kkt(P.n, P.m, _dp(P.F), P.Ns, _dp(P.h), _dp(P.c), _dp(P.a), P.b, P.prox,
-                        P.lam, P.alpha, P.lo, P.hi, _dp(x), _dp(z), _dp(xi), float(mu), _dp(out))
+    meq, A, beq = P.eq()
+    muv = _mu_vec(meq, mu)
+    Hd = P.Hd_f()
+    v = _load().orc_kkt(P.n, P.m, _dp(P.F), P.Ns, _dp(Hd), _dp(P.h), _dp(P.c), meq, _dp(A), _dp(beq),
+                        P.prox, P.lam, P.alpha, P.lo, P.hi, _dp(x), _dp(z), _dp(xi), _dp(muv), _dp(out))
     return (float(v), out) if parts else float(v)
 
 
 def objective(P: Problem, z) -> float:
     z = _f64(z)
-    return float(_load().orc_objective(P.n, P.m, _dp(P.F), P.Ns, _dp(P.h), _dp(P.c), P.prox,
+    Hd = P.Hd_f()
+    return float(_load().orc_objective(P.n, P.m, _dp(P.F), P.Ns, _dp(Hd), _dp(P.h), _dp(P.c), P.prox,
                                        P.lam, P.alpha, P.obj_const, _dp(z)))
 
 
@@ -259,7 +337,7 @@ class Result:
     x: np.ndarray
     z: np.ndarray
     xi: np.ndarray
-    mu: float
+    mu: object                     # float for at most one equality row, else an array
     iters: int
     status: int
     beta: float
@@ -287,31 +365,36 @@ class Result:
 
 def solve(P: Problem, *, p=None, s=None, seed=0, inst=0, iter0=0, beta0=1.0,
           beta_mode=BETA_FIXED, beta_sched=None, rb_mu=10.0, rb_tau=2.0, mlp_w=None,
-          mlp_ymax=np.log(10.0), check_every=10, max_iter=100, tol=0.0, state=None) -> Result:
-    """Run RAC-MBADMM from ``state`` (x, z, xi, mu) or from zeros.
+          mlp_ymax=np.log(10.0), check_every=10, max_iter=100, tol=0.0, state=None,
+          rp=False) -> Result:
+    """Run RAC-MBADMM (or RP-MBADMM with ``rp=True``) from ``state`` (x, z, xi, mu)
+    or from zeros.
 
     Give either p (number of blocks) or s (maximum block size, p = ceil(n/s))."""
     n = P.n
     if p is None:
         p = -(-n // int(s))
+    meq, A, beq = P.eq()
     if state is None:
         x, z, xi, mu = np.zeros(n), np.zeros(n), np.zeros(n), 0.0
     else:
         x, z, xi, mu = (_f64(state[0]).copy(), _f64(state[1]).copy(), _f64(state[2]).copy(),
-                        float(state[3]))
-    mu_c = C.c_double(mu)
+                        state[3])
+    muv = _mu_vec(meq, mu)
     hist = np.full((max(max_iter, 1), 4), np.nan)
     iters, status, fi, fb = C.c_int64(0), C.c_int(0), C.c_int64(-1), C.c_int64(-1)
     beta_out = C.c_double(0.0)
     sched = _f64(beta_sched)
     w = _f64(mlp_w)
+    Hd = P.Hd_f()
     rc = _load().orc_solve(
-        n, P.m, _dp(P.F), P.Ns, _dp(P.h), _dp(P.c), _dp(P.a), P.b, P.prox, P.lam, P.alpha,
-        P.lo, P.hi, int(p), int(seed), int(inst), int(iter0),
+        n, P.m, _dp(P.F), P.Ns, _dp(Hd), _dp(P.h), _dp(P.c), meq, _dp(A), _dp(beq), P.prox, P.lam,
+        P.alpha, P.lo, P.hi, int(p), 1 if rp else 0, int(seed), int(inst), int(iter0),
         int(beta_mode), float(beta0), _dp(sched), rb_mu, rb_tau, _dp(w), float(mlp_ymax),
         int(check_every), int(max_iter), float(tol),
-        _dp(x), _dp(z), _dp(xi), C.byref(mu_c),
+        _dp(x), _dp(z), _dp(xi), _dp(muv),
         _dp(hist), C.byref(iters), C.byref(status), C.byref(beta_out), C.byref(fi), C.byref(fb))
-    return Result(x=x, z=z, xi=xi, mu=mu_c.value, iters=int(iters.value), status=int(status.value),
+    mu_out = float(muv[0]) if meq <= 1 and P.A is None else muv[:meq].copy()
+    return Result(x=x, z=z, xi=xi, mu=mu_out, iters=int(iters.value), status=int(status.value),
                   beta=beta_out.value, hist=hist, rc=int(rc), fail_iter=int(fi.value),
                   fail_block=int(fb.value))

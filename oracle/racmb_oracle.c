@@ -10,20 +10,27 @@
  * Everything here is deliberately slow and obvious: FP64 throughout, plain
  * loops, no blocking or fusion, one thread.  Build with -ffp-contract=off.
  *
- * Problem (canonical form of Eq.(1) as specialised in Sec.3):
- *     min_x  1/2 x'(F'F/Ns + diag h)x + c'x + P(z) + obj_const
- *     s.t.   a'x = b   (optional single equality row; the SVM dual's y'z = 0)
+ * Problem (canonical form of Eq.(1) as specialised in Sec.3, with the general
+ * linear constraints of Eq.(1)/Eq.(4)):
+ *     min_x  1/2 x'(F'F/Ns + Hd + diag h)x + c'x + P(z) + obj_const
+ *     s.t.   A x = beq (meq >= 0 rows; the SVM dual's y'z = 0 is one row)
  *            x - z = 0 (the variable split of Eq.(7)/(8); z is solved as one block)
- * F is rowsF x n, column-major.  P is 0 (least squares), the elastic-net
- * penalty lambda*(alpha*|z|_1 + (1-alpha)/2*|z|_2^2) of Eq.(6) (squared norm,
- * matching the denominator of the z closed form in Sec.3.1), or the indicator
- * of the box [lo, hi] (the C-SVC dual of Eq.(9)).
+ * F is rowsF x n, column-major; Hd is an optional explicit dense symmetric
+ * n x n addend (column-major), used for kernel SVMs and general QPs; A is
+ * meq x n, row-major (row e is the constraint vector a_e).  P is 0 (least
+ * squares), the elastic-net penalty lambda*(alpha*|z|_1 + (1-alpha)/2*|z|_2^2)
+ * of Eq.(6) (squared norm, matching the denominator of the z closed form in
+ * Sec.3.1), or the indicator of the box [lo, hi] (the C-SVC dual of Eq.(9)).
  *
  * Augmented Lagrangian (Eq.(2) with one penalty beta on every constraint row):
- *     L = f(x) + P(z) - xi'(x - z) - mu (a'x - b) + beta/2 |x - z|^2 + beta/2 (a'x - b)^2
+ *     L = f(x) + P(z) - xi'(x - z) - mu'(A x - beq) + beta/2 |x - z|^2 + beta/2 |A x - beq|^2
  * One iteration (Eq.(3)): draw a random partition of x into p blocks, minimise L
  * exactly over each block in the drawn order (Gauss-Seidel), then over z, then
- * take the dual step xi <- xi - beta (x - z), mu <- mu - beta (a'x - b).
+ * take the dual step xi <- xi - beta (x - z), mu <- mu - beta (A x - beq).
+ * The randomly permuted variant RP-MBADMM (Sec.1: blocks fixed by a
+ * predetermined rule, only their update order drawn at random) keeps the
+ * contiguous blocks [floor(i n/p), floor((i+1) n/p)) and draws the order in
+ * which they are solved every iteration.
  */
 #include <math.h>
 #include <stdint.h>
@@ -167,48 +174,71 @@ static double max_abs(int64_t n, const double* v) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* (Hd x)_j for the explicit dense addend, one entry at a time.               */
+static double dense_row_dot(int64_t n, const double* Hd, int64_t j, const double* x) {
+  double s = 0.0;
+  for (int64_t k = 0; k < n; ++k) s += Hd[j + k * n] * x[k];
+  return s;
+}
+
+/* H x = F'F x/Ns + Hd x + h.x into Hx (n), with u = F x (rows) as scratch.  */
+static void apply_H(int64_t n, int64_t m, const double* F, double Ns, const double* Hd, const double* h,
+                    const double* x, double* u, double* Hx) {
+  matvec_F(m, n, F, x, u);
+  matvec_Ft(m, n, F, u, Hx);
+  for (int64_t j = 0; j < n; ++j) {
+    Hx[j] /= Ns;
+    if (Hd) Hx[j] += dense_row_dot(n, Hd, j, x);
+    if (h) Hx[j] += h[j] * x[j];
+  }
+}
+
 /* KKT residual of the split problem at (x, z, xi, mu).  The paper stops on
  * |x - z|_1 or on primal/dual tolerances it does not define; this definition is
  * the one the whole project uses:
  *   r_feas = |x - z|_inf / (1 + max(|x|_inf, |z|_inf))
- *            and, with an equality row, |a'x - b| / (1 + |b| + |a|_inf |x|_inf)
- *   r_stat = |grad f(x) - xi - mu a|_inf / scale,  grad f(x) = F'Fx/Ns + h.x + c
+ *            and, with equality rows, |A x - beq|_inf / (1 + |beq|_inf + |A|_max |x|_inf)
+ *            (|A|_max: the largest entry in magnitude; one row gives |a'x - b| / (1 + |b| + |a|_inf |x|_inf))
+ *   r_stat = |grad f(x) - xi - A'mu|_inf / scale,  grad f(x) = H x + c
  *   r_dual = distance of -xi to the subdifferential of P at z, / scale
- *   scale  = max(|F'Fx/Ns + h.x|_inf, |c|_inf, |xi|_inf, |mu| |a|_inf), floored at 1e-300
+ *   scale  = max(|H x|_inf, |c|_inf, |xi|_inf, |A'mu|_inf), floored at 1e-300
  * The KKT residual is the largest of the three; it is 0 exactly at a solution. */
-double orc_kkt(int64_t n, int64_t m, const double* F, double Ns, const double* h,
-               const double* c, const double* a, double b, int prox, double lam,
+double orc_kkt(int64_t n, int64_t m, const double* F, double Ns, const double* Hd, const double* h,
+               const double* c, int64_t meq, const double* A, const double* beq, int prox, double lam,
                double alpha, double lo, double hi, const double* x, const double* z,
-               const double* xi, double mu, double* parts /* 3 or NULL */) {
+               const double* xi, const double* mu, double* parts /* 3 or NULL */) {
   double* u = (double*)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
   double* Hx = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
-  matvec_F(m, n, F, x, u);
-  matvec_Ft(m, n, F, u, Hx);
-  for (int64_t j = 0; j < n; ++j) { Hx[j] /= Ns; if (h) Hx[j] += h[j] * x[j]; }
+  double* Amu = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  apply_H(n, m, F, Ns, Hd, h, x, u, Hx);
+  for (int64_t e = 0; e < meq; ++e)
+    for (int64_t j = 0; j < n; ++j) Amu[j] += A[e * n + j] * mu[e];
 
   double xmax = max_abs(n, x), zmax = max_abs(n, z);
   double dxz = 0.0;
   for (int64_t j = 0; j < n; ++j) if (fabs(x[j] - z[j]) > dxz) dxz = fabs(x[j] - z[j]);
   double r_feas = dxz / (1.0 + (xmax > zmax ? xmax : zmax));
-  double amax = 0.0;
-  if (a) {
-    double t = 0.0;
-    for (int64_t j = 0; j < n; ++j) t += a[j] * x[j];
-    amax = max_abs(n, a);
-    double req = fabs(t - b) / (1.0 + fabs(b) + amax * xmax);
+  if (meq > 0) {
+    double amax = max_abs(meq * n, A), bmax = max_abs(meq, beq), emax = 0.0;
+    for (int64_t e = 0; e < meq; ++e) {
+      double t = 0.0;
+      for (int64_t j = 0; j < n; ++j) t += A[e * n + j] * x[j];
+      if (fabs(t - beq[e]) > emax) emax = fabs(t - beq[e]);
+    }
+    double req = emax / (1.0 + bmax + amax * xmax);
     if (req > r_feas) r_feas = req;
   }
 
   double scale = max_abs(n, Hx);
-  double cm = max_abs(n, c), xim = max_abs(n, xi);
+  double cm = max_abs(n, c), xim = max_abs(n, xi), am = max_abs(n, Amu);
   if (cm > scale) scale = cm;
   if (xim > scale) scale = xim;
-  if (a && fabs(mu) * amax > scale) scale = fabs(mu) * amax;
+  if (meq > 0 && am > scale) scale = am;
   if (scale < 1e-300) scale = 1e-300;
 
   double st = 0.0, du = 0.0;
   for (int64_t j = 0; j < n; ++j) {
-    double g = Hx[j] + c[j] - xi[j] - (a ? mu * a[j] : 0.0);
+    double g = Hx[j] + c[j] - xi[j] - Amu[j];
     if (fabs(g) > st) st = fabs(g);
     double d = 0.0;  /* distance from -xi_j to the subdifferential of P at z_j */
     if (prox == ORC_PROX_NONE) {
@@ -233,6 +263,7 @@ double orc_kkt(int64_t n, int64_t m, const double* F, double Ns, const double* h
   if (parts) { parts[0] = r_feas; parts[1] = r_stat; parts[2] = r_dual; }
   free(u);
   free(Hx);
+  free(Amu);
   double k = r_feas;
   if (r_stat > k) k = r_stat;
   if (r_dual > k) k = r_dual;
@@ -240,7 +271,7 @@ double orc_kkt(int64_t n, int64_t m, const double* F, double Ns, const double* h
 }
 
 /* Objective at z: 1/2 z'Hz + c'z + P(z) + obj_const. */
-double orc_objective(int64_t n, int64_t m, const double* F, double Ns, const double* h,
+double orc_objective(int64_t n, int64_t m, const double* F, double Ns, const double* Hd, const double* h,
                      const double* c, int prox, double lam, double alpha, double obj_const,
                      const double* z) {
   double* u = (double*)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
@@ -248,17 +279,18 @@ double orc_objective(int64_t n, int64_t m, const double* F, double Ns, const dou
   double q = 0.0;
   for (int64_t r = 0; r < m; ++r) q += u[r] * u[r];
   q /= Ns;
-  double lin = 0.0, hz = 0.0, l1 = 0.0, l2 = 0.0;
+  double lin = 0.0, hz = 0.0, dz = 0.0, l1 = 0.0, l2 = 0.0;
   for (int64_t j = 0; j < n; ++j) {
     lin += c[j] * z[j];
     if (h) hz += h[j] * z[j] * z[j];
+    if (Hd) dz += z[j] * dense_row_dot(n, Hd, j, z);
     l1 += fabs(z[j]);
     l2 += z[j] * z[j];
   }
   double pen = 0.0;
   if (prox == ORC_PROX_EN) pen = lam * (alpha * l1 + 0.5 * (1.0 - alpha) * l2);
   free(u);
-  return 0.5 * (q + hz) + lin + pen + obj_const;
+  return 0.5 * (q + dz + hz) + lin + pen + obj_const;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -379,21 +411,26 @@ void orc_controller_features(double rp_now, double rd_now, double rp_old, double
 }
 
 /* ------------------------------------------------------------------------ */
-/* The solver.  State (x, z, xi, mu) is read on entry (warm start, all zeros for
- * a cold start) and written on exit.  hist has 4 doubles per iteration:
- * r_p, r_d, beta used, KKT (NaN where not evaluated).  Returns ORC_OK or an
- * error code; *status is the run outcome.                                   */
-int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
-              const double* c, const double* a, double b, int prox, double lam, double alpha,
-              double lo, double hi,
-              int64_t p, uint64_t seed, uint64_t inst, int64_t iter0,
+/* The solver.  State (x, z, xi, mu[meq]) is read on entry (warm start, all
+ * zeros for a cold start) and written on exit.  hist has 4 doubles per
+ * iteration: r_p, r_d, beta used, KKT (NaN where not evaluated), with
+ *   r_p = sqrt(|x - z|^2 + |A x - beq|^2)   (every constraint row of Eq.(2) stacked)
+ *   r_d = beta |z - z_prev|
+ * rp selects the variant: 0 RAC-MBADMM (a fresh random partition every
+ * iteration), 1 RP-MBADMM (contiguous fixed blocks, random block order).
+ * Returns ORC_OK or an error code; *status is the run outcome.               */
+int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* Hd, const double* h,
+              const double* c, int64_t meq, const double* A, const double* beq, int prox, double lam,
+              double alpha, double lo, double hi,
+              int64_t p, int rp, uint64_t seed, uint64_t inst, int64_t iter0,
               int beta_mode, double beta0, const double* beta_sched, double rb_mu, double rb_tau,
               const double* mlp_w, double mlp_ymax,
               int64_t check_every, int64_t max_iter, double tol,
-              double* x, double* z, double* xi, double* mu_io,
+              double* x, double* z, double* xi, double* mu,
               double* hist, int64_t* iters_out, int* status_out, double* beta_out,
               int64_t* fail_iter, int64_t* fail_block) {
-  if (n < 1 || m < 0 || p < 1 || p > n || !(beta0 > 0.0) || check_every < 1 || max_iter < 0)
+  if (n < 1 || m < 0 || meq < 0 || p < 1 || p > n || !(beta0 > 0.0) || check_every < 1 || max_iter < 0 ||
+      (rp != 0 && rp != 1) || (meq > 0 && (!A || !beq || !mu)))
     return ORC_ERR_ARG;
   int64_t smax = 0;
   for (int64_t i = 0; i < p; ++i) {
@@ -401,17 +438,19 @@ int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
     if (sz > smax) smax = sz;
   }
   int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)p);
+  int64_t* B = (int64_t*)malloc(sizeof(int64_t) * (size_t)smax);
   double* u = (double*)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
+  double* t = (double*)calloc((size_t)(meq > 0 ? meq : 1), sizeof(double));
   double* M = (double*)malloc(sizeof(double) * (size_t)(smax * smax));
   double* g = (double*)malloc(sizeof(double) * (size_t)smax);
   double* zprev = (double*)malloc(sizeof(double) * (size_t)n);
-  double mu = *mu_io;
   double beta = beta0;
 
-  /* residual maintenance: u = F x, t = a'x */
+  /* residual maintenance: u = F x, t = A x */
   matvec_F(m, n, F, x, u);
-  double t = 0.0;
-  if (a) for (int64_t j = 0; j < n; ++j) t += a[j] * x[j];
+  for (int64_t e = 0; e < meq; ++e)
+    for (int64_t j = 0; j < n; ++j) t[e] += A[e * n + j] * x[j];
 
   int status = ORC_RUN_MAX_ITER;
   int rc = ORC_OK;
@@ -421,21 +460,31 @@ int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
   double rp_first = -1.0;
   for (k = 0; k < max_iter; ++k) {
     if (beta_mode == ORC_BETA_SCHEDULE) beta = beta_sched[k];
-    orc_permutation(seed, inst, (uint64_t)(iter0 + k), n, perm);
+    if (rp) orc_permutation(seed, inst, (uint64_t)(iter0 + k), p, order);   /* order of the fixed blocks */
+    else orc_permutation(seed, inst, (uint64_t)(iter0 + k), n, perm);       /* fresh partition */
     /* Gauss-Seidel over the blocks in drawn order */
     for (int64_t i = 0; i < p; ++i) {
-      int64_t s0 = orc_block_start(i, n, p), s = orc_block_start(i + 1, n, p) - s0;
-      const int32_t* B = perm + s0;
-      /* block matrix H_BB + beta (I + a_B a_B') with H = F'F/Ns + diag h (Assumption 2.1) */
+      int64_t s;
+      if (rp) {
+        int64_t s0 = orc_block_start(order[i], n, p);
+        s = orc_block_start(order[i] + 1, n, p) - s0;
+        for (int64_t q = 0; q < s; ++q) B[q] = s0 + q;
+      } else {
+        int64_t s0 = orc_block_start(i, n, p);
+        s = orc_block_start(i + 1, n, p) - s0;
+        for (int64_t q = 0; q < s; ++q) B[q] = perm[s0 + q];
+      }
+      /* block matrix H_BB + beta (I + A_B'A_B) with H = F'F/Ns + Hd + diag h (Assumption 2.1) */
       for (int64_t q = 0; q < s; ++q)
         for (int64_t r = 0; r < s; ++r) {
-          const double* fq = F + (int64_t)B[q] * m;
-          const double* fr = F + (int64_t)B[r] * m;
+          const double* fq = F + B[q] * m;
+          const double* fr = F + B[r] * m;
           double acc = 0.0;
           for (int64_t row = 0; row < m; ++row) acc += fq[row] * fr[row];
           double v = acc / Ns;
+          if (Hd) v += Hd[B[q] + B[r] * n];
           if (q == r) v += beta + (h ? h[B[q]] : 0.0);
-          if (a) v += beta * a[B[q]] * a[B[r]];
+          for (int64_t e = 0; e < meq; ++e) v += beta * A[e * n + B[q]] * A[e * n + B[r]];
           M[q + r * s] = v;
         }
       /* gradient of L with respect to x_B at the current point */
@@ -445,8 +494,9 @@ int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
         double acc = 0.0;
         for (int64_t row = 0; row < m; ++row) acc += fj[row] * u[row];
         double v = acc / Ns + c[j] - xi[j] + beta * (x[j] - z[j]);
+        if (Hd) v += dense_row_dot(n, Hd, j, x);
         if (h) v += h[j] * x[j];
-        if (a) v += -mu * a[j] + beta * a[j] * (t - b);
+        for (int64_t e = 0; e < meq; ++e) v += A[e * n + j] * (beta * (t[e] - beq[e]) - mu[e]);
         g[q] = v;
       }
       if (cholesky(s, M)) {
@@ -462,7 +512,7 @@ int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
         x[j] += d;
         const double* fj = F + j * m;
         for (int64_t row = 0; row < m; ++row) u[row] += fj[row] * d;
-        if (a) t += a[j] * d;
+        for (int64_t e = 0; e < meq; ++e) t[e] += A[e * n + j] * d;
       }
     }
     /* z block, then the dual step (Eq.(3) last line) */
@@ -478,22 +528,23 @@ int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
       double dz = z[j] - zprev[j];
       rd2 += dz * dz;
     }
-    if (a) {
-      mu -= beta * (t - b);
-      rp2 += (t - b) * (t - b);
+    for (int64_t e = 0; e < meq; ++e) {
+      double r = t[e] - beq[e];
+      mu[e] -= beta * r;
+      rp2 += r * r;
     }
-    double rp = sqrt(rp2), rd = beta * sqrt(rd2);
+    double r_p = sqrt(rp2), r_d = beta * sqrt(rd2);
     double kkt = NAN;
     int check = ((k + 1) % check_every == 0) || (k + 1 == max_iter);
-    if (hist) { hist[4 * k + 0] = rp; hist[4 * k + 1] = rd; hist[4 * k + 2] = beta; hist[4 * k + 3] = NAN; }
-    if (rp_first < 0.0) rp_first = rp;
-    if (!isfinite(rp) || !isfinite(rd) || (rp_first > 0.0 && rp > 1e12 * rp_first)) {
+    if (hist) { hist[4 * k + 0] = r_p; hist[4 * k + 1] = r_d; hist[4 * k + 2] = beta; hist[4 * k + 3] = NAN; }
+    if (rp_first < 0.0) rp_first = r_p;
+    if (!isfinite(r_p) || !isfinite(r_d) || (rp_first > 0.0 && r_p > 1e12 * rp_first)) {
       status = ORC_RUN_DIVERGED;
       ++k;
       goto done;
     }
     if (check) {
-      kkt = orc_kkt(n, m, F, Ns, h, c, a, b, prox, lam, alpha, lo, hi, x, z, xi, mu, NULL);
+      kkt = orc_kkt(n, m, F, Ns, Hd, h, c, meq, A, beq, prox, lam, alpha, lo, hi, x, z, xi, mu, NULL);
       if (hist) hist[4 * k + 3] = kkt;
       if (kkt <= tol) { status = ORC_RUN_CONVERGED; ++k; goto done; }
     }
@@ -501,15 +552,15 @@ int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
     if ((k + 1) % check_every == 0 && beta_mode != ORC_BETA_SCHEDULE && beta_mode != ORC_BETA_FIXED) {
       double mult = 1.0;
       double rb = 1.0;
-      if (rp > rb_mu * rd) rb = rb_tau;
-      else if (rd > rb_mu * rp) rb = 1.0 / rb_tau;
+      if (r_p > rb_mu * r_d) rb = rb_tau;
+      else if (r_d > rb_mu * r_p) rb = 1.0 / rb_tau;
       if (beta_mode == ORC_BETA_RESBAL) {
         mult = rb;
       } else { /* ORC_BETA_MLP; residual balancing is the fallback */
         int64_t k0 = k + 1 - check_every;
-        double rp_old = hist ? hist[4 * k0 + 0] : rp, rd_old = hist ? hist[4 * k0 + 1] : rd;
+        double rp_old = hist ? hist[4 * k0 + 0] : r_p, rd_old = hist ? hist[4 * k0 + 1] : r_d;
         double f[MLP_IN], h1[MLP_H], h2[MLP_H];
-        orc_controller_features(rp, rd, rp_old, rd_old, kkt, kkt_prev, last_l10, decisions, f);
+        orc_controller_features(r_p, r_d, rp_old, rd_old, kkt, kkt_prev, last_l10, decisions, f);
         double y = mlp_w ? mlp_forward1(mlp_w, mlp_ymax, f, h1, h2, NULL) : NAN;
         mult = isfinite(y) ? exp(y) : rb;
       }
@@ -520,10 +571,9 @@ int orc_solve(int64_t n, int64_t m, const double* F, double Ns, const double* h,
     if (check) kkt_prev = kkt;
   }
 done:
-  *mu_io = mu;
   if (iters_out) *iters_out = k;
   if (status_out) *status_out = status;
   if (beta_out) *beta_out = beta;
-  free(perm); free(u); free(M); free(g); free(zprev);
+  free(perm); free(order); free(B); free(u); free(t); free(M); free(g); free(zprev);
   return rc;
 }
