@@ -1,43 +1,44 @@
 """Benchmark of the RAC-MBADMM hot path on one MI355X.
 
-Workload (default): LASSO, D 20000 x 2000 iid N(0,1) with unit-norm columns,
-stored in FP32; x_true with 5% non-zeros of magnitude U(1,3); noise 0.05;
-lambda = 0.1 lambda_max; blocks of 64 variables (p = 32); synthetic data.
+Headline workload: the batched elastic-net regularisation paths, 256 independent
+instances of uneven size (N in [1000, 20000] and n in [100, 4000], log-uniform),
+Gaussian data stored in BF16, each solved at 16 points of a log lambda grid
+(alpha = 0.5, lambda_j = lambda_max 0.01^(j/15)): 4096 lanes, blocks of 64.
+Synthetic data, generated on the device with seeded generators.
 
-A "step" is one RAC-MBADMM iteration (partition draw, all block Grams and
-factors, the Gauss-Seidel sweep, z block, dual step, and every T = 10
-iterations the KKT check and the penalty decision) of the candidate solver:
-mixed precision (FP32 block Grams on the matrix cores, FP64 everything else)
-with the learned penalty controller when trained weights are present, else
-residual balancing.  `value` is iterations per second with the data already in
-HBM.  The line also reports, on the same data:
-  time_to_tol  -- wall time to the first KKT check <= 1e-6 for the candidate
-                  and for the plain FP64 fixed-beta solver (FP64 data, FP64
-                  Grams, beta = 0.1 lambda as in Sec.3.1),
-  roofline     -- the dominant kernel's achieved rate from HIP events recorded
-                  around every 8th launch inside the timed region,
-  cpu_baseline -- the FP64 oracle on a bounded sample of the same workload,
-  batched      -- the batched elastic-net paths (256 instances of uneven size,
-                  N in [1000, 20000] and n in [100, 4000] log-uniform, BF16
-                  data, 16 lambda lanes each): lane-iterations per second with
-                  every lane active, per-launch phase times with the roofline of
-                  the batched sweep, and the time until every lane reaches KKT
-                  <= 1e-6 for the candidate (mixed precision, learned penalty)
-                  and for the plain FP64 fixed-penalty batch on the same values,
-  hidim        -- the high-dimensional LASSO, D 10000 x 100000 Gaussian (BF16),
-                  1% non-zeros, lambda = 0.05 lambda_max, blocks of 128
-                  (p = 782): time to KKT <= 1e-6 for the candidate (mixed
-                  precision, learned penalty) and for the plain FP64
-                  fixed-penalty solver on the same values (FP64 copy of the
-                  data), the latter capped at --hidim-cap iterations.
+A "step" is one RAC-MBADMM iteration (Eq.(3)) of every lane of the batch: the
+instances' partition draws, the shared block Grams, the lanes' block inverses,
+the Gauss-Seidel sweeps, the z blocks and dual steps, and every T = 10
+iterations the KKT check and the penalty decision.  The candidate is the mixed
+precision solver (BF16 block Grams on the matrix cores, FP64 everything else)
+with the learned penalty controller, chunks of T iterations replayed from a
+hipGraph.  `value` is lane-iterations per second with every lane active and the
+data already in HBM.  The line also reports:
+  time_to_tol  -- wall time until every lane is at KKT <= 1e-6, for the
+                  candidate and for the plain FP64 fixed-penalty batch on the
+                  same stored values (beta = 0.1 lambda_j, Sec.3.1);
+  roofline     -- the batched sweep k_tsweep (FP64 matrix cores): its
+                  algorithmic flops over its average launch time, from HIP
+                  events around every launch of a timing run of the same length;
+  cpu_baseline -- the FP64 oracle on sampled lanes of the same workload, the
+                  lanes run in parallel threads (one lane per thread);
+  legs         -- the single-instance workloads: least squares 2000x200 (FP64),
+                  LASSO 20000x2000 (FP32), the linear SVM dual 20000x256 (FP32)
+                  and the high-dimensional LASSO 10000x100000 (BF16), each with
+                  its own throughput, sweep roofline and time to tolerance.
+A ratio between two solvers is "speedup" when both reached the tolerance,
+"speedup_at_least" when only the candidate did (the other stopped at its
+iteration cap), and absent when the candidate did not.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -48,12 +49,41 @@ if ROOT not in sys.path:
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 MFMA_PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
 METRIC = "time-to-1e-6 KKT residual & ADMM iters/s: learned-β batched vs plain FP64"
-TIMING_STRIDE = 8            # sweeps timed with HIP events in the throughput run: iterations k % 8 == 0
+TIMING_STRIDE = 8            # sweeps timed with HIP events in a throughput run: iterations k % 8 == 0
 WEIGHTS = os.path.join(ROOT, "paper_1907_01995_amd", "controller_weights.npy")
+T_CHECK = 10
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def ratio(cand, plain, key="seconds"):
+    """Speedup of cand over plain under the convergence rule stated above."""
+    if not cand.get("converged"):
+        return {"speedup_note": "candidate did not reach the tolerance: no ratio"}
+    r = plain[key] / cand[key]
+    return {"speedup": r} if plain.get("converged") else {"speedup_at_least": r}
+
+
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_threads():
+    """Worker threads for the oracle baseline: the host's share for one GPU (at most 16)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = int(env) if env and env.isdigit() else (os.cpu_count() or 1)
+    return max(1, min(16, n, os.cpu_count() or 1))
 
 
 def algorithmic(phase, N, n, p, bA):
@@ -85,9 +115,20 @@ def measured_traffic(kernel, workload):
     return rec["traffic_bytes_per_launch"]
 
 
-def batched_leg(args, racmb, W, torch, weights, log):
-    """Batched elastic-net paths: 256 uneven instances x 16 lambda lanes, BF16 data."""
-    t0 = time.time()
+def calibration_copy(torch):
+    """Plain 256 MiB device copies (counter calibration for rocprofv3 --pmc runs)."""
+    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+# ---------------------------------------------------------------------------
+# Headline: batched elastic-net paths
+
+def batched_workload(racmb, W, torch):
     Ns, ns = W.en_batch_sizes(256)
     insts = [W.en_instance_device(int(N), int(n), 1000 + i, storage="bf16") for i, (N, n) in enumerate(zip(Ns, ns))]
     probs = [racmb.regression_problem_tensor(d.F, d.y, lam=0.1 * d.lam_max, alpha=0.5, storage="bf16")
@@ -95,86 +136,323 @@ def batched_leg(args, racmb, W, torch, weights, log):
     lanes = [(i, racmb.PROX_EN, float(l), 0.5, 0.1 * float(l))
              for i, d in enumerate(insts) for l in W.lambda_grid(d.lam_max, 16, 0.01)]
     torch.cuda.synchronize()
+    return Ns, ns, insts, probs, lanes
+
+
+def batched_headline(args, racmb, W, torch, weights):
+    t0 = time.time()
+    Ns, ns, insts, probs, lanes = batched_workload(racmb, W, torch)
     elems = float(np.sum(Ns.astype(np.float64) * ns))
     log("batched workload generated in %.1fs (%d lanes, %.3e stored values)" % (time.time() - t0, len(lanes), elems))
     mode = racmb.BETA_MLP if weights is not None else racmb.BETA_RESBAL
-    cand = dict(s=64, seed=11, precision=racmb.PREC_MIXED, beta_mode=mode, mlp_weights=weights, check_every=10)
-    out = {"workload": "en_paths_256x16", "instances": 256, "lanes": len(lanes), "stored_values": elems,
-           "data_storage": "bf16", "block_size": 64, "alpha": 0.5, "lambda_grid": "lam_max * 0.01^(j/15), j<16",
-           "beta_mode": "mlp" if weights is not None else "residual_balancing"}
+    cand = dict(s=64, seed=11, precision=racmb.PREC_MIXED, beta_mode=mode, mlp_weights=weights,
+                check_every=T_CHECK)
+    cfg = {"workload": "en_paths_256x16", "instances": 256, "lanes": len(lanes), "stored_values": elems,
+           "N_range": [int(Ns.min()), int(Ns.max())], "n_range": [int(ns.min()), int(ns.max())],
+           "data_storage": "bf16", "block_size": 64, "alpha": 0.5,
+           "lambda_grid": "lam_max * 0.01^(j/15), j<16", "precision": "mixed (bf16 MFMA Gram, f64 rest)",
+           "beta_mode": "mlp" if weights is not None else "residual_balancing", "check_every": T_CHECK}
 
-    # ---- throughput: every lane active (tol 0), chunks replayed from the hipGraph
-    b = racmb.Batch(probs, lanes, max_iter=10, tol=0.0, use_graph=True, tune=True, **cand)
-    for _ in range(max(args.batched_warmup // 10, 1)):
+    # ---- throughput: every lane active (tol 0).  One batch object runs chunks of T
+    # iterations, each replayed from the hipGraph captured on its first run; the warm-up
+    # chunks (at least one) capture the graph and fill the tuning cache, and the timed
+    # region is the next ceil(K/T) chunks (K rounded up to whole chunks, reported as steps).
+    warm_chunks = max(1, -(-args.warmup // T_CHECK))
+    timed_chunks = max(1, -(-args.steps // T_CHECK))
+    b = racmb.Batch(probs, lanes, max_iter=T_CHECK, tol=0.0, use_graph=True, tune=True, **cand)
+    for _ in range(warm_chunks):
         b.run()
     torch.cuda.synchronize()
     a = time.perf_counter()
     k = 0
-    for _ in range(max(args.batched_steps // 10, 1)):
+    for _ in range(timed_chunks):
         k += b.run()[0]
     torch.cuda.synchronize()
     dt = time.perf_counter() - a
     info = b.info()
-    out.update({"iterations": k, "seconds": dt, "ms_per_iteration": 1e3 * dt / k,
-                "lane_iterations_per_s": len(lanes) * k / dt, "team_size": info["team_size"],
-                "teams": info["teams"], "graph": info["graph"]})
-    log("batched throughput: %d iterations in %.3fs -> %.2f ms/iteration, %.3e lane-iterations/s %s"
-        % (k, dt, 1e3 * dt / k, len(lanes) * k / dt, info))
-    # ---- per-launch device time (events around every launch) for the roofline
-    b.set_timing(True)
-    for _ in range(max(args.batched_steps // 20, 1)):
-        b.run()
-    ph = b.timing()
     b.close()
     del b
-    rows = {}
-    for name, (ms, cnt) in ph.items():
-        if cnt:
-            rows[name] = {"avg_us": 1e3 * ms / cnt, "launches": cnt}
+    warm_iters = warm_chunks * T_CHECK
+    log("batched throughput: %d iterations in %.3fs -> %.2f ms/iteration, %.3e lane-iterations/s %s"
+        % (k, dt, 1e3 * dt / k, len(lanes) * k / dt, info))
+    cfg.update({"team_size_max": info["team_size"], "teams": info["teams"], "graph": info["graph"]})
+
+    # ---- per-launch device time (events around every launch) of a run of the same length
+    bt = racmb.Batch(probs, lanes, max_iter=int(k), tol=0.0, use_graph=True, tune=True, **cand)
+    bt.set_timing(True)
+    bt.run()
+    ph = bt.timing()
+    bt.close()
+    del bt
+    rows = {name: {"avg_us": 1e3 * ms / cnt, "launches": cnt} for name, (ms, cnt) in ph.items() if cnt}
     sw = ph["sweep"]
     avg = sw[0] / sw[1] / 1e3
     flops = 4.0 * 16 * elems                       # F_B'u and F_B d, every lane, every block
     nbytes = 2.0 * elems + 16 * 8.0 * (2 * float(np.sum(Ns)) + 6 * float(np.sum(ns)))
+    kern = "k_tsweep" if info["team_size"] else "k_bsweep"
     roof = {"bound": "mfma", "achieved": flops / avg / 1e12, "peak": MFMA_PEAK["f64"] / 1e12,
-            "unit": "TFLOP/s", "kernel": "k_tsweep" if info["team_size"] else "k_bsweep",
-            "avg_launch_us": avg * 1e6, "flops_per_launch": flops, "hbm_bytes_per_launch": nbytes,
-            "hbm_GBps": nbytes / avg / 1e9, "traffic": None}
+            "unit": "TFLOP/s", "kernel": kern, "avg_launch_us": avg * 1e6, "flops_per_launch": flops,
+            "hbm_bytes_per_launch": nbytes, "hbm_GBps": nbytes / avg / 1e9,
+            "traffic": measured_traffic(kern, "en_paths_256x16")}
     roof["frac"] = roof["achieved"] / roof["peak"]
     rows["sweep"]["TFLOPs"] = roof["achieved"]
-    out["roofline"] = roof
-    out["phases"] = rows
     log("batched phases %s" % rows)
+
+    out = {"metric": METRIC, "value": len(lanes) * k / dt, "unit": "lane-iters/s", "n_gpus": 1,
+           "steps": int(k), "warmup": warm_iters, "ms_per_step": 1e3 * dt / k, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic", "config": cfg,
+           "roofline": roof, "phases": rows}
 
     # ---- time until every lane's KKT <= 1e-6: candidate vs plain FP64 fixed beta
     if not args.no_time_to_tol:
         tt = {}
-        plain = dict(s=64, seed=11, precision=racmb.PREC_FP64, beta_mode=racmb.BETA_FIXED, check_every=10)
-        for name, kw, cap in (("candidate", cand, args.batched_cap), ("plain_fp64_fixed_beta", plain, 3 * args.batched_cap)):
+        plain = dict(s=64, seed=11, precision=racmb.PREC_FP64, beta_mode=racmb.BETA_FIXED, check_every=T_CHECK)
+        got = {}
+        for name, kw, cap in (("candidate", cand, args.batched_cap),
+                              ("plain_fp64_fixed_beta", plain, args.batched_plain_cap)):
             bb = racmb.Batch(probs, lanes, max_iter=cap, tol=1e-6, use_graph=True, tune=True, **kw)
             torch.cuda.synchronize()
             a = time.perf_counter()
             it, act = bb.run()
             torch.cuda.synchronize()
             tt[name] = {"seconds": time.perf_counter() - a, "iterations": it, "lanes_converged": len(lanes) - act,
-                        "all_converged": act == 0, "iteration_cap": cap}
-            got = {u: bb.lane(u) for u in range(0, len(lanes), 97)}
-            if name == "candidate":
-                zc = got
-            else:
-                zp = got
+                        "converged": act == 0, "iteration_cap": cap}
+            got[name] = {u: bb.lane(u) for u in range(0, len(lanes), 97)}
             bb.close()
             del bb
             log("batched time-to-tol %s: %s" % (name, tt[name]))
-        tt["speedup"] = tt["plain_fp64_fixed_beta"]["seconds"] / tt["candidate"]["seconds"]
+        tt.update(ratio(tt["candidate"], tt["plain_fp64_fixed_beta"]))
+        zc, zp = got["candidate"], got["plain_fp64_fixed_beta"]
         both = [u for u in zc if zc[u][0].status == racmb.RUN_CONVERGED and zp[u][0].status == racmb.RUN_CONVERGED]
         tt["sampled_lanes_converged_in_both"] = len(both)
         tt["candidate_vs_plain_rel_z_sampled"] = float(max(
             (np.max(np.abs(zc[u][2] - zp[u][2])) / max(np.max(np.abs(zp[u][2])), 1e-300) for u in both), default=0.0))
         out["time_to_tol"] = tt
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batched_cpu_baseline(args, Ns, ns, insts, lanes)
+    del probs, insts
+    torch.cuda.empty_cache()
     return out
 
 
-def hidim_leg(args, racmb, W, torch, weights, log):
+def batched_cpu_baseline(args, Ns, ns, insts, lanes):
+    """The FP64 oracle on a stratified sample of the batch's lanes, one lane per thread.
+
+    The instances are ordered by stored values N_i n_i and every (256/S)-th is taken,
+    one lane (the middle lambda of its grid) each; every sampled lane runs
+    `cpu_iters` iterations from a cold start.  The rate is the sample's
+    lane-iterations per wall second, scaled by the ratio of the sample's mean
+    stored values per lane to the whole workload's (the oracle's cost per
+    iteration is proportional to N_i n_i for a fixed block size)."""
+    import oracle as O
+    sizes = Ns.astype(np.float64) * ns
+    order = np.argsort(sizes, kind="stable")
+    S = args.cpu_lanes
+    pick = [int(order[int((q + 0.5) * len(order) / S)]) for q in range(S)]
+    jobs = []
+    for i in pick:
+        u = 16 * i + 8
+        _, _, lam, alpha, beta0 = lanes[u]
+        D = insts[i].host_D()
+        jobs.append((O.en_problem(D, insts[i].y, lam=lam, alpha=alpha), beta0, i))
+    threads = cpu_threads()
+
+    def one(job):
+        P, beta0, inst = job
+        return O.solve(P, s=64, seed=11, inst=inst, beta0=beta0, beta_mode=O.BETA_FIXED, max_iter=args.cpu_iters,
+                       check_every=T_CHECK).iters
+
+    a = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        its = list(ex.map(one, jobs))
+    wall = time.perf_counter() - a
+    scale = float(np.mean(sizes[pick]) / np.mean(sizes))
+    model, nproc = cpu_info()
+    rate = sum(its) / wall * scale
+    log("cpu baseline: %d lanes x %d iterations in %.1fs on %d threads (size scale %.3f) -> %.3g lane-iters/s"
+        % (S, args.cpu_iters, wall, threads, scale, rate))
+    return {"value": rate, "unit": "lane-iters/s", "cores": threads, "kind": "oracle",
+            "sample": "%d lanes (one per instance, instances stratified by N_i n_i, middle lambda), %d iterations "
+                      "each from a cold start, FP64 oracle, one lane per thread; %.1f s wall; rate scaled by the "
+                      "sample's mean stored values per lane over the workload's (%.3f)"
+                      % (S, args.cpu_iters, wall, scale),
+            "host_nproc": nproc, "cpu_model": model}
+
+
+# ---------------------------------------------------------------------------
+# Single-instance legs
+
+def sweep_roofline(phases, N, n, p, bA, kernel, workload):
+    ms, cnt = phases["sweep"]
+    avg = ms / cnt / 1e3
+    by, _ = algorithmic("sweep", N, n, p, bA)
+    roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "kernel": kernel, "avg_launch_us": avg * 1e6, "bytes_per_launch": by,
+            "traffic": measured_traffic(kernel, workload)}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    return roof
+
+
+def phase_rows(phases, N, n, p, bA):
+    rows = {}
+    for ph, (ms, cnt) in phases.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt / 1e3
+        by, fl = algorithmic(ph, N, n, p, bA)
+        rows[ph] = dict(avg_us=avg * 1e6, launches=cnt, GBps=by / avg / 1e9, TFLOPs=fl / avg / 1e12)
+    return rows
+
+
+def throughput(racmb, torch, prob, iters, warmup, kw):
+    """Iterations per second over `iters` iterations (sweeps of every 8th iteration
+    timed with HIP events), and the phase table of a separate run of the same length."""
+    if warmup > 0:
+        w = racmb.Solver(prob, max_iter=warmup, tol=0.0, **kw)
+        w.run()
+        w.close()
+    sol = racmb.Solver(prob, max_iter=iters, tol=0.0, **kw)
+    sol.set_timing(True, phases=["sweep"], stride=TIMING_STRIDE)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    res = sol.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    sweep_t = sol.timing()["sweep"]
+    info = sol.info()
+    sol.close()
+    tim = racmb.Solver(prob, max_iter=iters, tol=0.0, **kw)
+    tim.set_timing(True)
+    tim.run()
+    phases = tim.timing()
+    tim.close()
+    phases["sweep"] = sweep_t
+    return res.iters / dt, 1e3 * dt / max(res.iters, 1), phases, info
+
+
+def time_to_tol(racmb, torch, prob, kw, reps=2):
+    best, st = None, None
+    for rep in range(reps):
+        so = racmb.Solver(prob, tol=1e-6, **kw)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = so.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - a
+        best = dt if best is None else min(best, dt)
+        if rep == reps - 1:
+            st = so.state()
+            rec = {"seconds": best, "iters": r.iters, "kkt": r.kkt, "converged": r.status == racmb.RUN_CONVERGED,
+                   "objective": r.objective, "iteration_cap": kw["max_iter"]}
+        so.close()
+    return rec, st
+
+
+def lasso_leg(args, racmb, W, torch, weights):
+    """LASSO 20000 x 2000 (FP32, blocks of 64): iterations/s, sweep roofline, time to KKT <= 1e-6."""
+    import oracle as O
+    w = W.lasso_20000x2000("f32")
+    N, n, s = w.N, w.n, w.block_size
+    p = -(-n // s)
+    prob32 = racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=1.0, storage="f32")
+    mode = racmb.BETA_MLP if weights is not None else racmb.BETA_RESBAL
+    kw = dict(s=s, precision=racmb.PREC_MIXED, beta0=w.beta0, beta_mode=mode, mlp_weights=weights,
+              check_every=T_CHECK)
+    ips, ms, phases, info = throughput(racmb, torch, prob32, args.single_steps, 20, kw)
+    if args.calibrate_copy:
+        calibration_copy(torch)
+    out = {"workload": "lasso_20000x2000", "N": N, "n": n, "block_size": s, "p": p, "data_storage": "f32",
+           "precision": "mixed (f32 MFMA Gram, f64 rest)", "beta_mode": "mlp" if weights is not None else
+           "residual_balancing", "iters_per_s": ips, "ms_per_iteration": ms, "sweep_groups": info["K"],
+           "roofline": sweep_roofline(phases, N, n, p, 4, "k_sweep2", "lasso_20000x2000"),
+           "phases": phase_rows(phases, N, n, p, 4)}
+    log("lasso_20000x2000: %.1f it/s, sweep %.1f us" % (ips, out["roofline"]["avg_launch_us"]))
+    if not args.no_time_to_tol:
+        prob64 = racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=1.0, storage="f64")
+        cand, stc = time_to_tol(racmb, torch, prob32, dict(kw, max_iter=5000))
+        plain, stp = time_to_tol(racmb, torch, prob64, dict(s=s, precision=racmb.PREC_FP64, beta0=w.beta0,
+                                                            beta_mode=racmb.BETA_FIXED, check_every=T_CHECK,
+                                                            max_iter=20000))
+        tt = {"candidate": cand, "plain_fp64_fixed_beta": plain}
+        tt.update(ratio(cand, plain))
+        tt["candidate_vs_plain_rel_z"] = float(np.max(np.abs(stc[1] - stp[1])) / np.max(np.abs(stp[1])))
+        op = O.en_problem(w.D.astype(np.float64), w.y, lam=w.lam, alpha=1.0)
+        tt["oracle_kkt_of_candidate_iterate"] = O.kkt(op, stc[0], stc[1], stc[2], stc[3])
+        tt["oracle_objective_of_candidate_z_vs_reported_rel"] = abs(O.objective(op, stc[1]) - cand["objective"]) / \
+            abs(O.objective(op, stc[1]))
+        out["time_to_tol"] = tt
+        log("lasso_20000x2000 time-to-tol %s" % tt)
+        del prob64
+    del prob32
+    return out
+
+
+def ols_leg(args, racmb, W, torch):
+    """Least squares 2000 x 200 (FP64, p = 10, beta = 1, 300 iterations, seed 0), against the
+    oracle's 300 iterations (one thread) and the normal equations."""
+    import oracle as O
+    w = W.ols_2000x200()
+    prob = racmb.regression_problem(w.D, w.y, storage="f64")
+    kw = dict(s=w.block_size, precision=racmb.PREC_FP64, beta0=1.0, beta_mode=racmb.BETA_FIXED,
+              check_every=T_CHECK, seed=0)
+    ips, ms, phases, info = throughput(racmb, torch, prob, 300, 10, kw)
+    so = racmb.Solver(prob, max_iter=300, tol=0.0, **kw)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    r = so.run()
+    torch.cuda.synchronize()
+    gpu_s = time.perf_counter() - a
+    z = so.state()[1]
+    so.close()
+    op = O.en_problem(w.D, w.y)
+    a = time.perf_counter()
+    ro = O.solve(op, s=w.block_size, seed=0, beta0=1.0, max_iter=300, check_every=T_CHECK)
+    cpu_s = time.perf_counter() - a
+    ls = np.linalg.lstsq(w.D, w.y, rcond=None)[0]
+    out = {"workload": "ols_2000x200", "N": 2000, "n": 200, "p": 10, "data_storage": "f64", "precision": "fp64",
+           "iters_per_s": ips, "ms_per_iteration": ms, "seconds_300_iterations": gpu_s, "kkt": r.kkt,
+           "roofline": sweep_roofline(phases, 2000, 200, 10, 8, "k_sweep2", "ols_2000x200"),
+           "oracle_seconds_300_iterations": cpu_s, "oracle_threads": 1,
+           "rel_z_vs_oracle": float(np.max(np.abs(z - ro.z)) / np.max(np.abs(ro.z))),
+           "rel_z_vs_normal_equations": float(np.max(np.abs(z - ls)) / np.max(np.abs(ls)))}
+    log("ols_2000x200: %s" % out)
+    return out
+
+
+def svm_leg(args, racmb, W, torch):
+    """Linear SVM dual 20000 x 256 (FP32, blocks of 128, beta = 0.1 p): iterations/s, sweep
+    roofline, and the KKT residual reached within a fixed iteration budget."""
+    import oracle as O
+    w = W.svm_20000x256()
+    n, r, s = w.n, w.r, w.block_size
+    p = -(-n // s)
+    prob = racmb.svm_problem(w.X, w.labels, w.C, storage="f32")
+    kw = dict(s=s, precision=racmb.PREC_MIXED, beta0=w.beta0, beta_mode=racmb.BETA_FIXED, check_every=T_CHECK)
+    ips, ms, phases, info = throughput(racmb, torch, prob, args.single_steps, 10, kw)
+    so = racmb.Solver(prob, max_iter=args.svm_budget, tol=1e-6, **kw)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    res = so.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - a
+    x, z, xi, mu, _, _ = so.state()
+    so.close()
+    op = O.svm_problem(w.X.astype(np.float64), w.labels, w.C)
+    out = {"workload": "svm_20000x256", "n": n, "r": r, "block_size": s, "p": p, "data_storage": "f32",
+           "precision": "mixed (f32 MFMA Gram, f64 rest)", "beta": w.beta0, "beta_mode": "fixed (0.1 p)",
+           "iters_per_s": ips, "ms_per_iteration": ms,
+           "roofline": sweep_roofline(phases, r, n, p, 4, "k_sweep2", "svm_20000x256"),
+           "phases": phase_rows(phases, r, n, p, 4),
+           "budget": {"iterations": res.iters, "seconds": dt, "kkt": res.kkt,
+                      "converged": res.status == racmb.RUN_CONVERGED, "objective": res.objective,
+                      "oracle_kkt_of_iterate": O.kkt(op, x, z, xi, mu),
+                      "oracle_objective_of_z": O.objective(op, z)}}
+    log("svm_20000x256: %s" % out)
+    return out
+
+
+def hidim_leg(args, racmb, W, torch, weights):
     """High-dimensional LASSO 10000 x 100000: time to KKT <= 1e-6, candidate vs plain FP64."""
     t0 = time.time()
     w = W.lasso_10000x100000("bf16")
@@ -191,7 +469,7 @@ def hidim_leg(args, racmb, W, torch, weights, log):
         D = w.D if storage == "bf16" else w.D.astype(np.float64)
         gp = racmb.regression_problem(D, w.y, lam=w.lam, alpha=1.0, storage=storage)
         del D
-        so = racmb.Solver(gp, s=s, beta0=w.beta0, check_every=10, tol=1e-6, **kw)
+        so = racmb.Solver(gp, s=s, beta0=w.beta0, check_every=T_CHECK, tol=1e-6, **kw)
         torch.cuda.synchronize()
         a = time.perf_counter()
         r = so.run()
@@ -204,24 +482,25 @@ def hidim_leg(args, racmb, W, torch, weights, log):
         del so, gp
         torch.cuda.empty_cache()
         log("hidim time-to-tol %s: %s" % (name, out[name]))
-    ratio = out["plain_fp64_fixed_beta"]["seconds"] / out["candidate"]["seconds"]
-    out["speedup" if out["plain_fp64_fixed_beta"]["converged"] else "speedup_at_least"] = ratio
+    out.update(ratio(out["candidate"], out["plain_fp64_fixed_beta"]))
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=40, help="timed iterations of the batched headline")
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=10)
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=40)
-    ap.add_argument("--batched-warmup", type=int, default=10)
+    ap.add_argument("--cpu-lanes", type=int, default=32, help="sampled lanes of the oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle iterations per sampled lane")
     ap.add_argument("--batched-cap", type=int, default=500)
-    ap.add_argument("--no-hidim", action="store_true")
+    ap.add_argument("--batched-plain-cap", type=int, default=1500)
+    ap.add_argument("--single-steps", type=int, default=200, help="timed iterations of each single-instance leg")
+    ap.add_argument("--svm-budget", type=int, default=1000)
+    ap.add_argument("--no-legs", action="store_true", help="headline only")
+    ap.add_argument("--legs", default="ols,lasso,svm,hidim")
     ap.add_argument("--hidim-cap", type=int, default=1500,
                     help="iteration cap of the plain FP64 solver in the high-dimensional leg")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -237,140 +516,25 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    t_gen = time.time()
-    w = W.lasso_20000x2000("f32")
-    log("workload generated in %.1fs" % (time.time() - t_gen))
-    N, n, s = w.N, w.n, w.block_size
-    p = -(-n // s)
-
-    prob32 = racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=1.0, storage="f32")
     weights = None
-    beta_mode = racmb.BETA_RESBAL
     if os.path.exists(WEIGHTS):
         weights = torch.as_tensor(np.load(WEIGHTS).astype(np.float32), device="cuda")
-        beta_mode = racmb.BETA_MLP
-    cand_kw = dict(s=s, precision=racmb.PREC_MIXED, beta0=w.beta0, beta_mode=beta_mode,
-                   mlp_weights=weights, check_every=10)
 
-    # ---- throughput: K timed iterations after W warm-up iterations ----------
-    sol = racmb.Solver(prob32, max_iter=args.steps, tol=0.0, **cand_kw)
-    warm = racmb.Solver(prob32, max_iter=max(args.warmup, 1), tol=0.0, **cand_kw)
-    if args.warmup > 0:
-        warm.run()
-    warm.close()
-    # HIP events around the sweep launches (the dominant kernel) of every 8th
-    # iteration only: the average launch time comes from the timed run itself,
-    # and 25 event pairs disturb it far less than events around every launch
-    sol.set_timing(True, phases=["sweep"], stride=TIMING_STRIDE)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = sol.run()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    sweep_t = sol.timing()["sweep"]
-    info = sol.info()
-    ips = res.iters / elapsed
+    out = batched_headline(args, racmb, W, torch, weights)
     if args.calibrate_copy:
-        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    # every phase, timed in a separate run of the same length
-    tim = racmb.Solver(prob32, max_iter=args.steps, tol=0.0, **cand_kw)
-    tim.set_timing(True)
-    tim.run()
-    phases = tim.timing()
-    tim.close()
-    phases["sweep"] = sweep_t
-    log("throughput: %d iterations in %.4fs -> %.1f it/s; phases %s" % (res.iters, elapsed, ips, phases))
-
-    # ---- roofline of the dominant kernel --------------------------------------
-    dom = "sweep"
-    rows = {}
-    for ph, (ms, cnt) in phases.items():
-        if cnt == 0:
-            continue
-        avg = ms / cnt / 1e3
-        by, fl = algorithmic(ph, N, n, p, 4)
-        rows[ph] = dict(avg_us=avg * 1e6, launches=cnt, GBps=by / avg / 1e9, TFLOPs=fl / avg / 1e12)
-    by, fl = algorithmic(dom, N, n, p, 4)
-    avg = phases[dom][0] / phases[dom][1] / 1e3
-    t_hbm, t_mfma = by / HBM_PEAK, fl / MFMA_PEAK["f32"]
-    if dom == "gram" and t_mfma > t_hbm:
-        roof = {"bound": "mfma", "achieved": fl / avg / 1e12, "peak": MFMA_PEAK["f32"] / 1e12,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic("k_sweep2", "lasso_20000x2000")
-    roof["kernel"] = {"sweep": "k_sweep2", "gram": "k_gram", "factor": "k_factor_wave",
-                      "zdual": "k_zdual", "check": "k_kkt+k_control", "partition": "k_perm_*"}[dom]
-    roof["avg_launch_us"] = avg * 1e6
-
-    out = {"metric": METRIC, "value": ips, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / max(res.iters, 1),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-           "data": "synthetic",
-           "config": {"workload": "lasso_20000x2000", "N": N, "n": n, "block_size": s, "p": p,
-                      "data_storage": "f32", "precision": "mixed (f32 MFMA Gram, f64 rest)",
-                      "beta_mode": "mlp" if weights is not None else "residual_balancing",
-                      "check_every": 10, "sweep_groups": info["K"], "gram_row_chunks": info["R"]},
-           "roofline": roof, "phases": rows}
-
-    # ---- time to KKT <= 1e-6: candidate vs plain FP64 fixed beta ----------------
-    if not args.no_time_to_tol:
-        tt = {}
-        prob64 = racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=1.0, storage="f64")
-        cfgs = {"candidate": (prob32, dict(cand_kw, max_iter=5000)),
-                "plain_fp64_fixed_beta": (prob64, dict(s=s, precision=racmb.PREC_FP64, beta0=w.beta0,
-                                                       beta_mode=racmb.BETA_FIXED, check_every=10,
-                                                       max_iter=20000))}
-        sols = {}
-        for name, (pr, kw) in cfgs.items():
-            times = []
-            for rep in range(2):
-                so = racmb.Solver(pr, tol=1e-6, **kw)
-                torch.cuda.synchronize()
-                a = time.perf_counter()
-                r = so.run()
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - a)
-                if rep == 1:
-                    sols[name] = so.state()
-                    tt[name] = {"seconds": min(times), "iters": r.iters, "kkt": r.kkt,
-                                "converged": r.status == racmb.RUN_CONVERGED, "objective": r.objective}
-                so.close()
-            log("time-to-tol %s: %s" % (name, tt[name]))
-        zc, zp = sols["candidate"][1], sols["plain_fp64_fixed_beta"][1]
-        tt["speedup"] = tt["plain_fp64_fixed_beta"]["seconds"] / tt["candidate"]["seconds"]
-        tt["candidate_vs_plain_rel_z"] = float(np.max(np.abs(zc - zp)) / np.max(np.abs(zp)))
-        out["time_to_tol"] = tt
-        del prob64
-
-    # ---- CPU baseline: the FP64 oracle on a bounded sample ----------------------
-    if not args.no_cpu_baseline:
-        import oracle as O
-        op = O.en_problem(w.D.astype(np.float64), w.y, lam=w.lam, alpha=1.0)
-        k = args.cpu_iters
-        a = time.perf_counter()
-        ro = O.solve(op, s=s, beta0=w.beta0, beta_mode=O.BETA_RESBAL, max_iter=k, check_every=10)
-        dt = time.perf_counter() - a
-        out["cpu_baseline"] = {"value": ro.iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d iterations of lasso_20000x2000 (FP64 oracle, one thread, "
-                                         "%.1f s)" % (ro.iters, dt)}
-        if "time_to_tol" in out:
-            xc = sols["candidate"]
-            out["time_to_tol"]["oracle_kkt_of_candidate"] = O.kkt(op, xc[0], xc[1], xc[2], xc[3])
-            out["time_to_tol"]["oracle_objective_rel_err"] = abs(
-                O.objective(op, xc[1]) - out["time_to_tol"]["candidate"]["objective"]) / abs(
-                O.objective(op, xc[1]))
-    if not args.no_batched:
-        out["batched"] = batched_leg(args, racmb, W, torch, weights, log)
-    if not args.no_hidim and not args.no_time_to_tol:
-        out["hidim"] = hidim_leg(args, racmb, W, torch, weights, log)
+        calibration_copy(torch)
+    legs = {}
+    want = set() if args.no_legs else set(args.legs.split(","))
+    if "ols" in want:
+        legs["ols_2000x200"] = ols_leg(args, racmb, W, torch)
+    if "lasso" in want:
+        legs["lasso_20000x2000"] = lasso_leg(args, racmb, W, torch, weights)
+    if "svm" in want:
+        legs["svm_20000x256"] = svm_leg(args, racmb, W, torch)
+    if "hidim" in want and not args.no_time_to_tol:
+        legs["lasso_10000x100000"] = hidim_leg(args, racmb, W, torch, weights)
+    if legs:
+        out["legs"] = legs
     print(json.dumps(out), flush=True)
 
 
