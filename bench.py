@@ -25,7 +25,9 @@ data already in HBM.  The line also reports:
   legs         -- the single-instance workloads: least squares 2000x200 (FP64),
                   LASSO 20000x2000 (FP32), the linear SVM dual 20000x256 (FP32)
                   and the high-dimensional LASSO 10000x100000 (BF16), each with
-                  its own throughput, sweep roofline and time to tolerance.
+                  its own throughput, sweep roofline and time to tolerance; the
+                  two LASSO legs also time RP-MBADMM (fixed blocks, random
+                  order; Sec.1) to the same tolerance.
 A ratio between two solvers is "speedup" when both reached the tolerance,
 "speedup_at_least" when only the candidate did (the other stopped at its
 iteration cap), and absent when the candidate did not.
@@ -374,8 +376,10 @@ def lasso_leg(args, racmb, W, torch, weights):
         plain, stp = time_to_tol(racmb, torch, prob64, dict(s=s, precision=racmb.PREC_FP64, beta0=w.beta0,
                                                             beta_mode=racmb.BETA_FIXED, check_every=T_CHECK,
                                                             max_iter=20000))
-        tt = {"candidate": cand, "plain_fp64_fixed_beta": plain}
+        rp, _ = time_to_tol(racmb, torch, prob32, dict(kw, max_iter=5000, variant=racmb.VARIANT_RP))
+        tt = {"candidate": cand, "plain_fp64_fixed_beta": plain, "rp_candidate": rp}
         tt.update(ratio(cand, plain))
+        tt["rac_over_rp"] = ratio(cand, rp)
         tt["candidate_vs_plain_rel_z"] = float(np.max(np.abs(stc[1] - stp[1])) / np.max(np.abs(stp[1])))
         op = O.en_problem(w.D.astype(np.float64), w.y, lam=w.lam, alpha=1.0)
         tt["oracle_kkt_of_candidate_iterate"] = O.kkt(op, stc[0], stc[1], stc[2], stc[3])
@@ -463,6 +467,8 @@ def hidim_leg(args, racmb, W, torch, weights):
     mode = racmb.BETA_MLP if weights is not None else racmb.BETA_RESBAL
     runs = (("candidate", "bf16", dict(precision=racmb.PREC_MIXED, beta_mode=mode, mlp_weights=weights,
                                         max_iter=5000)),
+            ("rp_candidate", "bf16", dict(precision=racmb.PREC_MIXED, beta_mode=mode, mlp_weights=weights,
+                                          max_iter=5000, variant=racmb.VARIANT_RP)),
             ("plain_fp64_fixed_beta", "f64", dict(precision=racmb.PREC_FP64, beta_mode=racmb.BETA_FIXED,
                                                   max_iter=args.hidim_cap)))
     for name, storage, kw in runs:
@@ -483,6 +489,7 @@ def hidim_leg(args, racmb, W, torch, weights):
         torch.cuda.empty_cache()
         log("hidim time-to-tol %s: %s" % (name, out[name]))
     out.update(ratio(out["candidate"], out["plain_fp64_fixed_beta"]))
+    out["rac_over_rp"] = ratio(out["candidate"], out["rp_candidate"])
     return out
 
 

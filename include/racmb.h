@@ -71,6 +71,15 @@ typedef enum { RAC_PREC_FP64 = 0, RAC_PREC_MIXED = 1 } rac_precision;
  * divide when r_d > mu_rb r_p); the controller network (falls back to residual
  * balancing when its output is not finite); or a given per-iteration schedule. */
 typedef enum { RAC_BETA_FIXED = 0, RAC_BETA_RESBAL = 1, RAC_BETA_MLP = 2, RAC_BETA_SCHEDULE = 3 } rac_beta_mode;
+/* Which multi-block ADMM (Sec.1).  RAC: a fresh random partition of the variables every
+ * iteration (RAC-MBADMM, Eq.(3)).  RP: the randomly permuted variant the paper compares
+ * against -- the partition is fixed (block i = variables floor(i n/p) .. floor((i+1) n/p) - 1,
+ * a predetermined contiguous split) and only the order in which the p blocks are solved is
+ * drawn at random every iteration: the order of iteration k is the permutation of the p block
+ * indices given by rac_permutation(seed, instance, k, p).  The block matrices of a fixed
+ * partition change only with beta, so RP forms the block Grams once per solver and refactors
+ * the blocks only when beta has changed (the saving the paper measures in Tables 1-3). */
+typedef enum { RAC_VARIANT_RAC = 0, RAC_VARIANT_RP = 1 } rac_variant;
 
 typedef struct {
   int64_t n;            /* number of variables (>= 1) */
@@ -113,6 +122,8 @@ typedef struct {
                            each iteration's blocks into the sweep's register order (two copies of
                            about F's size, by iteration parity); negative: the sweep gathers the
                            block columns from F. */
+  int32_t variant;      /* rac_variant: RAC_VARIANT_RAC (0, default) or RAC_VARIANT_RP */
+  int32_t pad0;
 } rac_opts;
 
 typedef struct {
@@ -143,6 +154,15 @@ rac_status rac_solver_destroy(rac_solver s);
  * (the state is then not usable; the limit can be lowered for tests through the
  * environment variable RACMB_SWEEP_MAX_SPIN, read at rac_solver_create). */
 rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res);
+
+/* One call: solve `prob` with `opts` from the cold start x = z = xi = 0, mu = 0 (Eq.(3)
+ * iterated until the first KKT check <= opts.tol or opts.max_iter iterations), on `stream`.
+ * Creates a solver, runs it, copies the final x, z, xi (device, n doubles each; any may be
+ * NULL) and mu (host, may be NULL), and destroys the solver.  *res (host) as for
+ * rac_solver_run.  Errors as rac_solver_create / rac_solver_run; with RAC_ERR_NOT_PD the
+ * state at the failure is still written. */
+rac_status rac_solve(const rac_problem* prob, const rac_opts* opts, void* stream, double* x, double* z,
+                     double* xi, double* mu, rac_result* res);
 
 /* Copy the state in or out (device pointers, n doubles each; mu on the host).
  * Setting the state recomputes the maintained residuals u = Fx and t = a'x. */
@@ -202,6 +222,11 @@ rac_status rac_state_import(rac_solver s, const void* buf, size_t bytes);
  * holds perm[floor(i n/p) .. floor((i+1) n/p)).  Bit-identical to the oracle. */
 rac_status rac_permutation(uint64_t seed, uint64_t instance, int64_t iter, int64_t n,
                            int32_t* perm, void* stream);
+
+/* Host form of rac_permutation: the same permutation, bit for bit, computed on the CPU
+ * into perm (host, n int32).  No HIP call.  RAC_ERR_ARG for n < 1, n > INT32_MAX, iter < 0
+ * or perm == NULL. */
+rac_status rac_permutation_host(uint64_t seed, uint64_t instance, int64_t iter, int64_t n, int32_t* perm);
 
 /* KKT residual of the split problem at (x, z, xi, mu) (device vectors, n each):
  * out[0] = max of the three parts, out[1] = primal feasibility, out[2] =
@@ -302,6 +327,26 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
  * any may be NULL).  res->status is the lane's rac_run_status (RAC_ERR_NOT_PD is
  * returned when one of its blocks violated Assumption 2.1). */
 rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x, double* z, double* xi);
+/* Serialise / restore the state of every lane (x, z, xi, the previous z, u = F x, the
+ * lanes' penalties, multipliers, controller memory and status) and the iteration counter to /
+ * from a host buffer, for checkpoint/resume of a batch: a batch created with the same
+ * instances, lanes and options that imports the buffer continues bit for bit as the exporting
+ * batch would.  With buf == NULL, *bytes receives the size needed.  RAC_ERR_ARG for a buffer
+ * that is too small or was written by a batch of another shape. */
+rac_status rac_batch_state_export(rac_batch b, void* buf, size_t* bytes);
+rac_status rac_batch_state_import(rac_batch b, const void* buf, size_t bytes);
+
+/* One call: create a batch of ninst instances and nlanes lanes with opts, run it until every
+ * lane has retired or opts.max_iter iterations, write each lane's result to res[u] (host,
+ * nlanes) and its final x, z, xi to the device arrays x, z, xi (any may be NULL), which hold
+ * the lanes' vectors one after another in lane order (lane u at offset sum_{v<u} n of lane v's
+ * instance), and destroy the batch.  Returns RAC_ERR_NOT_PD when a lane retired on a failure
+ * of Assumption 2.1 (its res entry names the iteration and block; the other lanes' results are
+ * still written), else the errors of rac_batch_create / rac_batch_run. */
+rac_status rac_solve_batch(int32_t ninst, const rac_problem* inst, int32_t nlanes, const rac_lane* lanes,
+                           const rac_batch_opts* opts, void* stream, double* x, double* z, double* xi,
+                           rac_result* res);
+
 /* info (host, 8 int64): lanes, instances, block Gram tasks, inverse tasks, row
  * unroll of the LANE sweep, 1 if chunks are replayed from a hipGraph, workgroups of
  * the widest team of the TEAM sweep (0 when the LANE sweep runs), number of teams. */

@@ -289,6 +289,15 @@ __global__ void __launch_bounds__(256) k_bgram(const BInst* __restrict__ inst, c
                          0, 1, I.vec, G + (I.goff + tk.y) * (int64_t)SP * SP);
 }
 
+// Position of block blk in the solve order of an RP iteration (the failure report
+// names the position, as for a drawn partition); without an order, blk itself.
+__device__ __forceinline__ int64_t order_position(const int32_t* order, int64_t p, int64_t blk) {
+  if (!order) return blk;
+  for (int64_t i = 0; i < p; ++i)
+    if (order[i] == blk) return i;
+  return blk;
+}
+
 // Sum the partial Grams, add the diagonal and penalty terms, then invert the
 // block matrix by Gauss-Jordan elimination without pivoting.  For a symmetric
 // positive definite matrix the k-th pivot is the k-th diagonal entry of the
@@ -306,7 +315,7 @@ __global__ void __launch_bounds__(256) k_factor(const double* __restrict__ parti
                                                 const double* __restrict__ h, const double* __restrict__ a,
                                                 const double* beta_ptr, double beta_val,
                                                 double* __restrict__ out, int write_matrix, DevScalars* sc,
-                                                int64_t iter_global) {
+                                                int64_t iter_global, const int32_t* __restrict__ order) {
   constexpr int NA = SP / 16;
   __shared__ double rowk[2][SP];
   __shared__ double colk[2][SP];
@@ -391,7 +400,7 @@ __global__ void __launch_bounds__(256) k_factor(const double* __restrict__ parti
     const double piv = rowk[buf][k];           // the same value in every thread
     if (!(piv > 0.0) || !isfinite(piv)) {
       if (tid == 0 && sc) {
-        unsigned long long key = ((unsigned long long)iter_global << 32) | (unsigned)blk;
+        unsigned long long key = ((unsigned long long)iter_global << 32) | (unsigned)order_position(order, p, blk);
         atomicMin((unsigned long long*)&sc->fail_key, key);
       }
       failed = true;
@@ -463,7 +472,7 @@ __global__ void __launch_bounds__(64) k_factor_wave(const double* __restrict__ p
                                                     const double* __restrict__ h, const double* __restrict__ a,
                                                     const double* beta_ptr, double beta_val,
                                                     double* __restrict__ out, DevScalars* sc,
-                                                    int64_t iter_global) {
+                                                    int64_t iter_global, const int32_t* __restrict__ order) {
   static_assert(SP <= 64, "one lane per column");
   constexpr int HALF = SP > 32 ? SP / 2 : SP;
   __shared__ double buf[2 * SP];
@@ -517,7 +526,7 @@ __global__ void __launch_bounds__(64) k_factor_wave(const double* __restrict__ p
     if (!(d > 0.0) || !isfinite(d)) {
       failed = true;
       if (j == 0 && sc) {
-        const unsigned long long key = ((unsigned long long)iter_global << 32) | (unsigned)blk;
+        const unsigned long long key = ((unsigned long long)iter_global << 32) | (unsigned)order_position(order, p, blk);
         atomicMin((unsigned long long*)&sc->fail_key, key);
       }
       break;
@@ -589,7 +598,7 @@ hipError_t launch_factor(const FactorArgs& f, hipStream_t st) {
     if (f.sp == SPV) {                                                                                   \
       k_factor_wave<SPV><<<(unsigned)f.p, 64, 0, st>>>(f.partial, f.R, f.n, f.p, f.perm, f.Ns, f.h, f.a,  \
                                                        f.beta_ptr, f.beta_val, f.Minv, f.sc,           \
-                                                       f.iter_global);                                 \
+                                                       f.iter_global, f.order);                        \
       return hipGetLastError();                                                                        \
     }
     RAC_FACTORW(16) RAC_FACTORW(32) RAC_FACTORW(64)
@@ -599,7 +608,7 @@ hipError_t launch_factor(const FactorArgs& f, hipStream_t st) {
   if (f.sp == SPV) {                                                                                 \
     k_factor<SPV><<<(unsigned)f.p, 256, 0, st>>>(f.partial, f.R, f.n, f.p, f.perm, f.Ns, f.h, f.a,     \
                                                   f.beta_ptr, f.beta_val, f.Minv, f.write_matrix, f.sc, \
-                                                  f.iter_global);                                       \
+                                                  f.iter_global, f.order);                              \
     return hipGetLastError();                                                                        \
   }
   RAC_FACTOR(16) RAC_FACTOR(32) RAC_FACTOR(64) RAC_FACTOR(128)

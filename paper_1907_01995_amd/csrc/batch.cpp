@@ -188,13 +188,19 @@ struct Snapshot {
   std::vector<char> bytes;
 };
 
-rac_status state_copy(rac_batch b, bool save, Snapshot& s) {
+// Bytes of the lane state: x, z, xi, z_prev and u of every lane, the lanes' device
+// scalars, the iteration counter and the activity flags.
+size_t state_bytes(const rac_batch b) {
   int64_t xs = 0, us = 0;
   for (const BUnit& u : b->hunit) { xs += u.n; us += u.rows; }
-  const size_t sz = sizeof(double) * (4 * xs + us) + sizeof(DevScalars) * b->nunits + sizeof(int64_t) +
-                    sizeof(int32_t) * (b->ninst + 1);
-  if (save) s.bytes.resize(sz);
-  char* p = s.bytes.data();
+  return sizeof(double) * (4 * xs + us) + sizeof(DevScalars) * b->nunits + sizeof(int64_t) +
+         sizeof(int32_t) * (b->ninst + 1);
+}
+
+// Copies the lane state to (save) or from host memory p (state_bytes(b) bytes).
+rac_status state_xfer(rac_batch b, bool save, char* p) {
+  int64_t xs = 0, us = 0;
+  for (const BUnit& u : b->hunit) { xs += u.n; us += u.rows; }
   auto mv = [&](void* dev, size_t n) -> hipError_t {
     hipError_t e = save ? hipMemcpy(p, dev, n, hipMemcpyDeviceToHost) : hipMemcpy(dev, p, n, hipMemcpyHostToDevice);
     p += n;
@@ -211,6 +217,19 @@ rac_status state_copy(rac_batch b, bool save, Snapshot& s) {
   BCHK(mv(b->A.nactive, sizeof(int32_t)));
   return RAC_OK;
 }
+
+rac_status state_copy(rac_batch b, bool save, Snapshot& s) {
+  if (save) s.bytes.resize(state_bytes(b));
+  return state_xfer(b, save, s.bytes.data());
+}
+
+struct BatchStateHeader {
+  uint64_t magic;
+  int64_t nunits, ninst, state_bytes;
+  int64_t k;                // iterations run by the batch
+  int64_t scalars_bytes;
+};
+constexpr uint64_t kBatchStateMagic = 0x5241434241544348ULL;   // "RACBATCH"
 
 // Longest-processing-time assignment of the groups of one team width to k teams;
 // returns the largest team load and fills lists.
@@ -751,6 +770,40 @@ rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x,
     res->fail_block = h.fail_key == ~0ULL ? -1 : (int64_t)(h.fail_key & 0xffffffffULL);
   }
   return h.fail_key == ~0ULL ? RAC_OK : RAC_ERR_NOT_PD;
+}
+
+rac_status rac_batch_state_export(rac_batch b, void* buf, size_t* bytes) {
+  if (!b || !bytes) return RAC_ERR_ARG;
+  const size_t need = sizeof(BatchStateHeader) + state_bytes(b);
+  if (!buf) {
+    *bytes = need;
+    return RAC_OK;
+  }
+  if (*bytes < need) return RAC_ERR_ARG;
+  BCHK(hipStreamSynchronize(b->cs));
+  BatchStateHeader h{kBatchStateMagic, b->nunits, b->ninst, (int64_t)state_bytes(b), b->k,
+                     (int64_t)sizeof(DevScalars)};
+  std::memcpy(buf, &h, sizeof(h));
+  const rac_status r = state_xfer(b, true, (char*)buf + sizeof(h));
+  if (r != RAC_OK) return r;
+  *bytes = need;
+  return RAC_OK;
+}
+
+rac_status rac_batch_state_import(rac_batch b, const void* buf, size_t bytes) {
+  if (!b || !buf || bytes < sizeof(BatchStateHeader)) return RAC_ERR_ARG;
+  BatchStateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kBatchStateMagic || h.nunits != b->nunits || h.ninst != b->ninst ||
+      h.state_bytes != (int64_t)state_bytes(b) || h.scalars_bytes != (int64_t)sizeof(DevScalars) ||
+      bytes < sizeof(h) + (size_t)h.state_bytes)
+    return RAC_ERR_ARG;
+  BCHK(hipStreamSynchronize(b->cs));
+  const rac_status r = state_xfer(b, false, const_cast<char*>((const char*)buf) + sizeof(h));
+  if (r != RAC_OK) return r;
+  b->k = h.k;
+  BCHK(hipMemcpy(&b->host_active, b->A.nactive, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return RAC_OK;
 }
 
 rac_status rac_batch_info(rac_batch b, int64_t* info) {

@@ -186,6 +186,8 @@ struct FactorArgs {
   int write_matrix;        //  themselves when write_matrix != 0)
   DevScalars* sc;          // failure reporting (may be null)
   int64_t iter_global;
+  const int32_t* order;    // RP: solve order of iteration iter_global (a failure is reported at the
+                           // failing block's position in it); null: blocks are positions already
 };
 hipError_t launch_factor(const FactorArgs& a, hipStream_t st);
 
@@ -204,6 +206,8 @@ struct SweepArgs {
   int cooperative;         // launch with the cooperative API (else a plain launch, K <= resident limit)
   const void* Fp;          // packed tiles of this iteration written by the Gram kernel, or null (gather from F)
   int max_spin;            // polls before a sweep group gives up waiting (negative: the default)
+  const int32_t* order;    // RP: block solved at position i is order[i] (its inverse and packed tiles
+                           // are stored at that index); null: position i is block i
 };
 // Rows per sweep group for K groups and A rows per lane (0 if 64A rows do not cover a group).
 int64_t sweep_rows_per_group(int64_t rows, int K, int A);

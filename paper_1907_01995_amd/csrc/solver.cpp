@@ -197,6 +197,15 @@ struct rac_solver_s {
   hipEvent_t ev_check = nullptr;   // scalars of a chunk copied out: the next chunk's factor may run
   int64_t swept[2] = {-1, -1};     // iteration of the last sweep recorded in ev_sweep[parity] this run
   int64_t pre_k = -1;              // iteration whose partition, Gram and factor are already enqueued
+  // RP-MBADMM (fixed contiguous blocks, random order): the block Grams and the packed copy
+  // are formed once, the inverses whenever beta differs from the one they were formed with
+  bool rp = false;
+  int32_t* order = nullptr;        // solve orders of a chunk's iterations, [T][p]
+  PermWork pw_order{};
+  int32_t* iota = nullptr;         // the fixed partition: variable j at position j
+  bool rp_gram = false;            // Grams (and packed copy) formed
+  double fac_beta = NAN;           // beta of the current inverses (NaN: none)
+  std::vector<double> sched_host;  // the given schedule (RP decides refactoring on the host)
   DevScalars* hsc_pin = nullptr;   // pinned copy of the scalars read after each chunk
   DevScalars hsc{};
   // optional per-phase timing with HIP events on the run's stream
@@ -342,7 +351,68 @@ rac_status preissue_next_chunk(rac_solver s, int64_t k1, int64_t Tn, int64_t run
   return RAC_OK;
 }
 
+rac_status enqueue_check(rac_solver s, int64_t k0, int64_t Tc, int64_t run_offset, hipStream_t st, PhaseTimer& tm);
+
+// RP-MBADMM chunk (one stream): the orders of the chunk's iterations, then per
+// iteration the factor when beta has changed (the Grams once per solver), the
+// sweep in the drawn order, and the z/dual step.  Within a chunk beta changes
+// only under a given schedule; the controller changes it at the check, after
+// which the host reads it with the scalars.
+rac_status enqueue_rp_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
+  const rac_problem& P = s->P;
+  PhaseTimer tm{s, st};
+  const int64_t k0 = s->hsc.k;
+  const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
+  tm.k = -1;
+  HIPCHK(tm.begin(RAC_PHASE_PARTITION));
+  HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->p, s->pw_order, s->order, st));
+  HIPCHK(tm.end(RAC_PHASE_PARTITION));
+  for (int64_t t = 0; t < Tc; ++t) {
+    const int64_t k = k0 + t;
+    const int32_t* ord = s->order + t * s->p;
+    const double* beta_ptr = beta_of(s, run_offset + t);
+    tm.k = k;
+    if (!s->rp_gram) {
+      GramArgs g{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, s->iota, s->O.precision, s->R, s->sp,
+                 s->partial, PackDst{s->Fp, s->packRW, s->K, s->tileA, s->tileB}};
+      HIPCHK(tm.begin(st, RAC_PHASE_GRAM));
+      HIPCHK(launch_gram(g, st));
+      HIPCHK(tm.end(RAC_PHASE_GRAM));
+      s->rp_gram = true;
+      s->fac_beta = NAN;
+    }
+    const double bk = sched ? s->sched_host[run_offset + t] : s->hsc.beta;
+    if (!(bk == s->fac_beta)) {
+      FactorArgs f{};
+      f.partial = s->partial; f.R = s->R; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = s->iota;
+      f.Ns = P.Ns; f.h = P.h; f.a = P.a; f.beta_ptr = beta_ptr; f.beta_val = 0.0; f.Minv = s->Minv;
+      f.write_matrix = 0; f.sc = s->sc; f.iter_global = k; f.order = ord;
+      HIPCHK(tm.begin(st, RAC_PHASE_FACTOR));
+      HIPCHK(launch_factor(f, st));
+      HIPCHK(tm.end(RAC_PHASE_FACTOR));
+      s->fac_beta = bk;
+    }
+    SweepArgs w{P.F, P.F_dtype, P.ldF, s->rows, s->n, s->p, s->iota, s->Minv, s->sp, P.c, P.h, P.a,
+                P.b, P.Ns, s->x, s->z, s->xi, s->u, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
+                beta_ptr, s->tileA, s->tileB, 1, s->Fp, s->max_spin, ord};
+    HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
+    HIPCHK(launch_sweep(w, st));
+    HIPCHK(tm.end(RAC_PHASE_SWEEP));
+    s->epoch += (uint64_t)s->p;
+    UpdateArgs za{};
+    za.n = s->n; za.prox = P.prox; za.lam = P.lambda; za.alpha = P.alpha; za.lo = P.lo; za.hi = P.hi;
+    za.b = P.b; za.has_eq = P.a ? 1 : 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
+    za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
+    za.hist_base = k0 - run_offset; za.T = s->T; za.beta_ptr = beta_ptr; za.publish_beta = sched ? 1 : 0;
+    HIPCHK(tm.begin(st, RAC_PHASE_ZDUAL));
+    HIPCHK(launch_zdual(za, st));
+    HIPCHK(tm.end(RAC_PHASE_ZDUAL));
+  }
+  return enqueue_check(s, k0, Tc, run_offset, st, tm);
+}
+
 rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
+  if (s->rp) return enqueue_rp_chunk(s, Tc, run_offset, st);
   const rac_problem& P = s->P;
   PhaseTimer tm{s, st};
   const int64_t k0 = s->hsc.k;
@@ -399,6 +469,13 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
     HIPCHK(launch_zdual(za, st));
     HIPCHK(tm.end(RAC_PHASE_ZDUAL));
   }
+  return enqueue_check(s, k0, Tc, run_offset, st, tm);
+}
+
+// KKT check after a chunk of Tc iterations starting at k0, then the stopping test
+// and the penalty rule.
+rac_status enqueue_check(rac_solver s, int64_t k0, int64_t Tc, int64_t run_offset, hipStream_t st, PhaseTimer& tm) {
+  const rac_problem& P = s->P;
   KKTArgs ka{};
   ka.F = P.F; ka.dtype = P.F_dtype; ka.ldF = P.ldF; ka.rows = s->rows; ka.n = s->n; ka.Ns = P.Ns;
   ka.h = P.h; ka.c = P.c; ka.a = P.a; ka.b = P.b; ka.prox = P.prox; ka.lam = P.lambda;
@@ -459,6 +536,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
       if (!is_fin(O.beta_schedule[i]) || !(O.beta_schedule[i] > 0.0)) return RAC_ERR_ARG;
   }
   if (O.sweep_groups < 0 || O.sweep_groups > 256 || O.row_chunks < 0) return RAC_ERR_ARG;
+  if (O.variant != RAC_VARIANT_RAC && O.variant != RAC_VARIANT_RP) return RAC_ERR_ARG;
 
   rac_solver s = new (std::nothrow) rac_solver_s();
   if (!s) return RAC_ERR_NOMEM;
@@ -469,6 +547,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   s->p = O.num_blocks;
   s->T = O.check_every;
   s->sp = padded(smax);
+  s->rp = O.variant == RAC_VARIANT_RP;
   {
     int A = 0, B = 0, K = 0;
     if (choose_tile(prob->F_dtype, prob->rows, smax, O.sweep_groups, &A, &B, &K)) {
@@ -480,7 +559,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if (s->K > s->rows) s->K = (int)s->rows;
   // overlap the assemble phase with the sweep when all sweep groups fit on the device at once
-  const bool can_overlap = s->tileA > 0 && s->K > 1 &&
+  const bool can_overlap = !s->rp && s->tileA > 0 && s->K > 1 &&
                            s->K <= sweep_max_resident(prob->F_dtype, s->tileA, s->tileB) && O.overlap >= 0;
   s->R = O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows);
   if (can_overlap && O.row_chunks == 0) {
@@ -517,7 +596,15 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if ((r = alloc_perm_work(s->buf, s->T, n, &s->pw, &s->perm)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->partial, (size_t)(s->p * s->R) * s->sp * s->sp)) != RAC_OK) return fail(r);
-  if ((r = s->buf.alloc(&s->Minv, (size_t)2 * s->p * s->sp * s->sp)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->Minv, (size_t)(s->rp ? 1 : 2) * s->p * s->sp * s->sp)) != RAC_OK) return fail(r);
+  if (s->rp) {
+    if ((r = alloc_perm_work(s->buf, s->T, s->p, &s->pw_order, &s->order)) != RAC_OK) return fail(r);
+    if ((r = s->buf.alloc(&s->iota, (size_t)n)) != RAC_OK) return fail(r);
+    std::vector<int32_t> id((size_t)n);
+    for (int64_t j = 0; j < n; ++j) id[(size_t)j] = (int32_t)j;
+    if (hipMemcpy(s->iota, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RAC_ERR_DEVICE);
+  }
   if ((r = s->buf.alloc(&s->x, (size_t)n)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->z, (size_t)n)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->xi, (size_t)n)) != RAC_OK) return fail(r);
@@ -541,9 +628,10 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
     s->Fp_bytes = (size_t)sweep_packed_elems(s->p, s->K, s->tileA, s->tileB) * esz;
     s->packRW = sweep_rows_per_group(s->rows, s->K, s->tileA);
     if (s->packRW <= 0) return fail(RAC_ERR_ARG);
-    if ((r = s->buf.alloc(&s->Fp, 2 * s->Fp_bytes)) != RAC_OK) return fail(r);
+    const size_t copies = s->rp ? 1 : 2;   // RP: one copy, written once
+    if ((r = s->buf.alloc(&s->Fp, copies * s->Fp_bytes)) != RAC_OK) return fail(r);
     // positions that no entry of F maps to stay zero for the solver's lifetime
-    if (hipMemset(s->Fp, 0, 2 * s->Fp_bytes) != hipSuccess) return fail(RAC_ERR_DEVICE);
+    if (hipMemset(s->Fp, 0, copies * s->Fp_bytes) != hipSuccess) return fail(RAC_ERR_DEVICE);
   }
   if (can_overlap) {
     if (hipStreamCreateWithFlags(&s->sB, hipStreamNonBlocking) != hipSuccess) return fail(RAC_ERR_DEVICE);
@@ -560,7 +648,8 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
     if (O.max_iter > 0 &&
         hipMemcpy(s->d_sched, O.beta_schedule, sizeof(double) * O.max_iter, hipMemcpyHostToDevice) != hipSuccess)
       return fail(RAC_ERR_DEVICE);
-    s->O.beta_schedule = nullptr;   // the host array is not kept
+    if (s->rp) s->sched_host.assign(O.beta_schedule, O.beta_schedule + O.max_iter);
+    s->O.beta_schedule = nullptr;   // the caller's array is not kept
   }
   if (hipMemset(s->x, 0, sizeof(double) * n) != hipSuccess ||
       hipMemset(s->z, 0, sizeof(double) * n) != hipSuccess ||
@@ -644,6 +733,7 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
       res->fail_iter = (int64_t)(s->hsc.fail_key >> 32);
       res->fail_block = (int64_t)(s->hsc.fail_key & 0xffffffffULL);
       rc = RAC_ERR_NOT_PD;
+      s->fac_beta = NAN;   // RP: the inverses of this beta are not usable
       break;
     }
     if (s->hsc.status == 1) { run_status = RAC_RUN_CONVERGED; break; }

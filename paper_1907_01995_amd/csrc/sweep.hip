@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_sweep(const T* __restrict__ F, int64_t 
                                                const double* __restrict__ xi, double* u,
                                                DevScalars* sc, const double* beta_ptr,
                                                double* partials, uint64_t* flags, uint64_t epoch_base,
-                                               int max_spin) {
+                                               int max_spin, const int32_t* __restrict__ order) {
   const int K = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t r0 = block_start(g, rows, K), r1 = block_start(g + 1, rows, K);
@@ -59,8 +59,9 @@ __global__ void __launch_bounds__(256) k_sweep(const T* __restrict__ F, int64_t 
   double t = sc->t;
 
   for (int64_t i = 0; i < p; ++i) {
-    const int64_t s0 = block_start(i, n, p);
-    const int sb = (int)(block_start(i + 1, n, p) - s0);
+    const int64_t bi = order ? (int64_t)order[i] : i;   // block solved at position i
+    const int64_t s0 = block_start(bi, n, p);
+    const int sb = (int)(block_start(bi + 1, n, p) - s0);
     for (int j = tid; j < sb; j += 256) cols[j] = perm[s0 + j];
     __syncthreads();
 
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(256) k_sweep(const T* __restrict__ F, int64_t 
       gl[j] = v;
     }
     __syncthreads();
-    const double* Mi = Minv + i * (int64_t)sp * sp;
+    const double* Mi = Minv + bi * (int64_t)sp * sp;
     for (int j = tid; j < sb; j += 256) {
       double s = 0.0;
       for (int k = 0; k < sb; ++k) s += Mi[(int64_t)k * sp + j] * gl[k];
@@ -231,6 +232,7 @@ struct Sweep2Args {
   int vec;                 // column starts allow A-element vector loads
   const void* Fp;          // packed tiles of this iteration's blocks, or null (gather from F)
   int max_spin;            // polls of one batch of partials before a group gives up
+  const int32_t* order;    // RP: position i solves block order[i]; null: block i
 };
 
 // Lane l holds rows r0 + A l + a (a < A) of the group's range: A consecutive
@@ -389,10 +391,15 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     if (s.a) v -= mu * s.a[col];
     return v;
   };
-  auto bsize = [&](int64_t i) { return (int)(block_start(i + 1, s.n, s.p) - block_start(i, s.n, s.p)); };
-  // tile of block i: packed copy, else gathered through the block's column indices
+  // block solved at position i (its inverse and packed tiles are stored at that index)
+  auto bid = [&](int64_t i) -> int64_t { return s.order ? (int64_t)s.order[i] : i; };
+  auto bsize = [&](int64_t i) {
+    const int64_t b = bid(i);
+    return (int)(block_start(b + 1, s.n, s.p) - block_start(b, s.n, s.p));
+  };
+  // tile of the block at position i: packed copy, else gathered through the block's column indices
   auto fetch = [&](int64_t i, Tile<T, A, B>& tile) {
-    if (Fp) load_packed<T, A, B>(Fp, i, K, g, lane, wave, tile);
+    if (Fp) load_packed<T, A, B>(Fp, bid(i), K, g, lane, wave, tile);
     else load_tile<T, A, B>(F, s.ldF, r0, r1, sh_cols[i & 1], bsize(i), lane, wave, s.vec, tile);
   };
   double ureg[A];
@@ -405,7 +412,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   double mreg[MREG ? KM : 1];
   auto load_minv = [&](int64_t i, int sbi) {
     if constexpr (MREG) {
-      const double* Mi = s.Minv + i * (int64_t)s.sp * s.sp;
+      const double* Mi = s.Minv + bid(i) * (int64_t)s.sp * s.sp;
 #pragma unroll
       for (int e = 0; e < KM; ++e) {   // rows part*KM .. of the inverse's column jc
         const int k = part * KM + e;
@@ -416,7 +423,8 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   double ga = 0.0, gbn = 0.0;
   {
     const int sb0 = bsize(0);
-    if (tid < sb0) sh_cols[0][tid] = s.perm[tid];
+    const int64_t c0 = block_start(bid(0), s.n, s.p);
+    if (tid < sb0) sh_cols[0][tid] = s.perm[c0 + tid];
     if (tid == 0) sh_abort = 0;
     __syncthreads();
     fetch(0, ta);
@@ -450,7 +458,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
     const int sb = bsize(i);
     const int32_t* cols = sh_cols[i & 1];
     const bool more = i + 1 < s.p;
-    const int64_t s1 = block_start(i + 1, s.n, s.p);
+    const int64_t s1 = more ? block_start(bid(i + 1), s.n, s.p) : 0;   // first column of the next block
     const int sb1 = more ? bsize(i + 1) : 0;
     if (tid < sb1) sh_cols[(i + 1) & 1][tid] = s.perm[s1 + tid];   // indices of the next block
     // partial F_B'u over this group's rows, transposed across lanes
@@ -570,7 +578,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
         }
       } else {
         // the inverse's entries in batches of 16 loads in flight, then summed in k order
-        const double* Mi = s.Minv + i * (int64_t)s.sp * s.sp;
+        const double* Mi = s.Minv + bid(i) * (int64_t)s.sp * s.sp;
         if (jc < sb) {
           for (int k0 = part; k0 < sb; k0 += 16 * P) {
             double mv[16];
@@ -699,11 +707,11 @@ hipError_t sweep_launch(const SweepArgs& s, hipStream_t st) {
                   (void*)&s.perm, (void*)&s.Minv, (void*)&s.sp, (void*)&s.c, (void*)&s.h,
                   (void*)&s.a, (void*)&s.b, (void*)&s.Ns, (void*)&s.x, (void*)&s.z, (void*)&s.xi,
                   (void*)&s.u, (void*)&s.sc, (void*)&beta_ptr, (void*)&s.partials,
-                  (void*)&s.flags, (void*)&s.epoch_base, (void*)&max_spin};
+                  (void*)&s.flags, (void*)&s.epoch_base, (void*)&max_spin, (void*)&s.order};
   if (s.K == 1) {
     k_sweep<T><<<1, 256, 0, st>>>(F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.c, s.h, s.a,
                                   s.b, s.Ns, s.x, s.z, s.xi, s.u, s.sc, beta_ptr, s.partials,
-                                  s.flags, s.epoch_base, max_spin);
+                                  s.flags, s.epoch_base, max_spin, s.order);
     return hipGetLastError();
   }
   return hipLaunchCooperativeKernel((const void*)k_sweep<T>, dim3((unsigned)s.K), dim3(256), args, 0,
@@ -725,7 +733,7 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
   if (s.tileA > 0) {
     Sweep2Args a{s.F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.c, s.h, s.xi, s.z, s.beta_ptr,
                  s.a, s.b, s.Ns, s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0, s.Fp,
-                 s.max_spin >= 0 ? s.max_spin : kMaxSpin};
+                 s.max_spin >= 0 ? s.max_spin : kMaxSpin, s.order};
     const int64_t rw = sweep_rows_per_group(s.rows, s.K, s.tileA);
     if (rw == 0) return hipErrorInvalidValue;
     a.RW = rw;

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from dataclasses import dataclass
 
 import numpy as np
@@ -23,6 +24,7 @@ DT_F64, DT_F32, DT_BF16 = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 BETA_FIXED, BETA_RESBAL, BETA_MLP, BETA_SCHEDULE = 0, 1, 2, 3
 BSWEEP_AUTO, BSWEEP_LANE, BSWEEP_TEAM = 0, 1, 2
+VARIANT_RAC, VARIANT_RP = 0, 1
 MAX_BLOCK = 128
 MLP_IN, MLP_HIDDEN = 8, 64
 MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
@@ -35,7 +37,8 @@ EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_so
             "rac_permutation", "rac_kkt", "rac_objective", "rac_regression_c", "rac_block_matrices",
             "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_batch_create",
             "rac_batch_destroy", "rac_batch_run", "rac_batch_lane", "rac_batch_info", "rac_batch_set_timing",
-            "rac_batch_timing", "rac_status_str"]
+            "rac_batch_timing", "rac_status_str", "rac_solve", "rac_solve_batch", "rac_permutation_host",
+            "rac_batch_state_export", "rac_batch_state_import"]
 
 
 class RacError(RuntimeError):
@@ -59,7 +62,7 @@ class Opts_(C.Structure):
                 ("beta_schedule", C.POINTER(C.c_double)), ("mlp_weights", C.c_void_p),
                 ("mlp_ymax", C.c_double), ("check_every", C.c_int64), ("max_iter", C.c_int64),
                 ("tol", C.c_double), ("sweep_groups", C.c_int32), ("row_chunks", C.c_int32),
-                ("overlap", C.c_int32), ("packed", C.c_int32)]
+                ("overlap", C.c_int32), ("packed", C.c_int32), ("variant", C.c_int32), ("pad0", C.c_int32)]
 
 
 class Lane_(C.Structure):
@@ -131,6 +134,12 @@ def load():
         "rac_batch_info": [vp, C.POINTER(i64)],
         "rac_batch_set_timing": [vp, C.c_int32],
         "rac_batch_timing": [vp, dp, C.POINTER(i64)],
+        "rac_solve": [C.POINTER(Problem_), C.POINTER(Opts_), vp, vp, vp, vp, dp, C.POINTER(Result_)],
+        "rac_solve_batch": [C.c_int32, C.POINTER(Problem_), C.c_int32, C.POINTER(Lane_), C.POINTER(BatchOpts_),
+                            vp, vp, vp, vp, C.POINTER(Result_)],
+        "rac_permutation_host": [u64, u64, i64, i64, C.POINTER(C.c_int32)],
+        "rac_batch_state_export": [vp, vp, C.POINTER(C.c_size_t)],
+        "rac_batch_state_import": [vp, vp, C.c_size_t],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -289,7 +298,7 @@ class Solver:
     def __init__(self, prob: Problem, *, p=None, s=None, seed=0, instance=0, precision=PREC_FP64,
                  beta0=1.0, beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0, beta_schedule=None,
                  mlp_weights=None, mlp_ymax=float(np.log(10.0)), check_every=10, max_iter=100,
-                 tol=0.0, sweep_groups=0, row_chunks=0, overlap=True, packed=True):
+                 tol=0.0, sweep_groups=0, row_chunks=0, overlap=True, packed=True, variant=VARIANT_RAC):
         self.lib = load()
         self.prob = prob
         if p is None:
@@ -305,7 +314,7 @@ class Solver:
                           float(rb_mu), float(rb_tau), sched_ptr,
                           None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax),
                           int(check_every), int(max_iter), float(tol), int(sweep_groups), int(row_chunks),
-                          0 if overlap else -1, 0 if packed else -1)
+                          0 if overlap else -1, 0 if packed else -1, int(variant), 0)
         self._ps = prob.struct()
         h = C.c_void_p()
         _check(self.lib.rac_solver_create(C.byref(self._ps), C.byref(self.opts), C.byref(h)),
@@ -319,6 +328,12 @@ class Solver:
             self.h = None
 
     def __del__(self):
+        # At interpreter shutdown the HIP runtime may already be finalised (torch and
+        # profiler tools register their own exit handlers), and rac_*_destroy
+        # synchronises the device and frees memory: make no HIP call then, the
+        # process exit releases the device memory.  Call close() for a prompt release.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -415,6 +430,39 @@ class Solver:
 
 
 # ---------------------------------------------------------------------------
+
+def solve(prob: Problem, *, p=None, s=None, seed=0, instance=0, precision=PREC_FP64, beta0=1.0,
+          beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0, beta_schedule=None, mlp_weights=None,
+          mlp_ymax=float(np.log(10.0)), check_every=10, max_iter=100, tol=0.0, variant=VARIANT_RAC,
+          allow_not_pd=False):
+    """rac_solve: one call from the cold start; returns (Result, x, z, xi, mu) with numpy vectors."""
+    torch = _torch()
+    if p is None:
+        p = -(-prob.n // int(s))
+    sched = None if beta_schedule is None else np.ascontiguousarray(beta_schedule, dtype=np.float64)
+    o = Opts_(int(p), int(seed), int(instance), int(precision), int(beta_mode), float(beta0), float(rb_mu),
+              float(rb_tau), None if sched is None else sched.ctypes.data_as(C.POINTER(C.c_double)),
+              None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax), int(check_every),
+              int(max_iter), float(tol), 0, 0, 0, 0, int(variant), 0)
+    dev = prob.c.device
+    x, z, xi = (torch.empty(prob.n, dtype=torch.float64, device=dev) for _ in range(3))
+    mu = C.c_double()
+    r = Result_()
+    ps = prob.struct()
+    code = load().rac_solve(C.byref(ps), C.byref(o), _stream(), _ptr(x), _ptr(z), _ptr(xi), C.byref(mu), C.byref(r))
+    if code != RAC_OK and not (allow_not_pd and code == RAC_ERR_NOT_PD):
+        raise RacError(code, "rac_solve")
+    res = Result(r.iters, r.status, r.kkt, r.beta, r.objective, r.fail_iter, r.fail_block)
+    return res, x.cpu().numpy(), z.cpu().numpy(), xi.cpu().numpy(), mu.value
+
+
+def permutation_host(seed, instance, it, n):
+    """rac_permutation_host: the partition draw on the CPU (numpy int32), no GPU call."""
+    out = np.empty(int(n), dtype=np.int32)
+    _check(load().rac_permutation_host(int(seed), int(instance), int(it), int(n),
+                                       out.ctypes.data_as(C.POINTER(C.c_int32))), "rac_permutation_host")
+    return out
+
 
 def permutation(seed, instance, it, n, device="cuda"):
     torch = _torch()
@@ -515,6 +563,12 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        # At interpreter shutdown the HIP runtime may already be finalised (torch and
+        # profiler tools register their own exit handlers), and rac_*_destroy
+        # synchronises the device and frees memory: make no HIP call then, the
+        # process exit releases the device memory.  Call close() for a prompt release.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -548,8 +602,50 @@ class Batch:
         _check(self.lib.rac_batch_timing(self.h, ms, cnt), "rac_batch_timing")
         return {name: (ms[q], cnt[q]) for q, name in enumerate(Solver.PHASES)}
 
+    def export_state(self) -> bytes:
+        nb = C.c_size_t()
+        _check(self.lib.rac_batch_state_export(self.h, None, C.byref(nb)), "rac_batch_state_export")
+        buf = C.create_string_buffer(nb.value)
+        _check(self.lib.rac_batch_state_export(self.h, buf, C.byref(nb)), "rac_batch_state_export")
+        return buf.raw[:nb.value]
+
+    def import_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(self.lib.rac_batch_state_import(self.h, buf, len(blob)), "rac_batch_state_import")
+
     def info(self):
         v = (C.c_int64 * 8)()
         _check(self.lib.rac_batch_info(self.h, v), "rac_batch_info")
         return dict(lanes=v[0], instances=v[1], gram_tasks=v[2], inverse_tasks=v[3], unroll=v[4], graph=v[5],
                     team_size=v[6], teams=v[7])
+
+
+def solve_batch(probs, lanes, *, s=64, seed=0, precision=PREC_FP64, beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0,
+                mlp_weights=None, mlp_ymax=float(np.log(10.0)), check_every=10, max_iter=100, tol=0.0,
+                use_graph=True, tune=False, sweep=BSWEEP_AUTO, allow_not_pd=False):
+    """rac_solve_batch: one call; returns a list of (Result, x, z, xi) per lane (numpy vectors)."""
+    torch = _torch()
+    lib = load()
+    probs = list(probs)
+    ps = (Problem_ * len(probs))(*[p.struct() for p in probs])
+    ls = (Lane_ * len(lanes))(*[Lane_(int(a), int(b), float(c), float(d), float(e)) for a, b, c, d, e in lanes])
+    o = BatchOpts_(int(s), int(seed), int(precision), int(beta_mode), float(rb_mu), float(rb_tau),
+                   None if mlp_weights is None else mlp_weights.data_ptr(), float(mlp_ymax), int(check_every),
+                   int(max_iter), float(tol), 1 if use_graph else 0, 1 if tune else 0, int(sweep), 0)
+    ns = [probs[l[0]].n for l in lanes]
+    tot = int(sum(ns))
+    dev = probs[0].c.device
+    x, z, xi = (torch.empty(tot, dtype=torch.float64, device=dev) for _ in range(3))
+    res = (Result_ * len(lanes))()
+    code = lib.rac_solve_batch(len(probs), ps, len(lanes), ls, C.byref(o), _stream(), _ptr(x), _ptr(z), _ptr(xi),
+                               res)
+    if code != RAC_OK and not (allow_not_pd and code == RAC_ERR_NOT_PD):
+        raise RacError(code, "rac_solve_batch")
+    xs, zs, xis = x.cpu().numpy(), z.cpu().numpy(), xi.cpu().numpy()
+    out, off = [], 0
+    for u, n in enumerate(ns):
+        r = res[u]
+        out.append((Result(r.iters, r.status, r.kkt, r.beta, r.objective, r.fail_iter, r.fail_block),
+                    xs[off:off + n].copy(), zs[off:off + n].copy(), xis[off:off + n].copy()))
+        off += n
+    return out

@@ -74,3 +74,25 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(racmb, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         racmb.load()
+
+
+@pytest.mark.skipif(not racmb.lib_available(), reason="libracmb.so not built")
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 200, 2001, 65536])
+def test_host_permutation_matches_oracle(n):
+    """rac_permutation_host (the library's CPU form of the partition draw) against the
+    oracle's, bit for bit; the device form is compared with the oracle in the GPU tests."""
+    import numpy as np
+    import oracle as O
+    rng = np.random.default_rng(n + 1)
+    for _ in range(3):
+        seed, inst, it = int(rng.integers(0, 2**63)), int(rng.integers(0, 300)), int(rng.integers(0, 5000))
+        assert np.array_equal(racmb.permutation_host(seed, inst, it, n), O.permutation(seed, inst, it, n))
+
+
+@pytest.mark.skipif(not racmb.lib_available(), reason="libracmb.so not built")
+def test_host_permutation_rejects_bad_arguments():
+    lib = racmb.load()
+    out = (C.c_int32 * 4)()
+    assert lib.rac_permutation_host(1, 0, 0, 0, out) == racmb.RAC_ERR_ARG
+    assert lib.rac_permutation_host(1, 0, -1, 4, out) == racmb.RAC_ERR_ARG
+    assert lib.rac_permutation_host(1, 0, 0, 4, None) == racmb.RAC_ERR_ARG
