@@ -223,6 +223,20 @@ rac_status rac_state_import(rac_solver s, const void* buf, size_t bytes);
 rac_status rac_permutation(uint64_t seed, uint64_t instance, int64_t iter, int64_t n,
                            int32_t* perm, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rac_permutation without any allocation
+ * and without synchronising.  The sort's scratch is a fixed device array of this library,
+ * RAC_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; n is limited to
+ * RAC_NOALLOC_MAX_N (RAC_ERR_ARG beyond it, for n < 1, iter < 0 or perm == NULL).  perm
+ * (device, n int32) receives the same permutation as rac_permutation gives, bit for bit,
+ * once the work enqueued on `stream` has run.  Every call on a GPU uses that GPU's one
+ * scratch array: calls that overlap on one GPU (concurrent streams, or host threads
+ * enqueueing at once) race and must be serialised by the caller. */
+#define RAC_NOALLOC_MAX_N 262144
+#define RAC_NOALLOC_SCRATCH_BYTES 6291712
+rac_status rac_permutation_noalloc(uint64_t seed, uint64_t instance, int64_t iter, int64_t n, int32_t* perm,
+                                   void* stream);
+
 /* Host form of rac_permutation: the same permutation, bit for bit, computed on the CPU
  * into perm (host, n int32).  No HIP call.  RAC_ERR_ARG for n < 1, n > INT32_MAX, iter < 0
  * or perm == NULL. */

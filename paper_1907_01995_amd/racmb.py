@@ -38,7 +38,7 @@ EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_so
             "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_batch_create",
             "rac_batch_destroy", "rac_batch_run", "rac_batch_lane", "rac_batch_info", "rac_batch_set_timing",
             "rac_batch_timing", "rac_status_str", "rac_solve", "rac_solve_batch", "rac_permutation_host",
-            "rac_batch_state_export", "rac_batch_state_import"]
+            "rac_batch_state_export", "rac_batch_state_import", "rac_permutation_noalloc"]
 
 
 class RacError(RuntimeError):
@@ -140,6 +140,7 @@ def load():
         "rac_permutation_host": [u64, u64, i64, i64, C.POINTER(C.c_int32)],
         "rac_batch_state_export": [vp, vp, C.POINTER(C.c_size_t)],
         "rac_batch_state_import": [vp, vp, C.c_size_t],
+        "rac_permutation_noalloc": [u64, u64, i64, i64, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -461,6 +462,17 @@ def permutation_host(seed, instance, it, n):
     out = np.empty(int(n), dtype=np.int32)
     _check(load().rac_permutation_host(int(seed), int(instance), int(it), int(n),
                                        out.ctypes.data_as(C.POINTER(C.c_int32))), "rac_permutation_host")
+    return out
+
+
+NOALLOC_MAX_N = 262144
+
+
+def permutation_noalloc(seed, instance, it, n, out):
+    """rac_permutation_noalloc into the caller's int32 device tensor `out` (at least n entries),
+    enqueued on torch's current stream without allocating or synchronising."""
+    _check(load().rac_permutation_noalloc(int(seed), int(instance), int(it), int(n), _ptr(out), _stream()),
+           "rac_permutation_noalloc")
     return out
 
 
