@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 #define RAC_MAX_BLOCK 128   /* largest block size ceil(n/p) the kernels accept */
+#define RAC_MAX_EQ 16       /* largest number of equality rows of the dense form */
 #define RAC_MLP_IN 8        /* controller features */
 #define RAC_MLP_HIDDEN 64   /* controller hidden width */
 #define RAC_MLP_NPARAM (RAC_MLP_HIDDEN * RAC_MLP_IN + RAC_MLP_HIDDEN + \
@@ -96,6 +97,22 @@ typedef struct {
   double lambda, alpha; /* elastic net: lambda >= 0, 0 <= alpha <= 1 */
   double lo, hi;        /* box bounds (lo <= hi) */
   double obj_const;     /* constant added to the reported objective */
+  /* Dense form: the general QP of Eq.(1) with an explicit Hessian and several equality
+   * rows (Eq.(4)).  When Hd is not NULL the quadratic is H = Hd + diag h, with Hd a
+   * symmetric n x n matrix (device, column-major, leading dimension ldH >= n, element type
+   * H_dtype: RAC_DT_F64 or RAC_DT_F32); F must then be NULL and rows 0, and Ns is not used.
+   * The equality rows A x = beq are given as A (device, row-major meq x n, FP64) and beq
+   * (device, meq) with 0 <= meq <= RAC_MAX_EQ, and a must be NULL.  In the factor form
+   * (Hd NULL) meq must be 0 and the single row, if any, is a.  The Gaussian-kernel C-SVC
+   * dual of Eq.(9) is this form with Hd = Q (rac_svm_kernel_matrix), meq = 1, A = y, beq = 0.
+   * The dense form runs on one stream with the register-tile sweep (n up to 256 x 256 rows
+   * per group); RAC_ERR_UNSUPPORTED beyond that and in a batch. */
+  const void* Hd;
+  int64_t ldH;
+  int32_t H_dtype;
+  int32_t meq;
+  const double* A;
+  const double* beq;
 } rac_problem;
 
 typedef struct {
@@ -170,6 +187,12 @@ rac_status rac_solver_set_state(rac_solver s, const double* x, const double* z, 
                                 double mu, double beta, int64_t iter, void* stream);
 rac_status rac_solver_get_state(rac_solver s, double* x, double* z, double* xi, double* mu,
                                 double* beta, int64_t* iter, void* stream);
+
+/* Multipliers of the equality rows (host, count = meq in the dense form, 1 with a
+ * factor-form row a, else 0; RAC_ERR_ARG for another count).  Setting them replaces the
+ * multipliers of the current state (the dual variables of Eq.(3)'s last line). */
+rac_status rac_solver_get_multipliers(rac_solver s, double* mu, int64_t count);
+rac_status rac_solver_set_multipliers(rac_solver s, const double* mu, int64_t count);
 
 /* Phase timing (HIP events on the run's stream, accumulated over runs until the
  * next rac_solver_set_timing call).  Phases, in order: partition draw, block Gram
@@ -252,6 +275,13 @@ rac_status rac_permutation_host(uint64_t seed, uint64_t instance, int64_t iter, 
 rac_status rac_kkt(const rac_problem* prob, const double* x, const double* z, const double* xi,
                    double mu, void* stream, double* out);
 
+/* rac_kkt with every multiplier: mu (host, nmu doubles) holds one value per equality row
+ * (nmu = meq in the dense form, 1 with a factor-form row a, else 0).  In the dense form the
+ * equality feasibility is max_e |(A x - beq)_e| / (1 + |beq|_inf + |A|_inf |x|_inf) and the
+ * multiplier term of the stationarity is A'mu. */
+rac_status rac_kkt_mu(const rac_problem* prob, const double* x, const double* z, const double* xi,
+                      const double* mu, int64_t nmu, void* stream, double* out);
+
 /* Objective 1/2 z'Hz + c'z + P(z) + obj_const at device vector z (host result). */
 rac_status rac_objective(const rac_problem* prob, const double* z, void* stream, double* out);
 
@@ -265,6 +295,24 @@ rac_status rac_regression_c(const void* F, int32_t F_dtype, int64_t rows, int64_
 rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed, uint64_t instance,
                               int64_t iter, double beta, int32_t precision, double* out,
                               int64_t* sp_out, void* stream);
+
+/* Gaussian-kernel C-SVC (Sec.3.2, Eq.(9)): the dual's Hessian
+ *   Q_ij = y_i y_j exp(-gamma |x_i - x_j|^2)
+ * of n training points X (device, row-major n x r: point i's r features contiguous,
+ * X_dtype RAC_DT_F64 or RAC_DT_F32) with labels y (device, n, +-1), written to Q (device,
+ * column-major n x n, leading dimension ldQ >= n).  Squared distances are summed in FP64
+ * from the feature differences, so Q is exactly symmetric.  Pass Q as the dense form's Hd
+ * (with meq = 1, A = y, beq = 0, c = -e and the box [0, C]). */
+rac_status rac_svm_kernel_matrix(const void* X, int32_t X_dtype, int64_t n, int64_t r, const double* y, double gamma,
+                                 double* Q, int64_t ldQ, void* stream);
+/* Decision values f(v) = sum_j alpha_j y_j exp(-gamma |x_j - v|^2) + bias for m query points
+ * V (device, row-major m x r, same element type as X) into f (device, m).  The bias of the
+ * dual solution is minus the multiplier of y'alpha = 0 (b = -mu).  With labels (device, m)
+ * and accuracy (host) non-NULL, *accuracy receives the fraction of query points whose label
+ * has the sign of f (f = 0 counts as +1). */
+rac_status rac_svm_decision(const void* X, int32_t X_dtype, int64_t n, int64_t r, const double* y,
+                            const double* alpha, double gamma, double bias, const void* V, int64_t m, double* f,
+                            const double* labels, double* accuracy, void* stream);
 
 /* Controller network (8 -> 64 -> 64 -> 1, tanh hidden, y = ymax tanh(o)), FP32.
  * Parameters (device, RAC_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64], b2[64],

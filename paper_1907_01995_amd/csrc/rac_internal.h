@@ -208,6 +208,7 @@ struct SweepArgs {
   int max_spin;            // polls before a sweep group gives up waiting (negative: the default)
   const int32_t* order;    // RP: block solved at position i is order[i] (its inverse and packed tiles
                            // are stored at that index); null: position i is block i
+  int dense;               // dense form: F is the symmetric n x n Hessian and u is x (register-tile sweep only)
 };
 // Rows per sweep group for K groups and A rows per lane (0 if 64A rows do not cover a group).
 int64_t sweep_rows_per_group(int64_t rows, int K, int A);
@@ -219,6 +220,41 @@ int sweep_max_resident(int32_t dtype, int A, int B);
 // Register-tile shapes with a compiled sweep kernel (A rows per lane, B columns per wavefront).
 bool sweep_tile_supported(int32_t dtype, int A, int B);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
+
+// Dense form (dense.hip): H_beta = Hd + beta A'A, c_eff = c - A'(beta beq + mu), the
+// block matrices gathered from H_beta, t = A x with the multiplier step, the KKT residual
+// and the objective, and the Gaussian-kernel matrix and decision values of the SVM dual.
+hipError_t launch_hbeta(const void* Hd, int32_t dtype, int64_t ldH, int64_t n, int meq, const double* A,
+                        const double* beta_ptr, double* Hb, hipStream_t st);
+hipError_t launch_ceff(int64_t n, int meq, const double* A, const double* beq, const double* mu,
+                       const double* beta_ptr, const double* c, double* ceff, hipStream_t st);
+hipError_t launch_hgather(const void* H, int32_t dtype, int64_t ldH, int64_t n, int64_t p, const int32_t* perm,
+                          int sp, double* out, hipStream_t st);
+hipError_t launch_eq(int64_t n, int meq, const double* A, const double* beq, const double* x, const double* beta_ptr,
+                     double* t, double* mu, double* r2, double* red, uint32_t* done, DevScalars* sc, hipStream_t st);
+struct DenseKKTArgs {
+  const void* Hd; int32_t dtype; int64_t ldH; int64_t n;
+  const double* h; const double* c; int meq; const double* A; const double* beq;
+  const double* t;         // A x at the current x (meq)
+  const double* mu;        // multipliers (meq)
+  int32_t prox; double lam, alpha, lo, hi;
+  const double* x; const double* z; const double* xi;
+  double* part;            // [kKKTChunks][n] column products
+  double* red; uint32_t* done;
+  double* out;             // KKT: [4]; objective: [1]
+};
+hipError_t launch_dkkt(const DenseKKTArgs& k, hipStream_t st);
+hipError_t launch_dobjective(const DenseKKTArgs& k, const double* z, double cst, hipStream_t st);
+hipError_t launch_gauss_q(const void* X, int32_t dtype, int64_t n, int64_t r, const double* y, double gamma,
+                          double* Q, int64_t ldQ, hipStream_t st);
+hipError_t launch_decision(const void* X, int32_t dtype, int64_t n, int64_t r, const double* alpha,
+                           const double* y, double gamma, const void* V, int64_t m, double bias, double* f,
+                           hipStream_t st);
+hipError_t launch_accuracy(const double* f, const double* labels, int64_t m, double* red, uint32_t* done,
+                           double* out, hipStream_t st);
+// Column products Hd_j'v over row chunks into part [nch][n] (nch returned through *nch).
+hipError_t launch_hd_dots(const void* Hd, int32_t dtype, int64_t ldH, int64_t n, const double* v, double* part,
+                          int* nch, hipStream_t st);
 
 struct UpdateArgs {
   int64_t n; int32_t prox; double lam, alpha, lo, hi; double b; int has_eq;
@@ -232,6 +268,7 @@ struct UpdateArgs {
   int64_t T;               // check period (window start bookkeeping)
   const double* beta_ptr;  // penalty of this iteration
   int publish_beta;        // copy *beta_ptr into sc->beta (given schedules)
+  const double* extra_rp2; // dense form: |A x - beq|^2 added to r_p^2 (formed with the multiplier step), or null
 };
 hipError_t launch_zdual(const UpdateArgs& a, hipStream_t st);
 

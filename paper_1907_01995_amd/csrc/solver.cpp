@@ -50,11 +50,21 @@ size_t dtype_size(int32_t dt) {
   }
 }
 
+bool is_dense(const rac_problem* P) { return P->Hd != nullptr; }
+
 rac_status validate_problem(const rac_problem* P) {
   if (!P) return RAC_ERR_ARG;
-  if (P->n < 1 || P->rows < 1 || !P->F || P->ldF < P->rows || !P->c) return RAC_ERR_ARG;
-  if (P->n > (int64_t)INT32_MAX) return RAC_ERR_ARG;
-  if (dtype_size(P->F_dtype) == 0) return RAC_ERR_ARG;
+  if (P->n < 1 || !P->c || P->n > (int64_t)INT32_MAX) return RAC_ERR_ARG;
+  if (is_dense(P)) {
+    // dense form: explicit Hessian, several equality rows, no factor F
+    if (P->F || P->rows != 0 || P->a || P->ldH < P->n) return RAC_ERR_ARG;
+    if (P->H_dtype != RAC_DT_F64 && P->H_dtype != RAC_DT_F32) return RAC_ERR_ARG;
+    if (P->meq < 0 || P->meq > RAC_MAX_EQ || (P->meq > 0 && (!P->A || !P->beq))) return RAC_ERR_ARG;
+  } else {
+    if (P->rows < 1 || !P->F || P->ldF < P->rows) return RAC_ERR_ARG;
+    if (dtype_size(P->F_dtype) == 0) return RAC_ERR_ARG;
+    if (P->meq != 0 || P->A || P->beq) return RAC_ERR_ARG;
+  }
   if (P->prox < RAC_PROX_NONE || P->prox > RAC_PROX_BOX) return RAC_ERR_ARG;
   if (!is_fin(P->Ns) || !(P->Ns > 0.0) || !is_fin(P->b) || !is_fin(P->obj_const)) return RAC_ERR_ARG;
   if (P->prox == RAC_PROX_ELASTIC_NET &&
@@ -206,6 +216,18 @@ struct rac_solver_s {
   bool rp_gram = false;            // Grams (and packed copy) formed
   double fac_beta = NAN;           // beta of the current inverses (NaN: none)
   std::vector<double> sched_host;  // the given schedule (RP decides refactoring on the host)
+  // dense form (explicit Hessian Hd, meq equality rows): the sweep reads H_beta = Hd + beta A'A
+  // (or Hd itself without rows) and c_eff = c - A'(beta beq + mu); x is its own residual
+  bool dense = false;
+  int meq = 0;
+  double* Hb = nullptr;            // H_beta (n x n FP64) when meq > 0
+  double hb_beta = NAN;            // beta of H_beta (NaN: not formed)
+  double* ceff = nullptr;          // c_eff (n) when meq > 0
+  double* mu_vec = nullptr;        // multipliers (meq)
+  double* t_vec = nullptr;         // A x after the last sweep (meq)
+  double* eq_r2 = nullptr;         // |A x - beq|^2 of the last iteration
+  double* eq_red = nullptr;        // per-row scratch of the multiplier step (RAC_MAX_EQ)
+  uint32_t* eq_done = nullptr;
   DevScalars* hsc_pin = nullptr;   // pinned copy of the scalars read after each chunk
   DevScalars hsc{};
   // optional per-phase timing with HIP events on the run's stream
@@ -411,7 +433,94 @@ rac_status enqueue_rp_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStr
   return enqueue_check(s, k0, Tc, run_offset, st, tm);
 }
 
+// The matrix the dense form's sweep and block matrices read: H_beta, or Hd without rows.
+const void* dense_H(rac_solver s, int32_t* dtype, int64_t* ld) {
+  if (s->Hb) { *dtype = RAC_DT_F64; *ld = s->n; return s->Hb; }
+  *dtype = s->P.H_dtype;
+  *ld = s->P.ldH;
+  return s->P.Hd;
+}
+
+// Dense-form chunk (one stream): the partitions (RAC) or orders (RP) of the chunk;
+// per iteration H_beta when beta changed, c_eff for the current multipliers, the
+// block matrices gathered from H_beta and factored (RP: only when beta changed),
+// the sweep with x as the group-resident residual, t = A x with the multiplier
+// step, and the z/dual step; then the check.
+rac_status enqueue_dense_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
+  const rac_problem& P = s->P;
+  PhaseTimer tm{s, st};
+  const int64_t k0 = s->hsc.k;
+  const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
+  tm.k = -1;
+  HIPCHK(tm.begin(RAC_PHASE_PARTITION));
+  if (s->rp) HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->p, s->pw_order, s->order, st));
+  else HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
+  HIPCHK(tm.end(RAC_PHASE_PARTITION));
+  for (int64_t t = 0; t < Tc; ++t) {
+    const int64_t k = k0 + t;
+    const double* beta_ptr = beta_of(s, run_offset + t);
+    const double bk = sched ? s->sched_host[run_offset + t] : s->hsc.beta;
+    const int32_t* perm = s->rp ? s->iota : s->perm + t * s->n;
+    const int32_t* ord = s->rp ? s->order + t * s->p : nullptr;
+    tm.k = k;
+    HIPCHK(tm.begin(st, RAC_PHASE_GRAM));
+    if (s->Hb && !(bk == s->hb_beta)) {
+      HIPCHK(launch_hbeta(P.Hd, P.H_dtype, P.ldH, s->n, s->meq, P.A, beta_ptr, s->Hb, st));
+      s->hb_beta = bk;
+      s->fac_beta = NAN;
+    }
+    if (s->meq > 0) HIPCHK(launch_ceff(s->n, s->meq, P.A, P.beq, s->mu_vec, beta_ptr, P.c, s->ceff, st));
+    int32_t hdt = 0;
+    int64_t hld = 0;
+    const void* H = dense_H(s, &hdt, &hld);
+    const bool refactor = !s->rp || !(bk == s->fac_beta);
+    if (refactor) HIPCHK(launch_hgather(H, hdt, hld, s->n, s->p, perm, s->sp, s->partial, st));
+    HIPCHK(tm.end(RAC_PHASE_GRAM));
+    if (refactor) {
+      FactorArgs f{};
+      f.partial = s->partial; f.R = 1; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
+      f.Ns = 1.0; f.h = P.h; f.a = nullptr; f.beta_ptr = beta_ptr; f.beta_val = 0.0; f.Minv = s->Minv;
+      f.write_matrix = 0; f.sc = s->sc; f.iter_global = k; f.order = ord;
+      HIPCHK(tm.begin(st, RAC_PHASE_FACTOR));
+      HIPCHK(launch_factor(f, st));
+      HIPCHK(tm.end(RAC_PHASE_FACTOR));
+      s->fac_beta = bk;
+    }
+    SweepArgs w{H, hdt, hld, s->n, s->n, s->p, perm, s->Minv, s->sp, s->meq > 0 ? s->ceff : P.c, P.h, nullptr,
+                0.0, 1.0, s->x, s->z, s->xi, s->x, s->sc, s->sweep_part, s->flags, s->epoch, s->K,
+                beta_ptr, s->tileA, s->tileB, 1, nullptr, s->max_spin, ord, 1};
+    HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
+    HIPCHK(launch_sweep(w, st));
+    HIPCHK(tm.end(RAC_PHASE_SWEEP));
+    s->epoch += (uint64_t)s->p;
+    UpdateArgs za{};
+    za.n = s->n; za.prox = P.prox; za.lam = P.lambda; za.alpha = P.alpha; za.lo = P.lo; za.hi = P.hi;
+    za.b = 0.0; za.has_eq = 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
+    za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
+    za.hist_base = k0 - run_offset; za.T = s->T; za.beta_ptr = beta_ptr; za.publish_beta = sched ? 1 : 0;
+    za.extra_rp2 = s->meq > 0 ? s->eq_r2 : nullptr;
+    HIPCHK(tm.begin(st, RAC_PHASE_ZDUAL));
+    if (s->meq > 0)
+      HIPCHK(launch_eq(s->n, s->meq, P.A, P.beq, s->x, beta_ptr, s->t_vec, s->mu_vec, s->eq_r2, s->eq_red,
+                       s->eq_done, s->sc, st));
+    HIPCHK(launch_zdual(za, st));
+    HIPCHK(tm.end(RAC_PHASE_ZDUAL));
+  }
+  return enqueue_check(s, k0, Tc, run_offset, st, tm);
+}
+
+DenseKKTArgs dense_kkt_args(const rac_problem& P, const double* x, const double* z, const double* xi,
+                            const double* t, const double* mu, double* part, double* red, uint32_t* done,
+                            double* out) {
+  DenseKKTArgs d{};
+  d.Hd = P.Hd; d.dtype = P.H_dtype; d.ldH = P.ldH; d.n = P.n; d.h = P.h; d.c = P.c; d.meq = P.meq;
+  d.A = P.A; d.beq = P.beq; d.t = t; d.mu = mu; d.prox = P.prox; d.lam = P.lambda; d.alpha = P.alpha;
+  d.lo = P.lo; d.hi = P.hi; d.x = x; d.z = z; d.xi = xi; d.part = part; d.red = red; d.done = done; d.out = out;
+  return d;
+}
+
 rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
+  if (s->dense) return enqueue_dense_chunk(s, Tc, run_offset, st);
   if (s->rp) return enqueue_rp_chunk(s, Tc, run_offset, st);
   const rac_problem& P = s->P;
   PhaseTimer tm{s, st};
@@ -476,6 +585,20 @@ rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset,
 // and the penalty rule.
 rac_status enqueue_check(rac_solver s, int64_t k0, int64_t Tc, int64_t run_offset, hipStream_t st, PhaseTimer& tm) {
   const rac_problem& P = s->P;
+  if (s->dense) {
+    tm.k = -1;
+    HIPCHK(tm.begin(st, RAC_PHASE_CHECK));
+    HIPCHK(launch_dkkt(dense_kkt_args(P, s->x, s->z, s->xi, s->t_vec, s->mu_vec, s->kkt_part, s->red, s->done,
+                                      s->kkt_out), st));
+    ControlArgs ca{};
+    ca.sc = s->sc; ca.kkt_out = s->kkt_out; ca.beta_mode = s->O.beta_mode; ca.rb_mu = s->O.rb_mu;
+    ca.rb_tau = s->O.rb_tau; ca.tol = s->O.tol; ca.mlp_w = s->O.mlp_weights; ca.mlp_ymax = s->O.mlp_ymax;
+    ca.decide = ((k0 + Tc) % s->T == 0) ? 1 : 0; ca.hist = s->hist; ca.hist_cap = s->hist_cap;
+    ca.hist_base = k0 - run_offset;
+    HIPCHK(launch_control(ca, st));
+    HIPCHK(tm.end(RAC_PHASE_CHECK));
+    return RAC_OK;
+  }
   KKTArgs ka{};
   ka.F = P.F; ka.dtype = P.F_dtype; ka.ldF = P.ldF; ka.rows = s->rows; ka.n = s->n; ka.Ns = P.Ns;
   ka.h = P.h; ka.c = P.c; ka.a = P.a; ka.b = P.b; ka.prox = P.prox; ka.lam = P.lambda;
@@ -548,10 +671,18 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   s->T = O.check_every;
   s->sp = padded(smax);
   s->rp = O.variant == RAC_VARIANT_RP;
+  s->dense = is_dense(prob);
+  s->meq = s->dense ? prob->meq : 0;
+  if (s->dense) s->rows = n;   // the sweep's rows are the Hessian's: x is its own residual
+  // element type the sweep reads: F, or in the dense form H_beta (FP64) / Hd
+  const int32_t sweep_dt = s->dense ? (s->meq > 0 ? (int32_t)RAC_DT_F64 : prob->H_dtype) : prob->F_dtype;
   {
     int A = 0, B = 0, K = 0;
-    if (choose_tile(prob->F_dtype, prob->rows, smax, O.sweep_groups, &A, &B, &K)) {
+    if (choose_tile(sweep_dt, s->rows, smax, O.sweep_groups, &A, &B, &K)) {
       s->tileA = A; s->tileB = B; s->K = K;
+    } else if (s->dense) {
+      delete s;
+      return RAC_ERR_UNSUPPORTED;   // the dense form runs on the register-tile sweep only
     } else {
       s->tileA = s->tileB = 0;
       s->K = O.sweep_groups > 0 ? O.sweep_groups : auto_sweep_groups(prob->rows);
@@ -559,9 +690,9 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if (s->K > s->rows) s->K = (int)s->rows;
   // overlap the assemble phase with the sweep when all sweep groups fit on the device at once
-  const bool can_overlap = !s->rp && s->tileA > 0 && s->K > 1 &&
+  const bool can_overlap = !s->rp && !s->dense && s->tileA > 0 && s->K > 1 &&
                            s->K <= sweep_max_resident(prob->F_dtype, s->tileA, s->tileB) && O.overlap >= 0;
-  s->R = O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows);
+  s->R = s->dense ? 1 : (O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows));
   if (can_overlap && O.row_chunks == 0) {
     // leave the sweep's K compute units free of Gram workgroups: a sweep group needs
     // a whole compute unit, so the next iteration's Gram would otherwise delay it
@@ -596,7 +727,23 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if ((r = alloc_perm_work(s->buf, s->T, n, &s->pw, &s->perm)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->partial, (size_t)(s->p * s->R) * s->sp * s->sp)) != RAC_OK) return fail(r);
-  if ((r = s->buf.alloc(&s->Minv, (size_t)(s->rp ? 1 : 2) * s->p * s->sp * s->sp)) != RAC_OK) return fail(r);
+  if ((r = s->buf.alloc(&s->Minv, (size_t)(s->rp || s->dense ? 1 : 2) * s->p * s->sp * s->sp)) != RAC_OK)
+    return fail(r);
+  if (s->dense) {
+    if (s->meq > 0) {
+      if ((r = s->buf.alloc(&s->Hb, (size_t)n * n)) != RAC_OK) return fail(r);
+      if ((r = s->buf.alloc(&s->ceff, (size_t)n)) != RAC_OK) return fail(r);
+    }
+    if ((r = s->buf.alloc(&s->mu_vec, (size_t)RAC_MAX_EQ)) != RAC_OK) return fail(r);
+    if ((r = s->buf.alloc(&s->t_vec, (size_t)RAC_MAX_EQ)) != RAC_OK) return fail(r);
+    if ((r = s->buf.alloc(&s->eq_r2, 1)) != RAC_OK) return fail(r);
+    if ((r = s->buf.alloc(&s->eq_red, (size_t)RAC_MAX_EQ)) != RAC_OK) return fail(r);
+    if ((r = s->buf.alloc(&s->eq_done, 1)) != RAC_OK) return fail(r);
+    if (hipMemset(s->mu_vec, 0, sizeof(double) * RAC_MAX_EQ) != hipSuccess ||
+        hipMemset(s->t_vec, 0, sizeof(double) * RAC_MAX_EQ) != hipSuccess ||
+        hipMemset(s->eq_r2, 0, sizeof(double)) != hipSuccess || hipMemset(s->eq_done, 0, sizeof(uint32_t)) != hipSuccess)
+      return fail(RAC_ERR_DEVICE);
+  }
   if (s->rp) {
     if ((r = alloc_perm_work(s->buf, s->T, s->p, &s->pw_order, &s->order)) != RAC_OK) return fail(r);
     if ((r = s->buf.alloc(&s->iota, (size_t)n)) != RAC_OK) return fail(r);
@@ -623,7 +770,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->mv_part, (size_t)s->mv_nparts * s->rows)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->uz, (size_t)s->rows)) != RAC_OK) return fail(r);
   // packed copies of the blocks for the register-tile sweep (one per iteration parity)
-  if (s->tileA > 0 && O.packed >= 0 && s->rows <= INT32_MAX) {
+  if (s->tileA > 0 && O.packed >= 0 && s->rows <= INT32_MAX && !s->dense) {
     const size_t esz = prob->F_dtype == RAC_DT_F64 ? 8 : (prob->F_dtype == RAC_DT_F32 ? 4 : 2);
     s->Fp_bytes = (size_t)sweep_packed_elems(s->p, s->K, s->tileA, s->tileB) * esz;
     s->packRW = sweep_rows_per_group(s->rows, s->K, s->tileA);
@@ -648,7 +795,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
     if (O.max_iter > 0 &&
         hipMemcpy(s->d_sched, O.beta_schedule, sizeof(double) * O.max_iter, hipMemcpyHostToDevice) != hipSuccess)
       return fail(RAC_ERR_DEVICE);
-    if (s->rp) s->sched_host.assign(O.beta_schedule, O.beta_schedule + O.max_iter);
+    if (s->rp || s->dense) s->sched_host.assign(O.beta_schedule, O.beta_schedule + O.max_iter);
     s->O.beta_schedule = nullptr;   // the caller's array is not kept
   }
   if (hipMemset(s->x, 0, sizeof(double) * n) != hipSuccess ||
@@ -746,10 +893,15 @@ rac_status rac_solver_run(rac_solver s, void* stream, rac_result* res) {
     HIPCHK(hipStreamWaitEvent(st, s->ev_start, 0));
   }
   // objective at z
-  e = fx_into_u(s, s->z, s->uz, st);
-  if (e != RAC_OK) return e;
-  HIPCHK(launch_objective_red(s->rows, s->n, s->P.Ns, s->P.h, s->P.c, s->P.prox, s->P.lambda,
-                              s->P.alpha, s->P.obj_const, s->z, s->uz, s->red, s->done, s->obj_out, st));
+  if (s->dense) {
+    HIPCHK(launch_dobjective(dense_kkt_args(s->P, s->x, s->z, s->xi, s->t_vec, s->mu_vec, s->kkt_part, s->red,
+                                            s->done, s->obj_out), s->z, s->P.obj_const, st));
+  } else {
+    e = fx_into_u(s, s->z, s->uz, st);
+    if (e != RAC_OK) return e;
+    HIPCHK(launch_objective_red(s->rows, s->n, s->P.Ns, s->P.h, s->P.c, s->P.prox, s->P.lambda,
+                                s->P.alpha, s->P.obj_const, s->z, s->uz, s->red, s->done, s->obj_out, st));
+  }
   double obj = NAN;
   HIPCHK(hipMemcpyAsync(&obj, s->obj_out, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -771,12 +923,20 @@ rac_status rac_solver_set_state(rac_solver s, const double* x, const double* z, 
   HIPCHK(hipMemcpyAsync(s->z, z, nb, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(s->xi, xi, nb, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(s->zprev, z, nb, hipMemcpyDeviceToDevice, st));
-  rac_status e = fx_into_u(s, s->x, s->u, st);
-  if (e != RAC_OK) return e;
+  if (!s->dense) {   // the dense form's residual is x itself
+    rac_status e = fx_into_u(s, s->x, s->u, st);
+    if (e != RAC_OK) return e;
+  }
   s->hsc = fresh_scalars(beta);
   s->hsc.mu = mu;
   s->hsc.k = iter;
   HIPCHK(hipMemcpyAsync(s->sc, &s->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, st));
+  if (s->dense && s->meq > 0) {   // mu sets the first row's multiplier, the others start at zero
+    double m[RAC_MAX_EQ] = {0.0};
+    m[0] = mu;
+    HIPCHK(hipMemcpyAsync(s->mu_vec, m, sizeof(double) * RAC_MAX_EQ, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   if (s->P.a) HIPCHK(launch_dot_red(s->P.a, s->x, s->n, s->red, s->done, &s->sc->t, st));
   HIPCHK(hipMemcpyAsync(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -877,9 +1037,14 @@ struct StateHeader {
 constexpr uint64_t kStateMagic = 0x52414353544154ULL;  // "RACSTAT"
 }  // namespace
 
+size_t state_size(rac_solver s) {
+  return sizeof(StateHeader) + sizeof(DevScalars) + sizeof(double) * (4 * s->n + s->rows) +
+         (s->dense ? sizeof(double) * 2 * RAC_MAX_EQ : 0);
+}
+
 rac_status rac_state_export(rac_solver s, void* buf, size_t* bytes) {
   if (!s || !bytes) return RAC_ERR_ARG;
-  const size_t need = sizeof(StateHeader) + sizeof(DevScalars) + sizeof(double) * (4 * s->n + s->rows);
+  const size_t need = state_size(s);
   if (!buf) {
     *bytes = need;
     return RAC_OK;
@@ -897,13 +1062,19 @@ rac_status rac_state_export(rac_solver s, void* buf, size_t* bytes) {
   HIPCHK(hipMemcpy(p, s->xi, nb, hipMemcpyDeviceToHost)); p += nb;
   HIPCHK(hipMemcpy(p, s->zprev, nb, hipMemcpyDeviceToHost)); p += nb;
   HIPCHK(hipMemcpy(p, s->u, sizeof(double) * s->rows, hipMemcpyDeviceToHost));
+  p += sizeof(double) * s->rows;
+  if (s->dense) {
+    HIPCHK(hipMemcpy(p, s->mu_vec, sizeof(double) * RAC_MAX_EQ, hipMemcpyDeviceToHost));
+    p += sizeof(double) * RAC_MAX_EQ;
+    HIPCHK(hipMemcpy(p, s->t_vec, sizeof(double) * RAC_MAX_EQ, hipMemcpyDeviceToHost));
+  }
   *bytes = need;
   return RAC_OK;
 }
 
 rac_status rac_state_import(rac_solver s, const void* buf, size_t bytes) {
   if (!s || !buf) return RAC_ERR_ARG;
-  const size_t need = sizeof(StateHeader) + sizeof(DevScalars) + sizeof(double) * (4 * s->n + s->rows);
+  const size_t need = state_size(s);
   if (bytes < need) return RAC_ERR_ARG;
   const char* p = (const char*)buf;
   StateHeader h;
@@ -920,6 +1091,12 @@ rac_status rac_state_import(rac_solver s, const void* buf, size_t bytes) {
   HIPCHK(hipMemcpy(s->xi, p, nb, hipMemcpyHostToDevice)); p += nb;
   HIPCHK(hipMemcpy(s->zprev, p, nb, hipMemcpyHostToDevice)); p += nb;
   HIPCHK(hipMemcpy(s->u, p, sizeof(double) * s->rows, hipMemcpyHostToDevice));
+  p += sizeof(double) * s->rows;
+  if (s->dense) {
+    HIPCHK(hipMemcpy(s->mu_vec, p, sizeof(double) * RAC_MAX_EQ, hipMemcpyHostToDevice));
+    p += sizeof(double) * RAC_MAX_EQ;
+    HIPCHK(hipMemcpy(s->t_vec, p, sizeof(double) * RAC_MAX_EQ, hipMemcpyHostToDevice));
+  }
   return RAC_OK;
 }
 
@@ -939,11 +1116,54 @@ rac_status rac_permutation(uint64_t seed, uint64_t instance, int64_t iter, int64
   return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
 }
 
+rac_status rac_kkt_mu(const rac_problem* prob, const double* x, const double* z, const double* xi,
+                      const double* mu, int64_t nmu, void* stream, double* out) {
+  rac_status v = validate_problem(prob);
+  if (v != RAC_OK) return v;
+  const int64_t rows_eq = is_dense(prob) ? prob->meq : (prob->a ? 1 : 0);
+  if (!x || !z || !xi || !out || nmu != rows_eq || (nmu > 0 && !mu)) return RAC_ERR_ARG;
+  for (int64_t e = 0; e < nmu; ++e)
+    if (!is_fin(mu[e])) return RAC_ERR_ARG;
+  if (!is_dense(prob)) return rac_kkt(prob, x, z, xi, nmu ? mu[0] : 0.0, stream, out);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = prob->n;
+  Buffers B;
+  double *t = nullptr, *mud = nullptr, *zero = nullptr, *r2 = nullptr, *ered = nullptr, *part = nullptr,
+         *red = nullptr, *o = nullptr;
+  uint32_t *done = nullptr, *edone = nullptr;
+  rac_status r;
+  if ((r = B.alloc(&t, RAC_MAX_EQ)) != RAC_OK || (r = B.alloc(&mud, RAC_MAX_EQ)) != RAC_OK ||
+      (r = B.alloc(&zero, 1)) != RAC_OK || (r = B.alloc(&r2, 1)) != RAC_OK || (r = B.alloc(&ered, RAC_MAX_EQ)) != RAC_OK ||
+      (r = B.alloc(&part, (size_t)kKKTChunks * n)) != RAC_OK || (r = B.alloc(&red, (size_t)kRedSlots)) != RAC_OK ||
+      (r = B.alloc(&o, 4)) != RAC_OK || (r = B.alloc(&done, 1)) != RAC_OK || (r = B.alloc(&edone, 1)) != RAC_OK) {
+    B.release();
+    return r;
+  }
+  DevScalars* scr = nullptr;
+  if ((r = B.alloc(&scr, 1)) != RAC_OK) { B.release(); return r; }
+  const double z0 = 0.0;
+  hipError_t e = hipMemsetAsync(done, 0, sizeof(uint32_t), st);
+  if (e == hipSuccess) e = hipMemsetAsync(edone, 0, sizeof(uint32_t), st);
+  if (e == hipSuccess) e = hipMemcpyAsync(zero, &z0, sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && nmu > 0) e = hipMemcpyAsync(mud, mu, sizeof(double) * nmu, hipMemcpyHostToDevice, st);
+  // t = A x (a multiplier step with beta = 0 leaves mu as given)
+  if (e == hipSuccess) e = launch_eq(n, prob->meq, prob->A, prob->beq, x, zero, t, mud, r2, ered, edone, scr, st);
+  if (e == hipSuccess) e = launch_dkkt(dense_kkt_args(*prob, x, z, xi, t, mud, part, red, done, o), st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, o, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  B.release();
+  return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
 rac_status rac_kkt(const rac_problem* prob, const double* x, const double* z, const double* xi,
                    double mu, void* stream, double* out) {
   rac_status v = validate_problem(prob);
   if (v != RAC_OK) return v;
   if (!x || !z || !xi || !out || !is_fin(mu)) return RAC_ERR_ARG;
+  if (is_dense(prob)) {
+    if (prob->meq > 1) return RAC_ERR_ARG;   // several multipliers: rac_kkt_mu
+    return rac_kkt_mu(prob, x, z, xi, &mu, prob->meq, stream, out);
+  }
   hipStream_t st = (hipStream_t)stream;
   Buffers B;
   double *u = nullptr, *part = nullptr, *red = nullptr, *o = nullptr;
@@ -979,6 +1199,25 @@ rac_status rac_objective(const rac_problem* prob, const double* z, void* stream,
   if (v != RAC_OK) return v;
   if (!z || !out) return RAC_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
+  if (is_dense(prob)) {
+    Buffers B;
+    double *part = nullptr, *red = nullptr, *o = nullptr;
+    uint32_t* done = nullptr;
+    rac_status r;
+    if ((r = B.alloc(&part, (size_t)kKKTChunks * prob->n)) != RAC_OK || (r = B.alloc(&red, (size_t)kRedSlots)) != RAC_OK ||
+        (r = B.alloc(&o, 1)) != RAC_OK || (r = B.alloc(&done, 1)) != RAC_OK) {
+      B.release();
+      return r;
+    }
+    hipError_t e = hipMemsetAsync(done, 0, sizeof(uint32_t), st);
+    if (e == hipSuccess)
+      e = launch_dobjective(dense_kkt_args(*prob, z, z, z, nullptr, nullptr, part, red, done, o), z, prob->obj_const,
+                            st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, o, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    B.release();
+    return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+  }
   Buffers B;
   double *u = nullptr, *part = nullptr, *red = nullptr, *o = nullptr;
   uint32_t* done = nullptr;
@@ -1021,6 +1260,7 @@ rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed,
   if (precision != RAC_PREC_FP64 && precision != RAC_PREC_MIXED) return RAC_ERR_ARG;
   const int64_t smax = (prob->n + p - 1) / p;
   if (smax > RAC_MAX_BLOCK) return RAC_ERR_ARG;
+  if (is_dense(prob) && prob->meq > 1) return RAC_ERR_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   const int sp = padded(smax);
   const int R = auto_row_chunks(p, prob->rows);
@@ -1031,15 +1271,22 @@ rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed,
   rac_status r = alloc_perm_work(B, 1, prob->n, &w, &perm);
   if (r == RAC_OK) r = B.alloc(&partial, (size_t)p * R * sp * sp);
   if (r != RAC_OK) { B.release(); return r; }
+  const bool dense = is_dense(prob);
   hipError_t e = launch_permutations(seed, instance, iter, 1, prob->n, w, perm, st);
   if (e == hipSuccess) {
-    GramArgs g{prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, p, perm, precision, R, sp, partial};
-    e = launch_gram(g, st);
+    if (dense) {
+      e = launch_hgather(prob->Hd, prob->H_dtype, prob->ldH, prob->n, p, perm, sp, partial, st);
+    } else {
+      GramArgs g{prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, p, perm, precision, R, sp, partial};
+      e = launch_gram(g, st);
+    }
   }
   if (e == hipSuccess) {
     FactorArgs f{};
-    f.partial = partial; f.R = R; f.sp = sp; f.n = prob->n; f.p = p; f.perm = perm; f.Ns = prob->Ns;
-    f.h = prob->h; f.a = prob->a; f.beta_ptr = nullptr; f.beta_val = beta; f.Minv = out;
+    f.partial = partial; f.R = dense ? 1 : R; f.sp = sp; f.n = prob->n; f.p = p; f.perm = perm;
+    f.Ns = dense ? 1.0 : prob->Ns;
+    f.h = prob->h; f.a = dense ? (prob->meq == 1 ? prob->A : nullptr) : prob->a; f.beta_ptr = nullptr;
+    f.beta_val = beta; f.Minv = out;
     f.write_matrix = 1; f.sc = nullptr; f.iter_global = iter;
     e = launch_factor(f, st);
   }
@@ -1047,6 +1294,73 @@ rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed,
   B.release();
   if (sp_out) *sp_out = sp;
   return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
+rac_status rac_solver_get_multipliers(rac_solver s, double* mu, int64_t count) {
+  if (!s || !mu) return RAC_ERR_ARG;
+  const int64_t rows_eq = s->dense ? s->meq : (s->P.a ? 1 : 0);
+  if (count != rows_eq) return RAC_ERR_ARG;
+  if (count == 0) return RAC_OK;
+  if (s->dense) {
+    HIPCHK(hipMemcpy(mu, s->mu_vec, sizeof(double) * count, hipMemcpyDeviceToHost));
+  } else {
+    HIPCHK(hipMemcpy(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
+    mu[0] = s->hsc.mu;
+  }
+  return RAC_OK;
+}
+
+rac_status rac_solver_set_multipliers(rac_solver s, const double* mu, int64_t count) {
+  if (!s || !mu) return RAC_ERR_ARG;
+  const int64_t rows_eq = s->dense ? s->meq : (s->P.a ? 1 : 0);
+  if (count != rows_eq) return RAC_ERR_ARG;
+  for (int64_t e = 0; e < count; ++e)
+    if (!is_fin(mu[e])) return RAC_ERR_ARG;
+  if (count == 0) return RAC_OK;
+  if (s->dense) HIPCHK(hipMemcpy(s->mu_vec, mu, sizeof(double) * count, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(&s->hsc, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
+  s->hsc.mu = mu[0];
+  HIPCHK(hipMemcpy(&s->sc->mu, &mu[0], sizeof(double), hipMemcpyHostToDevice));
+  return RAC_OK;
+}
+
+rac_status rac_svm_kernel_matrix(const void* X, int32_t X_dtype, int64_t n, int64_t r, const double* y, double gamma,
+                                 double* Q, int64_t ldQ, void* stream) {
+  if (!X || !y || !Q || n < 1 || r < 1 || ldQ < n || !is_fin(gamma) || !(gamma > 0.0)) return RAC_ERR_ARG;
+  if (X_dtype != RAC_DT_F64 && X_dtype != RAC_DT_F32) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_gauss_q(X, X_dtype, n, r, y, gamma, Q, ldQ, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
+}
+
+rac_status rac_svm_decision(const void* X, int32_t X_dtype, int64_t n, int64_t r, const double* y,
+                            const double* alpha, double gamma, double bias, const void* V, int64_t m, double* f,
+                            const double* labels, double* accuracy, void* stream) {
+  if (!X || !y || !alpha || !V || !f || n < 1 || r < 1 || m < 1 || !is_fin(gamma) || !(gamma > 0.0) ||
+      !is_fin(bias) || (accuracy && !labels))
+    return RAC_ERR_ARG;
+  if (X_dtype != RAC_DT_F64 && X_dtype != RAC_DT_F32) return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_decision(X, X_dtype, n, r, alpha, y, gamma, V, m, bias, f, st));
+  if (accuracy) {
+    Buffers B;
+    double *red = nullptr, *o = nullptr;
+    uint32_t* done = nullptr;
+    rac_status q;
+    if ((q = B.alloc(&red, 256)) != RAC_OK || (q = B.alloc(&o, 1)) != RAC_OK || (q = B.alloc(&done, 1)) != RAC_OK) {
+      B.release();
+      return q;
+    }
+    hipError_t e = hipMemsetAsync(done, 0, sizeof(uint32_t), st);
+    if (e == hipSuccess) e = launch_accuracy(f, labels, m, red, done, o, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(accuracy, o, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    B.release();
+    return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
 }
 
 rac_status rac_mlp_forward(const float* w, const float* feats, int64_t batch, float ymax, float* y, void* stream) {

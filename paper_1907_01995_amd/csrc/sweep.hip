@@ -233,6 +233,7 @@ struct Sweep2Args {
   const void* Fp;          // packed tiles of this iteration's blocks, or null (gather from F)
   int max_spin;            // polls of one batch of partials before a group gives up
   const int32_t* order;    // RP: position i solves block order[i]; null: block i
+  int dense;               // dense form: F is the symmetric Hessian (rows = variables) and u is x itself
 };
 
 // Lane l holds rows r0 + A l + a (a < A) of the group's range: A consecutive
@@ -611,21 +612,35 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       for (int j = 0; j < sb; ++j) dt += ab[j] * sh_d[j];
       t += dt;   // every thread forms the same sum in the same order
     }
-    // rows of u from the register tile, summed over the four wavefronts in order
+    if (s.dense) {
+      // dense form: the registers hold x of the group's rows; the block's steps land on
+      // the rows that are block columns (scattered through LDS, zero elsewhere)
+      for (int e = tid; e < 64 * A; e += 256) sh_red[e] = 0.0;
+      __syncthreads();
+      if (tid < sb) {
+        const int col = cols[tid];
+        if (col >= r0 && col < r1) sh_red[col - r0] = sh_d[tid];
+      }
+      __syncthreads();
 #pragma unroll
-    for (int aa = 0; aa < A; ++aa) {
-      double v = 0.0;
+      for (int aa = 0; aa < A; ++aa) ureg[aa] += sh_red[A * lane + aa];
+    } else {
+      // rows of u from the register tile, summed over the four wavefronts in order
 #pragma unroll
-      for (int bb = 0; bb < B; ++bb) v += cur.at(aa, bb) * sh_d[wave + 4 * bb];
-      sh_red[wave * 64 * A + 64 * aa + lane] = v;
+      for (int aa = 0; aa < A; ++aa) {
+        double v = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < B; ++bb) v += cur.at(aa, bb) * sh_d[wave + 4 * bb];
+        sh_red[wave * 64 * A + 64 * aa + lane] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int aa = 0; aa < A; ++aa) {
+        const int q = 64 * aa + lane;
+        ureg[aa] += ((sh_red[q] + sh_red[64 * A + q]) + sh_red[2 * 64 * A + q]) + sh_red[3 * 64 * A + q];
+      }
+      if (g == 0 && tid < sb) s.x[cols[tid]] += sh_d[tid];
     }
-    __syncthreads();
-#pragma unroll
-    for (int aa = 0; aa < A; ++aa) {
-      const int q = 64 * aa + lane;
-      ureg[aa] += ((sh_red[q] + sh_red[64 * A + q]) + sh_red[2 * 64 * A + q]) + sh_red[3 * 64 * A + q];
-    }
-    if (g == 0 && tid < sb) s.x[cols[tid]] += sh_d[tid];
     // the next block's iterate-independent gradient terms (its columns are untouched by this block)
     if (tid < sb1) {
       double v = rc - rxi + beta * (rx - rz);
@@ -733,7 +748,7 @@ hipError_t launch_sweep(const SweepArgs& s, hipStream_t st) {
   if (s.tileA > 0) {
     Sweep2Args a{s.F, s.ldF, s.rows, s.n, s.p, s.perm, s.Minv, s.sp, s.c, s.h, s.xi, s.z, s.beta_ptr,
                  s.a, s.b, s.Ns, s.x, s.u, s.sc, s.partials, s.flags, s.epoch_base, 0, 0, s.Fp,
-                 s.max_spin >= 0 ? s.max_spin : kMaxSpin, s.order};
+                 s.max_spin >= 0 ? s.max_spin : kMaxSpin, s.order, s.dense};
     const int64_t rw = sweep_rows_per_group(s.rows, s.K, s.tileA);
     if (rw == 0) return hipErrorInvalidValue;
     a.RW = rw;

@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_zdual(int64_t n, int32_t prox, double l
                                                double* zprev, DevScalars* sc, double* red,
                                                uint32_t* done, double* hist, int64_t hist_cap,
                                                int64_t hist_base, int64_t T, const double* beta_ptr,
-                                               int publish_beta) {
+                                               int publish_beta, const double* extra_rp2) {
   __shared__ double sh[4];
   const double beta = *beta_ptr;
   double rp2 = 0.0, rd2 = 0.0;
@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(256) k_zdual(int64_t n, int32_t prox, double l
     sc->mu -= beta * e;
     P += e * e;
   }
+  if (extra_rp2) P += *extra_rp2;   // dense form: the equality rows, formed with their multiplier step
   const double rp = sqrt(P), rd = beta * sqrt(D);
   const int64_t k = sc->k;
   if (publish_beta) sc->beta = beta;
@@ -434,7 +435,27 @@ hipError_t launch_zdual(const UpdateArgs& z, hipStream_t st) {
   if (blocks > kRedBlocks) blocks = kRedBlocks;
   k_zdual<<<(unsigned)blocks, 256, 0, st>>>(z.n, z.prox, z.lam, z.alpha, z.lo, z.hi, z.b, z.has_eq,
                                             z.x, z.z, z.xi, z.zprev, z.sc, z.red, z.done, z.hist,
-                                            z.hist_cap, z.hist_base, z.T, z.beta_ptr, z.publish_beta);
+                                            z.hist_cap, z.hist_base, z.T, z.beta_ptr, z.publish_beta, z.extra_rp2);
+  return hipGetLastError();
+}
+
+hipError_t launch_hd_dots(const void* Hd, int32_t dtype, int64_t ldH, int64_t n, const double* v, double* part,
+                          int* nch_out, hipStream_t st) {
+  const int64_t steps = (n + 255) / 256;
+  const int nch = (int)(steps < kKKTChunks ? steps : kKKTChunks);
+  int64_t cb = (n + 7) / 8;
+  if (cb > 65535) cb = 65535;
+  const dim3 grid((unsigned)cb, (unsigned)nch);
+  if (nch_out) *nch_out = nch;
+  if (dtype == RAC_DT_F64) {
+    const int vec = (ldH % 4 == 0) && ((uintptr_t)Hd % 16 == 0) && ((uintptr_t)v % 16 == 0);
+    k_kkt_dots<double><<<grid, 256, 0, st>>>((const double*)Hd, ldH, n, n, v, part, vec);
+  } else if (dtype == RAC_DT_F32) {
+    const int vec = (ldH % 4 == 0) && ((uintptr_t)Hd % 16 == 0) && ((uintptr_t)v % 16 == 0);
+    k_kkt_dots<float><<<grid, 256, 0, st>>>((const float*)Hd, ldH, n, n, v, part, vec);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

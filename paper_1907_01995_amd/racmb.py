@@ -26,6 +26,7 @@ BETA_FIXED, BETA_RESBAL, BETA_MLP, BETA_SCHEDULE = 0, 1, 2, 3
 BSWEEP_AUTO, BSWEEP_LANE, BSWEEP_TEAM = 0, 1, 2
 VARIANT_RAC, VARIANT_RP = 0, 1
 MAX_BLOCK = 128
+MAX_EQ = 16
 MLP_IN, MLP_HIDDEN = 8, 64
 MLP_NPARAM = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
@@ -38,7 +39,9 @@ EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_so
             "rac_mlp_forward", "rac_mlp_loss_grad", "rac_mlp_adam", "rac_batch_create",
             "rac_batch_destroy", "rac_batch_run", "rac_batch_lane", "rac_batch_info", "rac_batch_set_timing",
             "rac_batch_timing", "rac_status_str", "rac_solve", "rac_solve_batch", "rac_permutation_host",
-            "rac_batch_state_export", "rac_batch_state_import", "rac_permutation_noalloc"]
+            "rac_batch_state_export", "rac_batch_state_import", "rac_permutation_noalloc", "rac_kkt_mu",
+            "rac_solver_get_multipliers", "rac_solver_set_multipliers", "rac_svm_kernel_matrix",
+            "rac_svm_decision"]
 
 
 class RacError(RuntimeError):
@@ -52,7 +55,8 @@ class Problem_(C.Structure):
                 ("F_dtype", C.c_int32), ("prox", C.c_int32), ("Ns", C.c_double),
                 ("h", C.c_void_p), ("c", C.c_void_p), ("a", C.c_void_p), ("b", C.c_double),
                 ("lam", C.c_double), ("alpha", C.c_double), ("lo", C.c_double),
-                ("hi", C.c_double), ("obj_const", C.c_double)]
+                ("hi", C.c_double), ("obj_const", C.c_double), ("Hd", C.c_void_p), ("ldH", C.c_int64),
+                ("H_dtype", C.c_int32), ("meq", C.c_int32), ("A", C.c_void_p), ("beq", C.c_void_p)]
 
 
 class Opts_(C.Structure):
@@ -141,6 +145,11 @@ def load():
         "rac_batch_state_export": [vp, vp, C.POINTER(C.c_size_t)],
         "rac_batch_state_import": [vp, vp, C.c_size_t],
         "rac_permutation_noalloc": [u64, u64, i64, i64, vp, vp],
+        "rac_kkt_mu": [C.POINTER(Problem_), vp, vp, vp, dp, i64, vp, dp],
+        "rac_solver_get_multipliers": [vp, dp, i64],
+        "rac_solver_set_multipliers": [vp, dp, i64],
+        "rac_svm_kernel_matrix": [vp, C.c_int32, i64, i64, vp, C.c_double, vp, i64, vp],
+        "rac_svm_decision": [vp, C.c_int32, i64, i64, vp, vp, C.c_double, C.c_double, vp, i64, vp, vp, dp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -206,18 +215,35 @@ class Problem:
     lo: float = 0.0
     hi: float = 0.0
     obj_const: float = 0.0
+    Hd: object = None    # dense form: torch tensor (n, n) symmetric (column-major = row-major), f64 or f32
+    A: object = None     # dense form: torch tensor (meq, n) float64, row-major
+    beq: object = None   # dense form: torch tensor (meq,) float64
 
     @property
     def ldF(self) -> int:
         """Leading dimension of the column-major data: F is an (n, ldF)-strided tensor view."""
+        if self.F is None:
+            return 0
         assert self.F.stride(1) == 1 and self.F.stride(0) >= self.rows
         return int(self.F.stride(0))
 
+    @property
+    def meq(self) -> int:
+        return 0 if self.A is None else int(self.A.shape[0])
+
     def struct(self) -> Problem_:
-        return Problem_(self.n, self.rows, self.F.data_ptr(), self.ldF, _DT[self.storage], self.prox,
-                        self.Ns, None if self.h is None else self.h.data_ptr(), self.c.data_ptr(),
-                        None if self.a is None else self.a.data_ptr(), self.b, self.lam, self.alpha,
-                        self.lo, self.hi, self.obj_const)
+        hd_dt, ldH = DT_F64, 0
+        if self.Hd is not None:
+            assert self.Hd.stride(1) == 1
+            ldH = int(self.Hd.stride(0))
+            hd_dt = DT_F32 if self.Hd.dtype == _torch().float32 else DT_F64
+        return Problem_(self.n, self.rows, None if self.F is None else self.F.data_ptr(), self.ldF,
+                        _DT[self.storage], self.prox, self.Ns, None if self.h is None else self.h.data_ptr(),
+                        self.c.data_ptr(), None if self.a is None else self.a.data_ptr(), self.b, self.lam,
+                        self.alpha, self.lo, self.hi, self.obj_const,
+                        None if self.Hd is None else self.Hd.data_ptr(), ldH, hd_dt, self.meq,
+                        None if self.A is None else self.A.data_ptr(),
+                        None if self.beq is None else self.beq.data_ptr())
 
 
 def upload_columns(D, storage, device="cuda"):
@@ -280,6 +306,88 @@ def svm_problem(X, labels, Cbox, storage="f32", device="cuda") -> Problem:
     a = torch.as_tensor(yl, device=device)
     return Problem(F=F, storage=storage, rows=r, n=n, Ns=1.0, c=c, a=a, b=0.0, prox=PROX_BOX,
                    lo=0.0, hi=float(Cbox))
+
+
+def dense_problem(Hd, c, *, A=None, beq=None, h=None, prox=PROX_NONE, lam=0.0, alpha=1.0, lo=0.0, hi=0.0,
+                  obj_const=0.0, storage="f64", device="cuda") -> Problem:
+    """The general QP of Eq.(1): min 1/2 x'(Hd + diag h)x + c'x + P(z) s.t. A x = beq, x = z, with an
+    explicit symmetric Hd (numpy or device tensor, n x n; "f64" or "f32" storage, values exact in it)."""
+    torch = _torch()
+    load()
+    dt = torch.float64 if storage == "f64" else torch.float32
+    Ht = Hd.to(device, dt).contiguous() if hasattr(Hd, "data_ptr") else \
+        torch.as_tensor(np.ascontiguousarray(np.asarray(Hd).T), dtype=dt, device=device).contiguous()
+    n = int(Ht.shape[0])
+
+    def vec(v):
+        if v is None:
+            return None
+        return v.to(device, torch.float64).contiguous() if hasattr(v, "data_ptr") else \
+            torch.as_tensor(np.asarray(v, dtype=np.float64), device=device).contiguous()
+
+    At = None
+    bt = None
+    if A is not None:
+        At = vec(A).reshape(-1, n).contiguous()
+        bt = vec(beq).reshape(-1).contiguous()
+    return Problem(F=None, storage="f64", rows=0, n=n, Ns=1.0, c=vec(c), h=vec(h), prox=int(prox), lam=float(lam),
+                   alpha=float(alpha), lo=float(lo), hi=float(hi), obj_const=float(obj_const), Hd=Ht, A=At, beq=bt)
+
+
+def svm_kernel_matrix(X, labels, gamma, storage="f64", device="cuda"):
+    """rac_svm_kernel_matrix: Q_ij = y_i y_j exp(-gamma |x_i - x_j|^2) on the device (n x n float64)."""
+    torch = _torch()
+    dt = torch.float64 if storage == "f64" else torch.float32
+    Xt = torch.as_tensor(np.ascontiguousarray(X), dtype=dt, device=device).contiguous()
+    yt = torch.as_tensor(np.asarray(labels, dtype=np.float64), device=device)
+    n, r = Xt.shape
+    Q = torch.empty((n, n), dtype=torch.float64, device=device)
+    _check(load().rac_svm_kernel_matrix(_ptr(Xt), _DT[storage], n, r, _ptr(yt), float(gamma), _ptr(Q), n, _stream()),
+           "rac_svm_kernel_matrix")
+    return Q, Xt, yt
+
+
+def svm_kernel_problem(X, labels, Cbox, gamma, storage="f64", device="cuda"):
+    """Gaussian-kernel C-SVC dual (Sec.3.2, Eq.(9)) in the dense form: Hd = Q (built on the device),
+    c = -e, one equality row y'alpha = 0, box [0, C].  Returns (problem, device points, device labels)."""
+    torch = _torch()
+    Q, Xt, yt = svm_kernel_matrix(X, labels, gamma, storage, device)
+    n = Q.shape[0]
+    c = torch.full((n,), -1.0, dtype=torch.float64, device=device)
+    prob = Problem(F=None, storage="f64", rows=0, n=n, Ns=1.0, c=c, prox=PROX_BOX, lo=0.0, hi=float(Cbox), Hd=Q,
+                   A=yt.reshape(1, n).contiguous(), beq=torch.zeros(1, dtype=torch.float64, device=device))
+    return prob, Xt, yt
+
+
+def svm_decision(Xt, yt, alpha, gamma, bias, V, labels=None, storage="f64"):
+    """rac_svm_decision: decision values at query points V (numpy m x r) and, with labels, the accuracy."""
+    torch = _torch()
+    dt = torch.float64 if storage == "f64" else torch.float32
+    dev = Xt.device
+    at = torch.as_tensor(np.asarray(alpha, dtype=np.float64), device=dev)
+    Vt = torch.as_tensor(np.ascontiguousarray(V), dtype=dt, device=dev).contiguous()
+    m = Vt.shape[0]
+    f = torch.empty(m, dtype=torch.float64, device=dev)
+    lt = None if labels is None else torch.as_tensor(np.asarray(labels, dtype=np.float64), device=dev)
+    acc = C.c_double(float("nan"))
+    _check(load().rac_svm_decision(_ptr(Xt), _DT[storage], Xt.shape[0], Xt.shape[1], _ptr(yt), _ptr(at),
+                                   float(gamma), float(bias), _ptr(Vt), m, _ptr(f), _ptr(lt),
+                                   None if lt is None else C.byref(acc), _stream()), "rac_svm_decision")
+    return f.cpu().numpy(), (acc.value if lt is not None else None)
+
+
+def kkt_mu(prob: Problem, x, z, xi, mu):
+    """rac_kkt_mu: KKT residual parts with one multiplier per equality row."""
+    torch = _torch()
+    dev = prob.c.device
+    ts = [torch.as_tensor(np.asarray(v, dtype=np.float64), device=dev) for v in (x, z, xi)]
+    m = np.ascontiguousarray(np.atleast_1d(np.asarray(mu, dtype=np.float64)))
+    out = np.zeros(4)
+    ps = prob.struct()
+    _check(load().rac_kkt_mu(C.byref(ps), _ptr(ts[0]), _ptr(ts[1]), _ptr(ts[2]),
+                             m.ctypes.data_as(C.POINTER(C.c_double)), int(m.size), _stream(),
+                             out.ctypes.data_as(C.POINTER(C.c_double))), "rac_kkt_mu")
+    return out
 
 
 @dataclass
@@ -417,6 +525,19 @@ class Solver:
         _check(self.lib.rac_solver_history(self.h, out.ctypes.data_as(C.POINTER(C.c_double)),
                                            out.shape[0], C.byref(cnt)), "rac_solver_history")
         return out[:cnt.value]
+
+    def multipliers(self):
+        """Multipliers of the equality rows (numpy float64, one per row)."""
+        k = self.prob.meq if self.prob.Hd is not None else (1 if self.prob.a is not None else 0)
+        out = np.zeros(max(k, 1))
+        _check(self.lib.rac_solver_get_multipliers(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), k),
+               "rac_solver_get_multipliers")
+        return out[:k]
+
+    def set_multipliers(self, mu):
+        m = np.ascontiguousarray(np.atleast_1d(np.asarray(mu, dtype=np.float64)))
+        _check(self.lib.rac_solver_set_multipliers(self.h, m.ctypes.data_as(C.POINTER(C.c_double)), int(m.size)),
+               "rac_solver_set_multipliers")
 
     def export_state(self) -> bytes:
         nb = C.c_size_t()
