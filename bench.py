@@ -27,7 +27,11 @@ data already in HBM.  The line also reports:
                   and the high-dimensional LASSO 10000x100000 (BF16), each with
                   its own throughput, sweep roofline and time to tolerance; the
                   two LASSO legs also time RP-MBADMM (fixed blocks, random
-                  order; Sec.1) to the same tolerance.
+                  order; Sec.1) to the same tolerance; the dense form: the
+                  Gaussian-kernel SVM dual 20000x128 (kernel matrix, the
+                  paper's 10-iteration budget, held-out accuracy) and a general
+                  QP 8192x8192 with 8 equality rows; and the batched workload's
+                  paths solved stage by stage, warm-started against cold.
 A ratio between two solvers is "speedup" when both reached the tolerance,
 "speedup_at_least" when only the candidate did (the other stopped at its
 iteration cap), and absent when the candidate did not.
@@ -493,6 +497,110 @@ def hidim_leg(args, racmb, W, torch, weights):
     return out
 
 
+def svm_rbf_leg(args, racmb, W, torch):
+    """Gaussian-kernel C-SVC dual (Sec.3.2, Eq.(9)), 20000 training points x 128 features: the kernel
+    matrix on the device, the paper's budget of 10 iterations (beta = 0.1 p), iterations/s with the
+    dense sweep's roofline (one read of the n x n FP64 Hessian per sweep), the KKT residual after a
+    fixed budget, the bias b = -mu and the held-out accuracy of the decision function."""
+    X, y, Xt, yt, Cbox, gamma = W.svm_rbf(20000, 128, 5000)
+    n, s = X.shape[0], 64
+    p = -(-n // s)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    prob, Xd, yd = racmb.svm_kernel_problem(X, y, Cbox, gamma)
+    torch.cuda.synchronize()
+    t_kernel = time.perf_counter() - a
+    kw = dict(s=s, beta0=0.1 * p, beta_mode=racmb.BETA_FIXED, check_every=T_CHECK)
+    ips, ms, phases, info = throughput(racmb, torch, prob, args.dense_steps, 5, kw)
+    so = racmb.Solver(prob, max_iter=10, tol=0.0, **kw)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    r10 = so.run()
+    torch.cuda.synchronize()
+    t10 = time.perf_counter() - a
+    so.close()
+    sb = racmb.Solver(prob, max_iter=args.svm_budget, tol=1e-6, **kw)
+    a = time.perf_counter()
+    rb = sb.run()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - a
+    z = sb.state()[1]
+    bias = -float(sb.multipliers()[0])
+    sb.close()
+    _, acc = racmb.svm_decision(Xd, yd, z, gamma, bias, Xt, labels=yt)
+    _, acc_train = racmb.svm_decision(Xd, yd, z, gamma, bias, X, labels=y)
+    avg = phases["sweep"][0] / phases["sweep"][1] / 1e3
+    nbytes = float(n) * n * 8 + 6.0 * n * 8
+    roof = {"bound": "hbm", "achieved": nbytes / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "kernel": "k_sweep2 (dense form)", "avg_launch_us": avg * 1e6, "bytes_per_launch": nbytes}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {"workload": "svm_rbf_20000x128", "n": n, "r": 128, "gamma": gamma, "C": Cbox, "block_size": s, "p": p,
+           "kernel_matrix_seconds": t_kernel, "iters_per_s": ips, "ms_per_iteration": ms, "sweep_groups": info["K"],
+           "roofline": roof, "phases": {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in phases.items()
+                                         if v[1]},
+           "paper_budget_10_iterations": {"seconds": t10, "kkt": r10.kkt},
+           "budget": {"iterations": rb.iters, "seconds": tb, "kkt": rb.kkt,
+                      "converged": rb.status == racmb.RUN_CONVERGED},
+           "bias": bias, "test_accuracy": acc, "train_accuracy": acc_train}
+    del prob, Xd, yd
+    torch.cuda.empty_cache()
+    log("svm_rbf_20000x128: %s" % out)
+    return out
+
+
+def dense_qp_leg(args, racmb, W, torch):
+    """General QP of Eq.(1) with 8 equality rows (Eq.(4)) and the box [0, 1], dense 8192 x 8192
+    Hessian: iterations/s with the dense sweep's roofline, and time to KKT <= 1e-6, RAC and RP."""
+    n, meq, s = 8192, 8, 64
+    H, c, A, beq = W.dense_qp_device(n, meq)
+    prob = racmb.dense_problem(H, c, A=A, beq=beq, prox=racmb.PROX_BOX, lo=0.0, hi=1.0)
+    kw = dict(s=s, beta0=1.0, beta_mode=racmb.BETA_RESBAL, check_every=T_CHECK)
+    ips, ms, phases, info = throughput(racmb, torch, prob, args.dense_steps, 5, kw)
+    avg = phases["sweep"][0] / phases["sweep"][1] / 1e3
+    nbytes = float(n) * n * 8 + 6.0 * n * 8
+    roof = {"bound": "hbm", "achieved": nbytes / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "kernel": "k_sweep2 (dense form)", "avg_launch_us": avg * 1e6, "bytes_per_launch": nbytes}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {"workload": "qp_dense_8192_eq8_box", "n": n, "meq": meq, "block_size": s, "iters_per_s": ips,
+           "ms_per_iteration": ms, "sweep_groups": info["K"], "roofline": roof,
+           "phases": {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in phases.items() if v[1]}}
+    if not args.no_time_to_tol:
+        rac, _ = time_to_tol(racmb, torch, prob, dict(kw, max_iter=5000), reps=1)
+        rp, _ = time_to_tol(racmb, torch, prob, dict(kw, max_iter=5000, variant=racmb.VARIANT_RP), reps=1)
+        out["time_to_tol"] = {"rac": rac, "rp": rp, "rac_over_rp": ratio(rac, rp)}
+    del prob, H, A
+    torch.cuda.empty_cache()
+    log("qp_dense_8192_eq8: %s" % out)
+    return out
+
+
+def path_leg(args, racmb, W, torch, weights):
+    """Warm-started regularisation paths (Sec.3.1): the first 64 instances of the batched workload,
+    each path of 8 decreasing lambdas (lam_max .. 0.01 lam_max) solved stage by stage with every lane
+    started from the previous stage's solution, against the same 8 stages started cold (mixed
+    precision, BF16 data); total iterations and seconds to KKT <= 1e-6 at every point."""
+    Ns, ns, insts, probs, lanes = batched_workload(racmb, W, torch)
+    insts, probs = insts[:64], probs[:64]
+    lams = [W.lambda_grid(d.lam_max, 8, 0.01) for d in insts]
+    mode = racmb.BETA_MLP if weights is not None else racmb.BETA_RESBAL
+    kw = dict(alpha=0.5, s=64, seed=11, precision=racmb.PREC_MIXED, beta_mode=mode, mlp_weights=weights,
+              check_every=T_CHECK, max_iter=args.batched_cap, tol=1e-6, use_graph=True, tune=True)
+    out = {"workload": "en_paths (first 64 instances) as 8 sequential stages of 64 lanes"}
+    for name, warm in (("warm", True), ("cold", False)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        stages, iters = racmb.solve_path(probs, lams, warm=warm, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - a
+        conv = sum(1 for st in stages for r in st if r[0].status == racmb.RUN_CONVERGED)
+        out[name] = {"seconds": dt, "stage_iterations": iters, "total_iterations": int(sum(iters)),
+                     "points_converged": conv, "points": 8 * len(probs)}
+        log("path %s: %s" % (name, out[name]))
+    del probs, insts
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -507,7 +615,8 @@ def main():
     ap.add_argument("--single-steps", type=int, default=200, help="timed iterations of each single-instance leg")
     ap.add_argument("--svm-budget", type=int, default=1000)
     ap.add_argument("--no-legs", action="store_true", help="headline only")
-    ap.add_argument("--legs", default="ols,lasso,svm,hidim")
+    ap.add_argument("--legs", default="ols,lasso,svm,hidim,svm_rbf,qp,path")
+    ap.add_argument("--dense-steps", type=int, default=50, help="timed iterations of the dense-form legs")
     ap.add_argument("--hidim-cap", type=int, default=1500,
                     help="iteration cap of the plain FP64 solver in the high-dimensional leg")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -540,6 +649,12 @@ def main():
         legs["svm_20000x256"] = svm_leg(args, racmb, W, torch)
     if "hidim" in want and not args.no_time_to_tol:
         legs["lasso_10000x100000"] = hidim_leg(args, racmb, W, torch, weights)
+    if "svm_rbf" in want:
+        legs["svm_rbf_20000x128"] = svm_rbf_leg(args, racmb, W, torch)
+    if "qp" in want:
+        legs["qp_dense_8192_eq8_box"] = dense_qp_leg(args, racmb, W, torch)
+    if "path" in want and not args.no_time_to_tol:
+        legs["en_paths_warm_vs_cold"] = path_leg(args, racmb, W, torch, weights)
     if legs:
         out["legs"] = legs
     print(json.dumps(out), flush=True)

@@ -389,6 +389,15 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
  * any may be NULL).  res->status is the lane's rac_run_status (RAC_ERR_NOT_PD is
  * returned when one of its blocks violated Assumption 2.1). */
 rac_status rac_batch_lane(rac_batch b, int32_t lane, rac_result* res, double* x, double* z, double* xi);
+/* Warm start of one lane (a point of a regularisation path started from a neighbouring
+ * point's solution, Sec.3.1): replaces the lane's x, z, xi (device, n doubles each, of its
+ * instance), its multiplier mu and penalty beta (> 0), recomputes its residuals u = F x and
+ * t = a'x, and restarts its controller memory and iteration count.  The lane must not have
+ * retired (RAC_ERR_ARG otherwise); typically called between rac_batch_create and the first
+ * rac_batch_run. */
+rac_status rac_batch_set_lane_state(rac_batch b, int32_t lane, const double* x, const double* z, const double* xi,
+                                    double mu, double beta);
+
 /* Serialise / restore the state of every lane (x, z, xi, the previous z, u = F x, the
  * lanes' penalties, multipliers, controller memory and status) and the iteration counter to /
  * from a host buffer, for checkpoint/resume of a batch: a batch created with the same

@@ -807,6 +807,49 @@ rac_status rac_batch_state_import(rac_batch b, const void* buf, size_t bytes) {
   return RAC_OK;
 }
 
+rac_status rac_batch_set_lane_state(rac_batch b, int32_t lane, const double* x, const double* z, const double* xi,
+                                    double mu, double beta) {
+  if (!b || lane < 0 || lane >= b->nunits || !x || !z || !xi || !std::isfinite(mu) || !std::isfinite(beta) ||
+      !(beta > 0.0))
+    return RAC_ERR_ARG;
+  const BUnit& U = b->hunit[lane];
+  BCHK(hipStreamSynchronize(b->cs));
+  DevScalars h;
+  BCHK(hipMemcpy(&h, b->A.sc + lane, sizeof(DevScalars), hipMemcpyDeviceToHost));
+  if (h.status != 0) return RAC_ERR_ARG;   // a retired lane stays retired
+  const size_t nb = sizeof(double) * U.n;
+  BCHK(hipMemcpy(b->A.X + U.xoff, x, nb, hipMemcpyDeviceToDevice));
+  BCHK(hipMemcpy(b->A.Z + U.xoff, z, nb, hipMemcpyDeviceToDevice));
+  BCHK(hipMemcpy(b->A.XI + U.xoff, xi, nb, hipMemcpyDeviceToDevice));
+  BCHK(hipMemcpy(b->A.ZP + U.xoff, z, nb, hipMemcpyDeviceToDevice));
+  // the lane's residuals u = F x and t = a'x for its instance's data
+  const int np = (int)std::min<int64_t>(64, std::max<int64_t>(1, (U.n + 255) / 256));
+  double *part = nullptr, *red = nullptr, *tv = nullptr;
+  uint32_t* done = nullptr;
+  DevBufs tmp;
+  if (!tmp.alloc(&part, (size_t)np * U.rows) || !tmp.alloc(&red, (size_t)kRedSlots) || !tmp.alloc(&tv, 1) ||
+      !tmp.alloc(&done, 4)) {
+    tmp.release();
+    return RAC_ERR_NOMEM;
+  }
+  hipError_t e = hipMemset(done, 0, 4 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(tv, 0, sizeof(double));
+  if (e == hipSuccess)
+    e = launch_matvec_F_parts(U.F, b->A.dtype, U.ldF, U.rows, U.n, b->A.X + U.xoff, b->A.U + U.uoff, part, np,
+                              b->cs);
+  if (e == hipSuccess && U.a) e = launch_dot_red(U.a, b->A.X + U.xoff, U.n, red, done, tv, b->cs);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->cs);
+  double t = 0.0;
+  if (e == hipSuccess) e = hipMemcpy(&t, tv, sizeof(double), hipMemcpyDeviceToHost);
+  tmp.release();
+  if (e != hipSuccess) return RAC_ERR_DEVICE;
+  DevScalars f = fresh(beta);
+  f.mu = mu;
+  f.t = t;
+  BCHK(hipMemcpy(b->A.sc + lane, &f, sizeof(DevScalars), hipMemcpyHostToDevice));
+  return RAC_OK;
+}
+
 rac_status rac_batch_info(rac_batch b, int64_t* info) {
   if (!b || !info) return RAC_ERR_ARG;
   info[0] = b->nunits;

@@ -41,7 +41,7 @@ EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_so
             "rac_batch_timing", "rac_status_str", "rac_solve", "rac_solve_batch", "rac_permutation_host",
             "rac_batch_state_export", "rac_batch_state_import", "rac_permutation_noalloc", "rac_kkt_mu",
             "rac_solver_get_multipliers", "rac_solver_set_multipliers", "rac_svm_kernel_matrix",
-            "rac_svm_decision"]
+            "rac_svm_decision", "rac_batch_set_lane_state"]
 
 
 class RacError(RuntimeError):
@@ -150,6 +150,7 @@ def load():
         "rac_solver_set_multipliers": [vp, dp, i64],
         "rac_svm_kernel_matrix": [vp, C.c_int32, i64, i64, vp, C.c_double, vp, i64, vp],
         "rac_svm_decision": [vp, C.c_int32, i64, i64, vp, vp, C.c_double, C.c_double, vp, i64, vp, vp, dp, vp],
+        "rac_batch_set_lane_state": [vp, C.c_int32, vp, vp, vp, C.c_double, C.c_double],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -735,6 +736,16 @@ class Batch:
         _check(self.lib.rac_batch_timing(self.h, ms, cnt), "rac_batch_timing")
         return {name: (ms[q], cnt[q]) for q, name in enumerate(Solver.PHASES)}
 
+    def set_lane_state(self, u, x, z, xi, mu=0.0, beta=None):
+        """Warm start of lane u from (x, z, xi, mu) (numpy or device tensors) with penalty beta."""
+        torch = _torch()
+        dev = self.probs[0].c.device
+        ts = [v.to(dev, torch.float64).contiguous() if hasattr(v, "data_ptr") else
+              torch.as_tensor(np.asarray(v, dtype=np.float64), device=dev) for v in (x, z, xi)]
+        b = self.lanes[u][4] if beta is None else beta
+        _check(self.lib.rac_batch_set_lane_state(self.h, int(u), _ptr(ts[0]), _ptr(ts[1]), _ptr(ts[2]), float(mu),
+                                                 float(b)), "rac_batch_set_lane_state")
+
     def export_state(self) -> bytes:
         nb = C.c_size_t()
         _check(self.lib.rac_batch_state_export(self.h, None, C.byref(nb)), "rac_batch_state_export")
@@ -782,3 +793,26 @@ def solve_batch(probs, lanes, *, s=64, seed=0, precision=PREC_FP64, beta_mode=BE
                     xs[off:off + n].copy(), zs[off:off + n].copy(), xis[off:off + n].copy()))
         off += n
     return out
+
+
+def solve_path(probs, lams, *, alpha, s=64, seed=0, beta_frac=0.1, warm=True, **kw):
+    """A regularisation path (Sec.3.1) of every instance, solved stage by stage: stage j is one
+    batch with one lane per instance at lambda lams[i][j] (penalty beta_frac * lambda), each lane
+    started from the same instance's stage j-1 solution (warm=True) or cold.  Returns per stage
+    the (Result, x, z, xi) of every instance's lane, and the iterations each stage ran."""
+    stages, iters = [], []
+    prev = None
+    npts = len(lams[0])
+    for j in range(npts):
+        lanes = [(i, PROX_EN, float(lams[i][j]), float(alpha), beta_frac * float(lams[i][j])) for i in range(len(probs))]
+        b = Batch(probs, lanes, s=s, seed=seed, **kw)
+        if warm and prev is not None:
+            for i, (r, x, z, xi) in enumerate(prev):
+                b.set_lane_state(i, x, z, xi, 0.0, lanes[i][4])
+        it, _ = b.run()
+        out = [b.lane(i) for i in range(len(probs))]
+        b.close()
+        stages.append(out)
+        iters.append(it)
+        prev = out
+    return stages, iters

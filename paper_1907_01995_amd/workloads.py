@@ -241,3 +241,45 @@ def en_instance_device(N, n, seed, nnz_frac=0.1, noise=0.05, alpha=0.5, storage=
     yd = torch.as_tensor(y, device=device)
     lam_max = float(torch.max(torch.abs(F.double() @ yd)).item()) / (N * alpha)
     return DeviceRegression(F, y, lam_max, storage)
+
+
+# Dense-form workloads ----------------------------------------------------------
+
+def svm_rbf(n=20000, r=128, n_test=5000, shift=1.5, flip=0.05, Cbox=1.0, data_seed=6, storage="f64"):
+    """Gaussian-kernel C-SVC data (Sec.3.2): two Gaussian classes with means +-shift/sqrt(r) * 1
+    (centres 2 shift apart) and identity covariance, a fraction `flip` of the training labels flipped; a held-out test set
+    drawn from the same classes without flips.  gamma = 1/r (the common default of kernel SVM
+    packages).  Returns (X, labels, X_test, labels_test, C, gamma), X row-major n x r."""
+    rng = np.random.default_rng(data_seed)
+
+    def draw(m):
+        y = rng.choice([-1.0, 1.0], size=m)
+        X = (shift / np.sqrt(r)) * y[:, None] * np.ones((1, r)) + rng.standard_normal((m, r))
+        return to_storage(X, storage), y
+
+    X, y = draw(n)
+    idx = rng.choice(n, size=int(round(flip * n)), replace=False)
+    y = y.copy()
+    y[idx] = -y[idx]
+    Xt, yt = draw(n_test)
+    return np.ascontiguousarray(X), y, np.ascontiguousarray(Xt), yt, float(Cbox), 1.0 / r
+
+
+def dense_qp_device(n=8192, meq=8, data_seed=7, device="cuda"):
+    """General QP of Eq.(1) in the dense form, generated on the device: Hd = G'G/m + 0.01 I with
+    G (m = n/2 rows) iid N(0,1) (symmetrised exactly), c iid N(0,1), meq equality rows A iid N(0,1)
+    and beq = A x0 with x0 ~ U(0.1, 0.9) (feasible inside the box [0, 1]).  Returns torch tensors
+    (Hd n x n float64, c, A, beq)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(data_seed))
+    m = n // 2
+    G = torch.randn((m, n), generator=g, device=device, dtype=torch.float64)
+    H = (G.T @ G) / m
+    H = 0.5 * (H + H.T) + 0.01 * torch.eye(n, device=device, dtype=torch.float64)
+    del G
+    c = torch.randn(n, generator=g, device=device, dtype=torch.float64)
+    A = torch.randn((meq, n), generator=g, device=device, dtype=torch.float64)
+    x0 = 0.1 + 0.8 * torch.rand(n, generator=g, device=device, dtype=torch.float64)
+    beq = A @ x0
+    return H.contiguous(), c, A.contiguous(), beq

@@ -127,3 +127,35 @@ def test_batch_checkpoint_resume_is_bit_exact(storage, prec, sweep):
     assert e.value.code == racmb.RAC_ERR_ARG
     for h in (b, c, d):
         h.close()
+
+
+def test_warm_started_lambda_path_matches_oracle_path():
+    """A decreasing lambda path (Sec.3.1) run stage by stage with each lane started from
+    the previous stage's solution: every stage equals the oracle started from the same
+    state (FP64, fixed iteration count), and the converged path equals cold solves."""
+    from paper_1907_01995_amd import workloads as W
+    rng = np.random.default_rng(4)
+    ws = [W.gaussian_en(int(rng.integers(200, 600)), int(rng.integers(30, 120)), 0.1, 0.05, 0.1, 0.5, 500 + i, 16,
+                        "f64") for i in range(3)]
+    gps = [racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=0.5, storage="f64") for w in ws]
+    lmax = [np.max(np.abs(w.D.T @ w.y)) / (w.N * 0.5) for w in ws]
+    lams = [W.lambda_grid(lm, 5, 0.05) for lm in lmax]
+    say("warm path, fixed iterations")
+    stages, iters = racmb.solve_path(gps, lams, alpha=0.5, s=16, seed=9, max_iter=25, check_every=5, tol=0.0)
+    for i, w in enumerate(ws):
+        st = None
+        for j in range(5):
+            P = O.en_problem(w.D, w.y, lam=lams[i][j], alpha=0.5)
+            ref = O.solve(P, s=16, seed=9, inst=i, beta0=0.1 * lams[i][j], max_iter=25, check_every=5, state=st)
+            r, x, z, xi = stages[j][i]
+            assert rel(z, ref.z) < 1e-8 and rel(xi, ref.xi) < 1e-8 and rel(x, ref.x) < 1e-8, (i, j)
+            st = (ref.x, ref.z, ref.xi, 0.0)
+    say("warm path to tolerance against cold solves")
+    kw = dict(alpha=0.5, s=16, seed=9, max_iter=3000, check_every=10, tol=1e-9, beta_mode=racmb.BETA_RESBAL)
+    warm, it_w = racmb.solve_path(gps, lams, warm=True, **kw)
+    cold, it_c = racmb.solve_path(gps, lams, warm=False, **kw)
+    for j in range(5):
+        for i in range(3):
+            assert warm[j][i][0].status == racmb.RUN_CONVERGED and cold[j][i][0].status == racmb.RUN_CONVERGED
+            np.testing.assert_allclose(warm[j][i][2], cold[j][i][2], rtol=1e-6, atol=1e-8)
+    assert sum(it_w) <= sum(it_c)
