@@ -113,6 +113,15 @@ typedef struct {
   int32_t meq;
   const double* A;
   const double* beq;
+  /* Sparse factor form (the high-sparsity data of Sec.3.1, Tables 3-7): when colptr is
+   * not NULL, F (rows x n) is given in compressed sparse columns: colptr (device, n + 1
+   * int64, colptr[0] = 0), rowidx (device, colptr[n] int32 row indices, strictly increasing
+   * within each column) and F holding the colptr[n] values (F_dtype RAC_DT_F64 or
+   * RAC_DT_F32); ldF is not used.  The sparse form runs its sweep in one workgroup on one
+   * stream; its residual update uses device-scope atomic additions, so iterates agree with
+   * the dense computation to rounding but not bitwise from run to run. */
+  const int64_t* colptr;
+  const int32_t* rowidx;
 } rac_problem;
 
 typedef struct {
@@ -284,6 +293,11 @@ rac_status rac_kkt_mu(const rac_problem* prob, const double* x, const double* z,
 
 /* Objective 1/2 z'Hz + c'z + P(z) + obj_const at device vector z (host result). */
 rac_status rac_objective(const rac_problem* prob, const double* z, void* stream, double* out);
+
+/* Regression set-up for sparse data: c = -F'y/Ns with F in compressed sparse columns
+ * (colptr, rowidx, values as in rac_problem). */
+rac_status rac_regression_c_csc(const int64_t* colptr, const int32_t* rowidx, const void* values, int32_t dtype,
+                                int64_t rows, int64_t n, double Ns, const double* y, double* c, void* stream);
 
 /* Regression set-up on the device: c = -F'y/Ns (y device, rows doubles). */
 rac_status rac_regression_c(const void* F, int32_t F_dtype, int64_t rows, int64_t n, int64_t ldF,

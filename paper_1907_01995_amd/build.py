@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libracmb.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["perm.hip", "assemble.hip", "sweep.hip", "update.hip", "mlp.hip", "batch.hip", "tsweep.hip", "solver.cpp",
-           "batch.cpp", "api.cpp", "noalloc.hip", "dense.hip"]
+           "batch.cpp", "api.cpp", "noalloc.hip", "dense.hip", "sparse.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -460,7 +460,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
   int64_t maxn = 0;
   for (int i = 0; i < ninst; ++i) {
     const rac_problem& P = inst[i];
-    if (P.Hd || P.meq != 0 || P.A) return RAC_ERR_UNSUPPORTED;   // the dense form is single-instance only
+    if (P.Hd || P.meq != 0 || P.A || P.colptr) return RAC_ERR_UNSUPPORTED;   // dense and sparse forms: single instance
     if (P.n < 1 || P.rows < 1 || !P.F || P.ldF < P.rows || !P.c || P.F_dtype != dtype) return RAC_ERR_ARG;
     if (P.n > 8192 || !std::isfinite(P.Ns) || !(P.Ns > 0.0) || !std::isfinite(P.b)) return RAC_ERR_ARG;
     if (dtype != RAC_DT_F64 && dtype != RAC_DT_F32 && dtype != RAC_DT_BF16) return RAC_ERR_ARG;

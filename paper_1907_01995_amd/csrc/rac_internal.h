@@ -256,6 +256,21 @@ hipError_t launch_accuracy(const double* f, const double* labels, int64_t m, dou
 hipError_t launch_hd_dots(const void* Hd, int32_t dtype, int64_t ldH, int64_t n, const double* v, double* part,
                           int* nch, hipStream_t st);
 
+// Sparse factor form (sparse.hip): F as compressed sparse columns.
+struct SparseF {
+  const int64_t* colptr;   // n + 1 offsets
+  const int32_t* rowidx;   // row of each stored entry, strictly increasing within a column
+  const void* val;         // values, dtype RAC_DT_F64 or RAC_DT_F32
+  int32_t dtype;
+};
+hipError_t launch_sgram(const SparseF& F, int64_t n, int64_t p, const int32_t* perm, int sp, double* out,
+                        hipStream_t st);
+hipError_t launch_ssweep(const SparseF& F, const SweepArgs& w, hipStream_t st);
+// out[j] = scale * F_j'v
+hipError_t launch_sdots(const SparseF& F, int64_t n, const double* v, double scale, double* out, hipStream_t st);
+// u = F x (u zeroed first; device-scope atomic additions)
+hipError_t launch_sspmv(const SparseF& F, int64_t rows, int64_t n, const double* x, double* u, hipStream_t st);
+
 struct UpdateArgs {
   int64_t n; int32_t prox; double lam, alpha, lo, hi; double b; int has_eq;
   const double* x; double* z; double* xi; double* zprev;
@@ -288,6 +303,9 @@ struct KKTArgs {
 };
 constexpr int kKKTChunks = 4;   // row chunks of the two-pass KKT check
 hipError_t launch_kkt(const KKTArgs& a, hipStream_t st);
+// The per-column terms and reduction of the check from column products already in a.part
+// (nch row chunks of n values each).
+hipError_t launch_kkt_terms(const KKTArgs& a, int nch, hipStream_t st);
 
 struct ControlArgs {
   DevScalars* sc; const double* kkt_out; int32_t beta_mode; double rb_mu, rb_tau, tol;

@@ -51,6 +51,8 @@ size_t dtype_size(int32_t dt) {
 }
 
 bool is_dense(const rac_problem* P) { return P->Hd != nullptr; }
+bool is_sparse(const rac_problem* P) { return P->colptr != nullptr; }
+SparseF sparse_of(const rac_problem& P) { return SparseF{P.colptr, P.rowidx, P.F, P.F_dtype}; }
 
 rac_status validate_problem(const rac_problem* P) {
   if (!P) return RAC_ERR_ARG;
@@ -60,8 +62,14 @@ rac_status validate_problem(const rac_problem* P) {
     if (P->F || P->rows != 0 || P->a || P->ldH < P->n) return RAC_ERR_ARG;
     if (P->H_dtype != RAC_DT_F64 && P->H_dtype != RAC_DT_F32) return RAC_ERR_ARG;
     if (P->meq < 0 || P->meq > RAC_MAX_EQ || (P->meq > 0 && (!P->A || !P->beq))) return RAC_ERR_ARG;
+    if (P->colptr || P->rowidx) return RAC_ERR_ARG;
+  } else if (is_sparse(P)) {
+    // sparse factor form: F holds the values of the compressed sparse columns
+    if (P->rows < 1 || P->rows > (int64_t)INT32_MAX || !P->F || !P->rowidx) return RAC_ERR_ARG;
+    if (P->F_dtype != RAC_DT_F64 && P->F_dtype != RAC_DT_F32) return RAC_ERR_ARG;
+    if (P->meq != 0 || P->A || P->beq) return RAC_ERR_ARG;
   } else {
-    if (P->rows < 1 || !P->F || P->ldF < P->rows) return RAC_ERR_ARG;
+    if (P->rows < 1 || !P->F || P->ldF < P->rows || P->rowidx) return RAC_ERR_ARG;
     if (dtype_size(P->F_dtype) == 0) return RAC_ERR_ARG;
     if (P->meq != 0 || P->A || P->beq) return RAC_ERR_ARG;
   }
@@ -219,6 +227,7 @@ struct rac_solver_s {
   // dense form (explicit Hessian Hd, meq equality rows): the sweep reads H_beta = Hd + beta A'A
   // (or Hd itself without rows) and c_eff = c - A'(beta beq + mu); x is its own residual
   bool dense = false;
+  bool sparse = false;             // F in compressed sparse columns: one-workgroup sweep, one stream
   int meq = 0;
   double* Hb = nullptr;            // H_beta (n x n FP64) when meq > 0
   double hb_beta = NAN;            // beta of H_beta (NaN: not formed)
@@ -260,6 +269,10 @@ DevScalars fresh_scalars(double beta) {
 }
 
 rac_status fx_into_u(rac_solver s, const double* x, double* u, hipStream_t st) {
+  if (s->sparse) {
+    HIPCHK(launch_sspmv(sparse_of(s->P), s->rows, s->n, x, u, st));
+    return RAC_OK;
+  }
   HIPCHK(launch_matvec_F_parts(s->P.F, s->P.F_dtype, s->P.ldF, s->rows, s->n, x, u, s->mv_part,
                                s->mv_nparts, st));
   return RAC_OK;
@@ -509,6 +522,60 @@ rac_status enqueue_dense_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hip
   return enqueue_check(s, k0, Tc, run_offset, st, tm);
 }
 
+// Sparse-form chunk (one stream): partitions (RAC) or orders (RP); per iteration the
+// block Grams from the sparse columns (RP: once) and their inverses (RP: when beta
+// changed), the one-workgroup sweep, and the z/dual step; then the check.
+rac_status enqueue_sparse_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
+  const rac_problem& P = s->P;
+  const SparseF SF = sparse_of(P);
+  PhaseTimer tm{s, st};
+  const int64_t k0 = s->hsc.k;
+  const bool sched = s->O.beta_mode == RAC_BETA_SCHEDULE;
+  tm.k = -1;
+  HIPCHK(tm.begin(RAC_PHASE_PARTITION));
+  if (s->rp) HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->p, s->pw_order, s->order, st));
+  else HIPCHK(launch_permutations(s->O.seed, s->O.instance, k0, Tc, s->n, s->pw, s->perm, st));
+  HIPCHK(tm.end(RAC_PHASE_PARTITION));
+  for (int64_t t = 0; t < Tc; ++t) {
+    const int64_t k = k0 + t;
+    const double* beta_ptr = beta_of(s, run_offset + t);
+    const double bk = sched ? s->sched_host[run_offset + t] : s->hsc.beta;
+    const int32_t* perm = s->rp ? s->iota : s->perm + t * s->n;
+    const int32_t* ord = s->rp ? s->order + t * s->p : nullptr;
+    tm.k = k;
+    if (!s->rp || !s->rp_gram) {
+      HIPCHK(tm.begin(st, RAC_PHASE_GRAM));
+      HIPCHK(launch_sgram(SF, s->n, s->p, perm, s->sp, s->partial, st));
+      HIPCHK(tm.end(RAC_PHASE_GRAM));
+      if (s->rp) { s->rp_gram = true; s->fac_beta = NAN; }
+    }
+    if (!s->rp || !(bk == s->fac_beta)) {
+      FactorArgs f{};
+      f.partial = s->partial; f.R = 1; f.sp = s->sp; f.n = s->n; f.p = s->p; f.perm = perm;
+      f.Ns = P.Ns; f.h = P.h; f.a = P.a; f.beta_ptr = beta_ptr; f.beta_val = 0.0; f.Minv = s->Minv;
+      f.write_matrix = 0; f.sc = s->sc; f.iter_global = k; f.order = ord;
+      HIPCHK(tm.begin(st, RAC_PHASE_FACTOR));
+      HIPCHK(launch_factor(f, st));
+      HIPCHK(tm.end(RAC_PHASE_FACTOR));
+      s->fac_beta = bk;
+    }
+    SweepArgs w{P.F, P.F_dtype, 0, s->rows, s->n, s->p, perm, s->Minv, s->sp, P.c, P.h, P.a, P.b, P.Ns, s->x,
+                s->z, s->xi, s->u, s->sc, nullptr, nullptr, 0, 1, beta_ptr, 0, 0, 0, nullptr, s->max_spin, ord, 0};
+    HIPCHK(tm.begin(st, RAC_PHASE_SWEEP));
+    HIPCHK(launch_ssweep(SF, w, st));
+    HIPCHK(tm.end(RAC_PHASE_SWEEP));
+    UpdateArgs za{};
+    za.n = s->n; za.prox = P.prox; za.lam = P.lambda; za.alpha = P.alpha; za.lo = P.lo; za.hi = P.hi;
+    za.b = P.b; za.has_eq = P.a ? 1 : 0; za.x = s->x; za.z = s->z; za.xi = s->xi; za.zprev = s->zprev;
+    za.sc = s->sc; za.red = s->red; za.done = s->done; za.hist = s->hist; za.hist_cap = s->hist_cap;
+    za.hist_base = k0 - run_offset; za.T = s->T; za.beta_ptr = beta_ptr; za.publish_beta = sched ? 1 : 0;
+    HIPCHK(tm.begin(st, RAC_PHASE_ZDUAL));
+    HIPCHK(launch_zdual(za, st));
+    HIPCHK(tm.end(RAC_PHASE_ZDUAL));
+  }
+  return enqueue_check(s, k0, Tc, run_offset, st, tm);
+}
+
 DenseKKTArgs dense_kkt_args(const rac_problem& P, const double* x, const double* z, const double* xi,
                             const double* t, const double* mu, double* part, double* red, uint32_t* done,
                             double* out) {
@@ -521,6 +588,7 @@ DenseKKTArgs dense_kkt_args(const rac_problem& P, const double* x, const double*
 
 rac_status enqueue_iteration_chunk(rac_solver s, int64_t Tc, int64_t run_offset, hipStream_t st) {
   if (s->dense) return enqueue_dense_chunk(s, Tc, run_offset, st);
+  if (s->sparse) return enqueue_sparse_chunk(s, Tc, run_offset, st);
   if (s->rp) return enqueue_rp_chunk(s, Tc, run_offset, st);
   const rac_problem& P = s->P;
   PhaseTimer tm{s, st};
@@ -607,7 +675,12 @@ rac_status enqueue_check(rac_solver s, int64_t k0, int64_t Tc, int64_t run_offse
   ka.out = s->kkt_out; ka.part = s->kkt_part;
   tm.k = -1;
   HIPCHK(tm.begin(st, RAC_PHASE_CHECK));
-  HIPCHK(launch_kkt(ka, st));
+  if (s->sparse) {
+    HIPCHK(launch_sdots(sparse_of(P), s->n, s->u, 1.0, s->kkt_part, st));
+    HIPCHK(launch_kkt_terms(ka, 1, st));
+  } else {
+    HIPCHK(launch_kkt(ka, st));
+  }
   ControlArgs ca{};
   ca.sc = s->sc; ca.kkt_out = s->kkt_out; ca.beta_mode = s->O.beta_mode; ca.rb_mu = s->O.rb_mu;
   ca.rb_tau = s->O.rb_tau; ca.tol = s->O.tol; ca.mlp_w = s->O.mlp_weights; ca.mlp_ymax = s->O.mlp_ymax;
@@ -672,13 +745,17 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   s->sp = padded(smax);
   s->rp = O.variant == RAC_VARIANT_RP;
   s->dense = is_dense(prob);
+  s->sparse = is_sparse(prob);
   s->meq = s->dense ? prob->meq : 0;
   if (s->dense) s->rows = n;   // the sweep's rows are the Hessian's: x is its own residual
   // element type the sweep reads: F, or in the dense form H_beta (FP64) / Hd
   const int32_t sweep_dt = s->dense ? (s->meq > 0 ? (int32_t)RAC_DT_F64 : prob->H_dtype) : prob->F_dtype;
   {
     int A = 0, B = 0, K = 0;
-    if (choose_tile(sweep_dt, s->rows, smax, O.sweep_groups, &A, &B, &K)) {
+    if (s->sparse) {
+      s->tileA = s->tileB = 0;   // the sparse sweep is one workgroup
+      s->K = 1;
+    } else if (choose_tile(sweep_dt, s->rows, smax, O.sweep_groups, &A, &B, &K)) {
       s->tileA = A; s->tileB = B; s->K = K;
     } else if (s->dense) {
       delete s;
@@ -690,9 +767,9 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if (s->K > s->rows) s->K = (int)s->rows;
   // overlap the assemble phase with the sweep when all sweep groups fit on the device at once
-  const bool can_overlap = !s->rp && !s->dense && s->tileA > 0 && s->K > 1 &&
+  const bool can_overlap = !s->rp && !s->dense && !s->sparse && s->tileA > 0 && s->K > 1 &&
                            s->K <= sweep_max_resident(prob->F_dtype, s->tileA, s->tileB) && O.overlap >= 0;
-  s->R = s->dense ? 1 : (O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows));
+  s->R = (s->dense || s->sparse) ? 1 : (O.row_chunks > 0 ? O.row_chunks : auto_row_chunks(s->p, prob->rows));
   if (can_overlap && O.row_chunks == 0) {
     // leave the sweep's K compute units free of Gram workgroups: a sweep group needs
     // a whole compute unit, so the next iteration's Gram would otherwise delay it
@@ -727,7 +804,8 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   }
   if ((r = alloc_perm_work(s->buf, s->T, n, &s->pw, &s->perm)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->partial, (size_t)(s->p * s->R) * s->sp * s->sp)) != RAC_OK) return fail(r);
-  if ((r = s->buf.alloc(&s->Minv, (size_t)(s->rp || s->dense ? 1 : 2) * s->p * s->sp * s->sp)) != RAC_OK)
+  if ((r = s->buf.alloc(&s->Minv, (size_t)(s->rp || s->dense || s->sparse ? 1 : 2) * s->p * s->sp * s->sp)) !=
+      RAC_OK)
     return fail(r);
   if (s->dense) {
     if (s->meq > 0) {
@@ -770,7 +848,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if ((r = s->buf.alloc(&s->mv_part, (size_t)s->mv_nparts * s->rows)) != RAC_OK) return fail(r);
   if ((r = s->buf.alloc(&s->uz, (size_t)s->rows)) != RAC_OK) return fail(r);
   // packed copies of the blocks for the register-tile sweep (one per iteration parity)
-  if (s->tileA > 0 && O.packed >= 0 && s->rows <= INT32_MAX && !s->dense) {
+  if (s->tileA > 0 && O.packed >= 0 && s->rows <= INT32_MAX && !s->dense && !s->sparse) {
     const size_t esz = prob->F_dtype == RAC_DT_F64 ? 8 : (prob->F_dtype == RAC_DT_F32 ? 4 : 2);
     s->Fp_bytes = (size_t)sweep_packed_elems(s->p, s->K, s->tileA, s->tileB) * esz;
     s->packRW = sweep_rows_per_group(s->rows, s->K, s->tileA);
@@ -795,7 +873,7 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
     if (O.max_iter > 0 &&
         hipMemcpy(s->d_sched, O.beta_schedule, sizeof(double) * O.max_iter, hipMemcpyHostToDevice) != hipSuccess)
       return fail(RAC_ERR_DEVICE);
-    if (s->rp || s->dense) s->sched_host.assign(O.beta_schedule, O.beta_schedule + O.max_iter);
+    if (s->rp || s->dense || s->sparse) s->sched_host.assign(O.beta_schedule, O.beta_schedule + O.max_iter);
     s->O.beta_schedule = nullptr;   // the caller's array is not kept
   }
   if (hipMemset(s->x, 0, sizeof(double) * n) != hipSuccess ||
@@ -1165,6 +1243,34 @@ rac_status rac_kkt(const rac_problem* prob, const double* x, const double* z, co
     return rac_kkt_mu(prob, x, z, xi, &mu, prob->meq, stream, out);
   }
   hipStream_t st = (hipStream_t)stream;
+  if (is_sparse(prob)) {
+    Buffers B;
+    double *u = nullptr, *part = nullptr, *red = nullptr, *o = nullptr;
+    uint32_t* done = nullptr;
+    rac_status r;
+    if ((r = B.alloc(&u, (size_t)prob->rows)) != RAC_OK || (r = B.alloc(&part, (size_t)prob->n)) != RAC_OK ||
+        (r = B.alloc(&red, (size_t)kRedSlots)) != RAC_OK || (r = B.alloc(&o, 4)) != RAC_OK ||
+        (r = B.alloc(&done, 4)) != RAC_OK) {
+      B.release();
+      return r;
+    }
+    const SparseF SF = sparse_of(*prob);
+    hipError_t e = hipMemsetAsync(done, 0, 4 * sizeof(uint32_t), st);
+    if (e == hipSuccess) e = launch_sspmv(SF, prob->rows, prob->n, x, u, st);
+    if (e == hipSuccess) e = launch_sdots(SF, prob->n, u, 1.0, part, st);
+    if (e == hipSuccess) {
+      KKTArgs ka{};
+      ka.n = prob->n; ka.Ns = prob->Ns; ka.h = prob->h; ka.c = prob->c; ka.a = prob->a; ka.b = prob->b;
+      ka.prox = prob->prox; ka.lam = prob->lambda; ka.alpha = prob->alpha; ka.lo = prob->lo; ka.hi = prob->hi;
+      ka.x = x; ka.z = z; ka.xi = xi; ka.mu_ptr = nullptr; ka.mu_val = mu; ka.red = red; ka.done = done; ka.out = o;
+      ka.part = part;
+      e = launch_kkt_terms(ka, 1, st);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(out, o, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    B.release();
+    return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+  }
   Buffers B;
   double *u = nullptr, *part = nullptr, *red = nullptr, *o = nullptr;
   uint32_t* done = nullptr;
@@ -1230,8 +1336,10 @@ rac_status rac_objective(const rac_problem* prob, const double* z, void* stream,
     return r;
   }
   hipError_t e = hipMemsetAsync(done, 0, 4 * sizeof(uint32_t), st);
-  if (e == hipSuccess)
-    e = launch_matvec_F_parts(prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, z, u, part, np, st);
+  if (e == hipSuccess) {
+    if (is_sparse(prob)) e = launch_sspmv(sparse_of(*prob), prob->rows, prob->n, z, u, st);
+    else e = launch_matvec_F_parts(prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, z, u, part, np, st);
+  }
   if (e == hipSuccess)
     e = launch_objective_red(prob->rows, prob->n, prob->Ns, prob->h, prob->c, prob->prox, prob->lambda,
                              prob->alpha, prob->obj_const, z, u, red, done, o, st);
@@ -1239,6 +1347,17 @@ rac_status rac_objective(const rac_problem* prob, const double* z, void* stream,
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   B.release();
   return e == hipSuccess ? RAC_OK : RAC_ERR_DEVICE;
+}
+
+rac_status rac_regression_c_csc(const int64_t* colptr, const int32_t* rowidx, const void* values, int32_t dtype,
+                                int64_t rows, int64_t n, double Ns, const double* y, double* c, void* stream) {
+  if (!colptr || !rowidx || !values || !y || !c || rows < 1 || n < 1 || !is_fin(Ns) || !(Ns > 0.0) ||
+      (dtype != RAC_DT_F64 && dtype != RAC_DT_F32))
+    return RAC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(launch_sdots(SparseF{colptr, rowidx, values, dtype}, n, y, -1.0 / Ns, c, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return RAC_OK;
 }
 
 rac_status rac_regression_c(const void* F, int32_t F_dtype, int64_t rows, int64_t n, int64_t ldF, double Ns,
@@ -1276,6 +1395,8 @@ rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed,
   if (e == hipSuccess) {
     if (dense) {
       e = launch_hgather(prob->Hd, prob->H_dtype, prob->ldH, prob->n, p, perm, sp, partial, st);
+    } else if (is_sparse(prob)) {
+      e = launch_sgram(sparse_of(*prob), prob->n, p, perm, sp, partial, st);
     } else {
       GramArgs g{prob->F, prob->F_dtype, prob->ldF, prob->rows, prob->n, p, perm, precision, R, sp, partial};
       e = launch_gram(g, st);
@@ -1283,7 +1404,7 @@ rac_status rac_block_matrices(const rac_problem* prob, int64_t p, uint64_t seed,
   }
   if (e == hipSuccess) {
     FactorArgs f{};
-    f.partial = partial; f.R = dense ? 1 : R; f.sp = sp; f.n = prob->n; f.p = p; f.perm = perm;
+    f.partial = partial; f.R = (dense || is_sparse(prob)) ? 1 : R; f.sp = sp; f.n = prob->n; f.p = p; f.perm = perm;
     f.Ns = dense ? 1.0 : prob->Ns;
     f.h = prob->h; f.a = dense ? (prob->meq == 1 ? prob->A : nullptr) : prob->a; f.beta_ptr = nullptr;
     f.beta_val = beta; f.Minv = out;

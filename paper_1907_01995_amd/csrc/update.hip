@@ -439,6 +439,14 @@ hipError_t launch_zdual(const UpdateArgs& z, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_kkt_terms(const KKTArgs& k, int nch, hipStream_t st) {
+  int64_t tb = (k.n + 255) / 256;
+  if (tb > kRedBlocks) tb = kRedBlocks;
+  k_kkt_terms<<<(unsigned)tb, 256, 0, st>>>(k.n, nch, k.part, k.Ns, k.h, k.c, k.a, k.b, k.prox, k.lam, k.alpha,
+                                            k.lo, k.hi, k.x, k.z, k.xi, k.mu_ptr, k.mu_val, k.red, k.done, k.out);
+  return hipGetLastError();
+}
+
 hipError_t launch_hd_dots(const void* Hd, int32_t dtype, int64_t ldH, int64_t n, const double* v, double* part,
                           int* nch_out, hipStream_t st) {
   const int64_t steps = (n + 255) / 256;

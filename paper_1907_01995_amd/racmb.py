@@ -41,7 +41,7 @@ EXPORTED = ["rac_solver_create", "rac_solver_destroy", "rac_solver_run", "rac_so
             "rac_batch_timing", "rac_status_str", "rac_solve", "rac_solve_batch", "rac_permutation_host",
             "rac_batch_state_export", "rac_batch_state_import", "rac_permutation_noalloc", "rac_kkt_mu",
             "rac_solver_get_multipliers", "rac_solver_set_multipliers", "rac_svm_kernel_matrix",
-            "rac_svm_decision", "rac_batch_set_lane_state"]
+            "rac_svm_decision", "rac_batch_set_lane_state", "rac_regression_c_csc"]
 
 
 class RacError(RuntimeError):
@@ -56,7 +56,8 @@ class Problem_(C.Structure):
                 ("h", C.c_void_p), ("c", C.c_void_p), ("a", C.c_void_p), ("b", C.c_double),
                 ("lam", C.c_double), ("alpha", C.c_double), ("lo", C.c_double),
                 ("hi", C.c_double), ("obj_const", C.c_double), ("Hd", C.c_void_p), ("ldH", C.c_int64),
-                ("H_dtype", C.c_int32), ("meq", C.c_int32), ("A", C.c_void_p), ("beq", C.c_void_p)]
+                ("H_dtype", C.c_int32), ("meq", C.c_int32), ("A", C.c_void_p), ("beq", C.c_void_p),
+                ("colptr", C.c_void_p), ("rowidx", C.c_void_p)]
 
 
 class Opts_(C.Structure):
@@ -151,6 +152,7 @@ def load():
         "rac_svm_kernel_matrix": [vp, C.c_int32, i64, i64, vp, C.c_double, vp, i64, vp],
         "rac_svm_decision": [vp, C.c_int32, i64, i64, vp, vp, C.c_double, C.c_double, vp, i64, vp, vp, dp, vp],
         "rac_batch_set_lane_state": [vp, C.c_int32, vp, vp, vp, C.c_double, C.c_double],
+        "rac_regression_c_csc": [vp, vp, vp, C.c_int32, i64, i64, C.c_double, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -219,11 +221,13 @@ class Problem:
     Hd: object = None    # dense form: torch tensor (n, n) symmetric (column-major = row-major), f64 or f32
     A: object = None     # dense form: torch tensor (meq, n) float64, row-major
     beq: object = None   # dense form: torch tensor (meq,) float64
+    colptr: object = None  # sparse form: torch int64 tensor (n + 1,); F then holds the values
+    rowidx: object = None  # sparse form: torch int32 tensor (nnz,)
 
     @property
     def ldF(self) -> int:
         """Leading dimension of the column-major data: F is an (n, ldF)-strided tensor view."""
-        if self.F is None:
+        if self.F is None or self.colptr is not None:
             return 0
         assert self.F.stride(1) == 1 and self.F.stride(0) >= self.rows
         return int(self.F.stride(0))
@@ -244,7 +248,9 @@ class Problem:
                         self.alpha, self.lo, self.hi, self.obj_const,
                         None if self.Hd is None else self.Hd.data_ptr(), ldH, hd_dt, self.meq,
                         None if self.A is None else self.A.data_ptr(),
-                        None if self.beq is None else self.beq.data_ptr())
+                        None if self.beq is None else self.beq.data_ptr(),
+                        None if self.colptr is None else self.colptr.data_ptr(),
+                        None if self.rowidx is None else self.rowidx.data_ptr())
 
 
 def upload_columns(D, storage, device="cuda"):
@@ -307,6 +313,33 @@ def svm_problem(X, labels, Cbox, storage="f32", device="cuda") -> Problem:
     a = torch.as_tensor(yl, device=device)
     return Problem(F=F, storage=storage, rows=r, n=n, Ns=1.0, c=c, a=a, b=0.0, prox=PROX_BOX,
                    lo=0.0, hi=float(Cbox))
+
+
+def sparse_regression_problem(colptr, rowidx, values, y, rows, lam=0.0, alpha=1.0, storage="f64", h=None,
+                              device="cuda") -> Problem:
+    """Elastic net (Sec.3.1) with sparse data F (rows x n) in compressed sparse columns (numpy or device
+    tensors: colptr int64 n + 1, rowidx int32, values exact in `storage`, "f64" or "f32"):
+    H = F'F/N, c = -F'y/N computed on the device."""
+    torch = _torch()
+    load()
+
+    def dev(a, dt):
+        return a.to(device, dt).contiguous() if hasattr(a, "data_ptr") else \
+            torch.as_tensor(np.asarray(a), dtype=dt, device=device).contiguous()
+
+    cp = dev(colptr, torch.int64)
+    ri = dev(rowidx, torch.int32)
+    vals = dev(values, torch.float64 if storage == "f64" else torch.float32)
+    n = int(cp.shape[0]) - 1
+    yt = dev(y, torch.float64)
+    c = torch.empty(n, dtype=torch.float64, device=device)
+    _check(load().rac_regression_c_csc(_ptr(cp), _ptr(ri), _ptr(vals), _DT[storage], int(rows), n, float(rows),
+                                       _ptr(yt), _ptr(c), _stream()), "rac_regression_c_csc")
+    ht = None if h is None else dev(h, torch.float64)
+    yy = float(torch.dot(yt, yt).item())
+    return Problem(F=vals, storage=storage, rows=int(rows), n=n, Ns=float(rows), c=c, h=ht,
+                   prox=PROX_EN if lam > 0 else PROX_NONE, lam=float(lam), alpha=float(alpha),
+                   obj_const=yy / (2.0 * rows), colptr=cp, rowidx=ri)
 
 
 def dense_problem(Hd, c, *, A=None, beq=None, h=None, prox=PROX_NONE, lam=0.0, alpha=1.0, lo=0.0, hi=0.0,

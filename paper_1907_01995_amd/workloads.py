@@ -283,3 +283,87 @@ def dense_qp_device(n=8192, meq=8, data_seed=7, device="cuda"):
     x0 = 0.1 + 0.8 * torch.rand(n, generator=g, device=device, dtype=torch.float64)
     beq = A @ x0
     return H.contiguous(), c, A.contiguous(), beq
+
+
+# Sparse workloads ----------------------------------------------------------------
+
+@dataclass
+class SparseRegression:
+    """Elastic-net instance with sparse data in compressed sparse columns (numpy)."""
+    name: str
+    N: int
+    n: int
+    colptr: np.ndarray     # int64, n + 1
+    rowidx: np.ndarray     # int32, nnz (strictly increasing within a column)
+    values: np.ndarray     # float64 values exact in `storage`
+    y: np.ndarray
+    lam: float
+    alpha: float
+    storage: str
+
+    def dense(self) -> np.ndarray:
+        """The same data as a dense N x n float64 array (Fortran order)."""
+        D = np.zeros((self.N, self.n), order="F")
+        for j in range(self.n):
+            a, b = self.colptr[j], self.colptr[j + 1]
+            D[self.rowidx[a:b], j] = self.values[a:b]
+        return D
+
+
+def sparse_regression(N=2000, n=600, density=0.02, nnz_frac=0.5, noise=0.05, lam_frac=0.1, alpha=0.5,
+                      data_seed=8, storage="f64", name="sparse_en") -> SparseRegression:
+    """Sparse elastic-net data (stands in for the high-sparsity regressions of Sec.3.1, Tables 3-7):
+    every column holds round(density N) entries at distinct uniformly drawn rows with N(0,1) values;
+    x_true has a fraction nnz_frac of non-zeros N(0,1); y = D x_true + noise N(0,1);
+    lambda = lam_frac lambda_max, lambda_max = |D'y|_inf / (N alpha)."""
+    rng = np.random.default_rng(data_seed)
+    k = max(1, int(round(density * N)))
+    rows = np.stack([np.sort(rng.choice(N, size=k, replace=False)) for _ in range(n)]).astype(np.int32)
+    vals = to_storage(rng.standard_normal((n, k)), storage).astype(np.float64)
+    colptr = (np.arange(n + 1, dtype=np.int64) * k)
+    rowidx = rows.reshape(-1)
+    values = vals.reshape(-1)
+    x_true = np.zeros(n)
+    nz = rng.choice(n, size=max(1, int(round(nnz_frac * n))), replace=False)
+    x_true[nz] = rng.standard_normal(nz.size)
+    y = np.zeros(N)
+    np.add.at(y, rowidx, values * np.repeat(x_true, k))
+    y += noise * rng.standard_normal(N)
+    Dty = np.zeros(n)
+    for j in range(n):
+        Dty[j] = values[j * k:(j + 1) * k] @ y[rowidx[j * k:(j + 1) * k]]
+    lam = lam_frac * np.max(np.abs(Dty)) / (N * alpha)
+    return SparseRegression(name, N, n, colptr, rowidx, values, y, float(lam), float(alpha), storage)
+
+
+def sparse_regression_device(N, n, density, nnz_frac=0.5, noise=0.05, lam_frac=0.1, alpha=0.5, data_seed=9,
+                             device="cuda"):
+    """Large sparse elastic-net data generated on the device (torch's seeded generator): every column
+    holds k = round(density N) entries at distinct rows -- the sorted draws of k integers from
+    [0, N - k] plus 0, 1, ..., k - 1 -- with N(0,1) FP32 values; x_true with a fraction nnz_frac of
+    N(0,1) non-zeros; y = D x_true + noise N(0,1); lambda = lam_frac lambda_max.
+    Returns (colptr, rowidx, values, y, lam) as device tensors / floats."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(data_seed))
+    k = max(1, int(round(density * N)))
+    draws = torch.randint(0, N - k + 1, (n, k), generator=g, device=device, dtype=torch.int64)
+    rows = torch.sort(draws, dim=1).values + torch.arange(k, device=device, dtype=torch.int64)[None, :]
+    rowidx = rows.reshape(-1).to(torch.int32).contiguous()
+    del draws, rows
+    values = torch.randn(n * k, generator=g, device=device, dtype=torch.float32)
+    colptr = torch.arange(n + 1, device=device, dtype=torch.int64) * k
+    xt = torch.zeros(n, device=device, dtype=torch.float64)
+    nz = torch.randperm(n, generator=g, device=device)[:max(1, int(round(nnz_frac * n)))]
+    xt[nz] = torch.randn(nz.numel(), generator=g, device=device, dtype=torch.float64)
+    y = torch.zeros(N, device=device, dtype=torch.float64)
+    det = torch.are_deterministic_algorithms_enabled()
+    torch.use_deterministic_algorithms(True)   # a fixed summation order, so y is the same on every run
+    try:
+        y.index_put_((rowidx.to(torch.int64),), values.double() * xt.repeat_interleave(k), accumulate=True)
+    finally:
+        torch.use_deterministic_algorithms(det)
+    y += noise * torch.randn(N, generator=g, device=device, dtype=torch.float64)
+    Dty = (values.double() * y[rowidx.to(torch.int64)]).reshape(n, k).sum(dim=1)
+    lam = lam_frac * float(Dty.abs().max().item()) / (N * alpha)
+    return colptr, rowidx, values, y, lam
