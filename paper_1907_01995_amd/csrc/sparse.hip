@@ -8,11 +8,11 @@
 // sorted row lists (a sparse dot product), summed in row order.
 //
 // Sweep (Eq.(3), blocks in the drawn order): one persistent workgroup keeps the
-// Gauss-Seidel order; per block, each wavefront forms F_j'u for its columns
-// (lanes over the column's entries, u read from device memory at agent scope),
-// the step d = -M_B^{-1} g_B follows from the inverse, and u += F_B d is applied
-// with device-scope FP64 atomic additions (several columns of a block may share
-// a row).  The atomics make the order of same-row contributions within a block
+// Gauss-Seidel order; per block, the products F_ij u_i of the block's stored
+// entries are formed flat over all threads (u read from device memory at agent
+// scope) and summed per column in entry order, the step d = -M_B^{-1} g_B
+// follows from the inverse, and u += F_B d is applied with device-scope FP64
+// atomic additions (several columns of a block may share a row).  The atomics make the order of same-row contributions within a block
 // timing-dependent, so iterates agree with the oracle to rounding, not bitwise
 // from run to run.
 #include "rac_internal.h"
@@ -112,12 +112,22 @@ struct SSweepArgs {
   double* x; const double* z; const double* xi; double* u; DevScalars* sc; const double* beta_ptr;
 };
 
+// The block's stored entries are processed flat (entry f of the block's
+// columns in block order, chunks of kFlat): every thread takes entries f = tid,
+// tid + 256, ... in batches whose loads are all issued before any is used, so
+// the dependent loads (row index, then u at that row) overlap across entries.
+constexpr int kFlat = 12288;   // entries per chunk: their products (FP64) in LDS
+constexpr int kBatch = 8;      // entries per thread whose loads are in flight together
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_ssweep(SSweepArgs s) {
   __shared__ double sh_g[kMaxBlock];
   __shared__ double sh_d[kMaxBlock];
   __shared__ int32_t cols[kMaxBlock];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int64_t cst[kMaxBlock];        // first stored entry of each block column
+  __shared__ int32_t boff[kMaxBlock + 1];   // block-local entry offsets of the columns
+  __shared__ double prod[kFlat];            // F_ij u_i of the chunk's entries
+  const int tid = threadIdx.x;
   const T* val = (const T*)s.val;
   const double beta = *s.beta_ptr;
   const double mu = s.sc->mu;
@@ -126,30 +136,80 @@ __global__ void __launch_bounds__(256) k_ssweep(SSweepArgs s) {
     const int64_t bi = s.order ? (int64_t)s.order[i] : i;
     const int64_t s0 = block_start(bi, s.n, s.p);
     const int sb = (int)(block_start(bi + 1, s.n, s.p) - s0);
-    if (tid < sb) cols[tid] = s.perm[s0 + tid];
+    if (tid < sb) {
+      const int col = s.perm[s0 + tid];
+      cols[tid] = col;
+      cst[tid] = s.colptr[col];
+      boff[tid + 1] = (int32_t)(s.colptr[col + 1] - s.colptr[col]);
+      sh_g[tid] = 0.0;
+    }
+    if (tid == 0) boff[0] = 0;
     __syncthreads();
-    // gradient: one wavefront per column, lanes over the column's entries
-    for (int j = wave; j < sb; j += 4) {
-      const int col = cols[j];
-      const int64_t e0 = s.colptr[col], e1 = s.colptr[col + 1];
-      double acc = 0.0;
-      for (int64_t e = e0 + lane; e < e1; e += 64) acc += sv(val, e) * ld_u(s.u + s.rowidx[e]);
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        const double xc = s.x[col];
-        double v = acc / s.Ns + s.c[col] - s.xi[col] + beta * (xc - s.z[col]);
-        if (s.h) v += s.h[col] * xc;
-        if (s.a) v += -mu * s.a[col] + beta * s.a[col] * (t - s.b);
-        sh_g[j] = v;
+    if (tid == 0)
+      for (int j = 0; j < sb; ++j) boff[j + 1] += boff[j];
+    __syncthreads();
+    const int E = boff[sb];
+    // gradient partials F_B'u, chunk by chunk; column sums in entry order
+    for (int f0 = 0; f0 < E; f0 += kFlat) {
+      const int fe = f0 + kFlat < E ? f0 + kFlat : E;
+      for (int fb = f0 + tid; fb < fe; fb += 256 * kBatch) {
+        int32_t row[kBatch];
+        double v[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          const int f = fb + 256 * q;
+          int64_t e = 0;   // past the chunk: entry 0 of the matrix, which exists (E >= 1), value unused
+          if (f < fe) {    // the column of entry f: the last j with boff[j] <= f
+            int lo = 0, hi = sb - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (boff[mid] <= f) lo = mid; else hi = mid - 1;
+            }
+            e = cst[lo] + (f - boff[lo]);
+          }
+          row[q] = s.rowidx[e];
+          v[q] = sv(val, e);
+        }
+        double uu[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) uu[q] = ld_u(s.u + row[q]);
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          const int f = fb + 256 * q;
+          if (f < fe) prod[f - f0] = v[q] * uu[q];
+        }
       }
+      __syncthreads();
+      if (tid < sb) {
+        const int a = boff[tid] > f0 ? boff[tid] : f0, b = boff[tid + 1] < fe ? boff[tid + 1] : fe;
+        double acc = sh_g[tid];
+        for (int f = a; f < b; ++f) acc += prod[f - f0];
+        sh_g[tid] = acc;
+      }
+      __syncthreads();
+    }
+    if (tid < sb) {
+      const int col = cols[tid];
+      const double xc = s.x[col];
+      double v = sh_g[tid] / s.Ns + s.c[col] - s.xi[col] + beta * (xc - s.z[col]);
+      if (s.h) v += s.h[col] * xc;
+      if (s.a) v += -mu * s.a[col] + beta * s.a[col] * (t - s.b);
+      sh_g[tid] = v;
     }
     __syncthreads();
-    // step d = -M_B^{-1} g (columns of the inverse, summed in k order)
+    // step d = -M_B^{-1} g: thread j takes column j of the inverse in batches of 16 loads, summed in k order
     const double* Mi = s.Minv + bi * (int64_t)s.sp * s.sp;
-    for (int j = tid; j < sb; j += 256) {
+    if (tid < sb) {
       double acc = 0.0;
-      for (int k = 0; k < sb; ++k) acc += Mi[(int64_t)k * s.sp + j] * sh_g[k];
-      sh_d[j] = -acc;
+      for (int k0 = 0; k0 < sb; k0 += 16) {
+        double mv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) mv[q] = k0 + q < sb ? Mi[(int64_t)(k0 + q) * s.sp + tid] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (k0 + q < sb) acc += mv[q] * sh_g[k0 + q];
+      }
+      sh_d[tid] = -acc;
     }
     __syncthreads();
     if (s.a) {
@@ -158,11 +218,31 @@ __global__ void __launch_bounds__(256) k_ssweep(SSweepArgs s) {
       t += dt;   // every thread forms the same sum in the same order
     }
     // residual update u += F_B d (device-scope atomics: columns may share rows), then x_B
-    for (int j = wave; j < sb; j += 4) {
-      const int col = cols[j];
-      const double dj = sh_d[j];
-      const int64_t e0 = s.colptr[col], e1 = s.colptr[col + 1];
-      for (int64_t e = e0 + lane; e < e1; e += 64) add_u(s.u + s.rowidx[e], sv(val, e) * dj);
+    for (int fb = tid; fb < E; fb += 256 * kBatch) {
+      int32_t row[kBatch];
+      double v[kBatch];
+      double dj[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int f = fb + 256 * q;
+        int64_t e = 0;   // past the block: entry 0 of the matrix, value unused
+        int j = 0;
+        if (f < E) {
+          int lo = 0, hi = sb - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (boff[mid] <= f) lo = mid; else hi = mid - 1;
+          }
+          j = lo;
+          e = cst[j] + (f - boff[j]);
+        }
+        row[q] = s.rowidx[e];
+        v[q] = sv(val, e);
+        dj[q] = sh_d[j];
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+        if (fb + 256 * q < E) add_u(s.u + row[q], v[q] * dj[q]);
     }
     if (tid < sb) s.x[cols[tid]] += sh_d[tid];
     // the additions complete at device scope before the next block's loads of u
