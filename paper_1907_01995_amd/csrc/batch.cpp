@@ -94,10 +94,10 @@ struct rac_batch_s {
   TeamArgs TA{};
   std::vector<TGroup> hgroups;
   std::vector<double> gcost;   // predicted cost of a group (LPT key)
-  std::vector<int> gwidth;     // team width a group runs on (16 or 32)
-  int max_teams = 0;           // resident / 16
+  std::vector<int> gwidth;     // team width a group runs on (1: solo, 16 or 32)
+  int max_teams = 0;           // teams of the widest split: one per resident workgroup
   int resident = 0;            // team-sweep workgroups resident at once (the launch size)
-  int k32 = 0, k16 = 0;        // current layout
+  int k32 = 0, k16 = 0, ks = 0;   // current layout: teams of 32 and 16 workgroups, solo workers
   int32_t* dteam_w = nullptr;
   int64_t* dteam_part = nullptr;
   int32_t* dblk_team = nullptr;
@@ -257,21 +257,22 @@ double lpt(const rac_batch b, int width, int k, std::vector<std::vector<int32_t>
 // each when the resident workgroups split evenly over the eight XCDs; the table
 // gives every workgroup of the launch its team (or -1) and member index.  The
 // epoch flags restart from zero, since a team may change its width.
-rac_status set_team_layout(rac_batch b, int k32, int k16) {
-  std::vector<std::vector<int32_t>> l32, l16;
+rac_status set_team_layout(rac_batch b, int k32, int k16, int ks) {
+  std::vector<std::vector<int32_t>> l32, l16, l1;
   lpt(b, 32, k32, &l32);
   lpt(b, 16, k16, &l16);
-  const int nteams = k32 + k16;
+  lpt(b, 1, ks, &l1);
+  const int nteams = k32 + k16 + ks;
   std::vector<int32_t> off(nteams + 1, 0), flat, tw(nteams);
   std::vector<int64_t> tpart(nteams);
   int64_t poff = 0;
   for (int t = 0; t < nteams; ++t) {
-    const std::vector<int32_t>& L = t < k32 ? l32[t] : l16[t - k32];
+    const std::vector<int32_t>& L = t < k32 ? l32[t] : (t < k32 + k16 ? l16[t - k32] : l1[t - k32 - k16]);
     off[t] = (int32_t)flat.size();
     flat.insert(flat.end(), L.begin(), L.end());
-    tw[t] = t < k32 ? 32 : 16;
+    tw[t] = t < k32 ? 32 : (t < k32 + k16 ? 16 : 1);
     tpart[t] = poff;
-    poff += 2 * 1024 * (int64_t)tw[t];
+    if (tw[t] > 1) poff += 2 * 1024 * (int64_t)tw[t];   // solo workers exchange nothing
   }
   off[nteams] = (int32_t)flat.size();
   const int R = b->resident;
@@ -279,9 +280,15 @@ rac_status set_team_layout(rac_batch b, int k32, int k16) {
   if (R % 8 == 0 && R / 8 >= 32) {
     const int per = R / 8;
     std::vector<int> used(8, 0);
-    for (int t = 0; t < nteams; ++t) {       // widest first: teams of 32, then of 16
+    for (int t = 0; t < nteams; ++t) {       // widest first: teams of 32, of 16, then solo workers
       int x = 0;
-      while (x < 8 && used[x] + tw[t] > per) ++x;
+      if (tw[t] == 1) {                      // solo workers go to the least used XCD
+        for (int y = 1; y < 8; ++y)
+          if (used[y] < used[x]) x = y;
+        if (used[x] + 1 > per) x = 8;
+      } else {
+        while (x < 8 && used[x] + tw[t] > per) ++x;
+      }
       if (x == 8) return RAC_ERR_ARG;        // cannot happen: the widths sum to at most R
       for (int m = 0; m < tw[t]; ++m) {
         const int blk = 8 * (used[x] + m) + x;
@@ -309,6 +316,7 @@ rac_status set_team_layout(rac_batch b, int k32, int k16) {
   b->TA.nblocks = R;
   b->k32 = k32;
   b->k16 = k16;
+  b->ks = ks;
   if (b->gexec) {   // a captured graph holds the old launch configuration
     (void)hipGraphExecDestroy(b->gexec);
     (void)hipGraphDestroy(b->graph);
@@ -321,19 +329,48 @@ rac_status set_team_layout(rac_batch b, int k32, int k16) {
 // Layouts worth trying, best predicted first: every split of the resident
 // workgroups into teams of 32 and 16 that gives each width it needs a team,
 // ranked by the largest predicted team load.
-std::vector<std::pair<int, int>> team_layouts(rac_batch b) {
-  bool need32 = false, need16 = false;
-  for (int w : b->gwidth) (w == 32 ? need32 : need16) = true;
+struct Layout {
+  int k32, k16, ks;
+  bool operator==(const Layout& o) const { return k32 == o.k32 && k16 == o.k16 && ks == o.ks; }
+};
+
+// A solo workgroup reads the block's columns as aligned 4-element vectors at clamped
+// rows, so the quad that holds a column's last row may reach past it, up to the
+// column's leading dimension: that needs ldF a multiple of 4, F aligned to 4 elements,
+// and the last column's ldF elements inside F's device allocation.
+static bool solo_layout_ok(const rac_problem& P) {
+  const size_t esz = P.F_dtype == RAC_DT_F64 ? 8 : (P.F_dtype == RAC_DT_F32 ? 4 : 2);
+  if (P.ldF % 4 != 0 || (uintptr_t)P.F % (4 * esz) != 0) return false;
+  void* base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(P.F)) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (uintptr_t)P.F + (size_t)P.n * (size_t)P.ldF * esz <= (uintptr_t)base + size;
+}
+
+// Layouts worth trying, best predicted first: every split of the resident
+// workgroups into solo workers (in steps of 8) and teams of 32 and 16 that gives
+// each width it needs a worker, ranked by the largest predicted load.
+std::vector<Layout> team_layouts(rac_batch b) {
+  bool need32 = false, need16 = false, need1 = false;
+  for (int w : b->gwidth) (w == 32 ? need32 : (w == 16 ? need16 : need1)) = true;
   const int R = b->resident;
-  std::vector<std::pair<double, std::pair<int, int>>> c;
-  for (int k32 = 0; 32 * k32 <= R; ++k32) {
-    const int k16 = (R - 32 * k32) / 16;
-    if ((need32 && k32 == 0) || (need16 && k16 == 0)) continue;
-    const int u32 = need32 ? k32 : 0, u16 = need16 ? k16 : 0;
-    c.push_back({std::max(lpt(b, 32, u32, nullptr), lpt(b, 16, u16, nullptr)), {u32, u16}});
+  std::vector<std::pair<double, Layout>> c;
+  for (int ks = need1 ? 8 : 0; ks <= (need1 ? R : 0); ks += 8) {
+    const int Rt = R - ks;
+    for (int k32 = 0; 32 * k32 <= Rt; ++k32) {
+      const int k16 = (Rt - 32 * k32) / 16;
+      if ((need32 && k32 == 0) || (need16 && k16 == 0)) continue;
+      const int u32 = need32 ? k32 : 0, u16 = need16 ? k16 : 0;
+      const double load = std::max(std::max(lpt(b, 32, u32, nullptr), lpt(b, 16, u16, nullptr)),
+                                   lpt(b, 1, ks, nullptr));
+      c.push_back({load, Layout{u32, u16, ks}});
+    }
   }
   std::stable_sort(c.begin(), c.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
-  std::vector<std::pair<int, int>> out;
+  std::vector<Layout> out;
   for (auto& e : c)
     if (std::find(out.begin(), out.end(), e.second) == out.end()) out.push_back(e.second);
   return out;
@@ -343,17 +380,17 @@ std::vector<std::pair<int, int>> team_layouts(rac_batch b) {
 // state) and keep the fastest.
 rac_status autotune_team(rac_batch b) {
   const std::string path = tune_cache_path();
-  std::vector<std::pair<int, int>> cand = team_layouts(b);
+  std::vector<Layout> cand = team_layouts(b);
   if (cand.size() > 3) cand.resize(3);
   if (FILE* f = std::fopen(path.c_str(), "r")) {
     char line[640], key[512];
-    int a = 0, c = 0;
+    int a = 0, c = 0, d = 0;
     while (std::fgets(line, sizeof(line), f))
-      if (std::sscanf(line, "%511s %d %d", key, &a, &c) == 3)
+      if (std::sscanf(line, "%511s %d %d %d", key, &a, &c, &d) == 4)
         for (auto& cd : cand)
-          if (b->tune_key == key && cd.first == a && cd.second == c) {
+          if (b->tune_key == key && cd.k32 == a && cd.k16 == c && cd.ks == d) {
             std::fclose(f);
-            return set_team_layout(b, a, c);
+            return set_team_layout(b, a, c, d);
           }
     std::fclose(f);
   }
@@ -364,9 +401,9 @@ rac_status autotune_team(rac_batch b) {
   BCHK(hipEventCreate(&e0));
   BCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  std::pair<int, int> pick = cand[0];
+  Layout pick = cand[0];
   for (auto& cd : cand) {
-    r = set_team_layout(b, cd.first, cd.second);
+    r = set_team_layout(b, cd.k32, cd.k16, cd.ks);
     if (r != RAC_OK) return r;
     BCHK(hipEventRecord(e0, b->cs));
     r = enqueue_chunk(b, b->T, b->cs);
@@ -385,10 +422,10 @@ rac_status autotune_team(rac_batch b) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (FILE* f = std::fopen(path.c_str(), "a")) {
-    std::fprintf(f, "%s %d %d\n", b->tune_key.c_str(), pick.first, pick.second);
+    std::fprintf(f, "%s %d %d %d\n", b->tune_key.c_str(), pick.k32, pick.k16, pick.ks);
     std::fclose(f);
   }
-  return set_team_layout(b, pick.first, pick.second);
+  return set_team_layout(b, pick.k32, pick.k16, pick.ks);
 }
 
 // Time one chunk with each sweep row unroll on this batch (from the same
@@ -583,8 +620,14 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
     bool fits = true;
     int64_t need = 0;
     std::vector<int> width(ninst, 0);
+    int64_t solo_rows = kSoloRows;
+    if (const char* e = std::getenv("RACMB_SOLO_ROWS")) solo_rows = std::atoll(e);
     for (int i = 0; i < ninst; ++i) {
       if (by_inst[i].empty()) continue;
+      if (inst[i].rows <= solo_rows && solo_layout_ok(inst[i])) {   // one workgroup streams the instance
+        width[i] = 1;
+        continue;
+      }
       width[i] = member_rows(inst[i].rows, 16) <= 64 * ntmax ? 16 : 32;
       if (member_rows(inst[i].rows, width[i]) > 64 * ntmax) fits = false;
       need = std::max<int64_t>(need, member_rows(inst[i].rows, width[i]));
@@ -598,9 +641,11 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
         const rac_problem& P = inst[i];
         const int vec4 = (P.ldF % 4 == 0) && ((uintptr_t)P.F % (uintptr_t)(4 * esz) == 0);
         const int vec8 = (P.ldF % 8 == 0) && ((uintptr_t)P.F % 16 == 0);
-        // predicted time of one of the group's blocks (us): exchanges plus the member's products
+        // predicted time of one of the group's blocks (us): a team's exchanges plus the member's
+        // products, or a solo workgroup's products over all rows and its solves (both measured)
         const double rw = (double)((P.rows + width[i] - 1) / width[i]);
-        const double cost = (double)b->hinst[i].p * (14.0 + 12.0 * rw / 640.0);
+        const double cost = (double)b->hinst[i].p *
+                            (width[i] == 1 ? 28.0 + 29.0 * (double)P.rows / 1000.0 : 14.0 + 12.0 * rw / 640.0);
         for (size_t g0 = 0; g0 < by_inst[i].size(); g0 += 16) {
           TGroup G{};
           G.inst = i;
@@ -614,7 +659,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
         }
       }
       const int ng = (int)b->hgroups.size();
-      const int maxt = resident / 16;
+      const int maxt = resident;   // at most one team (or solo worker) per workgroup
       b->resident = resident;
       b->max_teams = maxt;
       b->TA.NT = NT;
@@ -643,9 +688,9 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
       b->TA.blk_team = b->dblk_team;
       b->TA.blk_member = b->dblk_member;
       b->team = true;
-      const std::vector<std::pair<int, int>> lay = team_layouts(b);
+      const std::vector<Layout> lay = team_layouts(b);
       if (lay.empty()) return fail(RAC_ERR_UNSUPPORTED);
-      const rac_status r = set_team_layout(b, lay[0].first, lay[0].second);
+      const rac_status r = set_team_layout(b, lay[0].k32, lay[0].k16, lay[0].ks);
       if (r != RAC_OK) return fail(r);
     } else if (O.sweep == RAC_BSWEEP_TEAM) {
       return fail(RAC_ERR_UNSUPPORTED);
@@ -655,11 +700,11 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
   if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) return fail(RAC_ERR_DEVICE);
   char key[256];
   if (b->team) {
-    int n32 = 0;
-    for (int w : b->gwidth) n32 += w == 32;
-    std::snprintf(key, sizeof(key), "tsweep2:dt%d:sp%d:lanes%d:groups%d:g32_%d:rows%lld:NT%d:R%d:T%d:gfx950", dtype,
-                  b->SP, nlanes, (int)b->hgroups.size(), n32, (long long)(rows_sum / 1024), b->TA.NT, b->resident,
-                  b->T);
+    int n32 = 0, n1 = 0;
+    for (int w : b->gwidth) { n32 += w == 32; n1 += w == 1; }
+    std::snprintf(key, sizeof(key), "tsweep3:dt%d:sp%d:lanes%d:groups%d:g32_%d:g1_%d:rows%lld:NT%d:R%d:T%d:gfx950",
+                  dtype, b->SP, nlanes, (int)b->hgroups.size(), n32, n1, (long long)(rows_sum / 1024), b->TA.NT,
+                  b->resident, b->T);
   }
   else
     std::snprintf(key, sizeof(key), "bsweep:dt%d:sp%d:lanes%d:rows%lld:T%d:gfx950", dtype, b->SP, nlanes,
@@ -858,7 +903,7 @@ rac_status rac_batch_info(rac_batch b, int64_t* info) {
   info[3] = b->A.ninv;
   info[4] = b->A.unroll;
   info[5] = b->graph_used ? 1 : 0;
-  info[6] = b->team ? (b->k32 > 0 ? 32 : 16) : 0;
+  info[6] = b->team ? (b->k32 > 0 ? 32 : (b->k16 > 0 ? 16 : 1)) : 0;
   info[7] = b->team ? b->TA.nteams : 0;
   return RAC_OK;
 }

@@ -119,6 +119,305 @@ __device__ __forceinline__ double quad_at(const RawQ<T>& r, int i) {
   }
 }
 
+// Solo groups (a team of one workgroup): the group's instance is small enough
+// that one compute unit runs its products at the matrix cores' rate without a
+// cross-unit exchange.  The workgroup streams all rows of the block's columns
+// and of u (u of the 16 lanes stays in device memory, rows in 16-row tiles
+// dealt to the wavefronts round-robin, loads issued several tiles ahead), reduces
+// the gradient partials over its wavefronts in LDS, solves the 16 lanes'
+// blocks itself, all at once (thread (column, part): a 16-row slice of every
+// lane's product with its inverse, the inverses read from device memory a few
+// lanes ahead), and applies the update product to u tile by tile.  Tile layouts are those of the team path below; the arithmetic of a
+// group depends only on the group (a group is solo or not by its instance's
+// row count alone), so every team layout gives the same results.
+
+// Loads through the global address space (the pointers come from descriptor tables, so
+// the compiler would otherwise issue flat loads, which also count against lgkmcnt).
+template <typename V>
+__device__ __forceinline__ V gld(const void* p) {
+  return *(const __attribute__((address_space(1))) V*)p;
+}
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ RawQ<T> gld_quad(const T* p) {
+  RawQ<T> r;
+  if constexpr (sizeof(T) == 2) {
+    const u32x2_t v = gld<u32x2_t>(p);
+    r.v.x = v.x;
+    r.v.y = v.y;
+  } else if constexpr (sizeof(T) == 4) {
+    const f32x4_t v = gld<f32x4_t>(p);
+    r.v = make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    const f64x2_t a = gld<f64x2_t>(p), b = gld<f64x2_t>(p + 2);
+    r.a = make_double2(a.x, a.y);
+    r.b = make_double2(b.x, b.y);
+  }
+  return r;
+}
+// Zeroes the elements i >= nv (nv <= 0: all) of a quad loaded at a clamped address.
+// Applied where the quad is consumed, so that its load can stay in flight until then.
+template <typename T>
+__device__ __forceinline__ RawQ<T> quad_keep(RawQ<T> r, int64_t nv) {
+  if constexpr (sizeof(T) == 2) {
+    r.v.x &= nv >= 2 ? 0xffffffffu : (nv == 1 ? 0x0000ffffu : 0u);
+    r.v.y &= nv >= 4 ? 0xffffffffu : (nv == 3 ? 0x0000ffffu : 0u);
+  } else if constexpr (sizeof(T) == 4) {
+    r.v.x = nv > 0 ? r.v.x : 0.f;
+    r.v.y = nv > 1 ? r.v.y : 0.f;
+    r.v.z = nv > 2 ? r.v.z : 0.f;
+    r.v.w = nv > 3 ? r.v.w : 0.f;
+  } else {
+    r.a.x = nv > 0 ? r.a.x : 0.0;
+    r.a.y = nv > 1 ? r.a.y : 0.0;
+    r.b.x = nv > 2 ? r.b.x : 0.0;
+    r.b.y = nv > 3 ? r.b.y : 0.0;
+  }
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void solo_group(const BatchArgs& B, const TGroup* G, int t, double (*red)[16][64],
+                                           double* lds, int32_t* cols, double* TS, int32_t* SU) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane >> 4, j = lane & 15;
+  const int jc = tid & 63, part = tid >> 6;   // solve layout: column jc, rows 16 part .. 16 part + 15 of M^{-1}
+  const int nl = G->nl;
+  const BInst I = B.inst[G->inst];
+  const T* F = (const T*)I.F;
+  const int64_t n = I.n, p = I.p, rows = I.rows, ldF = I.ldF;
+  const int ntile = (int)((rows + 15) >> 4);
+  const int mine = ntile > wave ? (ntile - wave + NW - 1) / NW : 0;   // this wavefront's tiles
+  const int uj = j < nl ? G->lane[j] : -1;
+  const bool actj = uj >= 0 && B.sc[uj].status == 0;
+  double* Uj = actj ? B.U + B.units[uj].uoff : nullptr;
+  const double* Ubase = actj ? Uj : B.U;     // a valid address for the loads of idle slots
+  const int64_t rpi = 4 * (j & 3) + (j >> 2);
+  const int32_t* pm = B.perm + I.poff + (int64_t)t * n;
+  // LDS (lds: 4096 doubles): [64 columns][16 slots] each of
+  double* P = lds;                 // gradient partials, then gradients
+  double* D = lds + 1024;          // steps
+  double* GB = lds + 2048;         // iterate-fixed gradient terms
+  // red: the products' partials per wavefront, then the solve's partial products;
+  // TS: t = a'x of the 16 slots; SU: the lane of each slot, or -1 when the slot is idle
+  __syncthreads();                 // the previous group is done with TS and SU
+  if (tid < 16) {
+    const int u = tid < nl ? G->lane[tid] : -1;
+    const bool act = u >= 0 && B.sc[u].status == 0;
+    SU[tid] = act ? u : -1;
+    TS[tid] = act ? B.sc[u].t : 0.0;
+  }
+  __syncthreads();
+  const int32_t* su = SU;
+  // slots of inverse rows in flight ahead of their use (the first MD issued before the
+  // gradient product, which they overlap), and the pipeline stages of the tile loads of the
+  // two products (deeper pipelines measured no faster and spill registers)
+  constexpr int MD = 4, SDG = 4, SDU = 4;
+  for (int64_t blk = 0; blk < p; ++blk) {
+    const int64_t s0 = block_start(blk, n, p);
+    const int sb = (int)(block_start(blk + 1, n, p) - s0);
+    __syncthreads();                       // the previous block is done with cols and the LDS arrays
+    if (tid < 64) cols[tid] = tid < sb ? pm[s0 + tid] : pm[s0];
+    __syncthreads();
+    // the iterate-fixed gradient terms of every (column, slot) and the first MD inverses
+    // are issued before the products, which they overlap
+    double gbv[4], xcv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int L = 4 * part + e;   // thread: column jc, slots 4 part .. 4 part + 3
+      gbv[e] = 0.0;
+      xcv[e] = 0.0;
+      if (su[L] >= 0 && jc < sb) {
+        const BUnit* U = B.units + su[L];
+        const int col = cols[jc];
+        const double xc = B.X[U->xoff + col];
+        double g = U->c[col] - B.XI[U->xoff + col] + B.sc[su[L]].beta * (xc - B.Z[U->xoff + col]);
+        if (U->h) g += U->h[col] * xc;
+        if (U->a) g -= B.sc[su[L]].mu * U->a[col];
+        gbv[e] = g;
+        xcv[e] = xc;
+      }
+    }
+    double mreg[MD][16];
+    // rows 16 part .. 16 part + 15 of column jc of slot L's inverse (addresses clamped into
+    // the block; rows past sb are masked where they are used)
+    auto minv_issue = [&](int L, double (&dst)[16]) {
+      const int u = su[L];
+      const double* Mo = B.Minv + (u >= 0 ? (B.units[u].moff + blk) * (int64_t)B.sp * B.sp : 0);
+      const int jj = jc < B.sp ? jc : B.sp - 1;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int k = 16 * part + e;
+        dst[e] = gld<double>(Mo + (int64_t)(k < B.sp ? k : B.sp - 1) * B.sp + jj);
+      }
+    };
+#pragma unroll
+    for (int L = 0; L < MD; ++L) minv_issue(L, mreg[L]);
+    // 1. P = F_B'[u_1 .. u_16] over all rows
+    const T* fcg[4];             // columns 16 ct + j of the block (the first column past sb)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) fcg[ct] = F + (int64_t)cols[16 * ct + j] * ldF;
+    f64x4 acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    {
+      RawQ<T> gq[SDG][4];
+      double uv[SDG][4];
+      // tile loads without branches: every address is clamped into the columns (rows past
+      // the end and tiles past the wavefront's last read the column's last aligned quad, u
+      // its last row), and the rows past the end are zeroed where the quad is consumed, so
+      // that SDG - 1 tiles of loads stay in flight together
+      auto gload = [&](int sidx, RawQ<T> (&dst)[4], double (&ud)[4]) {
+        const int64_t r0 = 16 * (int64_t)(wave + NW * sidx) + 4 * q;
+        const int64_t rc = r0 < ldF - 4 ? r0 : ldF - 4;
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) dst[ct] = gld_quad<T>(fcg[ct] + rc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ud[i] = gld<double>(Ubase + (r0 + i < rows ? r0 + i : rows - 1));
+      };
+#pragma unroll
+      for (int sidx = 0; sidx < SDG - 1; ++sidx) gload(sidx, gq[sidx], uv[sidx]);
+      for (int base = 0; base < mine; base += SDG) {
+#pragma unroll
+        for (int k = 0; k < SDG; ++k) {
+          const int sidx = base + k;
+          gload(sidx + SDG - 1, gq[(k + SDG - 1) % SDG], uv[(k + SDG - 1) % SDG]);
+          // rows past the end (all rows of tiles past the wavefront's last) count zero; the
+          // products of consecutive steps are independent
+          const int64_t nv = rows - (16 * (int64_t)(wave + NW * sidx) + 4 * q);
+          RawQ<T> fq[4];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) fq[ct] = quad_keep<T>(gq[k][ct], nv);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+              acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(quad_at<T>(fq[ct], i), uv[k][i], acc[ct], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    // acc[ct][r] of lane (q, j) = P[column 16 ct + 4 r + q][slot j]; summed over the wavefronts in order
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][4 * ct + r][lane] = acc[ct][r];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) GB[jc * 16 + 4 * part + e] = gbv[e];
+    __syncthreads();
+    // 2. the gradients of the 16 slots: partials summed over the wavefronts in order, then
+    //    scaled and completed with the iterate-fixed terms (the slot of a thread is tid mod 16)
+    {
+      const int sl = tid & 15, u = su[sl];
+      double ns = 1.0, beta = 0.0, bb = 0.0;
+      const double* av = nullptr;
+      if (u >= 0) {
+        const BUnit* U = B.units + u;
+        ns = U->Ns;
+        av = U->a;
+        bb = U->b;
+        beta = B.sc[u].beta;
+      }
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int e = tid + 256 * rr, el = e >> 6, ln = e & 63;
+        const double v = ((red[0][el][ln] + red[1][el][ln]) + red[2][el][ln]) + red[3][el][ln];
+        const int col = 16 * (el >> 2) + 4 * (el & 3) + (ln >> 4);
+        double g = 0.0;
+        if (u >= 0 && col < sb) {
+          g = v / ns + GB[col * 16 + sl];
+          if (av) g += beta * av[cols[col]] * (TS[sl] - bb);
+        }
+        P[col * 16 + sl] = g;
+      }
+    }
+    __syncthreads();
+    // 3. d = -M^{-1} g of the 16 slots at once: thread (jc, part) forms the 16-row slice
+    //    part of every slot's product for column jc, the inverses MD slots ahead; the
+    //    slices of a column are added in order
+    double* PG = &red[0][0][0];   // [16 slots][4 parts][64 columns]
+#pragma unroll
+    for (int L = 0; L < 16; ++L) {
+      double a2 = 0.0;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double m = 16 * part + e < sb ? mreg[L % MD][e] : 0.0;
+        a2 += m * P[(16 * part + e) * 16 + L];
+      }
+      PG[(L * 4 + part) * 64 + jc] = a2;
+      if (L + MD < 16) minv_issue(L + MD, mreg[L % MD]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int L = 4 * part + e, u = su[L];   // u is the same over the wavefront
+      double d = 0.0;
+      if (u >= 0 && jc < sb) {
+        const double* pg = PG + L * 256 + jc;
+        d = -(((pg[0] + pg[64]) + pg[128]) + pg[192]);
+      }
+      D[jc * 16 + L] = d;
+      if (u >= 0) {
+        const BUnit* U = B.units + u;
+        if (jc < sb) B.X[U->xoff + cols[jc]] = xcv[e] + d;
+        if (U->a) {
+          const double dt = wave_sum(jc < sb ? U->a[cols[jc]] * d : 0.0);
+          if (jc == 0) TS[L] += dt;
+        }
+      }
+    }
+    __syncthreads();
+    // 4. [u_1 .. u_16] += F_B [d_1 .. d_16], tile by tile
+    {
+      double dreg[16];             // d of columns 4 m + q (zero past sb and for idle slots)
+#pragma unroll
+      for (int m = 0; m < 16; ++m) dreg[m] = actj ? D[(4 * m + q) * 16 + j] : 0.0;
+      const T* fcu[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) fcu[m] = F + (int64_t)cols[4 * m + q] * ldF;
+      T uq[SDU][16];
+      double uv[SDU][4];
+      // clamped loads again: a row past the end reads the column's last row and is not
+      // stored; columns past the block read the block's first column, times d = 0
+      auto uload = [&](int sidx, T (&dst)[16], double (&ud)[4]) {
+        const int64_t rr = 16 * (int64_t)(wave + NW * sidx) + rpi;
+        const int64_t rrc = rr < rows ? rr : rows - 1;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) dst[m] = gld<T>(fcu[m] + rrc);
+        const int64_t r0 = 16 * (int64_t)(wave + NW * sidx) + 4 * q;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ud[i] = gld<double>(Ubase + (r0 + i < rows ? r0 + i : rows - 1));
+      };
+#pragma unroll
+      for (int sidx = 0; sidx < SDU - 1; ++sidx) uload(sidx, uq[sidx], uv[sidx]);
+      for (int base = 0; base < mine; base += SDU) {
+#pragma unroll
+        for (int k = 0; k < SDU; ++k) {
+          const int sidx = base + k;
+          uload(sidx + SDU - 1, uq[(k + SDU - 1) % SDU], uv[(k + SDU - 1) % SDU]);
+          {   // four independent accumulator chains (columns m mod 4), added in order
+            f64x4 ac[4] = {{uv[k][0], uv[k][1], uv[k][2], uv[k][3]}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0},
+                           {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+            for (int m = 0; m < 16; ++m)
+              ac[m & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(to_f64(uq[k][m]), dreg[m], ac[m & 3], 0, 0, 0);
+            const f64x4 a4 = (ac[0] + ac[1]) + (ac[2] + ac[3]);
+            const int64_t r0 = 16 * (int64_t)(wave + NW * sidx) + 4 * q;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)   // per-lane predicated stores (rows past the end, idle slots)
+              if (actj && sidx < mine && r0 + i < rows) Uj[r0 + i] = a4[i];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < 16 && su[tid] >= 0 && B.units[su[tid]].a) B.sc[su[tid]].t = TS[tid];
+}
+
 // Register layout (wavefront v, lane = 16 q + j): tile = v + NW s covers rows
 // rb + 16 tile .. +15; ur[s][i] holds u[rb + 16 tile + 4 q + i] of lane slot j.
 // That is the B operand of the gradient product (k = q, n = j) and, with the
@@ -152,8 +451,19 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
   __shared__ double shg[NW][64];
   __shared__ int32_t colsb[2][64];           // column indices of this block and the next
   __shared__ int32_t give_up;
+  __shared__ double solo_ts[16];
+  __shared__ int32_t solo_su[16];
   if (tid == 0) give_up = 0;
   const int g0 = TA.team_off[team], g1 = TA.team_off[team + 1];
+  if (W == 1) {   // a solo worker: its groups one after another, no exchange
+    for (int gi = g0; gi < g1; ++gi) {
+      const TGroup* G = TA.groups + TA.team_list[gi];
+      bool any = false;
+      for (int L = 0; L < G->nl; ++L) any |= B.sc[G->lane[L]].status == 0;
+      if (any) solo_group<T>(B, G, t, red, minv_lds, colsb[0], solo_ts, solo_su);
+    }
+    return;
+  }
   for (int gi = g0; gi < g1; ++gi) {
     const TGroup* G = TA.groups + TA.team_list[gi];
     const int nl = G->nl;

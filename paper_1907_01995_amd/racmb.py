@@ -470,12 +470,13 @@ class Solver:
             self.lib.rac_solver_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # At interpreter shutdown the HIP runtime may already be finalised (torch and
         # profiler tools register their own exit handlers), and rac_*_destroy
         # synchronises the device and frees memory: make no HIP call then, the
         # process exit releases the device memory.  Call close() for a prompt release.
-        if sys.is_finalizing():
+        # (The check is bound at definition time: module globals may be gone by then.)
+        if _finalizing():
             return
         try:
             self.close()
@@ -729,12 +730,13 @@ class Batch:
             self.lib.rac_batch_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # At interpreter shutdown the HIP runtime may already be finalised (torch and
         # profiler tools register their own exit handlers), and rac_*_destroy
         # synchronises the device and frees memory: make no HIP call then, the
         # process exit releases the device memory.  Call close() for a prompt release.
-        if sys.is_finalizing():
+        # (The check is bound at definition time: module globals may be gone by then.)
+        if _finalizing():
             return
         try:
             self.close()

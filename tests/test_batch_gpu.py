@@ -20,6 +20,17 @@ def say(*a):
     print(*a, flush=True)
 
 
+@pytest.fixture(autouse=True, params=["solo", "teams"])
+def group_mode(request, monkeypatch):
+    """Every test runs with the default assignment (instances of up to 3072 rows run their
+    lane groups solo, one workgroup each) and with every group on a team of workgroups."""
+    if request.param == "teams":
+        monkeypatch.setenv("RACMB_SOLO_ROWS", "0")
+    else:
+        monkeypatch.delenv("RACMB_SOLO_ROWS", raising=False)
+    return request.param
+
+
 def rel(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
 
@@ -200,3 +211,25 @@ def test_batch_phase_timing_counts_every_launch():
     res, x, z, xi = b.lane(0)
     ref = oracle_lane(ops[lanes[0][0]], lanes[0], s=32, seed=1, max_iter=20, check_every=10)
     assert rel(z, ref.z) < 1e-8                       # timing does not change the iteration
+
+
+def test_solo_and_team_groups_in_one_launch():
+    """Instances on both sides of the solo bound (3072 rows) in one batch: solo groups and
+    teams run in the same launch; every lane matches the oracle (FP64)."""
+    rng = np.random.default_rng(31)
+    shapes = [(4100, 90), (800, 130), (3072, 64), (3073, 40), (150, 33)]
+    gps, ops, lanes = [], [], []
+    for i, (N, n) in enumerate(shapes):
+        w = W.gaussian_en(N, n, 0.1, 0.05, 0.1, 0.5, 700 + i, 32, "f64")
+        gps.append(racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=0.5, storage="f64"))
+        ops.append(O.en_problem(w.D, w.y, lam=w.lam, alpha=0.5))
+        for k in range(3 if i != 1 else 18):
+            lanes.append((i, racmb.PROX_EN, w.lam * 2.0 ** (1 - 0.5 * k), 0.5, float(10 ** rng.uniform(-1.0, 0.5))))
+    b = racmb.Batch(gps, lanes, s=32, seed=8, max_iter=30, check_every=10, use_graph=True,
+                    sweep=racmb.BSWEEP_TEAM)
+    b.run()
+    say(b.info())
+    for u, lane in enumerate(lanes):
+        res, x, z, xi = b.lane(u)
+        ref = oracle_lane(ops[lane[0]], lane, s=32, seed=8, max_iter=30, check_every=10)
+        assert rel(z, ref.z) < 1e-8 and rel(xi, ref.xi) < 1e-8 and rel(x, ref.x) < 1e-8, u
