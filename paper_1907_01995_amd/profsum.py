@@ -26,7 +26,8 @@ import sys
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = {"k_sweep2": ["csrc/sweep.hip", "csrc/rac_internal.h"]}
+KERNEL_SOURCES = {"k_sweep2": ["csrc/sweep.hip", "csrc/rac_internal.h"],
+                  "k_tsweep": ["csrc/tsweep.hip", "csrc/batch.cpp", "csrc/rac_internal.h"]}
 
 
 def short_name(name: str) -> str:
