@@ -95,6 +95,13 @@ struct rac_batch_s {
   std::vector<TGroup> hgroups;
   std::vector<double> gcost;   // predicted cost of a group (LPT key)
   std::vector<int> gwidth;     // team width a group runs on (1: solo, 16 or 32)
+  // the two width sets: with solo groups (chosen at creation) and teams only, and the
+  // predicted cost of each group under each; solo_on: the first set is in use
+  std::vector<int> gw_solo, gw_team;
+  std::vector<double> gc_solo, gc_team;
+  bool solo_on = false;
+  int lay0_k32 = 0, lay0_k16 = 0, lay0_ks = 0;   // layout of the solo set (tuned at creation)
+  int32_t decided_active = -1;                   // active lanes when the widths were last decided
   int max_teams = 0;           // teams of the widest split: one per resident workgroup
   int resident = 0;            // team-sweep workgroups resident at once (the launch size)
   int k32 = 0, k16 = 0, ks = 0;   // current layout: teams of 32 and 16 workgroups, solo workers
@@ -228,6 +235,7 @@ struct BatchStateHeader {
   int64_t nunits, ninst, state_bytes;
   int64_t k;                // iterations run by the batch
   int64_t scalars_bytes;
+  int64_t solo_on;          // the lane groups' widths in use (solo groups or teams only)
 };
 constexpr uint64_t kBatchStateMagic = 0x5241434241544348ULL;   // "RACBATCH"
 
@@ -374,6 +382,49 @@ std::vector<Layout> team_layouts(rac_batch b) {
   for (auto& e : c)
     if (std::find(out.begin(), out.end(), e.second) == out.end()) out.push_back(e.second);
   return out;
+}
+
+// Use the widths with solo groups (solo = true, the creation layout) or teams only (the
+// best predicted team layout).  Groups change arithmetic with their width (a solo group
+// sums its products in another order), so the choice must not depend on timing.
+rac_status set_widths(rac_batch b, bool solo) {
+  if (solo == b->solo_on) return RAC_OK;
+  b->gwidth = solo ? b->gw_solo : b->gw_team;
+  b->gcost = solo ? b->gc_solo : b->gc_team;
+  b->solo_on = solo;
+  if (solo) return set_team_layout(b, b->lay0_k32, b->lay0_k16, b->lay0_ks);
+  const std::vector<Layout> lay = team_layouts(b);
+  if (lay.empty()) return RAC_ERR_UNSUPPORTED;
+  return set_team_layout(b, lay[0].k32, lay[0].k16, lay[0].ks);
+}
+
+// Whether the solo widths still pay for the lanes that are active.  A solo group holds one
+// workgroup for its whole sweep: that pays while many groups share the device, not once
+// few remain (a team finishes one group's sweep several times sooner).  Each width set is
+// scored by its predicted sweep time, the larger of the active groups' workgroup-time over
+// the resident workgroups and the longest active group; teams only are taken when they
+// are predicted at least 20% faster.  The decision depends on the lanes' status alone,
+// never on the layout or on timing.
+rac_status decide_widths(rac_batch b) {
+  if (!b->team || !b->solo_on || b->host_active == b->decided_active) return RAC_OK;
+  b->decided_active = b->host_active;
+  std::vector<int32_t> st(b->nunits, 1);
+  BCHK(hipMemcpy2D(st.data(), sizeof(int32_t), &b->A.sc[0].status, sizeof(DevScalars), sizeof(int32_t),
+                   b->nunits, hipMemcpyDeviceToHost));
+  double area_s = 0.0, long_s = 0.0, area_t = 0.0, long_t = 0.0;
+  for (size_t g = 0; g < b->hgroups.size(); ++g) {
+    const TGroup& G = b->hgroups[g];
+    bool any = false;
+    for (int q = 0; q < G.nl; ++q) any |= st[G.lane[q]] == 0;
+    if (!any) continue;
+    area_s += b->gw_solo[g] * b->gc_solo[g];
+    long_s = std::max(long_s, b->gc_solo[g]);
+    area_t += b->gw_team[g] * b->gc_team[g];
+    long_t = std::max(long_t, b->gc_team[g]);
+  }
+  const double R = (double)b->resident;
+  const double t_solo = std::max(area_s / R, long_s), t_team = std::max(area_t / R, long_t);
+  return t_team < 0.8 * t_solo ? set_widths(b, false) : RAC_OK;
 }
 
 // Time one chunk with each of the best predicted team layouts (from the same
@@ -622,15 +673,51 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
     std::vector<int> width(ninst, 0);
     int64_t solo_rows = kSoloRows;
     if (const char* e = std::getenv("RACMB_SOLO_ROWS")) solo_rows = std::atoll(e);
+    // Predicted time of one of a group's blocks (us): a team's exchanges plus its member's
+    // products, or a solo workgroup's products over all rows and its solves (both measured).
+    auto block_cost = [](int64_t rows, int w) {
+      return w == 1 ? 28.0 + 29.0 * (double)rows / 1000.0 : 14.0 + 12.0 * (double)((rows + w - 1) / w) / 640.0;
+    };
+    // Candidates for solo groups: at most solo_rows rows, laid out for the clamped vector
+    // loads.  A solo group holds one workgroup for the whole sweep, so none may take longer
+    // than the predicted sweep: while the longest solo group exceeds the larger of the
+    // workgroup-time bound (all groups' workgroup-time over the resident workgroups) and
+    // the longest team group, its instance goes to a team instead.
+    std::vector<int> wteam(ninst, 0);
+    std::vector<char> solo(ninst, 0);
     for (int i = 0; i < ninst; ++i) {
       if (by_inst[i].empty()) continue;
-      if (inst[i].rows <= solo_rows && solo_layout_ok(inst[i])) {   // one workgroup streams the instance
-        width[i] = 1;
-        continue;
+      wteam[i] = member_rows(inst[i].rows, 16) <= 64 * ntmax ? 16 : 32;
+      solo[i] = inst[i].rows <= solo_rows && solo_layout_ok(inst[i]);
+    }
+    const double rw_all = (double)std::max(1, tsweep_max_resident(dtype, ntmax));
+    const char* force = std::getenv("RACMB_SOLO_FORCE");   // every candidate solo (tests of the solo path)
+    for (;;) {
+      if (force && *force == '1') break;
+      double area = 0.0, longest_team = 0.0, worst = 0.0;
+      int wi = -1;
+      for (int i = 0; i < ninst; ++i) {
+        if (by_inst[i].empty()) continue;
+        const double ng = (double)((by_inst[i].size() + 15) / 16), p_i = (double)b->hinst[i].p;
+        const int w = solo[i] ? 1 : wteam[i];
+        const double c = p_i * block_cost(inst[i].rows, w);
+        area += ng * w * c;
+        if (!solo[i]) longest_team = std::max(longest_team, c);
       }
-      width[i] = member_rows(inst[i].rows, 16) <= 64 * ntmax ? 16 : 32;
-      if (member_rows(inst[i].rows, width[i]) > 64 * ntmax) fits = false;
-      need = std::max<int64_t>(need, member_rows(inst[i].rows, width[i]));
+      const double bound = std::max(area / rw_all, longest_team);
+      for (int i = 0; i < ninst; ++i) {
+        if (!solo[i]) continue;
+        const double c = (double)b->hinst[i].p * block_cost(inst[i].rows, 1);
+        if (c > bound && c > worst) { worst = c; wi = i; }
+      }
+      if (wi < 0) break;
+      solo[wi] = 0;
+    }
+    for (int i = 0; i < ninst; ++i) {       // the tiles a member needs: every instance may run on a team
+      if (by_inst[i].empty()) continue;
+      width[i] = solo[i] ? 1 : wteam[i];     // solo: one workgroup streams the whole instance
+      if (member_rows(inst[i].rows, wteam[i]) > 64 * ntmax) fits = false;
+      need = std::max<int64_t>(need, member_rows(inst[i].rows, wteam[i]));
     }
     const int NT = need <= 64 * 8 ? 8 : ntmax;
     const int resident = fits ? tsweep_max_resident(dtype, NT) : 0;
@@ -641,11 +728,8 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
         const rac_problem& P = inst[i];
         const int vec4 = (P.ldF % 4 == 0) && ((uintptr_t)P.F % (uintptr_t)(4 * esz) == 0);
         const int vec8 = (P.ldF % 8 == 0) && ((uintptr_t)P.F % 16 == 0);
-        // predicted time of one of the group's blocks (us): a team's exchanges plus the member's
-        // products, or a solo workgroup's products over all rows and its solves (both measured)
-        const double rw = (double)((P.rows + width[i] - 1) / width[i]);
-        const double cost = (double)b->hinst[i].p *
-                            (width[i] == 1 ? 28.0 + 29.0 * (double)P.rows / 1000.0 : 14.0 + 12.0 * rw / 640.0);
+        const double cost = (double)b->hinst[i].p * block_cost(P.rows, width[i]);
+        const double cost_team = (double)b->hinst[i].p * block_cost(P.rows, wteam[i]);
         for (size_t g0 = 0; g0 < by_inst[i].size(); g0 += 16) {
           TGroup G{};
           G.inst = i;
@@ -656,6 +740,11 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
           b->hgroups.push_back(G);
           b->gcost.push_back(cost);
           b->gwidth.push_back(width[i]);
+          b->gw_solo.push_back(width[i]);
+          b->gw_team.push_back(wteam[i]);
+          b->gc_solo.push_back(cost);
+          b->gc_team.push_back(cost_team);
+          if (width[i] == 1) b->solo_on = true;
         }
       }
       const int ng = (int)b->hgroups.size();
@@ -714,6 +803,10 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
     rac_status r = b->team ? autotune_team(b) : autotune(b);
     if (r != RAC_OK) return fail(r);
   }
+  b->lay0_k32 = b->k32;
+  b->lay0_k16 = b->k16;
+  b->lay0_ks = b->ks;
+  b->decided_active = b->host_active;
   if (hipDeviceSynchronize() != hipSuccess) return fail(RAC_ERR_DEVICE);
   *out = b;
   return RAC_OK;
@@ -786,6 +879,10 @@ rac_status rac_batch_run(rac_batch b, void* stream, int64_t* iters, int32_t* act
       if (r != RAC_OK) return r;
     }
     done += Tc;
+    {
+      const rac_status r = decide_widths(b);
+      if (r != RAC_OK) return r;
+    }
   }
   b->k += done;
   BCHK(hipEventRecord(b->ev, b->cs));
@@ -828,7 +925,7 @@ rac_status rac_batch_state_export(rac_batch b, void* buf, size_t* bytes) {
   if (*bytes < need) return RAC_ERR_ARG;
   BCHK(hipStreamSynchronize(b->cs));
   BatchStateHeader h{kBatchStateMagic, b->nunits, b->ninst, (int64_t)state_bytes(b), b->k,
-                     (int64_t)sizeof(DevScalars)};
+                     (int64_t)sizeof(DevScalars), b->solo_on ? 1 : 0};
   std::memcpy(buf, &h, sizeof(h));
   const rac_status r = state_xfer(b, true, (char*)buf + sizeof(h));
   if (r != RAC_OK) return r;
@@ -849,6 +946,11 @@ rac_status rac_batch_state_import(rac_batch b, const void* buf, size_t bytes) {
   if (r != RAC_OK) return r;
   b->k = h.k;
   BCHK(hipMemcpy(&b->host_active, b->A.nactive, sizeof(int32_t), hipMemcpyDeviceToHost));
+  b->decided_active = b->host_active;
+  if (b->team && h.solo_on != (b->solo_on ? 1 : 0)) {   // the widths the exporting batch used
+    if (h.solo_on && b->gw_solo == b->gw_team) return RAC_ERR_ARG;
+    return set_widths(b, h.solo_on != 0);
+  }
   return RAC_OK;
 }
 
@@ -905,6 +1007,7 @@ rac_status rac_batch_info(rac_batch b, int64_t* info) {
   info[5] = b->graph_used ? 1 : 0;
   info[6] = b->team ? (b->k32 > 0 ? 32 : (b->k16 > 0 ? 16 : 1)) : 0;
   info[7] = b->team ? b->TA.nteams : 0;
+  info[8] = b->team ? (int64_t)std::count(b->gwidth.begin(), b->gwidth.end(), 1) : 0;
   return RAC_OK;
 }
 

@@ -166,11 +166,14 @@ struct TeamArgs {
   uint32_t* flags;         // [nteams][128]: [0, 64) partial epochs, [64, 128) step epochs
   uint32_t* abort_flag;    // raised when a wait gives up (the batch is then unusable)
 };
-// Instances with at most this many rows run their lane groups solo (one workgroup,
-// no exchange); larger ones on teams.  RACMB_SOLO_ROWS overrides it at batch creation.
-// (Measured on 256 elastic-net instances of 1000 to 20000 rows: 2500 rows gives the
-// shortest sweep; 0, 2000 and 3072 are 4 to 14% slower.)
-constexpr int64_t kSoloRows = 2500;
+// Instances with at most this many rows may run their lane groups solo (one workgroup,
+// no exchange); larger ones run on teams.  A candidate stays solo only while its group's
+// predicted sweep fits under the predicted sweep of the whole batch, and the groups go
+// to teams once few lanes remain active.  RACMB_SOLO_ROWS overrides the bound at batch
+// creation; RACMB_SOLO_FORCE=1 keeps every candidate solo at creation.  (Measured on 256
+// elastic-net instances of 1000 to 20000 rows: 4000 and 6000 rows give the shortest
+// sweep, 6.08 and 6.05 ms against 6.65 ms at 2500 and 7.54 ms with teams only.)
+constexpr int64_t kSoloRows = 4000;
 // Workgroups of the team sweep that can be resident at once (0 if NT unsupported).
 int tsweep_max_resident(int32_t dtype, int NT);
 hipError_t launch_tsweep(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st);

@@ -253,8 +253,10 @@ class Problem:
                         None if self.rowidx is None else self.rowidx.data_ptr())
 
 
-def upload_columns(D, storage, device="cuda"):
-    """Column-major rows x n data (numpy, values exact in `storage`) -> device tensor (n, rows)."""
+def upload_columns(D, storage, device="cuda", align=8):
+    """Column-major rows x n data (numpy, values exact in `storage`) -> device tensor view
+    (n, rows) whose columns start at multiples of `align` elements (leading dimension
+    rows rounded up; the padding is zero), so that the kernels can use aligned vector loads."""
     torch = _torch()
     Dt = np.ascontiguousarray(np.asarray(D).T)
     if storage == "f64":
@@ -263,7 +265,11 @@ def upload_columns(D, storage, device="cuda"):
         t = torch.from_numpy(Dt.astype(np.float32))
     else:  # bf16: values are exactly representable, so the conversion is exact
         t = torch.from_numpy(Dt.astype(np.float32)).to(torch.bfloat16)
-    return t.to(device).contiguous()
+    n, rows = t.shape
+    ld = -(-rows // align) * align
+    buf = torch.zeros((n, ld), dtype=t.dtype, device=device)
+    buf[:, :rows] = t.to(device)
+    return buf[:, :rows]
 
 
 def regression_problem(D, y, lam=0.0, alpha=1.0, storage="f64", h=None, device="cuda") -> Problem:
@@ -274,7 +280,7 @@ def regression_problem(D, y, lam=0.0, alpha=1.0, storage="f64", h=None, device="
     F = upload_columns(D, storage, device)
     yt = torch.as_tensor(np.asarray(y, dtype=np.float64), device=device)
     c = torch.empty(n, dtype=torch.float64, device=device)
-    _check(load().rac_regression_c(C.c_void_p(F.data_ptr()), _DT[storage], N, n, N, float(N),
+    _check(load().rac_regression_c(C.c_void_p(F.data_ptr()), _DT[storage], N, n, int(F.stride(0)), float(N),
                                    _ptr(yt), _ptr(c), _stream()), "rac_regression_c")
     ht = None if h is None else torch.as_tensor(np.asarray(h, dtype=np.float64), device=device)
     yy = float(np.dot(np.asarray(y, dtype=np.float64), np.asarray(y, dtype=np.float64)))
@@ -793,10 +799,10 @@ class Batch:
         _check(self.lib.rac_batch_state_import(self.h, buf, len(blob)), "rac_batch_state_import")
 
     def info(self):
-        v = (C.c_int64 * 8)()
+        v = (C.c_int64 * 9)()
         _check(self.lib.rac_batch_info(self.h, v), "rac_batch_info")
         return dict(lanes=v[0], instances=v[1], gram_tasks=v[2], inverse_tasks=v[3], unroll=v[4], graph=v[5],
-                    team_size=v[6], teams=v[7])
+                    team_size=v[6], teams=v[7], solo_groups=v[8])
 
 
 def solve_batch(probs, lanes, *, s=64, seed=0, precision=PREC_FP64, beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0,

@@ -22,12 +22,15 @@ def say(*a):
 
 @pytest.fixture(autouse=True, params=["solo", "teams"])
 def group_mode(request, monkeypatch):
-    """Every test runs with the default assignment (instances of up to 3072 rows run their
-    lane groups solo, one workgroup each) and with every group on a team of workgroups."""
+    """Every test runs twice: with the lane groups of every instance of up to 4000 rows solo
+    (one workgroup each; kept solo at creation even where the batch is too small for that to
+    pay) and with every group on a team of workgroups."""
+    monkeypatch.delenv("RACMB_SOLO_ROWS", raising=False)
     if request.param == "teams":
         monkeypatch.setenv("RACMB_SOLO_ROWS", "0")
+        monkeypatch.delenv("RACMB_SOLO_FORCE", raising=False)
     else:
-        monkeypatch.delenv("RACMB_SOLO_ROWS", raising=False)
+        monkeypatch.setenv("RACMB_SOLO_FORCE", "1")
     return request.param
 
 
@@ -214,10 +217,10 @@ def test_batch_phase_timing_counts_every_launch():
 
 
 def test_solo_and_team_groups_in_one_launch():
-    """Instances on both sides of the solo bound (3072 rows) in one batch: solo groups and
+    """Instances on both sides of the solo bound (4000 rows) in one batch: solo groups and
     teams run in the same launch; every lane matches the oracle (FP64)."""
     rng = np.random.default_rng(31)
-    shapes = [(4100, 90), (800, 130), (3072, 64), (3073, 40), (150, 33)]
+    shapes = [(4100, 90), (800, 130), (4000, 64), (4001, 40), (150, 33)]
     gps, ops, lanes = [], [], []
     for i, (N, n) in enumerate(shapes):
         w = W.gaussian_en(N, n, 0.1, 0.05, 0.1, 0.5, 700 + i, 32, "f64")
@@ -233,3 +236,52 @@ def test_solo_and_team_groups_in_one_launch():
         res, x, z, xi = b.lane(u)
         ref = oracle_lane(ops[lane[0]], lane, s=32, seed=8, max_iter=30, check_every=10)
         assert rel(z, ref.z) < 1e-8 and rel(xi, ref.xi) < 1e-8 and rel(x, ref.x) < 1e-8, u
+
+
+def test_solo_groups_go_to_teams_as_lanes_retire(group_mode):
+    """Solo groups at creation; once lanes converge and retire, the groups move to teams
+    (the decision is taken from the lanes' status alone).  The lanes still retire at the
+    oracle's iterations with its solution, graph replay and direct launches agree bit for
+    bit across the move, and a batch that imports a state exported after the move
+    continues bit for bit."""
+    if group_mode != "solo":
+        pytest.skip("teams only: no solo groups to move")
+    ws, gps, ops, lanes = en_batch(ninst=4, lanes_per=3, seed=5)
+    kw = dict(s=32, seed=2, beta_mode=racmb.BETA_RESBAL, check_every=10, tol=1e-7)
+    outs, infos = [], []
+    for graph in (True, False):
+        b = racmb.Batch(gps, lanes, max_iter=600, use_graph=graph, **kw)
+        infos.append(b.info()["solo_groups"])
+        it, act = b.run()
+        assert act == 0
+        infos.append(b.info()["solo_groups"])
+        outs.append([b.lane(u) for u in range(len(lanes))])
+        b.close()
+    say("solo groups before / after, graph and direct:", infos)
+    assert infos[0] > 0 and infos[1] == 0 and infos[2] > 0 and infos[3] == 0
+    for u, lane in enumerate(lanes):
+        (ra, xa, za, xia), (rb, xb, zb, xib) = outs[0][u], outs[1][u]
+        assert ra.iters == rb.iters and np.array_equal(za, zb) and np.array_equal(xa, xb), u
+        ref = oracle_lane(ops[lane[0]], lane, s=32, seed=2, beta_mode=O.BETA_RESBAL, max_iter=600,
+                          check_every=10, tol=1e-7)
+        assert ra.status == racmb.RUN_CONVERGED and ra.iters == ref.iters, (u, ra.iters, ref.iters)
+        assert rel(za, ref.z) < 1e-8
+    # checkpoint after the move: find a chunk at which the groups have moved and lanes remain
+    first = min(r.iters for r, *_ in outs[0])
+    last = max(r.iters for r, *_ in outs[0])
+    assert first < last
+    k = first + 10 if first + 10 < last else first
+    c = racmb.Batch(gps, lanes, max_iter=k, use_graph=True, **kw)
+    c.run()
+    moved = c.info()["solo_groups"] == 0
+    blob = c.export_state()
+    d = racmb.Batch(gps, lanes, max_iter=600, use_graph=True, **kw)
+    d.import_state(blob)
+    assert (d.info()["solo_groups"] == 0) == moved
+    d.run()
+    for u in range(len(lanes)):
+        r, x, z, xi = d.lane(u)
+        ra, xa, za, xia = outs[0][u]
+        assert r.iters == ra.iters and np.array_equal(z, za) and np.array_equal(x, xa), u
+    c.close()
+    d.close()

@@ -6,14 +6,20 @@ chunks, packed tiles and stream overlap):
     (which runs about one iteration per second at this size);
   * the timed configuration (mixed precision, learned penalty) run to
     KKT <= 1e-6; the oracle then recomputes the KKT residual and the objective
-    of the GPU's iterate, which must agree with what the GPU reported.
+    of the GPU's iterate, which must agree with what the GPU reported, and the
+    objective and z are compared with the oracle's own optimum of the same
+    values (stored by tests/golden/make_golden.py): 1e-6 relative objective,
+    1e-5 relative z.
 Batched elastic-net paths, 256 instances x 16 lambda lanes (BF16 data, team
 sweep, hipGraph, autotuned layout):
   * FP64 mode, ten iterations; sampled lanes (small instances, the median one,
     one that needs a team of 32, one with many blocks) compared element by
     element with the oracle;
   * the timed configuration run until every lane reaches KKT <= 1e-6; the
-    oracle recomputes the KKT residual of sampled lanes.
+    oracle recomputes the KKT residual of sampled lanes and their objective is
+    compared with the oracle's stored optimum (1e-6); the same solver continued
+    from those states to KKT <= 1e-10 then matches the stored z to 1e-5 (at
+    1e-6 an ill-conditioned lane, n > N with the smallest lambda, is 5e-5 away).
 svm_20000x256 (FP32 data, blocks of 128, the equality row):
   * FP64 mode, ten iterations against the oracle;
   * mixed precision, 500 iterations: z in the box, the KKT residual falling,
@@ -24,12 +30,18 @@ mixed precision with the learned penalty run to KKT <= 1e-6, then the oracle's
 KKT residual and objective of the GPU's iterate.
 """
 import os
+import sys
 
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_1907_01995_amd import racmb, workloads as W
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_golden  # noqa: E402  (reader of the stored oracle solutions)
+
+GOLDEN = os.path.dirname(os.path.abspath(make_golden.__file__))
 
 pytestmark = pytest.mark.gpu
 
@@ -99,6 +111,40 @@ def test_lasso_20000x2000_timed_configuration_reaches_tolerance(lasso_full):
     say("oracle kkt", k, "objective", ob)
     assert k <= 1e-6 and abs(k - r.kkt) <= 1e-6 * r.kkt
     assert abs(r.objective - ob) <= 1e-10 * (abs(ob) + op.obj_const)
+    check_golden(os.path.join(GOLDEN, "lasso_20000x2000_solution.txt"), ob, z)
+
+
+def golden_is_optimal(path, D, y, lam, alpha):
+    """The stored optimum checked against the elastic-net optimality conditions of Eq.(6),
+    recomputed with numpy from the same stored values: g = D'(Dz - y)/N + lam (1 - alpha) z
+    equals -lam alpha sign(z_j) on the support and lies in [-lam alpha, lam alpha] off it
+    (to 1e-8 of |D'y/N|_inf)."""
+    head, z = make_golden.read(path)
+    N = D.shape[0]
+    g = D.T @ (D @ z - y) / N + lam * (1 - alpha) * z
+    on = z != 0
+    tol = 1e-8 * np.max(np.abs(D.T @ y)) / N
+    assert np.max(np.abs(g[on] + lam * alpha * np.sign(z[on])), initial=0.0) <= tol
+    assert np.max(np.abs(g[~on]), initial=0.0) <= lam * alpha + tol
+
+
+def check_golden(path, objective, z, z_tol=1e-5):
+    """The oracle's own optimum of the same stored values (FP64, run to KKT <= 1e-9 by
+    tests/golden/make_golden.py): relative objective within 1e-6 and relative z error
+    within z_tol (1e-5, the mixed-precision bar; None: objective only) (Eq.(5)-(8))."""
+    head, zg = make_golden.read(path)
+    og = float(head["objective"])
+    ro = abs(objective - og) / abs(og)
+    zn = float(np.linalg.norm(zg))
+    err = float(np.linalg.norm(np.asarray(z) - zg))
+    say(os.path.basename(path), "rel objective", ro, "z error", err, "|z*|", zn)
+    assert ro <= 1e-6, ro
+    if z_tol is None:
+        return
+    if zn == 0.0:                 # lambda = lambda_max: the optimum is z = 0 (to rounding)
+        assert err <= 1e-12, err
+    else:
+        assert err <= z_tol * zn, err / zn
 
 
 @pytest.fixture(scope="module")
@@ -156,6 +202,7 @@ def test_en_paths_256x16_timed_configuration_reaches_tolerance(en_paths):
     it, act = b.run()
     say("iterations", it, "active", act, b.info())
     assert act == 0
+    picked, starts = [], []
     for i in sample:
         for j in (0, 7, 15):
             u = 16 * i + j
@@ -165,7 +212,30 @@ def test_en_paths_256x16_timed_configuration_reaches_tolerance(en_paths):
             say("lane", u, "iterations", res.iters, "kkt", res.kkt, "oracle kkt", k)
             assert res.status == racmb.RUN_CONVERGED
             assert k <= 1e-6 and abs(k - res.kkt) <= 1e-6 * max(res.kkt, 1e-300) + 1e-15
+            path = os.path.join(GOLDEN, "en_paths_256x16_lane%d_solution.txt" % u)
+            golden_is_optimal(path, insts[i].host_D(), insts[i].y, lanes[u][2], 0.5)
+            check_golden(path, O.objective(op, z), z, z_tol=None)   # objective at the timed tolerance
+            picked.append((i, u))
+            starts.append((x, z, xi, res.beta))
     b.close()
+    # A KKT residual of 1e-6 bounds z only through the problem's conditioning (the lane of the
+    # instance with n > N and the smallest lambda is 5e-5 away).  The same candidate solver,
+    # continued from these states to KKT <= 1e-10, reaches the FP64 optimum to 1e-5 in z.
+    say("sampled lanes continued in mixed precision to KKT <= 1e-10")
+    sub = sorted({i for i, _ in picked})
+    c = racmb.Batch([probs[i] for i in sub], [(sub.index(i),) + tuple(lanes[u][1:]) for i, u in picked], s=64,
+                    seed=11, precision=racmb.PREC_MIXED, beta_mode=racmb.BETA_MLP, mlp_weights=mlp_weights(),
+                    check_every=10, max_iter=20000, tol=1e-10, use_graph=True)
+    for v, (x, z, xi, beta) in enumerate(starts):
+        c.set_lane_state(v, x, z, xi, 0.0, beta)
+    it, act = c.run()
+    say("iterations", it, "active", act)
+    assert act == 0
+    for v, (i, u) in enumerate(picked):
+        res, x, z, xi = c.lane(v)
+        op = O.en_problem(insts[i].host_D(), insts[i].y, lam=lanes[u][2], alpha=0.5)
+        check_golden(os.path.join(GOLDEN, "en_paths_256x16_lane%d_solution.txt" % u), O.objective(op, z), z)
+    c.close()
 
 
 @pytest.fixture(scope="module")

@@ -466,3 +466,29 @@ def test_warm_started_lambda_path_ends_at_cold_solutions():
         total_warm += rw.iters
         total_cold += rc.iters
     assert total_warm <= total_cold
+
+
+def test_stored_lasso_20000x2000_solution_is_optimal():
+    """The stored oracle optimum of lasso_20000x2000 (tests/golden, written by make_golden.py)
+    checked against the LASSO optimality conditions of Eq.(6) with alpha = 1, recomputed with
+    numpy from the same stored values: g = D'(Dz - y)/N equals -lambda sign(z_j) on the support
+    and lies in [-lambda, lambda] off it (to 1e-9 of |D'y/N|_inf, the oracle's stopping
+    tolerance), and the stored objective is that of z."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_golden
+    w = W.lasso_20000x2000("f32")
+    head, z = make_golden.read(os.path.join(os.path.dirname(make_golden.__file__), "lasso_20000x2000_solution.txt"))
+    D = w.D.astype(np.float64)
+    N = D.shape[0]
+    r = D @ z - w.y
+    g = D.T @ r / N
+    on = z != 0
+    assert 0 < on.sum() < z.size
+    scale = np.max(np.abs(D.T @ w.y)) / N           # |c|_inf, the scale of the KKT residual
+    assert np.max(np.abs(g[on] + w.lam * np.sign(z[on]))) <= 1e-9 * scale
+    assert np.max(np.abs(g[~on])) <= w.lam
+    obj = 0.5 * (r @ r) / N + w.lam * np.abs(z).sum()
+    assert abs(obj - float(head["objective"])) <= 1e-12 * obj
+    assert abs(np.linalg.norm(z) - float(head["znorm"])) <= 1e-12 * np.linalg.norm(z)
