@@ -631,7 +631,7 @@ def sparse_leg(args, racmb, W, torch, name, N, n, density, s, tol_run):
     avg = ph["sweep"][0] / ph["sweep"][1] / 1e3
     nbytes = nnz * 8.0 + 6.0 * n * 8
     roof = {"bound": "hbm", "achieved": nbytes / avg / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "kernel": "k_ssweep", "avg_launch_us": avg * 1e6, "bytes_per_launch": nbytes,
+            "kernel": "k_ssweep_lds" if N <= 17408 else "k_ssweep", "avg_launch_us": avg * 1e6, "bytes_per_launch": nbytes,
             "blocks_per_launch": -(-n // s), "us_per_block": avg * 1e6 / -(-n // s)}
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {"workload": name, "N": N, "n": n, "density": density, "nnz": nnz, "block_size": s,

@@ -118,7 +118,7 @@ typedef struct {
    * int64, colptr[0] = 0), rowidx (device, colptr[n] int32 row indices, strictly increasing
    * within each column) and F holding the colptr[n] values (F_dtype RAC_DT_F64 or
    * RAC_DT_F32); ldF is not used.  The sparse form runs its sweep in one workgroup on one
-   * stream; its residual update uses device-scope atomic additions, so iterates agree with
+   * stream; its residual update uses atomic additions, so iterates agree with
    * the dense computation to rounding but not bitwise from run to run. */
   const int64_t* colptr;
   const int32_t* rowidx;

@@ -38,8 +38,12 @@ def pair(w, lam=None, alpha=None):
 
 
 @pytest.mark.parametrize("variant", [racmb.VARIANT_RAC, racmb.VARIANT_RP])
-@pytest.mark.parametrize("N,n,density,s,storage", [(1500, 601, 0.02, 64, "f64"), (800, 257, 0.05, 32, "f32"),
-                                                   (3000, 130, 0.01, 128, "f64"), (500, 90, 0.1, 16, "f64")])
+@pytest.mark.parametrize("N,n,density,s,storage", [
+    (1500, 601, 0.02, 64, "f64"), (800, 257, 0.05, 32, "f32"), (3000, 130, 0.01, 128, "f64"),
+    (500, 90, 0.1, 16, "f64"),
+    (3000, 260, 0.05, 128, "f64"),      # blocks of 19200 entries: u in LDS, chunks of 10240
+    (20000, 200, 0.002, 64, "f32"),     # more rows than LDS holds: u in device memory
+    (20000, 300, 0.005, 128, "f64")])   # ... with blocks of 12800 entries in chunks
 def test_sparse_en_parity(variant, N, n, density, s, storage):
     w = W.sparse_regression(N, n, density, data_seed=N + n, storage=storage)
     gp, op = pair(w)
