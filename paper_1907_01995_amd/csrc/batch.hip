@@ -133,13 +133,17 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
   double* buf = rowbuf[wave];
   if (U.a && j < SP) buf[j] = aj;
   __builtin_amdgcn_wave_barrier();
+  // the Gram's lower triangle, all SP loads of a lane in flight at once (addresses inside
+  // the block's SP x SP matrix even for lanes past SP; entries outside the block unused)
   double col[SP];
+  const int jl = j < SP ? j : SP - 1;
+#pragma unroll
+  for (int i = 0; i < SP; ++i) col[i] = Gb[i >= jl ? i * SP + jl : jl * SP + i];
 #pragma unroll
   for (int i = 0; i < SP; ++i) {
     double v;
     if (i < sb && j < sb) {
-      const double g = i >= j ? Gb[i * SP + j] : Gb[j * SP + i];
-      v = g / U.Ns;
+      v = col[i] / U.Ns;
       if (i == j) v += beta + hj;
       if (U.a) v += beta * buf[i] * aj;
     } else {
@@ -164,10 +168,10 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
     }
     const double invd = 1.0 / d;
     const bool piv = j == k;
-    const double keep = piv ? 0.0 : 1.0;
     const double m = piv ? -invd : r * invd;
+    // the pivot's own column is replaced (a select, exact); buf[k+q] = a_(k+q mod SP),k
 #pragma unroll
-    for (int q = 1; q < SP; ++q) col[q - 1] = fma(-buf[k + q], m, keep * col[q]);   // buf[k+q] = a_(k+q mod SP),k
+    for (int q = 1; q < SP; ++q) col[q - 1] = fma(-buf[k + q], m, piv ? 0.0 : col[q]);
     col[SP - 1] = m;
     __builtin_amdgcn_wave_barrier();
   }
