@@ -501,6 +501,13 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
     if (own) {
       obeta = B.sc[ou].beta; omu = B.sc[ou].mu; ot = B.sc[ou].t; oNs = OU->Ns; ob = OU->b;
     }
+    // the owned lane's descriptor and the group's layout flag, read once: read in the block
+    // loop they would be loads whose waits also wait for the staging loads issued before
+    const int64_t omoff = own ? OU->moff : 0, oxoff = own ? OU->xoff : 0;
+    const double* oc = own ? OU->c : nullptr;
+    const double* oh = own ? OU->h : nullptr;
+    const double* oa = own ? OU->a : nullptr;
+    const bool vec8 = G->vec8 != 0;
     const int32_t* pm = B.perm + I.poff + (int64_t)t * n;
     const int64_t rpi = 4 * (j & 3) + (j >> 2);       // row pi(j) of a tile in the update product
     // Block inverse of the owned lane (slot w), staged in LDS at the start of
@@ -508,7 +515,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
     double pf[16];
     auto minv_load = [&](int64_t bk) {
       const int sbk = (int)(block_start(bk + 1, n, p) - block_start(bk, n, p));
-      const double* Mo = own ? B.Minv + (OU->moff + bk) * (int64_t)B.sp * B.sp : nullptr;
+      const double* Mo = own ? B.Minv + (omoff + bk) * (int64_t)B.sp * B.sp : nullptr;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int el = tid + 256 * i, k = el >> 6, c = el & 63;
@@ -536,7 +543,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
       const int c = tid >> 2, sub = tid & 3;
       const bool cv = c < sbk;
       const int lastk = (nr - 1) >> 3;       // last chunk holding member rows (nr >= 1 when ntile >= 1)
-      if (G->vec8) {
+      if (vec8) {
         // 16-byte aligned columns (ldF a multiple of 8): a chunk crossing the
         // member's last row reads at most 7 further elements of the same padded
         // column, zeroed in LDS below
@@ -584,10 +591,12 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
       const int sbn = blk + 1 < p ? (int)(block_start(blk + 2, n, p) - block_start(blk + 1, n, p)) : 0;
       __syncthreads();                       // this block's cols and inverse are in LDS; the
       if (give_up) return;                   // previous block no longer reads the slice
-      if (tid < sbn) colsb[(blk + 1) & 1][tid] = pm[s0 + sb + tid];   // next block's indices
       minv_load(blk);                        // in flight together with the slice
       if constexpr (kSlice) if (ntile > 0) slice_load(cols, sb);   // all of the slice's loads in flight at once
       minv_store();
+      // the next block's indices: loaded after the staging loads, whose completion their
+      // wait then shares
+      if (tid < sbn) colsb[(blk + 1) & 1][tid] = pm[s0 + sb + tid];
       __syncthreads();
       ++e;
       const int par = (int)(e & 1u);
@@ -595,11 +604,11 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
       double gb = 0.0, acol = 0.0, oxc = 0.0, odel = 0.0;
       if (own && lane < sb) {
         const int col = cols[lane];
-        const double xc = B.X[OU->xoff + col];
+        const double xc = B.X[oxoff + col];
         oxc = xc;
-        gb = OU->c[col] - B.XI[OU->xoff + col] + obeta * (xc - B.Z[OU->xoff + col]);
-        if (OU->h) gb += OU->h[col] * xc;
-        if (OU->a) { acol = OU->a[col]; gb -= omu * acol; }
+        gb = oc[col] - B.XI[oxoff + col] + obeta * (xc - B.Z[oxoff + col]);
+        if (oh) gb += oh[col] * xc;
+        if (oa) { acol = oa[col]; gb -= omu * acol; }
       }
       // 1. partial F_B' u over this member's rows, all lanes of the group
       {
@@ -691,7 +700,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
           for (int m = 0; m < 32; ++m) s += v[m];
         }
         double g = s / oNs + gb;
-        if (OU->a) g += obeta * acol * (ot - ob);
+        if (oa) g += obeta * acol * (ot - ob);
         shg[wave][lane] = lane < sb ? g : 0.0;
         __builtin_amdgcn_wave_barrier();
         const double* Ml = minv_lds;
@@ -699,14 +708,14 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
 #pragma unroll 16
         for (int k = 0; k < 64; ++k) dq[k & 3] += Ml[k * 64 + lane] * shg[wave][k];
         odel = lane < sb ? -((dq[0] + dq[1]) + (dq[2] + dq[3])) : 0.0;
-        if (OU->a) ot += wave_sum(acol * odel);
+        if (oa) ot += wave_sum(acol * odel);
         st_c(delta + ((int64_t)par * 64 + lane) * 16 + L, odel);   // [column][slot]
         __builtin_amdgcn_s_waitcnt(0);
       }
       __syncthreads();
       if (give_up) return;
       if (tid == 0) st_flag(fl_step + w, e);
-      if (own && wave == 0 && lane < sb) B.X[OU->xoff + cols[lane]] = oxc + odel;   // only the owner writes x_B
+      if (own && wave == 0 && lane < sb) B.X[oxoff + cols[lane]] = oxc + odel;   // only the owner writes x_B
       // 3. every member: steps of all lanes, then its rows of u
       if (!wait_team(fl_step, W, e, lane, TA.abort_flag) && lane == 0) give_up = 1;
       {
@@ -774,7 +783,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
         if (actj && tile < ntile && r < re) Uj[r] = ur[s][i];
       }
     }
-    if (own && wave == 0 && lane == 0 && OU->a) B.sc[ou].t = ot;   // wavefront 0 carried t
+    if (own && wave == 0 && lane == 0 && oa) B.sc[ou].t = ot;   // wavefront 0 carried t
   }
 }
 
