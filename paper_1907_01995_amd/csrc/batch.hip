@@ -187,6 +187,224 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
 }
 
 // ---------------------------------------------------------------------------
+// Block inverses of 64 x 64 blocks on the FP64 matrix cores, one wavefront per
+// (lane, block).  The block matrix lives in the wavefront's registers as 4 x 4
+// tiles of 16 x 16 in the accumulator layout of v_mfma_f64_16x16x4f64: lane
+// (q, c) = (lane / 16, lane % 16) holds rows 4r + q (r = 0..3) of column c of
+// every tile.  The sweep takes the pivots four at a time: sweeping the set K of
+// four consecutive indices at once equals sweeping them one after the other, and
+// with P = A_KK, N = -P^{-1} (the 4 x 4 sweep of P), Y = A_K. (the rows of K) and
+// Z = N Y it is
+//   A_ij += sum_k Y_ki Z_kj   (i, j not in K; Y_ki = A_ik by symmetry),
+//   A_iK  = -(Y' N)_i        (i not in K),   A_Kj = -Z_j,   A_KK = N,
+// one rank-4 product per tile.  The rows of K are each lane's own registers in
+// the operand layouts (as operand A for the row tiles, as operand B for Y_j, and
+// Z_j likewise), Z is one more product with N in the first four rows of operand
+// A, and the columns of K come out of the same products once their accumulator
+// is cleared and their operand-B entries are -N.  The pivots of P's sweep are
+// those of the scalar sweep, checked against Assumption 2.1 as in k_binv.
+// Pivot blocks that hold no index below sb are identity and are not swept.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// 1/d from the hardware reciprocal and two Newton steps (d > 0 and finite; other
+// values only occur with a failed pivot, whose block is discarded).
+__device__ __forceinline__ double recip_f64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// The symmetric sweep of the 4 x 4 block P held by lanes (k, 4 rK + l), k, l < 4, of
+// the register y (its upper triangle, mirrored): S = -P^{-1}.  Every lane computes
+// the same values.  A non-positive or non-finite pivot sets failed.
+__device__ __forceinline__ void sweep4(double y, int rK, double (&S)[4][4], bool& failed) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int l = k; l < 4; ++l) {
+      S[k][l] = readlane_f64(y, 16 * k + 4 * rK + l);
+      S[l][k] = S[k][l];
+    }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double d = S[k][k];
+    failed = failed || !(d > 0.0) || !isfinite(d);
+    const double invd = recip_f64(d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i == k) continue;
+      const double mi = S[i][k] * invd;
+#pragma unroll
+      for (int l = i; l < 4; ++l) {
+        if (l == k) continue;
+        S[i][l] = fma(-mi, S[k][l], S[i][l]);
+        S[l][i] = S[i][l];
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      if (l == k) continue;
+      S[k][l] *= invd;
+      S[l][k] = S[k][l];
+    }
+    S[k][k] = -invd;
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_binv64(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
+                                                int ntasks, const int32_t* __restrict__ perm, int t,
+                                                const double* __restrict__ G, DevScalars* sc,
+                                                double* __restrict__ Minv) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  constexpr int SP = 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the task's values go to scalars
+  const int q = lane >> 4, c = lane & 15;
+  __shared__ double abuf[4][SP], hbuf[4][SP], nbuf[4][16];
+  const int task = blockIdx.x * 4 + wave;
+  if (task >= ntasks) return;   // wavefront-uniform; the kernel has no workgroup barrier
+  const int2 tk = tasks[task];
+  if (sc[tk.x].status != 0) return;
+  const BUnit U = units[tk.x];
+  const double beta = sc[tk.x].beta;
+  const int blk = tk.y;
+  const int64_t s0 = block_start(blk, U.n, U.p);
+  const int sb = (int)(block_start(blk + 1, U.n, U.p) - s0);
+  const int32_t* pm = perm + U.poff + (int64_t)t * U.n + s0;
+  {
+    const int col = lane < sb ? pm[lane] : 0;
+    abuf[wave][lane] = (U.a && lane < sb) ? U.a[col] : 0.0;
+    hbuf[wave][lane] = (U.h && lane < sb) ? U.h[col] : 0.0;
+  }
+  const double* Gb = G + (U.goff + blk) * (int64_t)SP * SP;
+  const double invNs = 1.0 / U.Ns;
+  f64x4 m[4][4];
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int J = 0; J < 4; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + 4 * r + q, j = 16 * J + c;
+        m[I][J][r] = Gb[i >= j ? i * SP + j : j * SP + i];   // the Gram's lower triangle
+      }
+  __builtin_amdgcn_wave_barrier();
+  // M = G/Ns + diag(h) + beta (I + a a'), identity outside the block; branch-free (a
+  // and h read as zero where absent, and adding a zero term is exact)
+  {
+    double dcol[4];
+#pragma unroll
+    for (int J = 0; J < 4; ++J) dcol[J] = beta + hbuf[wave][16 * J + c];
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + 4 * r + q, j = 16 * J + c;
+          double v = m[I][J][r] * invNs;
+          if (I == J) v += (4 * r + q == c) ? dcol[J] : 0.0;
+          m[I][J][r] = (i < sb && j < sb) ? v : ((i == j) ? 1.0 : 0.0);
+        }
+  }
+  if (U.a) {
+    // + beta a a' as a rank-1 product per tile: operand A holds beta a_i in its
+    // first column, operand B holds a_j in its first row (zero outside the block)
+    double ar[4], ac[4];
+#pragma unroll
+    for (int I = 0; I < 4; ++I) {
+      const double ai = abuf[wave][16 * I + c];
+      ar[I] = q == 0 ? beta * ai : 0.0;
+      ac[I] = q == 0 ? ai : 0.0;
+    }
+#pragma unroll
+    for (int I = 0; I < 4; ++I)
+#pragma unroll
+      for (int J = 0; J < 4; ++J) m[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[I], ac[J], m[I][J], 0, 0, 0);
+  }
+  // The 4 x 4 sweep of the next pivot block runs on the vector ALU while the matrix
+  // cores finish the current block: its P is read as soon as the tile that holds it
+  // has been updated.  After a failed pivot the arithmetic goes on and the output is
+  // zero.
+  bool failed = false;
+  double S[4][4];
+  sweep4(m[0][0][0], 0, S, failed);
+#pragma unroll
+  for (int K = 0; K < 16; ++K) {
+    if (4 * K >= sb) continue;                  // uniform; no early exit, so the loop unrolls
+    const int IK = K >> 2, rK = K & 3;
+    double Y[4];
+#pragma unroll
+    for (int J = 0; J < 4; ++J) Y[J] = m[IK][J][rK];
+    // N = S to every lane (the same values from every lane: no branch)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) nbuf[wave][e] = S[e >> 2][e & 3];
+    __builtin_amdgcn_wave_barrier();
+    const int cc = c - 4 * rK;                  // the lane's column inside K (tile column IK)
+    const bool inK = (unsigned)cc < 4u;
+    const double an = nbuf[wave][(c < 4 ? c : 0) * 4 + q];
+    const double bn = nbuf[wave][q * 4 + (inK ? cc : 0)];
+    const double aN = c < 4 ? an : 0.0;         // operand A: N in rows 0..3
+    const double keep = inK ? 0.0 : 1.0;        // clears the accumulator of the columns of K
+    __builtin_amdgcn_wave_barrier();
+    const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+    double Z[4];
+#pragma unroll
+    for (int J = 0; J < 4; ++J) Z[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(aN, Y[J], zero, 0, 0, 0)[0];
+    auto update = [&](int I, int J) {
+      f64x4 acc = m[I][J];
+      double b = Z[J];
+      if (J == IK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] *= keep;
+        b = inK ? -bn : b;
+      }
+      m[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[I], b, acc, 0, 0, 0);
+    };
+    const int I1 = ((K + 1) >> 2) & 3, r1 = (K + 1) & 3;
+    // the tile that holds the next P first, then the rest of its tile row
+#pragma unroll
+    for (int J = 0; J < 4; ++J) update(I1, (I1 + J) & 3);
+    if (K < 15) sweep4(m[I1][I1][r1], r1, S, failed);
+#pragma unroll
+    for (int o = 1; o < 4; ++o)
+#pragma unroll
+      for (int J = 0; J < 4; ++J) update((I1 + o) & 3, J);
+    if (K < 15) {
+      // interleave: one product, then a share of the sweep's vector instructions
+#pragma unroll
+      for (int g = 0; g < 12; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+      }
+    }
+#pragma unroll
+    for (int J = 0; J < 4; ++J) m[IK][J][rK] = (J == IK && inK) ? bn : -Z[J];
+  }
+  if (failed && lane == 0) {
+    unsigned long long key = ((unsigned long long)sc[tk.x].k << 32) | (unsigned)blk;
+    atomicMin((unsigned long long*)&sc[tk.x].fail_key, key);
+  }
+  double* out = Minv + (U.moff + blk) * (int64_t)SP * SP;
+#pragma unroll
+  for (int I = 0; I < 4; ++I)
+#pragma unroll
+    for (int J = 0; J < 4; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + 4 * r + q, j = 16 * J + c;
+        out[i * SP + j] = (!failed && i < sb && j < sb) ? -m[I][J][r] : 0.0;
+      }
+}
+
+// ---------------------------------------------------------------------------
 // One workgroup per lane: the whole Gauss-Seidel pass.  Per block:
 //   gradient pass: lane l takes rows l, l+64, ...; wavefront w takes block
 //   columns w, w+4, ... (16 of them); per-lane sums are reduced across lanes
@@ -497,7 +715,7 @@ hipError_t launch_binv(const BatchArgs& b, int t, hipStream_t st) {
   switch (b.sp) {
     case 16: k_binv<16><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
     case 32: k_binv<32><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
-    case 64: k_binv<64><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
+    case 64: k_binv64<<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

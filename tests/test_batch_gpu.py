@@ -61,11 +61,14 @@ def oracle_lane(op, lane, **kw):
     return O.solve(P, inst=i, beta0=beta0, **kw)
 
 
+@pytest.mark.parametrize("s", [32, 64])
 @pytest.mark.parametrize("sweep", [racmb.BSWEEP_TEAM, racmb.BSWEEP_LANE])
-def test_batch_lanes_match_oracle_fp64(sweep):
-    ws, gps, ops, lanes = en_batch()
-    say("batch fp64", len(lanes), "lanes, sweep", sweep)
-    b = racmb.Batch(gps, lanes, s=32, seed=7, max_iter=30, check_every=10, use_graph=True, sweep=sweep)
+def test_batch_lanes_match_oracle_fp64(sweep, s):
+    """Blocks of 64 take the matrix-core inverse (four pivots per step), blocks of 32 the
+    one-pivot-per-step inverse; both against the oracle's sequential sweep."""
+    ws, gps, ops, lanes = en_batch(s=s)
+    say("batch fp64", len(lanes), "lanes, sweep", sweep, "s", s)
+    b = racmb.Batch(gps, lanes, s=s, seed=7, max_iter=30, check_every=10, use_graph=True, sweep=sweep)
     it, act = b.run()
     assert it == 30 and act == len(lanes)
     info = b.info()
@@ -74,7 +77,7 @@ def test_batch_lanes_match_oracle_fp64(sweep):
     assert (info["team_size"] > 0) == (sweep == racmb.BSWEEP_TEAM)
     for u, lane in enumerate(lanes):
         res, x, z, xi = b.lane(u)
-        ref = oracle_lane(ops[lane[0]], lane, s=32, seed=7, max_iter=30, check_every=10)
+        ref = oracle_lane(ops[lane[0]], lane, s=s, seed=7, max_iter=30, check_every=10)
         assert res.iters == 30
         assert rel(z, ref.z) < 1e-8 and rel(xi, ref.xi) < 1e-8 and rel(x, ref.x) < 1e-8, u
 
@@ -93,16 +96,17 @@ def test_batch_graph_and_tuning_do_not_change_results():
             assert np.array_equal(u, v)
 
 
-def test_batch_lanes_retire_like_the_oracle():
-    ws, gps, ops, lanes = en_batch(ninst=4, lanes_per=3, seed=5)
-    b = racmb.Batch(gps, lanes, s=32, seed=2, beta_mode=racmb.BETA_RESBAL, max_iter=600, check_every=10,
+@pytest.mark.parametrize("s", [32, 64])
+def test_batch_lanes_retire_like_the_oracle(s):
+    ws, gps, ops, lanes = en_batch(ninst=4, lanes_per=3, seed=5, s=s)
+    b = racmb.Batch(gps, lanes, s=s, seed=2, beta_mode=racmb.BETA_RESBAL, max_iter=600, check_every=10,
                     tol=1e-7)
     it, act = b.run()
     assert act == 0
     iters = []
     for u, lane in enumerate(lanes):
         res, x, z, xi = b.lane(u)
-        ref = oracle_lane(ops[lane[0]], lane, s=32, seed=2, beta_mode=O.BETA_RESBAL, max_iter=600,
+        ref = oracle_lane(ops[lane[0]], lane, s=s, seed=2, beta_mode=O.BETA_RESBAL, max_iter=600,
                           check_every=10, tol=1e-7)
         assert res.status == racmb.RUN_CONVERGED and ref.status == O.RUN_CONVERGED
         assert res.iters == ref.iters, (u, res.iters, ref.iters)
@@ -111,17 +115,18 @@ def test_batch_lanes_retire_like_the_oracle():
     assert len(set(iters)) > 1        # lanes really retired at different iterations
 
 
-def test_batch_svm_lanes():
-    wv = [W.svm(n=int(n), r=12, block_size=32, data_seed=40 + k) for k, n in enumerate((300, 517))]
+@pytest.mark.parametrize("s", [32, 64])
+def test_batch_svm_lanes(s):
+    wv = [W.svm(n=int(n), r=12, block_size=s, data_seed=40 + k) for k, n in enumerate((300, 517))]
     gps = [racmb.svm_problem(w.X, w.labels, w.C) for w in wv]
     ops = [O.svm_problem(w.X.astype(np.float64), w.labels, w.C) for w in wv]
     lanes = [(0, racmb.PROX_BOX, 0.0, 1.0, 0.5), (0, racmb.PROX_BOX, 0.0, 1.0, 3.0),
              (1, racmb.PROX_BOX, 0.0, 1.0, 1.7)]
-    b = racmb.Batch(gps, lanes, s=32, seed=4, max_iter=50, check_every=10, use_graph=False)
+    b = racmb.Batch(gps, lanes, s=s, seed=4, max_iter=50, check_every=10, use_graph=False)
     b.run()
     for u, lane in enumerate(lanes):
         res, x, z, xi = b.lane(u)
-        ref = oracle_lane(ops[lane[0]], lane, s=32, seed=4, max_iter=50, check_every=10)
+        ref = oracle_lane(ops[lane[0]], lane, s=s, seed=4, max_iter=50, check_every=10)
         assert rel(x, ref.x) < 1e-8 and rel(z, ref.z) < 1e-8
 
 
@@ -139,23 +144,24 @@ def test_batch_mixed_precision_reaches_fp64_solution(storage):
         assert rel(z, ref.z) < 1e-5, u
 
 
-def test_batch_reports_assumption_failure_per_lane():
-    ws, gps, ops, lanes = en_batch(ninst=2, lanes_per=2, seed=11)
+@pytest.mark.parametrize("s", [32, 64])
+def test_batch_reports_assumption_failure_per_lane(s):
+    ws, gps, ops, lanes = en_batch(ninst=2, lanes_per=2, seed=11, s=s)
     h = np.zeros(ws[1].n)
     h[3] = -1e4
     gps[1] = racmb.regression_problem(ws[1].D, ws[1].y, lam=ws[1].lam, alpha=0.5, h=h)
     opbad = O.en_problem(ws[1].D, ws[1].y, lam=ws[1].lam, alpha=0.5, h=h)
-    b = racmb.Batch(gps, lanes, s=32, seed=3, max_iter=20, check_every=10)
+    b = racmb.Batch(gps, lanes, s=s, seed=3, max_iter=20, check_every=10)
     it, act = b.run()
     assert act == 2
     for u, lane in enumerate(lanes):
         res, x, z, xi = b.lane(u, allow_not_pd=True)
         if lane[0] == 1:
-            ref = oracle_lane(opbad, lane, s=32, seed=3, max_iter=20, check_every=10)
+            ref = oracle_lane(opbad, lane, s=s, seed=3, max_iter=20, check_every=10)
             assert ref.rc == O.ERR_NOT_PD
             assert (res.fail_iter, res.fail_block) == (ref.fail_iter, ref.fail_block)
         else:
-            ref = oracle_lane(ops[0], lane, s=32, seed=3, max_iter=20, check_every=10)
+            ref = oracle_lane(ops[0], lane, s=s, seed=3, max_iter=20, check_every=10)
             assert res.fail_iter == -1 and rel(z, ref.z) < 1e-8
 
 
