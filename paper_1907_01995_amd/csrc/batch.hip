@@ -14,6 +14,8 @@
 //             pivots; the pivot row (equal to the pivot column) is gathered
 //             with one LDS store per lane and read back as broadcasts -- no
 //             workgroup barriers;
+//   k_binv64  the same for blocks of 64, four pivots per step on the FP64
+//             matrix cores;
 //   k_tsweep  (tsweep.hip) the team sweep: the lanes of an instance in groups
 //             of up to 16, one read of the data for the whole group;
 //   k_bsweep  the per-lane fallback, one workgroup per lane: the Gauss-Seidel pass over the blocks,
@@ -222,9 +224,10 @@ __device__ __forceinline__ double recip_f64(double d) {
 }
 
 // The symmetric sweep of the 4 x 4 block P held by lanes (k, 4 rK + l), k, l < 4, of
-// the register y (its upper triangle, mirrored): S = -P^{-1}.  Every lane computes
-// the same values.  A non-positive or non-finite pivot sets failed.
-__device__ __forceinline__ void sweep4(double y, int rK, double (&S)[4][4], bool& failed) {
+// the register y: read_p gathers its upper triangle (mirrored) into S, pivot_step(k)
+// sweeps pivot k; after the four steps S = -P^{-1}.  Every lane computes the same
+// values.  A non-positive or non-finite pivot sets failed.
+__device__ __forceinline__ void read_p(double y, int rK, double (&S)[4][4]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -232,30 +235,29 @@ __device__ __forceinline__ void sweep4(double y, int rK, double (&S)[4][4], bool
       S[k][l] = readlane_f64(y, 16 * k + 4 * rK + l);
       S[l][k] = S[k][l];
     }
+}
+__device__ __forceinline__ void pivot_step(int k, double (&S)[4][4], bool& failed) {
+  const double d = S[k][k];
+  failed = failed | !(d > 0.0) | !isfinite(d);
+  const double invd = recip_f64(d);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double d = S[k][k];
-    failed = failed || !(d > 0.0) || !isfinite(d);
-    const double invd = recip_f64(d);
+  for (int i = 0; i < 4; ++i) {
+    if (i == k) continue;
+    const double mi = S[i][k] * invd;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (i == k) continue;
-      const double mi = S[i][k] * invd;
-#pragma unroll
-      for (int l = i; l < 4; ++l) {
-        if (l == k) continue;
-        S[i][l] = fma(-mi, S[k][l], S[i][l]);
-        S[l][i] = S[i][l];
-      }
-    }
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
+    for (int l = i; l < 4; ++l) {
       if (l == k) continue;
-      S[k][l] *= invd;
-      S[l][k] = S[k][l];
+      S[i][l] = fma(-mi, S[k][l], S[i][l]);
+      S[l][i] = S[i][l];
     }
-    S[k][k] = -invd;
   }
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    if (l == k) continue;
+    S[k][l] *= invd;
+    S[l][k] = S[k][l];
+  }
+  S[k][k] = -invd;
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_binv64(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
@@ -329,13 +331,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
       for (int J = 0; J < 4; ++J) m[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[I], ac[J], m[I][J], 0, 0, 0);
   }
-  // The 4 x 4 sweep of the next pivot block runs on the vector ALU while the matrix
-  // cores finish the current block: its P is read as soon as the tile that holds it
+  // Software pipeline: the 4 x 4 sweep of the next pivot block and the exchange of its
+  // N run on the vector ALU and the LDS between the current block's products (fenced
+  // so that the in-order issue alternates them), once the tile that holds the next P
   // has been updated.  After a failed pivot the arithmetic goes on and the output is
   // zero.
   bool failed = false;
   double S[4][4];
-  sweep4(m[0][0][0], 0, S, failed);
+  const int c_lt4 = c < 4 ? c : 0;
+  double aN, bn;                                // this block's N in the operand layouts
+  auto exchange = [&](int rK) {                 // N = S to every lane (same values: no branch)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) nbuf[wave][e] = S[e >> 2][e & 3];
+    __builtin_amdgcn_wave_barrier();
+    const int cc = c - 4 * rK;
+    const double an = nbuf[wave][c_lt4 * 4 + q];
+    bn = nbuf[wave][q * 4 + ((unsigned)cc < 4u ? cc : 0)];
+    aN = c < 4 ? an : 0.0;                      // operand A: N in rows 0..3
+    __builtin_amdgcn_wave_barrier();
+  };
+  read_p(m[0][0][0], 0, S);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) pivot_step(k, S, failed);
+  exchange(0);
 #pragma unroll
   for (int K = 0; K < 16; ++K) {
     if (4 * K >= sb) continue;                  // uniform; no early exit, so the loop unrolls
@@ -343,50 +361,53 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     double Y[4];
 #pragma unroll
     for (int J = 0; J < 4; ++J) Y[J] = m[IK][J][rK];
-    // N = S to every lane (the same values from every lane: no branch)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) nbuf[wave][e] = S[e >> 2][e & 3];
-    __builtin_amdgcn_wave_barrier();
     const int cc = c - 4 * rK;                  // the lane's column inside K (tile column IK)
     const bool inK = (unsigned)cc < 4u;
-    const double an = nbuf[wave][(c < 4 ? c : 0) * 4 + q];
-    const double bn = nbuf[wave][q * 4 + (inK ? cc : 0)];
-    const double aN = c < 4 ? an : 0.0;         // operand A: N in rows 0..3
     const double keep = inK ? 0.0 : 1.0;        // clears the accumulator of the columns of K
-    __builtin_amdgcn_wave_barrier();
+    const double bK = bn;
     const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+    const int I1 = ((K + 1) >> 2) & 3, r1 = (K + 1) & 3;
     double Z[4];
 #pragma unroll
-    for (int J = 0; J < 4; ++J) Z[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(aN, Y[J], zero, 0, 0, 0)[0];
+    for (int o = 0; o < 4; ++o) {               // in the order of the first products
+      const int J = (I1 + o) & 3;
+      Z[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(aN, Y[J], zero, 0, 0, 0)[0];
+    }
     auto update = [&](int I, int J) {
       f64x4 acc = m[I][J];
       double b = Z[J];
       if (J == IK) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] *= keep;
-        b = inK ? -bn : b;
+        b = inK ? -bK : b;
       }
       m[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[I], b, acc, 0, 0, 0);
     };
-    const int I1 = ((K + 1) >> 2) & 3, r1 = (K + 1) & 3;
     // the tile that holds the next P first, then the rest of its tile row
 #pragma unroll
     for (int J = 0; J < 4; ++J) update(I1, (I1 + J) & 3);
-    if (K < 15) sweep4(m[I1][I1][r1], r1, S, failed);
-#pragma unroll
-    for (int o = 1; o < 4; ++o)
-#pragma unroll
-      for (int J = 0; J < 4; ++J) update((I1 + o) & 3, J);
+    // the other 12 tiles, two products per step of the next block's sweep
     if (K < 15) {
-      // interleave: one product, then a share of the sweep's vector instructions
-#pragma unroll
-      for (int g = 0; g < 12; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
-      }
+      __builtin_amdgcn_sched_barrier(0);
+      read_p(m[I1][I1][r1], r1, S);
     }
 #pragma unroll
-    for (int J = 0; J < 4; ++J) m[IK][J][rK] = (J == IK && inK) ? bn : -Z[J];
+    for (int g = 0; g < 6; ++g) {
+      if (K < 15) __builtin_amdgcn_sched_barrier(0);
+      update((I1 + 1 + g / 2) & 3, (2 * g) & 3);
+      update((I1 + 1 + g / 2) & 3, (2 * g + 1) & 3);
+      if (K < 15 && g < 4) {
+        __builtin_amdgcn_sched_barrier(0);
+        pivot_step(g, S, failed);
+      }
+      if (K < 15 && g == 3) {
+        __builtin_amdgcn_sched_barrier(0);
+        exchange(r1);
+      }
+    }
+    if (K < 15) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int J = 0; J < 4; ++J) m[IK][J][rK] = (J == IK && inK) ? bK : -Z[J];
   }
   if (failed && lane == 0) {
     unsigned long long key = ((unsigned long long)sc[tk.x].k << 32) | (unsigned)blk;
