@@ -728,6 +728,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
         const rac_problem& P = inst[i];
         const int vec4 = (P.ldF % 4 == 0) && ((uintptr_t)P.F % (uintptr_t)(4 * esz) == 0);
         const int vec8 = (P.ldF % 8 == 0) && ((uintptr_t)P.F % 16 == 0);
+        const int span = solo_layout_ok(P) ? 1 : 0;
         const double cost = (double)b->hinst[i].p * block_cost(P.rows, width[i]);
         const double cost_team = (double)b->hinst[i].p * block_cost(P.rows, wteam[i]);
         for (size_t g0 = 0; g0 < by_inst[i].size(); g0 += 16) {
@@ -736,6 +737,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
           G.nl = (int32_t)std::min<size_t>(16, by_inst[i].size() - g0);
           G.vec4 = vec4;
           G.vec8 = vec8;
+          G.span = span;
           for (int q = 0; q < 16; ++q) G.lane[q] = q < G.nl ? by_inst[i][g0 + q] : -1;
           b->hgroups.push_back(G);
           b->gcost.push_back(cost);
@@ -759,9 +761,31 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
            b->buf.alloc(&b->TA.delta, (size_t)maxt * 2 * 1024) && b->buf.alloc(&b->TA.flags, (size_t)maxt * 128) &&
            b->buf.alloc(&b->TA.abort_flag, 1);
       if (!ok) return fail(RAC_ERR_NOMEM);
+      // Grouped KKT tasks (group, 64-column chunk).  Workgroups go to the eight XCDs in
+      // turn (workgroup k to XCD k mod 8), so the chunks of a group are dealt to one
+      // XCD's queue (its u is then read into one L2), the largest groups first onto the
+      // least loaded queue, and the queues are interleaved (an exhausted queue's turns
+      // are empty tasks, group -1, that keep the others on their XCDs); the order leaves
+      // every result unchanged.
       std::vector<int2> kt;
-      for (int g = 0; g < ng; ++g)
-        for (int64_t ch = 0; ch < (inst[b->hgroups[g].inst].n + 63) / 64; ++ch) kt.push_back(make_int2(g, (int)ch));
+      {
+        std::vector<int> order(ng);
+        for (int g = 0; g < ng; ++g) order[g] = g;
+        auto rows_of = [&](int g) { return inst[b->hgroups[g].inst].rows; };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rows_of(x) > rows_of(y); });
+        std::vector<std::vector<int2>> xq(8);
+        std::vector<double> load(8, 0.0);
+        for (int g : order) {
+          const int64_t nch = (inst[b->hgroups[g].inst].n + 63) / 64;
+          const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          for (int64_t ch = 0; ch < nch; ++ch) xq[x].push_back(make_int2(g, (int)ch));
+          load[x] += (double)nch * (double)rows_of(g);
+        }
+        size_t len = 0;
+        for (int x = 0; x < 8; ++x) len = std::max(len, xq[x].size());
+        for (size_t k = 0; k < len; ++k)
+          for (int x = 0; x < 8; ++x) kt.push_back(k < xq[x].size() ? xq[x][k] : make_int2(-1, 0));
+      }
       b->nkkt_tasks = (int)kt.size();
       if (!b->buf.alloc(&b->dkkt_tasks, kt.size())) return fail(RAC_ERR_NOMEM);
       if (hipMemcpy(b->dkkt_tasks, kt.data(), sizeof(int2) * kt.size(), hipMemcpyHostToDevice) != hipSuccess ||

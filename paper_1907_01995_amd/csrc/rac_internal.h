@@ -149,6 +149,8 @@ struct TGroup {            // up to 16 lanes of one instance
   int32_t inst; int32_t nl;
   int32_t vec4;            // F columns allow aligned 4-element vector loads
   int32_t vec8;            // ... and aligned 16-byte loads of two-byte data
+  int32_t span;            // vec4, and F's allocation holds n * ldF elements: loads clamped
+                           // into a column's ldF rows stay inside it
   int32_t lane[16];        // lane ids of slots 0 .. nl-1
 };
 struct TeamArgs {

@@ -794,9 +794,10 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
 // per-column terms of every active lane and their maxima / sums over the chunk,
 // written where the per-lane control kernel reads them (kpart[lane][chunk][10]).
 template <typename T>
-__global__ void __launch_bounds__(256) k_gkkt(BatchArgs B, const TGroup* __restrict__ groups,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_gkkt(BatchArgs B, const TGroup* __restrict__ groups,
                                               const int2* __restrict__ tasks) {
   const int2 tk = tasks[blockIdx.x];
+  if (tk.x < 0) return;                      // an empty task (keeps the others on their XCDs)
   const TGroup* G = groups + tk.x;
   const int chunk = tk.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, j = lane & 15;
@@ -816,6 +817,50 @@ __global__ void __launch_bounds__(256) k_gkkt(BatchArgs B, const TGroup* __restr
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct) acc[ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
   const int64_t ntile = (rows + 15) >> 4;
+  if (G->span) {
+    // branch-free tile loads, KD - 1 tiles in flight per wavefront: addresses clamped
+    // into the columns (rows past the end and tiles past the wavefront's last read the
+    // column's last aligned quad, u its last row; columns past the chunk read its last
+    // column, whose products are not used) and rows past the end zeroed where consumed
+    constexpr int KD = sizeof(T) == 2 ? 4 : (sizeof(T) == 4 ? 3 : 2);
+    const int mine = ntile > wave ? (int)((ntile - wave + 3) / 4) : 0;
+    const T* fcg[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) fcg[ct] = F + (c0 + (16 * ct + j < nc ? 16 * ct + j : nc - 1)) * ldF;
+    const double* Ubase = actj ? Uj : B.U;
+    RawQ<T> gq[KD][4];
+    double uv[KD][4];
+    auto gload = [&](int sidx, RawQ<T> (&dst)[4], double (&ud)[4]) {
+      const int64_t r0 = 16 * (int64_t)(wave + 4 * sidx) + 4 * q;
+      const int64_t rc = r0 < ldF - 4 ? r0 : ldF - 4;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) dst[ct] = gld_quad<T>(fcg[ct] + rc);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ud[i] = gld<double>(Ubase + (r0 + i < rows ? r0 + i : rows - 1));
+    };
+#pragma unroll
+    for (int sidx = 0; sidx < KD - 1; ++sidx) gload(sidx, gq[sidx], uv[sidx]);
+    for (int base = 0; base < mine; base += KD) {
+#pragma unroll
+      for (int k = 0; k < KD; ++k) {
+        const int sidx = base + k;
+        gload(sidx + KD - 1, gq[(k + KD - 1) % KD], uv[(k + KD - 1) % KD]);
+        const int64_t nv = rows - (16 * (int64_t)(wave + 4 * sidx) + 4 * q);
+        RawQ<T> fq[4];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) fq[ct] = quad_keep<T>(gq[k][ct], nv);
+        double ux[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ux[i] = actj && i < nv ? uv[k][i] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(quad_at<T>(fq[ct], i), ux[i], acc[ct], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  } else
   for (int64_t tile = wave; tile < ntile; tile += 4) {
     const int64_t r0 = 16 * tile + 4 * q;
     const int nv = rows - r0 >= 4 ? 4 : (rows > r0 ? (int)(rows - r0) : 0);
