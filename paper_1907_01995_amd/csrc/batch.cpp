@@ -620,6 +620,12 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
     if (I.p > maxp) maxp = I.p;
     b->hunit.push_back(U);
   }
+  // Gram tasks of the longest columns first: one workgroup streams a whole block, so the
+  // largest instances set the phase's tail unless they start early (the order leaves
+  // every result unchanged)
+  std::stable_sort(gt.begin(), gt.end(), [&](const int2& x, const int2& y) {
+    return inst[x.x].rows > inst[y.x].rows;
+  });
   b->ngt = (int)gt.size();
   BatchArgs& A = b->A;
   A.dtype = dtype; A.sp = b->SP; A.T = b->T; A.nunits = nlanes; A.ninst = ninst;
