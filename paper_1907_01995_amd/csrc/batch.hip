@@ -15,7 +15,8 @@
 //             with one LDS store per lane and read back as broadcasts -- no
 //             workgroup barriers;
 //   k_binv64  the same for blocks of 64, four pivots per step on the FP64
-//             matrix cores;
+//             matrix cores.  The inverses are symmetric; only their lower 16 x 16
+//             tiles are stored (minv_off);
 //   k_tsweep  (tsweep.hip) the team sweep: the lanes of an instance in groups
 //             of up to 16, one read of the data for the whole group;
 //   k_bsweep  the per-lane fallback, one workgroup per lane: the Gauss-Seidel pass over the blocks,
@@ -178,12 +179,12 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
     __builtin_amdgcn_wave_barrier();
   }
   double* out = Minv + (U.moff + blk) * (int64_t)SP * SP;
-  if (j < SP) {   // lanes past the padded size hold no column
+  if (j < SP) {   // lanes past the padded size hold no column; the lower tiles only
 #pragma unroll
     for (int q = 0; q < SP; ++q) {
       int i = q + sb;                           // register q holds row (q + sb) mod SP
       if (i >= SP) i -= SP;
-      out[i * SP + j] = (!failed && i < sb && j < sb) ? -col[q] : 0.0;
+      if ((i >> 4) >= (j >> 4)) out[minv_off(i, j)] = (!failed && i < sb && j < sb) ? -col[q] : 0.0;
     }
   }
 }
@@ -413,15 +414,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     unsigned long long key = ((unsigned long long)sc[tk.x].k << 32) | (unsigned)blk;
     atomicMin((unsigned long long*)&sc[tk.x].fail_key, key);
   }
-  double* out = Minv + (U.moff + blk) * (int64_t)SP * SP;
+  double* out = Minv + (U.moff + blk) * (int64_t)SP * SP;   // the lower tiles only
 #pragma unroll
   for (int I = 0; I < 4; ++I)
 #pragma unroll
-    for (int J = 0; J < 4; ++J)
+    for (int J = 0; J <= I; ++J)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + 4 * r + q, j = 16 * J + c;
-        out[i * SP + j] = (!failed && i < sb && j < sb) ? -m[I][J][r] : 0.0;
+        out[(I * (I + 1) / 2 + J) * 256 + (4 * r + q) * 16 + c] = (!failed && i < sb && j < sb) ? -m[I][J][r] : 0.0;
       }
 }
 
@@ -430,7 +431,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 //   gradient pass: lane l takes rows l, l+64, ...; wavefront w takes block
 //   columns w, w+4, ... (16 of them); per-lane sums are reduced across lanes
 //   by a transposed butterfly (15 + 2 exchanges for 16 columns);
-//   step d = -M^{-1} g from the lane's stored block inverse;
+//   step d = -M^{-1} g from the lane's stored block inverse (its lower tiles);
 //   update pass: thread r takes rows r, r+256, ... and adds F_B d to u.
 // The row loops keep UNR rows per lane in flight (autotuned).
 template <int B>
@@ -532,7 +533,7 @@ __global__ void __launch_bounds__(256) k_bsweep(const BUnit* __restrict__ units,
       constexpr int P = 256 / SP;
       double a2 = 0.0;
       if (j < sb)
-        for (int k = part; k < sb; k += P) a2 += Mi[(int64_t)k * SP + j] * gl[k];
+        for (int k = part; k < sb; k += P) a2 += Mi[minv_off(k, j)] * gl[k];
       psum[part * SP + j] = a2;
     }
     __syncthreads();

@@ -62,6 +62,15 @@ __host__ __device__ __forceinline__ int64_t block_start(int64_t i, int64_t n, in
   return (i * n) / p;
 }
 
+// The batch stores each block inverse (symmetric, sp x sp) as its lower 16 x 16 tiles:
+// tile (I, J), I >= J, row-major at (I (I + 1) / 2 + J) * 256.  Entry (i, j) is read
+// from the tile that holds (max, min) of the tiles' indices (in a diagonal tile both).
+__host__ __device__ __forceinline__ int64_t minv_off(int i, int j) {
+  const int I = i >> 4, J = j >> 4;
+  return I >= J ? (int64_t)((I * (I + 1) / 2 + J) * 256 + (i & 15) * 16 + (j & 15))
+                : (int64_t)((J * (J + 1) / 2 + I) * 256 + (j & 15) * 16 + (i & 15));
+}
+
 // Partition key of variable j at iteration `iter` (a SplitMix64 chain).
 __host__ __device__ __forceinline__ uint64_t perm_key(uint64_t seed, uint64_t inst, uint64_t iter,
                                                       uint64_t j) {

@@ -241,17 +241,16 @@ __device__ __forceinline__ void solo_group(const BatchArgs& B, const TGroup* G, 
       }
     }
     double mreg[MD][16];
-    // rows 16 part .. 16 part + 15 of column jc of slot L's inverse (addresses clamped into
-    // the block; rows past sb are masked where they are used)
+    // rows 16 part .. 16 part + 15 of column jc of slot L's inverse, from its stored lower
+    // tiles (tile (part, jc / 16) or the transpose of tile (jc / 16, part)); addresses
+    // clamped into the block, rows past sb masked where they are used
     auto minv_issue = [&](int L, double (&dst)[16]) {
       const int u = su[L];
       const double* Mo = B.Minv + (u >= 0 ? (B.units[u].moff + blk) * (int64_t)B.sp * B.sp : 0);
       const int jj = jc < B.sp ? jc : B.sp - 1;
+      const int pp = 16 * part < B.sp ? part : (B.sp >> 4) - 1;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int k = 16 * part + e;
-        dst[e] = gld<double>(Mo + (int64_t)(k < B.sp ? k : B.sp - 1) * B.sp + jj);
-      }
+      for (int e = 0; e < 16; ++e) dst[e] = gld<double>(Mo + minv_off(16 * pp + e, jj));
     };
 #pragma unroll
     for (int L = 0; L < MD; ++L) minv_issue(L, mreg[L]);
@@ -446,7 +445,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
   constexpr bool kSlice = sizeof(T) == 2;
   constexpr int SL = 64 * NT + 16;
   __shared__ __attribute__((aligned(16))) uint16_t slice[kSlice ? 64 * SL : 8];
-  __shared__ double minv_lds[64 * 64];      // block inverse of the owned lane
+  __shared__ double minv_lds[64 * 65];      // block inverse of the owned lane (row stride 65)
   __shared__ double red[NW][16][64];
   __shared__ double shg[NW][64];
   __shared__ int32_t colsb[2][64];           // column indices of this block and the next
@@ -510,21 +509,32 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
     const bool vec8 = G->vec8 != 0;
     const int32_t* pm = B.perm + I.poff + (int64_t)t * n;
     const int64_t rpi = 4 * (j & 3) + (j >> 2);       // row pi(j) of a tile in the update product
-    // Block inverse of the owned lane (slot w), staged in LDS at the start of
-    // each block together with the slice: thread tid loads entries tid + 256 i.
+    // Block inverse of the owned lane (slot w), staged in LDS at the start of each block
+    // together with the slice.  Thread tid takes entries (k, c) = (tid / 64 + 4 i,
+    // tid % 64): those of the stored lower tiles are loaded (whole tile rows, coalesced)
+    // and written to LDS at (k, c) and, below the diagonal tiles, at (c, k); the lanes of
+    // upper tiles load their row of the diagonal tile instead (same lines) and store
+    // nothing.  Row stride 65: the mirrored stores do not share banks.
     double pf[16];
     auto minv_load = [&](int64_t bk) {
       const int sbk = (int)(block_start(bk + 1, n, p) - block_start(bk, n, p));
       const double* Mo = own ? B.Minv + (omoff + bk) * (int64_t)B.sp * B.sp : nullptr;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int el = tid + 256 * i, k = el >> 6, c = el & 63;
-        pf[i] = (Mo && k < sbk && c < sbk) ? Mo[(int64_t)k * B.sp + c] : 0.0;
+        const int k = (tid >> 6) + 4 * i, c = tid & 63, I = i >> 2;
+        const int cl = (c >> 4) <= I ? c : 16 * I + (c & 15);
+        const int kk = k < B.sp ? k : B.sp - 1, cc = cl < B.sp ? cl : B.sp - 1;   // inside the block
+        const double v = Mo ? Mo[minv_off(kk, cc)] : 0.0;
+        pf[i] = (k < sbk && c < sbk) ? v : 0.0;
       }
     };
     auto minv_store = [&]() {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) minv_lds[tid + 256 * i] = pf[i];
+      for (int i = 0; i < 16; ++i) {
+        const int k = (tid >> 6) + 4 * i, c = tid & 63, I = i >> 2, J = c >> 4;
+        if (J <= I) minv_lds[k * 65 + c] = pf[i];
+        if (J < I) minv_lds[c * 65 + k] = pf[i];
+      }
     };
     // Two-byte data: the slice of a block is fetched into registers (chunk k of
     // column c = slice rows [8k, 8k + 8); rows past the member's range up to the
@@ -706,7 +716,7 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
         const double* Ml = minv_lds;
         double dq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 16
-        for (int k = 0; k < 64; ++k) dq[k & 3] += Ml[k * 64 + lane] * shg[wave][k];
+        for (int k = 0; k < 64; ++k) dq[k & 3] += Ml[k * 65 + lane] * shg[wave][k];
         odel = lane < sb ? -((dq[0] + dq[1]) + (dq[2] + dq[3])) : 0.0;
         if (oa) ot += wave_sum(acol * odel);
         st_c(delta + ((int64_t)par * 64 + lane) * 16 + L, odel);   // [column][slot]
