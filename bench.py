@@ -198,10 +198,10 @@ def batched_headline(args, racmb, W, torch, weights):
     sw = ph["sweep"]
     avg = sw[0] / sw[1] / 1e3
     flops = 4.0 * 16 * elems                       # F_B'u and F_B d, every lane, every block
-    # one read of F (BF16), of every lane's block inverses (64 x 64 FP64 per block) and of
-    # the lane vectors, and one write of u and x
+    # one read of F (BF16), of every lane's block inverses (the ten stored lower 16 x 16
+    # FP64 tiles of a 64 x 64 block) and of the lane vectors, and one write of u and x
     nblk = float(np.sum(-(-ns // 64)))
-    nbytes = 2.0 * elems + 16 * nblk * 64 * 64 * 8.0 + 16 * 8.0 * (2 * float(np.sum(Ns)) + 6 * float(np.sum(ns)))
+    nbytes = 2.0 * elems + 16 * nblk * 10 * 256 * 8.0 + 16 * 8.0 * (2 * float(np.sum(Ns)) + 6 * float(np.sum(ns)))
     kern = "k_tsweep" if info["team_size"] else "k_bsweep"
     roof = {"bound": "mfma", "achieved": flops / avg / 1e12, "peak": MFMA_PEAK["f64"] / 1e12,
             "unit": "TFLOP/s", "kernel": kern, "avg_launch_us": avg * 1e6, "flops_per_launch": flops,
