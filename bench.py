@@ -194,7 +194,9 @@ def batched_headline(args, racmb, W, torch, weights):
     ph = bt.timing()
     bt.close()
     del bt
-    rows = {name: {"avg_us": 1e3 * ms / cnt, "launches": cnt} for name, (ms, cnt) in ph.items() if cnt}
+    # per launch, and per iteration (the Grams and inverses of a chunk may be one launch)
+    rows = {name: {"avg_us": 1e3 * ms / cnt, "launches": cnt, "us_per_iteration": 1e3 * ms / k}
+            for name, (ms, cnt) in ph.items() if cnt}
     sw = ph["sweep"]
     avg = sw[0] / sw[1] / 1e3
     flops = 4.0 * 16 * elems                       # F_B'u and F_B d, every lane, every block

@@ -432,11 +432,15 @@ rac_status rac_solve_batch(int32_t ninst, const rac_problem* inst, int32_t nlane
                            const rac_batch_opts* opts, void* stream, double* x, double* z, double* xi,
                            rac_result* res);
 
-/* info (host, 9 int64): lanes, instances, block Gram tasks, inverse tasks, row
+/* info (host, 10 int64): lanes, instances, block Gram tasks, inverse tasks, row
  * unroll of the LANE sweep, 1 if chunks are replayed from a hipGraph, workgroups of
  * the widest team of the TEAM sweep (0 when the LANE sweep runs), number of teams,
  * lane groups currently run solo (one workgroup each; they go to teams once few
- * lanes remain active, a decision taken from the lanes' status alone). */
+ * lanes remain active, a decision taken from the lanes' status alone), and the block
+ * Gram / inverse slots: check_every when the Grams and inverses of a whole chunk are
+ * formed in one launch each at its start (the default while they fit an eighth of the
+ * device memory; RACMB_ASSEMBLY_SLOTS=1 at creation disables it), else 1.  Both give
+ * bit-identical results. */
 rac_status rac_batch_info(rac_batch b, int64_t* info);
 /* Per-phase device time of the batch's launches, as for rac_solver_set_timing /
  * rac_solver_timing (same phases; "factor" is the block inverses).  While timing is

@@ -275,13 +275,16 @@ __global__ void __launch_bounds__(256) k_gram(const T* __restrict__ F, int64_t l
 }
 
 // Batched form: one workgroup per (instance, block) task of a batch; the Gram of
-// each block is shared by all lanes of its instance.  Iteration t of the chunk
-// selects the instance's partition for that iteration.
+// each block is shared by all lanes of its instance.  Iteration t = t0 + blockIdx.y
+// of the chunk selects the instance's partition for that iteration and the Gram
+// slot G + t * gslot.
 template <typename T, int MODE, int SP>
 __global__ void __launch_bounds__(256) k_bgram(const BInst* __restrict__ inst, const int2* __restrict__ tasks,
-                                               const int32_t* __restrict__ perm, int t,
+                                               const int32_t* __restrict__ perm, int t0, int64_t gslot,
                                                const int32_t* __restrict__ inst_active,
                                                double* __restrict__ G) {
+  const int t = t0 + (int)blockIdx.y;
+  G += t * gslot;
   const int2 tk = tasks[blockIdx.x];
   if (!inst_active[tk.x]) return;
   const BInst I = inst[tk.x];
@@ -560,8 +563,8 @@ hipError_t bgram_launch(const BatchGramArgs& g, hipStream_t st) {
   (void)dummy;
 #define RAC_BGRAM(SPV)                                                                            \
   if (g.sp == SPV) {                                                                              \
-    k_bgram<T, MODE, SPV><<<(unsigned)g.ntasks, 256, 0, st>>>(g.inst, g.tasks, g.perm, g.t,       \
-                                                              g.inst_active, g.G);                \
+    k_bgram<T, MODE, SPV><<<dim3((unsigned)g.ntasks, (unsigned)g.nt), 256, 0, st>>>(              \
+        g.inst, g.tasks, g.perm, g.t, g.gslot, g.inst_active, g.G);                                \
     return hipGetLastError();                                                                    \
   }
   RAC_BGRAM(16) RAC_BGRAM(32) RAC_BGRAM(64)
@@ -570,7 +573,7 @@ hipError_t bgram_launch(const BatchGramArgs& g, hipStream_t st) {
 }
 
 hipError_t launch_bgram(const BatchGramArgs& g, hipStream_t st) {
-  if (g.ntasks <= 0) return hipSuccess;
+  if (g.ntasks <= 0 || g.nt <= 0) return hipSuccess;
   const bool mixed = g.precision == RAC_PREC_MIXED;
   switch (g.dtype) {
     case RAC_DT_F64: return bgram_launch<double, G_F64>(g, st);

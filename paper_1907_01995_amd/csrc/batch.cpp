@@ -81,6 +81,7 @@ struct rac_batch_s {
   BUnit* dunit = nullptr;
   int2* gtasks = nullptr;
   int ngt = 0;
+  int nslot = 1;               // Gram / inverse slots: one per iteration of a chunk, or one
   int32_t host_active = 0;
   int64_t k = 0;
   hipStream_t cs = nullptr;           // the batch's own stream (capturable)
@@ -154,18 +155,36 @@ rac_status enqueue_chunk(rac_batch b, int Tc, hipStream_t st) {
   BCHK(tm.begin());
   BCHK(launch_bperm(a, st));
   BCHK(tm.end(RAC_PHASE_PARTITION));
-  for (int t = 0; t < Tc; ++t) {
-    BatchGramArgs g{a.dtype, b->O.precision, a.sp, b->ngt, t, a.inst, b->gtasks, a.perm, a.inst_active,
-                    const_cast<double*>(a.G)};
+  // The Grams and inverses of an iteration depend only on its partition and on the
+  // penalties, which change only at the check that ends a chunk: with a slot per
+  // iteration they are formed for the whole chunk in one launch each (no launch tail
+  // per iteration); otherwise at each iteration into the one slot.
+  auto assemble = [&](int t0, int nt, int tk0) -> rac_status {
+    BatchGramArgs g{a.dtype, b->O.precision, a.sp, b->ngt, t0, nt, a.gslot, a.inst, b->gtasks, a.perm,
+                    a.inst_active, const_cast<double*>(a.G)};
     BCHK(tm.begin());
     BCHK(launch_bgram(g, st));
     BCHK(tm.end(RAC_PHASE_GRAM));
     BCHK(tm.begin());
-    BCHK(launch_binv(a, t, st));
+    BCHK(launch_binv(a, t0, nt, tk0, st));
     BCHK(tm.end(RAC_PHASE_FACTOR));
+    return RAC_OK;
+  };
+  const bool chunkwide = a.mslot != 0;
+  if (chunkwide) {
+    const rac_status e = assemble(0, Tc, 0);
+    if (e != RAC_OK) return e;
+  }
+  for (int t = 0; t < Tc; ++t) {
+    if (!chunkwide) {
+      const rac_status e = assemble(t, 1, t);
+      if (e != RAC_OK) return e;
+    }
+    BatchArgs at = a;                     // the sweep reads iteration t's inverses
+    at.Minv = a.Minv + t * a.mslot;
     BCHK(tm.begin());
-    if (b->team) BCHK(launch_tsweep(a, b->TA, t, st));
-    else BCHK(launch_bsweep(a, t, st));
+    if (b->team) BCHK(launch_tsweep(at, b->TA, t, st));
+    else BCHK(launch_bsweep(at, t, st));
     BCHK(tm.end(RAC_PHASE_SWEEP));
     BCHK(tm.begin());
     BCHK(launch_bzdual(a, st));
@@ -639,10 +658,26 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
   A.mlp_w = O.mlp_weights; A.mlp_ymax = O.mlp_ymax;
   A.unroll = 2;
   const size_t ss = (size_t)b->SP * b->SP;
+  // A Gram and inverse slot per iteration of a chunk while they take at most an eighth
+  // of the device memory and half of what is free (RACMB_ASSEMBLY_SLOTS=1: one slot)
+  int nslot = 1;
+  {
+    size_t mfree = 0, mtotal = 0;
+    const double per = (double)(goff + moff) * (double)ss * sizeof(double);
+    const char* es = std::getenv("RACMB_ASSEMBLY_SLOTS");
+    const bool one = es && std::atoi(es) == 1;
+    if (!one && b->T > 1 && hipMemGetInfo(&mfree, &mtotal) == hipSuccess &&
+        per * b->T <= (double)mtotal / 8 && per * b->T <= (double)mfree / 2)
+      nslot = b->T;
+    (void)hipGetLastError();
+  }
+  b->nslot = nslot;
+  A.gslot = nslot > 1 ? (int64_t)(goff * ss) : 0;
+  A.mslot = nslot > 1 ? (int64_t)(moff * ss) : 0;
   bool ok = b->buf.alloc(&b->dinst, ninst) && b->buf.alloc(&b->dunit, nlanes) &&
             b->buf.alloc(&b->gtasks, gt.size()) && b->buf.alloc(const_cast<int2**>(&A.inv_tasks), it.size()) &&
-            b->buf.alloc(&A.perm, poff) && b->buf.alloc(const_cast<double**>(&A.G), goff * ss) &&
-            b->buf.alloc(&A.Minv, moff * ss) && b->buf.alloc(&A.X, xoff) && b->buf.alloc(&A.Z, xoff) &&
+            b->buf.alloc(&A.perm, poff) && b->buf.alloc(const_cast<double**>(&A.G), goff * ss * nslot) &&
+            b->buf.alloc(&A.Minv, moff * ss * nslot) && b->buf.alloc(&A.X, xoff) && b->buf.alloc(&A.Z, xoff) &&
             b->buf.alloc(&A.XI, xoff) && b->buf.alloc(&A.ZP, xoff) && b->buf.alloc(&A.U, uoff) &&
             b->buf.alloc(&A.sc, nlanes) && b->buf.alloc(&A.kpart, (size_t)nlanes * A.KC * 10) &&
             b->buf.alloc(&A.inst_active, ninst) && b->buf.alloc(&A.nactive, 1) && b->buf.alloc(&A.kdev, 1);
@@ -1038,6 +1073,7 @@ rac_status rac_batch_info(rac_batch b, int64_t* info) {
   info[6] = b->team ? (b->k32 > 0 ? 32 : (b->k16 > 0 ? 16 : 1)) : 0;
   info[7] = b->team ? b->TA.nteams : 0;
   info[8] = b->team ? (int64_t)std::count(b->gwidth.begin(), b->gwidth.end(), 1) : 0;
+  info[9] = b->nslot;
   return RAC_OK;
 }
 

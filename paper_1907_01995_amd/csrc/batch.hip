@@ -113,9 +113,12 @@ __global__ void __launch_bounds__(1024) k_bperm(const BInst* __restrict__ inst, 
 // index is a compile-time constant.
 template <int SP>
 __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
-                                              int ntasks, const int32_t* __restrict__ perm, int t,
+                                              int ntasks, const int32_t* __restrict__ perm, BinvSlots sl,
                                               const double* __restrict__ G, DevScalars* sc,
                                               double* __restrict__ Minv) {
+  const int t = sl.t0 + (int)blockIdx.y;      // iteration of the chunk, and its Gram and inverse slots
+  G += t * sl.gslot;
+  Minv += t * sl.mslot;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ double rowbuf[4][2 * SP];
   const int task = blockIdx.x * 4 + wave;
@@ -164,7 +167,7 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
     if (!(d > 0.0) || !isfinite(d)) {
       failed = true;
       if (lane == 0) {
-        unsigned long long key = ((unsigned long long)sc[tk.x].k << 32) | (unsigned)blk;
+        unsigned long long key = ((unsigned long long)(sc[tk.x].k + t - sl.tk0) << 32) | (unsigned)blk;
         atomicMin((unsigned long long*)&sc[tk.x].fail_key, key);
       }
       break;
@@ -262,9 +265,12 @@ __device__ __forceinline__ void pivot_step(int k, double (&S)[4][4], bool& faile
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_binv64(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
-                                                int ntasks, const int32_t* __restrict__ perm, int t,
+                                                int ntasks, const int32_t* __restrict__ perm, BinvSlots sl,
                                                 const double* __restrict__ G, DevScalars* sc,
                                                 double* __restrict__ Minv) {
+  const int t = sl.t0 + (int)blockIdx.y;      // iteration of the chunk, and its Gram and inverse slots
+  G += t * sl.gslot;
+  Minv += t * sl.mslot;
   typedef double f64x4 __attribute__((ext_vector_type(4)));
   constexpr int SP = 64;
   const int lane = threadIdx.x & 63;
@@ -411,7 +417,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     for (int J = 0; J < 4; ++J) m[IK][J][rK] = (J == IK && inK) ? bK : -Z[J];
   }
   if (failed && lane == 0) {
-    unsigned long long key = ((unsigned long long)sc[tk.x].k << 32) | (unsigned)blk;
+    unsigned long long key = ((unsigned long long)(sc[tk.x].k + t - sl.tk0) << 32) | (unsigned)blk;
     atomicMin((unsigned long long*)&sc[tk.x].fail_key, key);
   }
   double* out = Minv + (U.moff + blk) * (int64_t)SP * SP;   // the lower tiles only
@@ -731,13 +737,14 @@ hipError_t launch_bperm(const BatchArgs& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_binv(const BatchArgs& b, int t, hipStream_t st) {
-  const unsigned grid = (unsigned)((b.ninv + 3) / 4);
-  if (grid == 0) return hipSuccess;
+hipError_t launch_binv(const BatchArgs& b, int t0, int nt, int tk0, hipStream_t st) {
+  const dim3 grid((unsigned)((b.ninv + 3) / 4), (unsigned)nt);
+  if (grid.x == 0 || nt <= 0) return hipSuccess;
+  const BinvSlots sl{t0, tk0, b.gslot, b.mslot};
   switch (b.sp) {
-    case 16: k_binv<16><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
-    case 32: k_binv<32><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
-    case 64: k_binv64<<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, t, b.G, b.sc, b.Minv); break;
+    case 16: k_binv<16><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, sl, b.G, b.sc, b.Minv); break;
+    case 32: k_binv<32><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, sl, b.G, b.sc, b.Minv); break;
+    case 64: k_binv64<<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, sl, b.G, b.sc, b.Minv); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -134,8 +134,8 @@ struct BUnit {             // one lane: an independent solve on instance `inst`
   int64_t moff;            // first block inverse of this lane
   int64_t poff;            // partitions of its instance
 };
-struct BatchGramArgs {
-  int32_t dtype; int32_t precision; int sp; int ntasks; int t;
+struct BatchGramArgs {      // Grams of iterations t .. t + nt - 1 of a chunk, iteration t' into G + t' gslot
+  int32_t dtype; int32_t precision; int sp; int ntasks; int t; int nt; int64_t gslot;
   const BInst* inst; const int2* tasks; const int32_t* perm; const int32_t* inst_active; double* G;
 };
 hipError_t launch_bgram(const BatchGramArgs& a, hipStream_t st);
@@ -152,6 +152,12 @@ struct BatchArgs {         // everything the per-lane kernels of one chunk need
   int32_t* inst_active; int32_t* nactive; int64_t* kdev;
   int32_t beta_mode; double rb_mu, rb_tau, tol; const float* mlp_w; double mlp_ymax;
   int unroll;              // sweep row unroll (autotuned: 1, 2 or 4)
+  int64_t gslot, mslot;    // doubles between the Gram / inverse slots of consecutive iterations of
+                           // a chunk (0: one slot, formed at each iteration)
+};
+struct BinvSlots {         // inverses of iterations t0 + blockIdx.y; tk0: the chunk iteration the
+  int t0; int tk0;         // lanes' counters stand at when the launch runs (failure reports)
+  int64_t gslot, mslot;
 };
 // Team sweep (tsweep.hip): lane groups of one instance advanced together.
 struct TGroup {            // up to 16 lanes of one instance
@@ -192,7 +198,7 @@ hipError_t launch_tsweep(const BatchArgs& b, const TeamArgs& ta, int t, hipStrea
 hipError_t launch_gkkt(const BatchArgs& b, const TGroup* groups, const int2* tasks, int ntasks, hipStream_t st);
 
 hipError_t launch_bperm(const BatchArgs& b, hipStream_t st);
-hipError_t launch_binv(const BatchArgs& b, int t, hipStream_t st);
+hipError_t launch_binv(const BatchArgs& b, int t0, int nt, int tk0, hipStream_t st);
 hipError_t launch_bsweep(const BatchArgs& b, int t, hipStream_t st);
 hipError_t launch_bzdual(const BatchArgs& b, hipStream_t st);
 // KKT (unless grouped_kkt: already formed by launch_gkkt), control, activity

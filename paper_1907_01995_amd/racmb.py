@@ -799,10 +799,10 @@ class Batch:
         _check(self.lib.rac_batch_state_import(self.h, buf, len(blob)), "rac_batch_state_import")
 
     def info(self):
-        v = (C.c_int64 * 9)()
+        v = (C.c_int64 * 10)()
         _check(self.lib.rac_batch_info(self.h, v), "rac_batch_info")
         return dict(lanes=v[0], instances=v[1], gram_tasks=v[2], inverse_tasks=v[3], unroll=v[4], graph=v[5],
-                    team_size=v[6], teams=v[7], solo_groups=v[8])
+                    team_size=v[6], teams=v[7], solo_groups=v[8], assembly_slots=v[9])
 
 
 def solve_batch(probs, lanes, *, s=64, seed=0, precision=PREC_FP64, beta_mode=BETA_FIXED, rb_mu=10.0, rb_tau=2.0,

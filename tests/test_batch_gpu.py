@@ -215,11 +215,41 @@ def test_batch_phase_timing_counts_every_launch():
     b.set_timing(True)
     b.run()
     ph = b.timing()
-    assert ph["sweep"][1] == 20 and ph["gram"][1] == 20 and ph["factor"][1] == 20 and ph["check"][1] == 2
+    # the Grams and inverses of a chunk are one launch each when every iteration has its slot
+    na = 2 if b.info()["assembly_slots"] == 10 else 20
+    assert ph["sweep"][1] == 20 and ph["gram"][1] == na and ph["factor"][1] == na and ph["check"][1] == 2
     assert all(ms > 0 for ms, cnt in ph.values() if cnt)
     res, x, z, xi = b.lane(0)
     ref = oracle_lane(ops[lanes[0][0]], lanes[0], s=32, seed=1, max_iter=20, check_every=10)
     assert rel(z, ref.z) < 1e-8                       # timing does not change the iteration
+
+
+@pytest.mark.parametrize("s", [32, 64])
+def test_chunk_assembly_matches_per_iteration_assembly(s, monkeypatch):
+    """The Grams and inverses of a whole chunk formed at its start in one launch each (a
+    slot per iteration), and at each iteration into one slot: bit-identical iterates and
+    the same Assumption 2.1 failure report (its iteration counted from the chunk's start)."""
+    ws, gps, ops, lanes = en_batch(ninst=3, lanes_per=2, seed=17, s=s)
+    h = np.zeros(ws[2].n)
+    h[5] = -1e4
+    gps[2] = racmb.regression_problem(ws[2].D, ws[2].y, lam=ws[2].lam, alpha=0.5, h=h)
+    outs = []
+    for slots in (10, 1):
+        if slots == 1:
+            monkeypatch.setenv("RACMB_ASSEMBLY_SLOTS", "1")
+        else:
+            monkeypatch.delenv("RACMB_ASSEMBLY_SLOTS", raising=False)
+        b = racmb.Batch(gps, lanes, s=s, seed=3, beta_mode=racmb.BETA_RESBAL, max_iter=40, check_every=10,
+                        use_graph=True)
+        assert b.info()["assembly_slots"] == slots
+        b.run()
+        outs.append([b.lane(u, allow_not_pd=True) for u in range(len(lanes))])
+        b.close()
+    for u, ((ra, *va), (rb, *vb)) in enumerate(zip(*outs)):
+        assert (ra.iters, ra.status, ra.fail_iter, ra.fail_block) == (rb.iters, rb.status, rb.fail_iter, rb.fail_block)
+        for p, q in zip(va, vb):
+            assert np.array_equal(p, q), u
+    assert any(r.fail_iter >= 0 for r, *_ in outs[0]) and any(r.fail_iter < 0 for r, *_ in outs[0])
 
 
 def test_solo_and_team_groups_in_one_launch():
