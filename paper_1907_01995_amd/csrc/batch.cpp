@@ -111,7 +111,7 @@ struct rac_batch_s {
   int32_t* dblk_team = nullptr;
   int32_t* dblk_member = nullptr;
   TGroup* dgroups = nullptr;
-  int2* dkkt_tasks = nullptr;   // (group, 64-column chunk) of the grouped KKT check
+  int2* dkkt_tasks = nullptr;   // (group, pair of 64-column chunks) of the grouped KKT check
   int nkkt_tasks = 0;
   int32_t* dteam_off = nullptr;
   int32_t* dteam_list = nullptr;
@@ -802,7 +802,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
            b->buf.alloc(&b->TA.delta, (size_t)maxt * 2 * 1024) && b->buf.alloc(&b->TA.flags, (size_t)maxt * 128) &&
            b->buf.alloc(&b->TA.abort_flag, 1);
       if (!ok) return fail(RAC_ERR_NOMEM);
-      // Grouped KKT tasks (group, 64-column chunk).  Workgroups go to the eight XCDs in
+      // Grouped KKT tasks (group, pair of 64-column chunks).  Workgroups go to the eight XCDs in
       // turn (workgroup k to XCD k mod 8), so the chunks of a group are dealt to one
       // XCD's queue (its u is then read into one L2), the largest groups first onto the
       // least loaded queue, and the queues are interleaved (an exhausted queue's turns
@@ -817,7 +817,7 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
         std::vector<std::vector<int2>> xq(8);
         std::vector<double> load(8, 0.0);
         for (int g : order) {
-          const int64_t nch = (inst[b->hgroups[g].inst].n + 63) / 64;
+          const int64_t nch = (inst[b->hgroups[g].inst].n + 127) / 128;
           const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
           for (int64_t ch = 0; ch < nch; ++ch) xq[x].push_back(make_int2(g, (int)ch));
           load[x] += (double)nch * (double)rows_of(g);

@@ -194,7 +194,7 @@ constexpr int64_t kSoloRows = 4000;
 // Workgroups of the team sweep that can be resident at once (0 if NT unsupported).
 int tsweep_max_resident(int32_t dtype, int NT);
 hipError_t launch_tsweep(const BatchArgs& b, const TeamArgs& ta, int t, hipStream_t st);
-// KKT terms of lane groups, one workgroup per (group, 64-column chunk) task.
+// KKT terms of lane groups, one workgroup per (group, pair of 64-column chunks) task.
 hipError_t launch_gkkt(const BatchArgs& b, const TGroup* groups, const int2* tasks, int ntasks, hipStream_t st);
 
 hipError_t launch_bperm(const BatchArgs& b, hipStream_t st);

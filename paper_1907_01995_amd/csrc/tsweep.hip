@@ -798,18 +798,20 @@ __global__ void __launch_bounds__(NW * 64) k_tsweep(BatchArgs B, TeamArgs TA, in
 }
 
 // ---------------------------------------------------------------------------
-// KKT terms of a lane group: one workgroup per (group, chunk of 64 columns).
-// P = F_chunk' [u_1 .. u_16] over all rows on the matrix cores (one read of the
-// data for the whole group; wavefront v takes tiles v, v+4, ...), then the
-// per-column terms of every active lane and their maxima / sums over the chunk,
-// written where the per-lane control kernel reads them (kpart[lane][chunk][10]).
+// KKT terms of a lane group: one workgroup per (group, pair of 64-column chunks).
+// P = F_pair' [u_1 .. u_16] over all rows on the matrix cores (one read of the
+// data for the whole group, and of u for two chunks; wavefront v takes tiles v,
+// v+4, ...), then, chunk by chunk, the per-column terms of every active lane and
+// their maxima / sums over the chunk, written where the per-lane control kernel
+// reads them (kpart[lane][chunk][10]).
 template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_gkkt(BatchArgs B, const TGroup* __restrict__ groups,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_gkkt(BatchArgs B, const TGroup* __restrict__ groups,
                                               const int2* __restrict__ tasks) {
+  constexpr int NCT = 8;                     // 16-column tiles of the pair
   const int2 tk = tasks[blockIdx.x];
   if (tk.x < 0) return;                      // an empty task (keeps the others on their XCDs)
   const TGroup* G = groups + tk.x;
-  const int chunk = tk.y;
+  const int pair = tk.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, j = lane & 15;
   const int nl = G->nl;
   bool any = false;
@@ -817,34 +819,34 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   if (!any) return;                          // uniform: the workgroup leaves together
   const BInst I = B.inst[G->inst];
   const T* F = (const T*)I.F;
-  const int64_t rows = I.rows, ldF = I.ldF, c0 = 64 * (int64_t)chunk;
-  const int nc = I.n - c0 < 64 ? (int)(I.n - c0) : 64;
+  const int64_t rows = I.rows, ldF = I.ldF, c0 = 128 * (int64_t)pair;
+  const int nc = I.n - c0 < 128 ? (int)(I.n - c0) : 128;   // columns of the pair
   const bool vec = G->vec4 != 0;
   const int uj = j < nl ? G->lane[j] : -1;
   const bool actj = uj >= 0 && B.sc[uj].status == 0;
   const double* Uj = B.U + (actj ? B.units[uj].uoff : 0);
-  f64x4 acc[4];
+  f64x4 acc[NCT];
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) acc[ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = (f64x4){0.0, 0.0, 0.0, 0.0};
   const int64_t ntile = (rows + 15) >> 4;
   if (G->span) {
     // branch-free tile loads, KD - 1 tiles in flight per wavefront: addresses clamped
     // into the columns (rows past the end and tiles past the wavefront's last read the
-    // column's last aligned quad, u its last row; columns past the chunk read its last
+    // column's last aligned quad, u its last row; columns past the pair read its last
     // column, whose products are not used) and rows past the end zeroed where consumed
-    constexpr int KD = sizeof(T) == 2 ? 4 : (sizeof(T) == 4 ? 3 : 2);
+    constexpr int KD = 2;
     const int mine = ntile > wave ? (int)((ntile - wave + 3) / 4) : 0;
-    const T* fcg[4];
+    const T* fcg[NCT];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) fcg[ct] = F + (c0 + (16 * ct + j < nc ? 16 * ct + j : nc - 1)) * ldF;
+    for (int ct = 0; ct < NCT; ++ct) fcg[ct] = F + (c0 + (16 * ct + j < nc ? 16 * ct + j : nc - 1)) * ldF;
     const double* Ubase = actj ? Uj : B.U;
-    RawQ<T> gq[KD][4];
+    RawQ<T> gq[KD][NCT];
     double uv[KD][4];
-    auto gload = [&](int sidx, RawQ<T> (&dst)[4], double (&ud)[4]) {
+    auto gload = [&](int sidx, RawQ<T> (&dst)[NCT], double (&ud)[4]) {
       const int64_t r0 = 16 * (int64_t)(wave + 4 * sidx) + 4 * q;
       const int64_t rc = r0 < ldF - 4 ? r0 : ldF - 4;
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct) dst[ct] = gld_quad<T>(fcg[ct] + rc);
+      for (int ct = 0; ct < NCT; ++ct) dst[ct] = gld_quad<T>(fcg[ct] + rc);
 #pragma unroll
       for (int i = 0; i < 4; ++i) ud[i] = gld<double>(Ubase + (r0 + i < rows ? r0 + i : rows - 1));
     };
@@ -856,17 +858,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         const int sidx = base + k;
         gload(sidx + KD - 1, gq[(k + KD - 1) % KD], uv[(k + KD - 1) % KD]);
         const int64_t nv = rows - (16 * (int64_t)(wave + 4 * sidx) + 4 * q);
-        RawQ<T> fq[4];
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) fq[ct] = quad_keep<T>(gq[k][ct], nv);
         double ux[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) ux[i] = actj && i < nv ? uv[k][i] : 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int ct = 0; ct < NCT; ++ct) {
+          const RawQ<T> fq = quad_keep<T>(gq[k][ct], nv);
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct)
-            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(quad_at<T>(fq[ct], i), ux[i], acc[ct], 0, 0, 0);
+          for (int i = 0; i < 4; ++i)
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(quad_at<T>(fq, i), ux[i], acc[ct], 0, 0, 0);
+        }
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -880,7 +881,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
     for (int i = 0; i < 4; ++i) uv[i] = (actj && i < nv) ? uv[i] : 0.0;
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
+    for (int ct = 0; ct < NCT; ++ct) {
       const int c = 16 * ct + j;
       const bool cv = c < nc && nv > 0;
       const RawQ<T> f = ld_quad<T>(F, cv ? (c0 + c) * ldF + r0 : 0, cv ? nv : 0, vec);
@@ -891,44 +892,50 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   }
   __shared__ double red[4][16][64];
   __shared__ double mred[16][16][10];
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) red[wave][4 * ct + r][lane] = acc[ct][r];
-  __syncthreads();
   // thread tid: slot tid & 15, columns 16 (tid >> 6) + 4 rr + ((tid & 63) >> 4), rr < 4
   const int slot = tid & 15, ln = tid & 63;
   const int us = slot < nl ? G->lane[slot] : -1;
   const bool acts = us >= 0 && B.sc[us].status == 0;
-  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (acts) {
-    const BUnit* D = B.units + us;
-    const double mu = B.sc[us].mu;
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int el = 4 * (tid >> 6) + rr;
-      const int cl = 16 * (el >> 2) + 4 * (el & 3) + (ln >> 4);
-      if (cl < nc) {
-        const double v = red[0][el][ln] + red[1][el][ln] + red[2][el][ln] + red[3][el][ln];
-        const int64_t col = c0 + cl;
-        kkt_column_terms(v, D->Ns, D->h ? D->h[col] : 0.0, D->c[col], D->a ? D->a[col] : 0.0,
-                         B.X[D->xoff + col], B.Z[D->xoff + col], B.XI[D->xoff + col], mu, D->prox, D->lam,
-                         D->alpha, D->lo, D->hi, m);
+  for (int h = 0; h < 2; ++h) {              // the pair's chunks, one after the other
+    const int chunk = 2 * pair + h, nch = nc - 64 * h;
+    if (nch <= 0) break;                       // uniform
+    if (h > 0) __syncthreads();                // the previous chunk's reads of red and mred are done
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave][4 * ct + r][lane] = acc[4 * h + ct][r];
+    __syncthreads();
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (acts) {
+      const BUnit* D = B.units + us;
+      const double mu = B.sc[us].mu;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int el = 4 * (tid >> 6) + rr;
+        const int cl = 16 * (el >> 2) + 4 * (el & 3) + (ln >> 4);
+        if (cl < nch) {
+          const double v = red[0][el][ln] + red[1][el][ln] + red[2][el][ln] + red[3][el][ln];
+          const int64_t col = c0 + 64 * h + cl;
+          kkt_column_terms(v, D->Ns, D->h ? D->h[col] : 0.0, D->c[col], D->a ? D->a[col] : 0.0,
+                           B.X[D->xoff + col], B.Z[D->xoff + col], B.XI[D->xoff + col], mu, D->prox, D->lam,
+                           D->alpha, D->lo, D->hi, m);
+        }
       }
     }
-  }
 #pragma unroll
-  for (int e = 0; e < 10; ++e) mred[slot][tid >> 4][e] = m[e];
-  __syncthreads();
-  if (tid < 16 && tid < nl) {
-    const int u = G->lane[tid];
-    if (B.sc[u].status == 0) {
-      double* outp = B.kpart + ((int64_t)u * B.KC + chunk) * 10;
+    for (int e = 0; e < 10; ++e) mred[slot][tid >> 4][e] = m[e];
+    __syncthreads();
+    if (tid < 16 && tid < nl) {
+      const int u = G->lane[tid];
+      if (B.sc[u].status == 0) {
+        double* outp = B.kpart + ((int64_t)u * B.KC + chunk) * 10;
 #pragma unroll
-      for (int e = 0; e < 10; ++e) {
-        double v = mred[tid][0][e];
-        for (int k = 1; k < 16; ++k) v = e < 9 ? fmax(v, mred[tid][k][e]) : v + mred[tid][k][e];
-        outp[e] = v;
+        for (int e = 0; e < 10; ++e) {
+          double v = mred[tid][0][e];
+          for (int k = 1; k < 16; ++k) v = e < 9 ? fmax(v, mred[tid][k][e]) : v + mred[tid][k][e];
+          outp[e] = v;
+        }
       }
     }
   }
