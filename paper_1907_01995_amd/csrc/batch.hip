@@ -7,7 +7,7 @@
 //
 // Kernels (one launch each per iteration, all lanes at once):
 //   k_bperm   one workgroup per (instance, iteration of the chunk): the
-//             instance's keys sorted by a bitonic network in LDS (n <= 8192);
+//             instance's keys sorted by a distribution sort in LDS (n <= 8192);
 //   k_bgram   (assemble.hip) one workgroup per (instance, block);
 //   k_binv    one wavefront per (lane, block): the block matrix in registers,
 //             one column per lane, inverted by Gauss-Jordan with symmetric
@@ -57,45 +57,82 @@ __device__ __forceinline__ double bmax(double v, double* sh) {
 }
 
 // ---------------------------------------------------------------------------
-// Partitions: bitonic sort of (key, index) pairs in LDS, padded to a power of
-// two with keys (~0, INT_MAX) that sort last.  The order is the exact
-// lexicographic order, so it equals the single-instance permutation.
+// Partitions: one workgroup per (instance, iteration of the chunk) sorts the
+// instance's variables by (key, index) with a distribution sort in LDS.  Keys
+// are uniform 64-bit values, so their top lg bits pick one of nb = 2^lg >= n
+// buckets (about one key per bucket): the buckets are counted, scanned into
+// output ranges, filled through per-bucket cursors (in arrival order), and each
+// variable's position inside its bucket is its rank among the bucket's members
+// under (key, index), with the members' keys recomputed from their indices.  The
+// order is the exact lexicographic order, so it equals the single-instance
+// permutation, whatever the atomics' arrival order.
+__device__ __forceinline__ uint32_t key_bucket(uint64_t key, int lg) {
+  return lg == 0 ? 0u : (uint32_t)(key >> (64 - lg));
+}
+
 __global__ void __launch_bounds__(1024) k_bperm(const BInst* __restrict__ inst, uint64_t seed,
                                                 const int64_t* __restrict__ kdev, int32_t* __restrict__ perm,
                                                 const int32_t* __restrict__ inst_active, int np2max) {
-  const int i = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
+  const int i = blockIdx.x, t = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (!inst_active[i]) return;
   const BInst I = inst[i];
   const int n = (int)I.n;
-  int np2 = 1;
-  while (np2 < n) np2 <<= 1;
+  int lg = 0;
+  while ((1 << lg) < n) ++lg;
+  const int nb = 1 << lg;                                   // nb <= np2max
   extern __shared__ unsigned char smem[];
-  uint64_t* key = reinterpret_cast<uint64_t*>(smem);
-  int32_t* idx = reinterpret_cast<int32_t*>(key + np2max);
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(smem);       // [np2max]: counts, then cursors
+  uint32_t* off = cnt + np2max;                            // [np2max + 1]: bucket starts
+  int32_t* slot = reinterpret_cast<int32_t*>(off + np2max + 1);   // [np2max]: members, by bucket
+  __shared__ uint32_t wsum[16];
   const uint64_t iter = (uint64_t)(*kdev + t);
-  for (int j = tid; j < np2; j += 1024) {
-    key[j] = j < n ? perm_key(seed, I.key_instance, iter, (uint64_t)j) : ~0ULL;
-    idx[j] = j < n ? j : 0x7fffffff;
+  for (int b = tid; b < nb; b += 1024) cnt[b] = 0u;
+  __syncthreads();
+  for (int j = tid; j < n; j += 1024) atomicAdd(&cnt[key_bucket(perm_key(seed, I.key_instance, iter, (uint64_t)j), lg)], 1u);
+  __syncthreads();
+  // exclusive scan of the counts: a contiguous segment per thread, the segments'
+  // sums scanned within each wavefront and then over the wavefronts
+  const int per = (nb + 1023) / 1024;
+  const int lo = tid * per < nb ? tid * per : nb, hi = lo + per < nb ? lo + per : nb;
+  uint32_t seg = 0u;
+  for (int b = lo; b < hi; ++b) seg += cnt[b];
+  uint32_t inc = seg;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0u;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  uint32_t run = base + inc - seg;
+  for (int b = lo; b < hi; ++b) {
+    const uint32_t c = cnt[b];
+    off[b] = run;
+    cnt[b] = run;                                           // the bucket's cursor
+    run += c;
+  }
+  if (tid == 0) off[nb] = (uint32_t)n;
+  __syncthreads();
+  for (int j = tid; j < n; j += 1024) {
+    const uint32_t b = key_bucket(perm_key(seed, I.key_instance, iter, (uint64_t)j), lg);
+    slot[atomicAdd(&cnt[b], 1u)] = j;
   }
   __syncthreads();
-  for (int size = 2; size <= np2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int e = tid; e < (np2 >> 1); e += 1024) {
-        const int lo = 2 * stride * (e / stride) + (e % stride), hi = lo + stride;
-        const bool asc = (lo & size) == 0;
-        const uint64_t kl = key[lo], kh = key[hi];
-        const int32_t il = idx[lo], ih = idx[hi];
-        const bool greater = kl > kh || (kl == kh && il > ih);
-        if (greater == asc) {
-          key[lo] = kh; key[hi] = kl;
-          idx[lo] = ih; idx[hi] = il;
-        }
-      }
-      __syncthreads();
-    }
-  }
   int32_t* out = perm + I.poff + (int64_t)t * n;
-  for (int j = tid; j < n; j += 1024) out[j] = idx[j];
+  for (int j = tid; j < n; j += 1024) {
+    const uint64_t key = perm_key(seed, I.key_instance, iter, (uint64_t)j);
+    const uint32_t b = key_bucket(key, lg);
+    const uint32_t s0 = off[b], s1 = off[b + 1];
+    uint32_t rank = 0u;
+    for (uint32_t s = s0; s < s1; ++s) {
+      const int32_t m = slot[s];
+      if (m == j) continue;
+      const uint64_t km = perm_key(seed, I.key_instance, iter, (uint64_t)m);
+      rank += (km < key || (km == key && m < j)) ? 1u : 0u;
+    }
+    out[s0 + rank] = j;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -724,11 +761,11 @@ hipError_t bkkt_launch(const BatchArgs& b, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_bperm(const BatchArgs& b, hipStream_t st) {
-  const size_t lds = (size_t)b.np2 * (sizeof(uint64_t) + sizeof(int32_t));
+  const size_t lds = (size_t)(3 * b.np2 + 1) * sizeof(uint32_t);   // counts, starts, members
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_bperm, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(8192 * (sizeof(uint64_t) + sizeof(int32_t))));
+                                       (int)((3 * 8192 + 1) * sizeof(uint32_t)));
     if (e != hipSuccess) return e;
     attr = true;
   }
