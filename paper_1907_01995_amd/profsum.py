@@ -10,7 +10,7 @@
 value of one counter per dispatch, per kernel.  `traffic` turns the FETCH_SIZE
 and WRITE_SIZE of a kernel (KiB per dispatch) into bytes per launch, each scaled
 by what the same counter reads for the plain device copy of known size that
-`bench.py --calibrate-copy` adds to the run (the copy dispatches within half of
+`bench.py --calibrate-copy` adds to the run (the copy dispatches within 10% of
 the largest), and records a hash of the kernel's sources so that a reader can tell
 whether the counters still describe the current kernel.
 """
@@ -85,12 +85,13 @@ def pmc(path, counter):
 
 def copy_calibration(path, counter):
     """Average counter value of the calibration copies: the copy-kernel dispatches
-    within half of the largest one (the small copies of the run are left out)."""
+    within 10% of the largest one (the calibration copies are the run's largest, all of
+    one size; smaller copies, such as a workload's uploads, are left out)."""
     vals = [v for k, vs in pmc_values(path, counter).items() if "copy" in k.lower() for v in vs]
     if not vals:
         raise SystemExit("no copy kernel in the counter file (run bench.py with --calibrate-copy)")
     top = max(vals)
-    big = [v for v in vals if v >= 0.5 * top]
+    big = [v for v in vals if v >= 0.9 * top]
     return len(big), sum(big) / len(big)
 
 

@@ -30,10 +30,12 @@ COPY = "__amd_rocclr_copyBuffer"
 def test_traffic_scales_each_counter_by_the_calibration_copy(tmp_path):
     copy_bytes = 256 << 20
     # the counter reads half the bytes a copy fetches (scale 2) and all it writes (scale 1);
-    # small copies of the run are left out of the calibration (below half of the largest)
+    # other copies of the run are left out of the calibration, also a workload's upload of
+    # 60% of the calibration size (only copies within 10% of the largest count)
     fetch_rows = [(SWEEP, 1000.0), (SWEEP, 1200.0), (COPY, copy_bytes / 2048.0), (COPY, copy_bytes / 2048.0),
-                  (COPY, 3.0)]
-    write_rows = [(SWEEP, 300.0), (SWEEP, 500.0), (COPY, copy_bytes / 1024.0), (COPY, 1.0)]
+                  (COPY, 0.6 * copy_bytes / 2048.0), (COPY, 3.0)]
+    write_rows = [(SWEEP, 300.0), (SWEEP, 500.0), (COPY, copy_bytes / 1024.0), (COPY, 0.6 * copy_bytes / 1024.0),
+                  (COPY, 1.0)]
     fa, wa = tmp_path / "fetch.csv", tmp_path / "write.csv"
     write_counters(fa, "FETCH_SIZE", fetch_rows)
     write_counters(wa, "WRITE_SIZE", write_rows)
