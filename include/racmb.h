@@ -30,7 +30,10 @@
  *    synchronise that stream before returning.
  *  - Errors are returned as rac_status codes, never thrown across the ABI.
  *    A non-finite scalar argument, a non-positive beta, p < 1 or p > n, and
- *    a block larger than RAC_MAX_BLOCK give RAC_ERR_ARG.
+ *    a block larger than RAC_MAX_BLOCK give RAC_ERR_ARG.  rac_solver_create and
+ *    rac_batch_create also read the problems' device arrays once (F or the sparse
+ *    values or Hd, A, beq, and c, h, a) and give RAC_ERR_ARG if one holds a NaN or an
+ *    infinity (on the null stream, before any other work).
  */
 #ifndef RACMB_H
 #define RACMB_H

@@ -573,6 +573,10 @@ rac_status rac_batch_create(int32_t ninst, const rac_problem* inst, int32_t nlan
     if (dtype != RAC_DT_F64 && dtype != RAC_DT_F32 && dtype != RAC_DT_BF16) return RAC_ERR_ARG;
     if (P.n > maxn) maxn = P.n;
   }
+  for (int i = 0; i < ninst; ++i) {
+    const rac_status v = check_problem_arrays(inst[i]);   // no NaN or infinity in the device arrays
+    if (v != RAC_OK) return v;
+  }
   for (int u = 0; u < nlanes; ++u) {
     const rac_lane& L = lanes[u];
     if (L.problem < 0 || L.problem >= ninst || !std::isfinite(L.beta0) || !(L.beta0 > 0.0)) return RAC_ERR_ARG;

@@ -345,6 +345,12 @@ hipError_t launch_scale_beta(DevScalars* sc, double mult, hipStream_t st);
 hipError_t launch_matvec_F_parts(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,
                                  const double* x, double* u, double* part, int nparts,
                                  hipStream_t st);
+// *flag |= 1 if any of rows x cols elements (column-major, leading dimension ld) is NaN or
+// infinite (BF16: exponent bits all set)
+hipError_t launch_nonfinite(const void* p, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, uint32_t* flag,
+                            hipStream_t st);
+// RAC_ERR_ARG if a device array of a problem holds a NaN or an infinity (one read of it)
+rac_status check_problem_arrays(const rac_problem& P);
 // out = scale F'u
 hipError_t launch_matvec_Ft(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,
                             const double* u, double scale, double* out, hipStream_t st);

@@ -177,6 +177,39 @@ int matvec_parts(int64_t n) {
 
 }  // namespace
 
+// The problem's device arrays hold no NaN or infinity (one read of each on the null
+// stream): F (or the sparse values, or the dense form's Hd, A and beq), c, h and a.
+rac_status rac::check_problem_arrays(const rac_problem& P) {
+  uint32_t* flag = nullptr;
+  if (hipMalloc(&flag, sizeof(uint32_t)) != hipSuccess) return RAC_ERR_NOMEM;
+  hipError_t e = hipMemset(flag, 0, sizeof(uint32_t));
+  auto chk = [&](const void* p, int32_t dtype, int64_t rows, int64_t cols, int64_t ld) {
+    if (e == hipSuccess && p) e = launch_nonfinite(p, dtype, rows, cols, ld, flag, nullptr);
+  };
+  if (P.Hd) {
+    chk(P.Hd, P.H_dtype, P.n, P.n, P.ldH);
+    if (P.meq > 0) {
+      chk(P.A, RAC_DT_F64, P.n, P.meq, P.n);      // row-major meq x n: meq runs of n
+      chk(P.beq, RAC_DT_F64, P.meq, 1, P.meq);
+    }
+  } else if (P.colptr) {
+    int64_t nnz = 0;
+    if (e == hipSuccess) e = hipMemcpy(&nnz, P.colptr + P.n, sizeof(int64_t), hipMemcpyDeviceToHost);
+    chk(P.F, P.F_dtype, nnz, 1, nnz);
+  } else {
+    chk(P.F, P.F_dtype, P.rows, P.n, P.ldF);
+  }
+  chk(P.c, RAC_DT_F64, P.n, 1, P.n);
+  chk(P.h, RAC_DT_F64, P.n, 1, P.n);
+  chk(P.a, RAC_DT_F64, P.n, 1, P.n);
+  uint32_t bad = 0;
+  if (e == hipSuccess) e = hipMemcpy(&bad, flag, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  (void)hipFree(flag);
+  if (e != hipSuccess) return RAC_ERR_DEVICE;
+  return bad ? RAC_ERR_ARG : RAC_OK;
+}
+
+
 struct rac_solver_s {
   rac_problem P{};
   rac_opts O{};
@@ -711,6 +744,8 @@ rac_status rac_solver_create(const rac_problem* prob, const rac_opts* opts, rac_
   if (!out || !opts) return RAC_ERR_ARG;
   *out = nullptr;
   rac_status v = validate_problem(prob);
+  if (v != RAC_OK) return v;
+  v = check_problem_arrays(*prob);
   if (v != RAC_OK) return v;
   rac_opts O = *opts;
   const int64_t n = prob->n;

@@ -510,6 +510,31 @@ hipError_t launch_matvec_F_parts(const void* F, int32_t dtype, int64_t ldF, int6
   }
 }
 
+// Whether any of rows x cols elements (column-major, leading dimension ld, element type
+// dtype) is NaN or infinite: a workgroup per column in turn, the flag raised once per
+// wavefront that saw one.  BF16 values are tested on their exponent bits.
+__global__ void __launch_bounds__(256) k_nonfinite(const void* __restrict__ p, int32_t dtype, int64_t rows,
+                                                   int64_t cols, int64_t ld, uint32_t* flag) {
+  bool bad = false;
+  for (int64_t c = blockIdx.x; c < cols; c += gridDim.x) {
+    const int64_t o = c * ld;
+    for (int64_t r = threadIdx.x; r < rows; r += 256) {
+      if (dtype == RAC_DT_F64) bad |= !isfinite(((const double*)p)[o + r]);
+      else if (dtype == RAC_DT_F32) bad |= !isfinite(((const float*)p)[o + r]);
+      else bad |= (((const uint16_t*)p)[o + r] & 0x7F80u) == 0x7F80u;
+    }
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+hipError_t launch_nonfinite(const void* p, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, uint32_t* flag,
+                            hipStream_t st) {
+  if (rows < 1 || cols < 1) return hipSuccess;
+  const int64_t blocks = cols < 65536 ? cols : 65536;
+  k_nonfinite<<<(unsigned)blocks, 256, 0, st>>>(p, dtype, rows, cols, ld, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_matvec_Ft(const void* F, int32_t dtype, int64_t ldF, int64_t rows, int64_t n,
                             const double* u, double scale, double* out, hipStream_t st) {
   int64_t blocks = (n + 3) / 4;

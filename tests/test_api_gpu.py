@@ -159,3 +159,35 @@ def test_warm_started_lambda_path_matches_oracle_path():
             assert warm[j][i][0].status == racmb.RUN_CONVERGED and cold[j][i][0].status == racmb.RUN_CONVERGED
             np.testing.assert_allclose(warm[j][i][2], cold[j][i][2], rtol=1e-6, atol=1e-8)
     assert sum(it_w) <= sum(it_c)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_nonfinite_device_arrays_are_rejected(storage):
+    """rac_solver_create and rac_batch_create read the problem's device arrays once and
+    reject a NaN or an infinity in F, c or h (RAC_ERR_ARG); the unmodified problem is
+    accepted."""
+    w = W.gaussian_en(300, 40, 0.1, 0.05, 0.1, 0.5, 77, 16, storage)
+    lane = [(0, racmb.PROX_EN, w.lam, 0.5, 1.0)]
+
+    def fresh():
+        return racmb.regression_problem(w.D, w.y, lam=w.lam, alpha=0.5, storage=storage, h=np.zeros(w.n))
+
+    gp = fresh()
+    racmb.Solver(gp, s=16, max_iter=1).close()
+    racmb.Batch([gp], lane, s=16, max_iter=1).close()
+    for what in ("F", "c", "h"):
+        for bad in (float("nan"), float("inf"), -float("inf")):
+            gp = fresh()
+            t = getattr(gp, what)
+            if what == "F":
+                t[3, 5] = bad          # column 3, row 5
+            else:
+                t[7] = bad
+            torch.cuda.synchronize()
+            say(storage, what, bad)
+            with pytest.raises(racmb.RacError) as e:
+                racmb.Solver(gp, s=16, max_iter=1)
+            assert e.value.code == racmb.RAC_ERR_ARG
+            with pytest.raises(racmb.RacError) as e:
+                racmb.Batch([gp], lane, s=16, max_iter=1)
+            assert e.value.code == racmb.RAC_ERR_ARG
