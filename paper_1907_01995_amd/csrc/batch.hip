@@ -301,7 +301,7 @@ __device__ __forceinline__ void pivot_step(int k, double (&S)[4][4], bool& faile
   S[k][k] = -invd;
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_binv64(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_binv64(const BUnit* __restrict__ units, const int2* __restrict__ tasks,
                                                 int ntasks, const int32_t* __restrict__ perm, BinvSlots sl,
                                                 const double* __restrict__ G, DevScalars* sc,
                                                 double* __restrict__ Minv) {
@@ -311,10 +311,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   typedef double f64x4 __attribute__((ext_vector_type(4)));
   constexpr int SP = 64;
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: the task's values go to scalars
-  const int q = lane >> 4, c = lane & 15;
-  __shared__ double abuf[4][SP], hbuf[4][SP], nbuf[4][16];
-  const int task = blockIdx.x * 4 + wave;
+  constexpr int wave = 0;                      // one wavefront per workgroup: a finished task's
+  const int q = lane >> 4, c = lane & 15;      // slot is reused at once
+  __shared__ double abuf[1][SP], hbuf[1][SP], nbuf[1][16];
+  const int task = blockIdx.x;
   if (task >= ntasks) return;   // wavefront-uniform; the kernel has no workgroup barrier
   const int2 tk = tasks[task];
   if (sc[tk.x].status != 0) return;
@@ -781,7 +781,7 @@ hipError_t launch_binv(const BatchArgs& b, int t0, int nt, int tk0, hipStream_t 
   switch (b.sp) {
     case 16: k_binv<16><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, sl, b.G, b.sc, b.Minv); break;
     case 32: k_binv<32><<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, sl, b.G, b.sc, b.Minv); break;
-    case 64: k_binv64<<<grid, 256, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, sl, b.G, b.sc, b.Minv); break;
+    case 64: k_binv64<<<dim3((unsigned)b.ninv, (unsigned)nt), 64, 0, st>>>(b.units, b.inv_tasks, b.ninv, b.perm, sl, b.G, b.sc, b.Minv); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
