@@ -365,7 +365,7 @@ template <typename T, int A, int B>
 __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
   constexpr int KM = (NC + P - 1) / P;            // Minv entries per thread
-  constexpr bool MREG = KM <= 16;                 // keep the next block's inverse in registers
+  constexpr bool MREG = KM <= 16;                 // keep the next block's inverse in registers, else in LDS
   constexpr int NL = 128 / P > 32 ? 32 : 128 / P;  // partial loads per batch (register budget: at most 32)
   const int K = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -381,6 +381,9 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   __shared__ int32_t sh_cols[2][kMaxBlock];
   __shared__ int sh_abort;
   __shared__ double sh_a[2][kMaxBlock];          // equality-row entries of this block's and the next block's columns
+  // blocks of more than 64 columns: the block's inverse (sp x sp, row stride sp), copied
+  // into LDS while the group waits for the partials
+  __shared__ __attribute__((aligned(16))) double sh_m[MREG ? 2 : kMaxBlock * kMaxBlock];
   const double beta = *s.beta_ptr;
   const double mu = s.sc->mu;
   double t = s.sc->t;
@@ -419,6 +422,21 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
         const int k = part * KM + e;
         mreg[e] = (jc < sbi && k < sbi) ? Mi[(int64_t)k * s.sp + jc] : 0.0;
       }
+    }
+  };
+  // The whole stored inverse of the block at position i (sp * sp doubles, sp a power of
+  // two from 16 to 128, so whole 1 KB runs) goes to LDS through the load-to-LDS path:
+  // wavefront w copies runs w, w + 4, ..., lane l bytes [16 l, 16 l + 16) of each.  No
+  // registers hold it, so nothing waits for it before the solve (the vector loads
+  // issued after it, the partials' polls, return after it).
+  auto minv_to_lds = [&](int64_t i) {
+    if constexpr (!MREG) {
+      const char* src = reinterpret_cast<const char*>(s.Minv + bid(i) * (int64_t)s.sp * s.sp) + 16 * lane;
+      const int nrun = s.sp * s.sp / 128;
+      for (int r = wave; r < nrun; r += 4)
+        __builtin_amdgcn_global_load_lds(src + (int64_t)r * 1024,
+                                         (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(sh_m) + r * 1024),
+                                         16, 0, 0);
     }
   };
   double ga = 0.0, gbn = 0.0;
@@ -510,6 +528,9 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
       }
     }
     __syncthreads();
+    // issued after the barrier: a barrier waits for the copy to land (the previous
+    // block's solve has finished reading sh_m, barrier at its end)
+    minv_to_lds(i);
     // This block's partials first; then the next block's tile and gradient
     // inputs, which stream in during the solve and the update (loads return in
     // order, so nothing below waits for them before the end of the block).
@@ -532,6 +553,9 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
 #pragma unroll
         for (int e = 0; e < NL; ++e) acc += v[e];
       }
+      // the copy of the inverse was issued before the polls, which have all returned:
+      // wait for it here, before the next block's loads are issued behind it
+      if constexpr (!MREG) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
       fetch(more ? i + 1 : i, nxt);
       if (tid < sb1) {
         const int col = sh_cols[(i + 1) & 1][tid];
@@ -578,20 +602,18 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
           acc += mreg[e + 1] * g2.y;
         }
       } else {
-        // the inverse's entries in batches of 16 loads in flight, then summed in k order
-        const double* Mi = s.Minv + bid(i) * (int64_t)s.sp * s.sp;
-        if (jc < sb) {
-          for (int k0 = part; k0 < sb; k0 += 16 * P) {
-            double mv[16];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-              const int k = k0 + e * P;
-              mv[e] = k < sb ? Mi[(int64_t)k * s.sp + jc] : 0.0;
-            }
-#pragma unroll
-            for (int e = 0; e < 16; ++e)
-              if (k0 + e * P < sb) acc += mv[e] * sh_g[k0 + e * P];
-          }
+        // the part's KM consecutive rows of column jc from the copy in LDS (consecutive
+        // threads read consecutive columns); rows past the block are not read
+        const int k0 = part * KM;
+        const double* mk = sh_m + (int64_t)k0 * s.sp + jc;
+        const double* gk = sh_g + k0;
+#pragma unroll 8
+        for (int e = 0; e < KM; e += 2) {
+          const double2 g2 = *reinterpret_cast<const double2*>(gk + e);
+          const double m0 = k0 + e < sb ? mk[(int64_t)e * s.sp] : 0.0;
+          const double m1 = k0 + e + 1 < sb ? mk[(int64_t)(e + 1) * s.sp] : 0.0;
+          acc += m0 * g2.x;
+          acc += m1 * g2.y;
         }
       }
       sh_pg[part * NC + jc] = acc;
