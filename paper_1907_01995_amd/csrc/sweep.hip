@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   __shared__ double sh_a[2][kMaxBlock];          // equality-row entries of this block's and the next block's columns
   // blocks of more than 64 columns: the block's inverse (sp x sp, row stride sp), copied
   // into LDS while the group waits for the partials
-  __shared__ __attribute__((aligned(16))) double sh_m[MREG ? 2 : kMaxBlock * kMaxBlock];
+  __shared__ __attribute__((aligned(16))) double sh_m[MREG ? 2 : NC * NC];
   const double beta = *s.beta_ptr;
   const double mu = s.sc->mu;
   double t = s.sc->t;
