@@ -69,7 +69,7 @@ template <typename T, int MODE, int SP>
 __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, int64_t rows, int64_t n,
                                           int64_t p, const int32_t* __restrict__ perm, int blk, int chunk,
                                           int R, int vec, double* __restrict__ out,
-                                          PackDst pk = PackDst{}) {
+                                          PackDst pk = PackDst{}, bool mirror = false) {
   typedef GramTraits<MODE> Tr;
   typedef typename Tr::E E;
   typedef typename Tr::Acc Acc;
@@ -250,7 +250,10 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
     }
     __syncthreads();
   }
-  // write the partial lower tiles in FP64
+  // write the partial lower tiles in FP64.  With `mirror` (a whole Gram, R = 1) every
+  // strictly lower entry is also written to its transposed place and the diagonal tiles'
+  // upper halves are left to those writes: the stored matrix is exactly symmetric, its
+  // lower triangle unchanged, and readers can take any row whole
 #pragma unroll
   for (int q = 0; q < MAXP; ++q) {
     if (wave + 4 * q < NPAIR) {
@@ -259,7 +262,9 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ F, int64_t ldF, 
         int row, col = ptj[q] * 16 + (lane & 15);
         if constexpr (MODE == G_F64) row = pti[q] * 16 + 4 * i + (lane >> 4);   // f64 output layout
         else row = pti[q] * 16 + 4 * (lane >> 4) + i;                           // f32 output layout
-        out[(int64_t)row * SP + col] = (double)acc[q][i];
+        const double v = (double)acc[q][i];
+        if (!mirror || row >= col) out[(int64_t)row * SP + col] = v;
+        if (mirror && row > col) out[(int64_t)col * SP + row] = v;
       }
     }
   }
@@ -289,7 +294,7 @@ __global__ void __launch_bounds__(256) k_bgram(const BInst* __restrict__ inst, c
   if (!inst_active[tk.x]) return;
   const BInst I = inst[tk.x];
   gram_body<T, MODE, SP>((const T*)I.F, I.ldF, I.rows, I.n, I.p, perm + I.poff + (int64_t)t * I.n, tk.y,
-                         0, 1, I.vec, G + (I.goff + tk.y) * (int64_t)SP * SP);
+                         0, 1, I.vec, G + (I.goff + tk.y) * (int64_t)SP * SP, PackDst{}, true);
 }
 
 // Position of block blk in the solve order of an RP iteration (the failure report

@@ -8,7 +8,9 @@
 // Kernels (one launch each per iteration, all lanes at once):
 //   k_bperm   one workgroup per (instance, iteration of the chunk): the
 //             instance's keys sorted by a distribution sort in LDS (n <= 8192);
-//   k_bgram   (assemble.hip) one workgroup per (instance, block);
+//   k_bgram   (assemble.hip) one workgroup per (instance, block), the Gram
+//             stored whole (exactly symmetric) so that the inverse kernels
+//             read its rows with coalesced loads;
 //   k_binv    one wavefront per (lane, block): the block matrix in registers,
 //             one column per lane, inverted by Gauss-Jordan with symmetric
 //             pivots; the pivot row (equal to the pivot column) is gathered
@@ -176,12 +178,13 @@ __global__ void __launch_bounds__(256) k_binv(const BUnit* __restrict__ units, c
   double* buf = rowbuf[wave];
   if (U.a && j < SP) buf[j] = aj;
   __builtin_amdgcn_wave_barrier();
-  // the Gram's lower triangle, all SP loads of a lane in flight at once (addresses inside
-  // the block's SP x SP matrix even for lanes past SP; entries outside the block unused)
+  // column j of the Gram (stored whole and exactly symmetric, so row i of the column is
+  // the lower entry), all SP loads of a lane in flight at once (addresses inside the
+  // block's SP x SP matrix even for lanes past SP; entries outside the block unused)
   double col[SP];
   const int jl = j < SP ? j : SP - 1;
 #pragma unroll
-  for (int i = 0; i < SP; ++i) col[i] = Gb[i >= jl ? i * SP + jl : jl * SP + i];
+  for (int i = 0; i < SP; ++i) col[i] = Gb[i * SP + jl];
 #pragma unroll
   for (int i = 0; i < SP; ++i) {
     double v;
@@ -339,7 +342,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + 4 * r + q, j = 16 * J + c;
-        m[I][J][r] = Gb[i >= j ? i * SP + j : j * SP + i];   // the Gram's lower triangle
+        m[I][J][r] = Gb[i * SP + j];   // the Gram is stored whole and exactly symmetric
       }
   __builtin_amdgcn_wave_barrier();
   // M = G/Ns + diag(h) + beta (I + a a'), identity outside the block; branch-free (a
