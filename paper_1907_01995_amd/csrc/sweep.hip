@@ -366,7 +366,10 @@ __global__ void __launch_bounds__(256) k_sweep2(Sweep2Args s) {
   constexpr int NC = 4 * B, P = 256 / NC;         // columns per block (max), threads per column
   constexpr int KM = (NC + P - 1) / P;            // Minv entries per thread
   constexpr bool MREG = KM <= 16;                 // keep the next block's inverse in registers, else in LDS
-  constexpr int NL = 128 / P > 32 ? 32 : 128 / P;  // partial loads per batch (register budget: at most 32)
+  // partial loads per batch: 40 where a tile takes at most 32 registers (one batch then
+  // covers 80 groups at two threads per column), else 32 (more spends registers the tile needs)
+  constexpr int NLMAX = A * B * (int)sizeof(T) / 4 <= 32 ? 40 : 32;
+  constexpr int NL = 128 / P > NLMAX ? NLMAX : 128 / P;
   const int K = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int jc = tid % NC, part = tid / NC;
