@@ -78,8 +78,11 @@ def test_rp_differs_from_rac():
     assert rel(outs[0], outs[1]) > 1e-6
 
 
-@pytest.mark.parametrize("storage,n,s", [("f32", 301, 32), ("f64", 300, 30), ("bf16", 257, 64)])
+@pytest.mark.parametrize("storage,n,s", [("f32", 301, 32), ("f64", 300, 30), ("bf16", 257, 64),
+                                          ("bf16", 700, 128), ("f64", 400, 100)])
 def test_rp_lasso_fixed_beta_parity_ragged(storage, n, s):
+    """Blocks of 100 to 128 columns (ragged: 116 and 117 at n = 700) take the sweep's
+    128-column tiles, whose block inverse is staged in LDS in the drawn order."""
     w = W.lasso(N=2500, n=n, data_seed=12, block_size=s, storage=storage)
     gp, op = en_pair(w)
     b0 = 1.0 / w.N
