@@ -470,7 +470,8 @@ def svm_leg(args, racmb, W, torch):
 
 
 def hidim_leg(args, racmb, W, torch, weights):
-    """High-dimensional LASSO 10000 x 100000: time to KKT <= 1e-6, candidate vs plain FP64."""
+    """High-dimensional LASSO 10000 x 100000: time to KKT <= 1e-6, candidate vs plain FP64, and the
+    candidate's iteration rate with the sweep's roofline (every 8th sweep timed) over 20 iterations."""
     t0 = time.time()
     w = W.lasso_10000x100000("bf16")
     log("hidim workload generated in %.1fs" % (time.time() - t0))
@@ -498,6 +499,15 @@ def hidim_leg(args, racmb, W, torch, weights):
                      "objective": r.objective, "ms_per_iteration": 1e3 * dt / max(r.iters, 1),
                      "iteration_cap": kw["max_iter"]}
         so.close()
+        if name == "candidate":
+            # the candidate's iteration rate and sweep roofline from a short fixed-length run
+            tkw = {k: v for k, v in kw.items() if k != "max_iter"}
+            tkw.update(s=s, beta0=w.beta0, check_every=T_CHECK)
+            ips, msit, phases, _ = throughput(racmb, torch, gp, 20, 2, tkw)
+            out.update(iters_per_s=ips, ms_per_iteration=msit,
+                       roofline=sweep_roofline(phases, w.N, w.n, out["p"], 2, "k_sweep2", "lasso_10000x100000"),
+                       phases=phase_rows(phases, w.N, w.n, out["p"], 2))
+            log("hidim throughput: %.1f it/s, sweep %.1f us" % (ips, out["roofline"]["avg_launch_us"]))
         del so, gp
         torch.cuda.empty_cache()
         log("hidim time-to-tol %s: %s" % (name, out[name]))
